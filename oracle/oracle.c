@@ -1,0 +1,725 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 CPU implementation of the indirect
+ * single-layer collocation BEM of "Dielectric Breakdown Prediction with
+ * GPU-Accelerated BEM" (arXiv 2003.12663), discretised with flat triangles,
+ * piecewise-constant virtual charge sigma and centroid collocation.  It exists
+ * only to check the GPU library: tests, the smoke check and the benchmark's
+ * CPU-baseline leg may call it; the product path never does.  It shares no
+ * source, header or table with the GPU library.
+ *
+ * Every step follows the paper in its own order:
+ *   - single-layer potential and its field (Sec. 2, Eq. SL and the field
+ *     formula that closes Sec. 2),
+ *   - conductor, floating-conductor and dielectric rows (Eqs. Final1-Final4,
+ *     with K' from Eq. ADL),
+ *   - regular / near-singular / singular classification of a (point,
+ *     triangle) pair by circumcentre distance D against eta * circumradius R
+ *     (Sec. 4),
+ *   - GMRES with a diagonal preconditioner (Sec. 5.2),
+ *   - field lines and the streamer-inception integral (Sec. 1, Eq.
+ *     Breakdowncrit).
+ * Readings where the paper is silent are listed with each function.
+ * No blocking, fusion or reordering beyond the definitions is done; OpenMP
+ * only splits independent rows, points or lines across threads.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+enum { ORC_DIRICHLET = 0, ORC_FLOATING = 1, ORC_INTERFACE = 2 };
+
+typedef struct {
+    int64_t n_vert;
+    const double* vert;      /* [n_vert][3] */
+    int64_t n_tri;
+    const int32_t* tri;      /* [n_tri][3], CCW about the normal that points into eps+ */
+    const int32_t* tri_body; /* [n_tri] */
+    int32_t n_body;
+    const int32_t* body_kind;
+    const double* eps_plus;
+    const double* eps_minus;
+    double eta;              /* regular iff D > eta * R */
+    int32_t constraint_form; /* 0: literal Eq. Final4, 1: net charge sum a_i sigma_i */
+} orc_problem;
+
+typedef struct {
+    double h, e_min, start_offset;
+    int32_t max_steps, direction;
+    double alpha_a, alpha_e0, alpha_p, k_str;
+} orc_trace_params;
+
+/* ------------------------------------------------------------------ vectors */
+static void sub3(const double a[3], const double b[3], double o[3]) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+
+/* ------------------------------------------------------------ panel geometry
+ * Flat triangle (v1, v2, v3): area, unit normal (right-hand rule, pointing
+ * into the eps+ side), centroid (the collocation point), circumcentre and
+ * circumradius (precomputed for the Sec. 4 classification).
+ */
+void orc_panel_geometry(const double v1[3], const double v2[3], const double v3[3],
+                        double cen[3], double nrm[3], double* area, double cc[3], double* R)
+{
+    double u[3], w[3], uxw[3];
+    sub3(v2, v1, u);
+    sub3(v3, v1, w);
+    cross3(u, w, uxw);
+    double len = norm3(uxw);
+    *area = 0.5 * len;
+    for (int k = 0; k < 3; ++k) {
+        nrm[k] = uxw[k] / len;
+        cen[k] = (v1[k] + v2[k] + v3[k]) / 3.0;
+    }
+    /* circumcentre: v1 + (|w|^2 (u x w) x u + |u|^2 w x (u x w)) / (2 |u x w|^2) */
+    double t1[3], t2[3];
+    cross3(uxw, u, t1);
+    cross3(w, uxw, t2);
+    double uu = dot3(u, u), ww = dot3(w, w), d = 2.0 * dot3(uxw, uxw);
+    for (int k = 0; k < 3; ++k) cc[k] = v1[k] + (ww * t1[k] + uu * t2[k]) / d;
+    double r[3];
+    sub3(v1, cc, r);
+    *R = norm3(r);
+}
+
+/* ------------------------------------------------------ 7-point Gauss rule
+ * Degree-5 symmetric rule on the triangle (Radon 1948; Stroud T2:5-1):
+ * the centroid with weight 9/40, and the orbits (a, a, 1-2a) for
+ * a = (6 -+ sqrt 15)/21 with weights (155 -+ sqrt 15)/1200.  Weights sum to
+ * one and multiply the area.
+ */
+void orc_quad7_rule(double bary[7][3], double wt[7])
+{
+    double s15 = sqrt(15.0);
+    double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+    double w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+    double pts[7][3] = {
+        {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0},
+        {a1, a1, 1.0 - 2.0 * a1}, {a1, 1.0 - 2.0 * a1, a1}, {1.0 - 2.0 * a1, a1, a1},
+        {a2, a2, 1.0 - 2.0 * a2}, {a2, 1.0 - 2.0 * a2, a2}, {1.0 - 2.0 * a2, a2, a2},
+    };
+    double ws[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
+    for (int q = 0; q < 7; ++q) {
+        wt[q] = ws[q];
+        for (int k = 0; k < 3; ++k) bary[q][k] = pts[q][k];
+    }
+}
+
+/* Regular integration: S = sum_q w_q A / (4 pi |x - y_q|),
+ * F = sum_q w_q A (x - y_q) / (4 pi |x - y_q|^3).  Unit density. */
+void orc_tri_quad7(const double x[3], const double v1[3], const double v2[3], const double v3[3],
+                   double* S, double F[3])
+{
+    double bary[7][3], wt[7];
+    orc_quad7_rule(bary, wt);
+    double cen[3], nrm[3], area, cc[3], R;
+    orc_panel_geometry(v1, v2, v3, cen, nrm, &area, cc, &R);
+    double s = 0.0, f[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 7; ++q) {
+        double y[3], d[3];
+        for (int k = 0; k < 3; ++k) y[k] = bary[q][0] * v1[k] + bary[q][1] * v2[k] + bary[q][2] * v3[k];
+        sub3(x, y, d);
+        double r = norm3(d);
+        double c = wt[q] * area / (4.0 * ORC_PI);
+        s += c / r;
+        for (int k = 0; k < 3; ++k) f[k] += c * d[k] / (r * r * r);
+    }
+    *S = s;
+    for (int k = 0; k < 3; ++k) F[k] = f[k];
+}
+
+/* ------------------------------------------------ analytic flat-triangle integrals
+ * Closed forms for a flat triangle of unit density (Wilton et al. 1984;
+ * Graglia 1993).  With w = (x - v1).n, rho = x - w n and, per edge a -> b,
+ * l = (b - a)/|b - a|, m = l x n (outward in-plane normal),
+ * s- = (a - rho).l, s+ = (b - rho).l, t = (a - rho).m, R- = |x - a|,
+ * R+ = |x - b|, R0^2 = t^2 + w^2:
+ *   f_e    = ln((R+ + s+)/(R- + s-))     (or the equal ln((R- - s-)/(R+ - s+))
+ *                                          when s+ + s- <= 0, to avoid cancellation)
+ *   beta_e = atan2(t s+, R0^2 + |w| R+) - atan2(t s-, R0^2 + |w| R-)
+ *   int 1/R dS        = sum_e t f_e - |w| sum_e beta_e
+ *   grad_x int 1/R dS = -sum_e m f_e - sign(w) n sum_e beta_e
+ * so S = (1/4pi) int 1/R dS and F = -grad S.  on_plane forces w = 0 and
+ * sign(w) = 0 (principal value, used when x is the triangle's own centroid).
+ */
+void orc_tri_analytic(const double x[3], const double v1[3], const double v2[3], const double v3[3],
+                      int on_plane, double* S, double F[3])
+{
+    const double* v[3] = {v1, v2, v3};
+    double e1[3], e2[3], cr[3], n[3];
+    sub3(v2, v1, e1);
+    sub3(v3, v1, e2);
+    cross3(e1, e2, cr);
+    double len = norm3(cr);
+    for (int k = 0; k < 3; ++k) n[k] = cr[k] / len;
+    double xv[3];
+    sub3(x, v1, xv);
+    double w = on_plane ? 0.0 : dot3(xv, n);
+    double rho[3];
+    for (int k = 0; k < 3; ++k) rho[k] = x[k] - w * n[k];
+    double aw = fabs(w);
+    double sum_tf = 0.0, sum_beta = 0.0, mf[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < 3; ++e) {
+        const double* a = v[e];
+        const double* b = v[(e + 1) % 3];
+        double ab[3], l[3], m[3];
+        sub3(b, a, ab);
+        double lab = norm3(ab);
+        for (int k = 0; k < 3; ++k) l[k] = ab[k] / lab;
+        cross3(l, n, m);
+        double ar[3], br[3], xa[3], xb[3];
+        sub3(a, rho, ar);
+        sub3(b, rho, br);
+        double sm = dot3(ar, l), sp = dot3(br, l), t = dot3(ar, m);
+        sub3(x, a, xa);
+        sub3(x, b, xb);
+        double Rm = norm3(xa), Rp = norm3(xb);
+        double R02 = t * t + w * w;
+        double f;
+        if (sp + sm > 0.0)
+            f = log((Rp + sp) / (Rm + sm));
+        else
+            f = log((Rm - sm) / (Rp - sp));
+        double beta = atan2(t * sp, R02 + aw * Rp) - atan2(t * sm, R02 + aw * Rm);
+        sum_tf += t * f;
+        sum_beta += beta;
+        for (int k = 0; k < 3; ++k) mf[k] += m[k] * f;
+    }
+    double sgn = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
+    *S = (sum_tf - aw * sum_beta) / (4.0 * ORC_PI);
+    for (int k = 0; k < 3; ++k) F[k] = (mf[k] + sgn * n[k] * sum_beta) / (4.0 * ORC_PI);
+}
+
+/* ------------------------------------------------------------- problem geometry */
+typedef struct {
+    int64_t N;
+    double* v;     /* [N][9] triangle vertices */
+    double* cen;   /* [N][3] */
+    double* nrm;   /* [N][3] */
+    double* area;  /* [N] */
+    double* cc;    /* [N][3] */
+    double* R;     /* [N] */
+    int32_t* fidx; /* [n_body] floating-body rank or -1 */
+    int32_t n_float;
+} orc_geom;
+
+static void geom_build(const orc_problem* p, orc_geom* g)
+{
+    int64_t N = p->n_tri;
+    g->N = N;
+    g->v = (double*)malloc(sizeof(double) * 9 * N);
+    g->cen = (double*)malloc(sizeof(double) * 3 * N);
+    g->nrm = (double*)malloc(sizeof(double) * 3 * N);
+    g->area = (double*)malloc(sizeof(double) * N);
+    g->cc = (double*)malloc(sizeof(double) * 3 * N);
+    g->R = (double*)malloc(sizeof(double) * N);
+    for (int64_t j = 0; j < N; ++j) {
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k) g->v[9 * j + 3 * c + k] = p->vert[3 * (int64_t)p->tri[3 * j + c] + k];
+        orc_panel_geometry(g->v + 9 * j, g->v + 9 * j + 3, g->v + 9 * j + 6, g->cen + 3 * j, g->nrm + 3 * j,
+                           g->area + j, g->cc + 3 * j, g->R + j);
+    }
+    g->fidx = (int32_t*)malloc(sizeof(int32_t) * (p->n_body > 0 ? p->n_body : 1));
+    g->n_float = 0;
+    for (int32_t b = 0; b < p->n_body; ++b) g->fidx[b] = (p->body_kind[b] == ORC_FLOATING) ? g->n_float++ : -1;
+}
+
+static void geom_free(orc_geom* g)
+{
+    free(g->v); free(g->cen); free(g->nrm); free(g->area); free(g->cc); free(g->R); free(g->fidx);
+}
+
+/* Sec. 4 classification: regular iff D > eta R with D the distance from x to
+ * the circumcentre.  The triangle's own centroid (self) is always singular. */
+static int pair_is_regular(const orc_problem* p, const orc_geom* g, const double x[3], int64_t j)
+{
+    double d[3];
+    sub3(x, g->cc + 3 * j, d);
+    return norm3(d) > p->eta * g->R[j];
+}
+
+/* Potential S and field F at x of triangle j with unit density.  self: x is
+ * the centroid of j itself (principal value). */
+static void pair_SF(const orc_problem* p, const orc_geom* g, const double x[3], int64_t j, int self,
+                    double* S, double F[3])
+{
+    const double* v = g->v + 9 * j;
+    if (!self && pair_is_regular(p, g, x, j))
+        orc_tri_quad7(x, v, v + 3, v + 6, S, F);
+    else
+        orc_tri_analytic(x, v, v + 3, v + 6, self, S, F);
+}
+
+int64_t orc_n_unknowns(const orc_problem* p)
+{
+    int64_t n = p->n_tri;
+    for (int32_t b = 0; b < p->n_body; ++b) n += (p->body_kind[b] == ORC_FLOATING);
+    return n;
+}
+
+/* Sec. 4 classification, exported for tests: 1 = regular, 0 = near or self. */
+int orc_classify(const orc_problem* p, int64_t P, const double* pts, int32_t* regular)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    for (int64_t i = 0; i < P; ++i)
+        for (int64_t j = 0; j < p->n_tri; ++j) regular[i * p->n_tri + j] = pair_is_regular(p, &g, pts + 3 * i, j);
+    geom_free(&g);
+    return 0;
+}
+
+/* One row of the collocation system (Eqs. Final1-Final4), unknowns ordered
+ * [sigma_1..sigma_N, V_1..V_Nfl], constraint rows last.
+ *   conductor row i      : sum_j S_ij sigma_j                     (= V_body)
+ *   floating row i in f  : sum_j S_ij sigma_j - V_f               (= 0)
+ *   interface row i      : (eps+ + eps-)/2 sigma_i
+ *                          + (eps+ - eps-) sum_{j != i} K'_ij sigma_j (= 0)
+ *   constraint row of f  : sum_{i in f} a_i eps+ (sigma_i / 2 + sum_{j != i} K'_ij sigma_j)
+ *                          scaled by 1/(eps+ sum_{i in f} a_i)    (= 0)
+ * with S_ij = S(x_i, tau_j) and K'_ij = n_i . F(x_i, tau_j).  The form
+ * constraint_form = 1 replaces the constraint row by sum_{i in f} a_i sigma_i
+ * (same scaling), its value on a closed body by the Gauss law.
+ */
+static void assemble_row(const orc_problem* p, const orc_geom* g, int64_t row, double* out)
+{
+    int64_t N = p->n_tri, n = N + g->n_float;
+    for (int64_t j = 0; j < n; ++j) out[j] = 0.0;
+    if (row < N) {
+        int64_t i = row;
+        int32_t b = p->tri_body[i];
+        int32_t kind = p->body_kind[b];
+        const double* xi = g->cen + 3 * i;
+        if (kind == ORC_DIRICHLET || kind == ORC_FLOATING) {
+            for (int64_t j = 0; j < N; ++j) {
+                double S, F[3];
+                pair_SF(p, g, xi, j, j == i, &S, F);
+                out[j] = S;
+            }
+            if (kind == ORC_FLOATING) out[N + g->fidx[b]] = -1.0;
+        } else {
+            double ep = p->eps_plus[b], em = p->eps_minus[b];
+            for (int64_t j = 0; j < N; ++j) {
+                if (j == i) {
+                    out[j] = 0.5 * (ep + em);
+                    continue;
+                }
+                double S, F[3];
+                pair_SF(p, g, xi, j, 0, &S, F);
+                out[j] = (ep - em) * dot3(g->nrm + 3 * i, F);
+            }
+        }
+        return;
+    }
+    /* constraint row of floating body f */
+    int32_t f = (int32_t)(row - N), fb = -1;
+    for (int32_t b = 0; b < p->n_body; ++b)
+        if (g->fidx[b] == f) fb = b;
+    double ep = p->eps_plus[fb];
+    double asum = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        if (p->tri_body[i] == fb) asum += g->area[i];
+    double scale = 1.0 / (ep * asum);
+    for (int64_t i = 0; i < N; ++i) {
+        if (p->tri_body[i] != fb) continue;
+        double ai = g->area[i];
+        if (p->constraint_form == 1) {
+            out[i] += scale * ep * ai;
+            continue;
+        }
+        const double* xi = g->cen + 3 * i;
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == i) {
+                out[j] += scale * ai * ep * 0.5;
+                continue;
+            }
+            double S, F[3];
+            pair_SF(p, g, xi, j, 0, &S, F);
+            out[j] += scale * ai * ep * dot3(g->nrm + 3 * i, F);
+        }
+    }
+}
+
+/* Dense row-major system matrix, n x n with n = N + N_float. */
+int orc_assemble(const orc_problem* p, double* A)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    int64_t n = p->n_tri + g.n_float;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < n; ++r) assemble_row(p, &g, r, A + r * n);
+    geom_free(&g);
+    return 0;
+}
+
+/* Selected rows only (for checks at sizes where the full matrix is too big). */
+int orc_assemble_rows(const orc_problem* p, int64_t n_rows, const int64_t* rows, double* out)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    int64_t n = p->n_tri + g.n_float;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < n_rows; ++r) assemble_row(p, &g, rows[r], out + r * n);
+    geom_free(&g);
+    return 0;
+}
+
+/* Right-hand side: V of the body on conductor rows, 0 elsewhere. */
+int orc_rhs(const orc_problem* p, const double* body_V, double* b)
+{
+    int64_t N = p->n_tri, n = orc_n_unknowns(p);
+    for (int64_t r = 0; r < n; ++r) b[r] = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        if (p->body_kind[p->tri_body[i]] == ORC_DIRICHLET) b[i] = body_V[p->tri_body[i]];
+    return 0;
+}
+
+/* ------------------------------------------------------------------ GMRES
+ * Restarted GMRES(m) (Saad & Schultz 1986) with right diagonal (Jacobi)
+ * preconditioning M = diag(A) (a zero diagonal entry is replaced by 1),
+ * classical Gram-Schmidt applied twice, Givens rotations, zero initial guess,
+ * stop when ||b - A x||_2 / ||b||_2 <= tol (checked on the true residual at
+ * each restart, and on the Givens estimate inside a cycle).
+ * Returns 0 on convergence, 1 otherwise; x holds the last iterate.
+ */
+static void matvec(int64_t n, const double* A, const double* x, double* y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        const double* a = A + i * n;
+        for (int64_t j = 0; j < n; ++j) s += a[j] * x[j];
+        y[i] = s;
+    }
+}
+
+int orc_gmres(int64_t n, const double* A, const double* b, double tol, int32_t restart, int32_t max_iter,
+              double* x, int32_t* iters_out, double* relres_out)
+{
+    int m = restart;
+    double* d = (double*)malloc(sizeof(double) * n);
+    double* V = (double*)malloc(sizeof(double) * n * (m + 1));
+    double* H = (double*)calloc((size_t)(m + 1) * m, sizeof(double));
+    double* cs = (double*)malloc(sizeof(double) * m);
+    double* sn = (double*)malloc(sizeof(double) * m);
+    double* g = (double*)malloc(sizeof(double) * (m + 1));
+    double* y = (double*)malloc(sizeof(double) * (m + 1));
+    double* z = (double*)malloc(sizeof(double) * n);
+    double* w = (double*)malloc(sizeof(double) * n);
+    double* h = (double*)malloc(sizeof(double) * (m + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = A[i * n + i];
+        if (d[i] == 0.0) d[i] = 1.0;
+        x[i] = 0.0;
+    }
+    double bnorm = 0.0;
+    for (int64_t i = 0; i < n; ++i) bnorm += b[i] * b[i];
+    bnorm = sqrt(bnorm);
+    int iters = 0, converged = 0;
+    double relres = 0.0;
+    if (bnorm == 0.0) {
+        converged = 1;
+    } else {
+        for (;;) {
+            matvec(n, A, x, w);
+            double beta = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                w[i] = b[i] - w[i];
+                beta += w[i] * w[i];
+            }
+            beta = sqrt(beta);
+            relres = beta / bnorm;
+            if (relres <= tol) { converged = 1; break; }
+            if (iters >= max_iter) break;
+            for (int64_t i = 0; i < n; ++i) V[i] = w[i] / beta;
+            for (int k = 0; k <= m; ++k) g[k] = 0.0;
+            g[0] = beta;
+            memset(H, 0, sizeof(double) * (size_t)(m + 1) * m);
+            int jend = 0;
+            for (int j = 0; j < m; ++j) {
+                for (int64_t i = 0; i < n; ++i) z[i] = V[j * n + i] / d[i];
+                matvec(n, A, z, w);
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int k = 0; k <= j; ++k) {
+                        double s = 0.0;
+                        for (int64_t i = 0; i < n; ++i) s += V[k * n + i] * w[i];
+                        h[k] = s;
+                    }
+                    for (int k = 0; k <= j; ++k) {
+                        for (int64_t i = 0; i < n; ++i) w[i] -= h[k] * V[k * n + i];
+                        H[k * m + j] += h[k];
+                    }
+                }
+                double hn = 0.0;
+                for (int64_t i = 0; i < n; ++i) hn += w[i] * w[i];
+                hn = sqrt(hn);
+                H[(j + 1) * m + j] = hn;
+                if (hn > 0.0)
+                    for (int64_t i = 0; i < n; ++i) V[(j + 1) * n + i] = w[i] / hn;
+                for (int k = 0; k < j; ++k) {
+                    double a = H[k * m + j], c = H[(k + 1) * m + j];
+                    H[k * m + j] = cs[k] * a + sn[k] * c;
+                    H[(k + 1) * m + j] = -sn[k] * a + cs[k] * c;
+                }
+                double a = H[j * m + j], c = H[(j + 1) * m + j];
+                double r = sqrt(a * a + c * c);
+                cs[j] = a / r;
+                sn[j] = c / r;
+                H[j * m + j] = r;
+                H[(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                ++iters;
+                jend = j + 1;
+                if (fabs(g[j + 1]) / bnorm <= tol || iters >= max_iter || hn == 0.0) break;
+            }
+            for (int k = jend - 1; k >= 0; --k) {
+                double s = g[k];
+                for (int q = k + 1; q < jend; ++q) s -= H[k * m + q] * y[q];
+                y[k] = s / H[k * m + k];
+            }
+            for (int64_t i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int k = 0; k < jend; ++k) s += V[k * n + i] * y[k];
+                x[i] += s / d[i];
+            }
+        }
+    }
+    *iters_out = iters;
+    *relres_out = relres;
+    free(d); free(V); free(H); free(cs); free(sn); free(g); free(y); free(z); free(w); free(h);
+    return converged ? 0 : 1;
+}
+
+/* ------------------------------------------------------------- field evaluation
+ * phi(x) = sum_j S_j(x) sigma_j and E(x) = sum_j F_j(x) sigma_j (field formula
+ * closing Sec. 2).  on_panel[p] >= 0 marks x as the centroid of that panel:
+ * the result is then the limit from the eps+ side, principal value plus
+ * sigma_p n_p / 2 (the jump of the single-layer normal derivative, Eq. ADL).
+ */
+static void field_at(const orc_problem* p, const orc_geom* g, const double* sigma, const double x[3], int64_t op,
+                     double* phi, double E[3])
+{
+    double ph = 0.0, e[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = 0; j < p->n_tri; ++j) {
+        double S, F[3];
+        pair_SF(p, g, x, j, j == op, &S, F);
+        ph += S * sigma[j];
+        for (int k = 0; k < 3; ++k) e[k] += F[k] * sigma[j];
+    }
+    if (op >= 0)
+        for (int k = 0; k < 3; ++k) e[k] += 0.5 * sigma[op] * g->nrm[3 * op + k];
+    *phi = ph;
+    for (int k = 0; k < 3; ++k) E[k] = e[k];
+}
+
+int orc_eval(const orc_problem* p, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel,
+             double* phi, double* E)
+{
+    orc_geom g;
+    geom_build(p, &g);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < P; ++i) {
+        double ph, e[3];
+        field_at(p, &g, sigma, pts + 3 * i, on_panel ? on_panel[i] : -1, &ph, e);
+        if (phi) phi[i] = ph;
+        for (int k = 0; k < 3; ++k) E[3 * i + k] = e[k];
+    }
+    geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------ segment hit test
+ * Moeller-Trumbore (1997) ray/triangle test restricted to the closed segment
+ * x0 -> x1 (t in [0,1]) and the closed triangle (u, v >= 0, u + v <= 1).  A
+ * segment parallel to the triangle plane does not hit.  Among all hits the
+ * smallest t wins, then the lowest panel index.  Returns the panel or -1.
+ */
+static int64_t segment_hit(const orc_problem* p, const orc_geom* g, const double x0[3], const double x1[3],
+                           double* t_hit)
+{
+    double dir[3];
+    sub3(x1, x0, dir);
+    int64_t best = -1;
+    double bt = 0.0;
+    for (int64_t j = 0; j < p->n_tri; ++j) {
+        const double* v = g->v + 9 * j;
+        double e1[3], e2[3], pv[3], tv[3], qv[3];
+        sub3(v + 3, v, e1);
+        sub3(v + 6, v, e2);
+        cross3(dir, e2, pv);
+        double det = dot3(e1, pv);
+        if (det == 0.0) continue;
+        double inv = 1.0 / det;
+        sub3(x0, v, tv);
+        double u = dot3(tv, pv) * inv;
+        if (u < 0.0 || u > 1.0) continue;
+        cross3(tv, e1, qv);
+        double vv = dot3(dir, qv) * inv;
+        if (vv < 0.0 || u + vv > 1.0) continue;
+        double t = dot3(e2, qv) * inv;
+        if (t < 0.0 || t > 1.0) continue;
+        if (best < 0 || t < bt) {
+            best = j;
+            bt = t;
+        }
+    }
+    *t_hit = bt;
+    return best;
+}
+
+int orc_segment_hit(const orc_problem* p, const double x0[3], const double x1[3], int64_t* panel, double* t)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    *panel = segment_hit(p, &g, x0, x1, t);
+    geom_free(&g);
+    return 0;
+}
+
+/* --------------------------------------------------------- field lines + criterion
+ * Field line dx/ds = dir E/|E| (Sec. 1: breakdown paths follow field lines),
+ * classical RK4 with arc-length step h.  Before a step: |E(x_n)| < e_min stops
+ * (code 4).  After a step: if the segment [x_n, x_{n+1}] hits a panel the step
+ * is discarded and the line stops with that panel's kind (1 conductor,
+ * 2 floating conductor, 3 dielectric interface).  max_steps accepted steps
+ * stop with code 0; a non-finite field or position stops with code 5.
+ * The streamer integral of Eq. Breakdowncrit, int alpha_eff(|E|) ds, is carried
+ * as an extra RK4 state: I += h/6 (a1 + 2 a2 + 2 a3 + a4) with the alpha of the
+ * four stage fields, alpha_eff(E) = alpha_a * max(E - alpha_e0, 0)^alpha_p.
+ */
+typedef void (*field_fn)(const void* ctx, const double x[3], double E[3]);
+typedef int (*hit_fn)(const void* ctx, const double x0[3], const double x1[3]);
+
+static double alpha_eff(const orc_trace_params* tp, double e)
+{
+    double d = e - tp->alpha_e0;
+    if (d <= 0.0) return 0.0;
+    return tp->alpha_a * pow(d, tp->alpha_p);
+}
+
+static void trace_one(const void* ctx, field_fn field, hit_fn hit, const orc_trace_params* tp, const double start[3],
+                      int32_t* n_steps, int32_t* stop, double* integral, double* path)
+{
+    double x[3] = {start[0], start[1], start[2]};
+    double I = 0.0, h = tp->h, dir = (tp->direction >= 0) ? 1.0 : -1.0;
+    int32_t n = 0, code = 0;
+    if (path)
+        for (int k = 0; k < 3; ++k) path[k] = x[k];
+    for (;;) {
+        if (n >= tp->max_steps) { code = 0; break; }
+        double E1[3], E2[3], E3[3], E4[3], k1[3], k2[3], k3[3], k4[3], y[3];
+        field(ctx, x, E1);
+        double m1 = norm3(E1);
+        if (!isfinite(m1)) { code = 5; break; }
+        if (m1 < tp->e_min) { code = 4; break; }
+        for (int k = 0; k < 3; ++k) k1[k] = dir * E1[k] / m1;
+        for (int k = 0; k < 3; ++k) y[k] = x[k] + 0.5 * h * k1[k];
+        field(ctx, y, E2);
+        double m2 = norm3(E2);
+        for (int k = 0; k < 3; ++k) k2[k] = dir * E2[k] / m2;
+        for (int k = 0; k < 3; ++k) y[k] = x[k] + 0.5 * h * k2[k];
+        field(ctx, y, E3);
+        double m3 = norm3(E3);
+        for (int k = 0; k < 3; ++k) k3[k] = dir * E3[k] / m3;
+        for (int k = 0; k < 3; ++k) y[k] = x[k] + h * k3[k];
+        field(ctx, y, E4);
+        double m4 = norm3(E4);
+        for (int k = 0; k < 3; ++k) k4[k] = dir * E4[k] / m4;
+        double xn[3];
+        for (int k = 0; k < 3; ++k) xn[k] = x[k] + h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+        if (!(isfinite(xn[0]) && isfinite(xn[1]) && isfinite(xn[2]))) { code = 5; break; }
+        if (hit) {
+            int c = hit(ctx, x, xn);
+            if (c > 0) { code = c; break; }
+        }
+        I += h / 6.0 * (alpha_eff(tp, m1) + 2.0 * alpha_eff(tp, m2) + 2.0 * alpha_eff(tp, m3) + alpha_eff(tp, m4));
+        for (int k = 0; k < 3; ++k) x[k] = xn[k];
+        ++n;
+        if (path)
+            for (int k = 0; k < 3; ++k) path[3 * n + k] = x[k];
+    }
+    *n_steps = n;
+    *stop = code;
+    *integral = I;
+}
+
+typedef struct {
+    const orc_problem* p;
+    const orc_geom* g;
+    const double* sigma;
+} bem_field_ctx;
+
+static void bem_field(const void* c, const double x[3], double E[3])
+{
+    const bem_field_ctx* b = (const bem_field_ctx*)c;
+    double phi;
+    field_at(b->p, b->g, b->sigma, x, -1, &phi, E);
+}
+
+static int bem_hit(const void* c, const double x0[3], const double x1[3])
+{
+    const bem_field_ctx* b = (const bem_field_ctx*)c;
+    double t;
+    int64_t j = segment_hit(b->p, b->g, x0, x1, &t);
+    if (j < 0) return 0;
+    int32_t kind = b->p->body_kind[b->p->tri_body[j]];
+    return kind == ORC_DIRICHLET ? 1 : (kind == ORC_FLOATING ? 2 : 3);
+}
+
+/* Field lines of the BEM field for sigma (first N entries of the solution). */
+int orc_trace(const orc_problem* p, const double* sigma, int64_t L, const double* starts, const orc_trace_params* tp,
+              int32_t* n_steps, int32_t* stop, double* integral, double* path)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    bem_field_ctx c = {p, &g, sigma};
+    int64_t stride = 3 * ((int64_t)tp->max_steps + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t l = 0; l < L; ++l)
+        trace_one(&c, bem_field, bem_hit, tp, starts + 3 * l, n_steps + l, stop + l, integral + l,
+                  path ? path + l * stride : NULL);
+    geom_free(&g);
+    return 0;
+}
+
+/* Field lines of point charges E(x) = sum_k q_k (x - c_k)/|x - c_k|^3 with no
+ * surfaces (a test harness for the RK4 stepping and the integral). */
+typedef struct {
+    int32_t n;
+    const double* c;
+    const double* q;
+} charges_ctx;
+
+static void charges_field(const void* cv, const double x[3], double E[3])
+{
+    const charges_ctx* c = (const charges_ctx*)cv;
+    E[0] = E[1] = E[2] = 0.0;
+    for (int32_t k = 0; k < c->n; ++k) {
+        double d[3];
+        sub3(x, c->c + 3 * k, d);
+        double r = norm3(d);
+        for (int i = 0; i < 3; ++i) E[i] += c->q[k] * d[i] / (r * r * r);
+    }
+}
+
+int orc_trace_charges(int32_t n_charges, const double* centres, const double* charges, int64_t L,
+                      const double* starts, const orc_trace_params* tp, int32_t* n_steps, int32_t* stop,
+                      double* integral, double* path)
+{
+    charges_ctx c = {n_charges, centres, charges};
+    int64_t stride = 3 * ((int64_t)tp->max_steps + 1);
+    for (int64_t l = 0; l < L; ++l)
+        trace_one(&c, charges_field, NULL, tp, starts + 3 * l, n_steps + l, stop + l, integral + l,
+                  path ? path + l * stride : NULL);
+    return 0;
+}
