@@ -1,0 +1,192 @@
+"""Benchmark of the whole BEM hot path on one MI355X.
+
+One step = the paper's pipeline on the coaxial rod-in-shell device with a
+floating ring and a dielectric spacer (19,732 flat panels + 1 floating
+potential): FP64 assembly of the collocation matrix, GMRES to 1e-10,
+the electric field at every panel centroid (exterior limit, "E surface"),
+and 256 field lines (RK4, h = 1e-4, <= 2000 steps) with the streamer
+integral, all from inputs already resident in GPU memory.
+
+Prints one JSON line.  value = panel-pair evaluations per second over the
+whole step (matrix entries + surface-field pairs + field-line pairs).
+The roofline entry is for the field-line kernel (the dominant kernel):
+algorithmic FP64 flops per launch / its average duration measured with HIP
+events on the stream it runs on.  cpu_baseline times the plain FP64 CPU
+oracle on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# algorithmic work per (point, panel) pair in flops (FMA = 2, rsqrt = 1):
+#   classification 9; per node: 3 sub, r^2 5, rsqrt 1, w r^-3 3, F += t d 6  (18 x 7 = 126);
+#   sigma_j * F accumulation 6  -> field-only pair 141
+#   potential-only pair (assembly of S rows): 9 + 7 x (3 + 5 + 1 + 2) = 86
+FLOP_FIELD_PAIR = 141
+FLOP_POT_PAIR = 86
+FP64_VALU_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lines", type=int, default=256)
+    ap.add_argument("--max-steps", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=256)
+    ap.add_argument("--cpu-sample-lines", type=int, default=2)
+    ap.add_argument("--cpu-sample-steps", type=int, default=25)
+    return ap.parse_args()
+
+
+def cpu_baseline(p, x, starts, args):
+    """The oracle on a bounded sample: a block of matrix rows and a few short lines."""
+    import oracle
+    o = oracle.Oracle(p)
+    rng = np.random.default_rng(12)
+    rows = np.sort(rng.choice(p.n_tri, size=args.cpu_sample_rows, replace=False))
+    t0 = time.perf_counter()
+    o.assemble_rows(rows)
+    t_rows = time.perf_counter() - t0
+    tp = oracle.trace_params(h=1e-4, max_steps=args.cpu_sample_steps)
+    t0 = time.perf_counter()
+    ns, st, _ = o.trace(x, starts[:args.cpu_sample_lines], tp)
+    t_lines = time.perf_counter() - t0
+    passes = int(np.sum(1 + 4 * ns + 4 * (st != 0)))
+    pairs = len(rows) * p.n_tri + passes * p.n_tri
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pairs / (t_rows + t_lines), "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(rows)} matrix rows x {p.n_tri} panels + {args.cpu_sample_lines} field lines x "
+                      f"{args.cpu_sample_steps} RK4 steps on the same mesh ({t_rows + t_lines:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2003_12663_amd as bem
+    from workloads import coax_problem_for_size, electrode_line_starts
+
+    torch.cuda.set_device(0)
+    p = coax_problem_for_size(20000)
+    N = p.n_tri
+    starts_h, _, _ = electrode_line_starts(p, args.lines, seed=2)
+    cen_h = p.vert[p.tri].mean(axis=1)
+    dev = torch.device("cuda", 0)
+    starts = torch.tensor(starts_h, device=dev)
+    cen = torch.tensor(cen_h, device=dev)
+    on_panel = torch.arange(N, dtype=torch.int32, device=dev)
+    tp = bem.trace_params(h=1e-4, max_steps=args.max_steps, e_min=1e-3)
+    ctx = bem.Context.from_problem(p, precision=bem.FP64, eta=6.0, restart=100)
+    print(f"[bench] coax N={N} lines={args.lines}", file=sys.stderr, flush=True)
+
+    def step():
+        ctx.assemble()
+        sol, info = ctx.solve(p.body_V, tol=1e-10, max_iter=5000)
+        _, E = ctx.eval_field(sol, cen, on_panel=on_panel, want_phi=False)
+        I, ns, st, ex = ctx.streamer_integral(sol, starts, tp)
+        return sol, info, I, ns, st
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    ctx.set_profiling(True)
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sol, info, I, ns, st = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_step:.1f} ms/step", file=sys.stderr, flush=True)
+
+    ns_h = ns.cpu().numpy()
+    st_h = st.cpu().numpy()
+    passes = int(np.sum(1 + 4 * ns_h + 4 * (st_h != 0)))    # field evaluations per step on the lines
+    n_unk = ctx.n
+    n_float_rows = int(np.sum(p.body_kind[p.tri_body] == bem.FLOATING))
+    pairs_matrix = N * N + n_float_rows * N
+    pairs_surface = N * N
+    pairs_lines = passes * N
+    pairs = pairs_matrix + pairs_surface + pairs_lines
+    stats = {k: ctx.kernel_stats(k) for k in ("geometry", "far_assemble", "near_mask_csr", "near_assemble",
+                                                "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
+                                                "eval_near_csr", "eval_far", "eval_near", "trace")}
+    tr_n, tr_ms = stats["trace"]
+    trace_ms = tr_ms / max(tr_n, 1)
+    trace_flops = pairs_lines * FLOP_FIELD_PAIR
+    achieved = trace_flops / (trace_ms * 1e-3) / 1e12
+    gv_n, gv_ms = stats["gemv"]
+    gemv_ms = gv_ms / max(gv_n, 1)
+    gemv_gbs = (8.0 * n_unk * n_unk) / (gemv_ms * 1e-3) / 1e9
+    fa_n, fa_ms = stats["far_assemble"]
+    phases = {k: (v[1] / args.steps) for k, v in stats.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p, sol[0].cpu().numpy(), starts_h, args)
+
+    out = {
+        "metric": "panel-pair evals/s",
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "coax rod-in-shell, floating torus, eps_r=4 spacer; FP64 assembly + GMRES(1e-10) + "
+                        "surface E at all centroids + 256 field lines (RK4 h=1e-4, <=2000 steps) with streamer "
+                        "integral",
+            "panels": N, "unknowns": n_unk, "lines": args.lines, "max_steps": args.max_steps, "eta": 6.0,
+            "gmres_restart": 100,
+        },
+        "field_evals_per_s": passes / (trace_ms * 1e-3),
+        "field_line_passes": passes,
+        "gmres_iters": info["iters"],
+        "gmres_rel_residual": info["rel_residual"],
+        "assembly_pairs_per_s": pairs_matrix / (fa_ms / max(fa_n, 1) * 1e-3),
+        "gemv_GBps": gemv_gbs,
+        "gemv_frac_hbm": gemv_gbs / HBM_PEAK_GBS,
+        "phase_ms_per_step": phases,
+        "streamer_integral_sum": float(I.sum().item()),
+        "stop_code_counts": {str(k): int(np.sum(st_h == k)) for k in range(6)},
+        "roofline": {"kernel": "k_trace (field lines + streamer integral)", "bound": "alu",
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": pairs_lines,
+                     "avg_launch_ms": trace_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

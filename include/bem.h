@@ -1,0 +1,193 @@
+/*
+ * bem.h -- C ABI of the MI355X (gfx950) boundary-element library for the
+ * indirect single-layer collocation method of "Dielectric Breakdown
+ * Prediction with GPU-Accelerated BEM" (arXiv 2003.12663).
+ *
+ * Discretisation: flat triangles tau_j, piecewise-constant virtual charge
+ * sigma_j, collocation at the centroids x_i.  Unknowns are ordered
+ * [sigma_1..sigma_N, V_1..V_Nfl] (one potential per floating body, in body
+ * order); constraint rows come last.
+ *
+ * Conventions shared by every call:
+ *  - "host" pointers are CPU memory; "dev" pointers are device memory of the
+ *    context's GPU (e.g. a torch tensor's data_ptr()).  The caller owns every
+ *    array; no call keeps a caller pointer after it returns.
+ *  - All device work is enqueued on the stream given to bem_create.  Calls
+ *    that return host-side results (bem_solve_gmres's info, counts) wait for
+ *    that stream.
+ *  - Every call returns a bem_status; on failure bem_last_error() gives a
+ *    thread-local message.  Inputs are validated before any kernel launch.
+ *  - One context per host thread at a time; contexts are independent.
+ *  - The library never falls back to the CPU: without a usable gfx950 GPU,
+ *    bem_create fails with BEM_ERR_HIP.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_ctx bem_ctx;
+
+typedef enum {
+    BEM_OK = 0,
+    BEM_ERR_INVALID = 1,    /* bad argument (index range, non-finite value, size, state of options) */
+    BEM_ERR_DEGENERATE = 2, /* a triangle with (numerically) zero area */
+    BEM_ERR_OOM = 3,        /* device memory would not suffice; detected before any allocation */
+    BEM_ERR_HIP = 4,        /* a HIP runtime call failed */
+    BEM_ERR_NOCONV = 5,     /* GMRES did not reach the tolerance; best iterate written, info filled */
+    BEM_ERR_STATE = 6       /* call order violated (e.g. solve before assemble) */
+} bem_status;
+
+/* Body kinds (paper Sec. 2, Fig. 2: conductor on a prescribed potential,
+ * floating conductor, insulator). */
+typedef enum {
+    BEM_DIRICHLET = 0, /* rows of Eq. Final1: sum_j S_ij sigma_j = V_body */
+    BEM_FLOATING = 1,  /* rows of Eq. Final2 (S sigma - V_f = 0) plus one row of Eq. Final4 per body */
+    BEM_INTERFACE = 2  /* rows of Eq. Final3 / Eq. nonconductors, using K' of Eq. ADL */
+} bem_kind;
+
+typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
+
+/* One body.  Triangle normals (right-hand rule of the vertex order) point
+ * into the eps_plus side. */
+typedef struct {
+    int32_t kind;      /* bem_kind */
+    double eps_plus;   /* permittivity on the normal side */
+    double eps_minus;  /* permittivity on the other side (INTERFACE only) */
+} bem_body;
+
+typedef struct {
+    int32_t precision;       /* bem_precision.  FP64: dense FP64 matrix.  MIXED: dense FP32 far
+                                field (near slots zero) + FP64 near CSR, FP64 Krylov vectors and
+                                iterative refinement. */
+    double eta;              /* Sec. 4 classification: (point, triangle) regular iff D > eta*R with
+                                D the distance to the circumcentre, R the circumradius.  >= 1.
+                                Regular pairs use the 7-point rule, the others closed forms. */
+    int32_t restart;         /* GMRES restart length m, 1..1000 */
+    int32_t constraint_form; /* 0: Eq. Final4 as printed (literal); 1: net charge sum a_i sigma_i = 0 */
+} bem_options;
+
+typedef struct {
+    int32_t iters;        /* Krylov iterations (summed over right-hand sides and refinements) */
+    double rel_residual;  /* max over right-hand sides of ||b - A x|| / ||b|| at exit */
+    int32_t refinements;  /* outer iterative-refinement steps (MIXED), else 0 */
+} bem_solve_info;
+
+/* Field-line parameters (paper Sec. 1: breakdown paths follow field lines;
+ * Eq. Breakdowncrit). */
+typedef struct {
+    double h;             /* RK4 arc-length step; must be < (eta - 1) * min circumradius */
+    double e_min;         /* stop (code 4) when |E| < e_min at the start of a step */
+    double start_offset;  /* informational (starts are given as points) */
+    int32_t max_steps;    /* stop (code 0) after this many accepted steps, 1..1e6 */
+    int32_t direction;    /* +1: follow E, -1: follow -E */
+    double alpha_a, alpha_e0, alpha_p; /* alpha_eff(E) = alpha_a * max(E - alpha_e0, 0)^alpha_p */
+    double k_str;         /* streamer constant: exceeds[l] = integral[l] > k_str */
+} bem_trace_params;
+
+/* Stop codes written by bem_trace_lines / bem_streamer_integral. */
+enum {
+    BEM_STOP_MAXSTEPS = 0,
+    BEM_STOP_DIRICHLET = 1, /* the step's segment hit a conductor panel; the step is discarded */
+    BEM_STOP_FLOATING = 2,  /* ... a floating-conductor panel */
+    BEM_STOP_INTERFACE = 3, /* ... a dielectric-interface panel */
+    BEM_STOP_WEAK = 4,      /* |E| < e_min */
+    BEM_STOP_NONFINITE = 5
+};
+
+/* Create a context: copies the mesh to the device and computes panel
+ * geometry (centroid, normal, area, circumcentre/radius, 7-point nodes).
+ *  vert      host [n_vert][3]
+ *  tri       host [n_tri][3] vertex indices, CCW about the eps+ normal
+ *  tri_body  host [n_tri] body index of each triangle
+ *  bodies    host [n_body]
+ *  opt       host; NULL = {FP64, eta 6, restart 100, literal constraint}
+ *  hip_stream  a hipStream_t (NULL = default stream) of the current device
+ * Errors: INVALID (indices, non-finite coordinates, kinds, options),
+ * DEGENERATE (area <= 1e-14 * longest edge^2), HIP. */
+bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const int32_t* tri,
+                      const int32_t* tri_body, int32_t n_body, const bem_body* bodies,
+                      const bem_options* opt, void* hip_stream, bem_ctx** out);
+void bem_destroy(bem_ctx* ctx);
+const char* bem_last_error(void);
+
+/* Number of unknowns n = N + N_float, and the leading dimension of the dense matrix. */
+int64_t bem_n_unknowns(const bem_ctx* ctx);
+
+/* Assemble the collocation system of Eqs. Final1-Final4 (Sec. 4 quadrature:
+ * regular pairs by the 7-point rule, near-singular and singular pairs by the
+ * closed forms for flat triangles, done in a second pass over a compacted
+ * near list).  Errors: OOM (checked before allocating), HIP. */
+bem_status bem_assemble(bem_ctx* ctx);
+
+/* Copy rows [row0, row0 + n_rows) of the assembled operator as FP64 into
+ * out (dev [n_rows][n]).  In MIXED mode this is the operator actually used:
+ * FP32 far entries widened, plus the FP64 near entries. */
+bem_status bem_copy_rows(bem_ctx* ctx, int64_t row0, int64_t n_rows, double* out);
+
+/* Number of near-singular and singular (row, panel) pairs of the assembly. */
+int64_t bem_near_pairs(const bem_ctx* ctx);
+
+/* Right-hand sides for body potentials: b (dev [nrhs][n]); body_V host [nrhs][n_body]
+ * (entries of non-DIRICHLET bodies are ignored). */
+bem_status bem_rhs(bem_ctx* ctx, int32_t nrhs, const double* body_V, double* b);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1) for nrhs vectors,
+ * x, y dev [nrhs][n], FP64 (the Krylov matvec of Sec. 3). */
+bem_status bem_matvec(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, int32_t transpose);
+
+/* Solve A sol = b(body_V) for nrhs load cases by restarted GMRES with the
+ * diagonal (Jacobi) preconditioner applied on the right (Sec. 5.2), CGS2
+ * orthogonalisation, zero initial guess, stopping at ||b - A x|| <= tol ||b||.
+ * MIXED: GMRES on the mixed operator inside FP64 iterative refinement.
+ *  body_V host [nrhs][n_body]; sol dev [nrhs][n]; info host (may be NULL).
+ * Errors: STATE (not assembled), INVALID, NOCONV (best iterate written). */
+bem_status bem_solve_gmres(bem_ctx* ctx, int32_t nrhs, const double* body_V, double tol,
+                           int32_t max_iter, double* sol, bem_solve_info* info);
+
+/* Potential and field at P points (the field formula closing Sec. 2):
+ * phi(x) = sum_j S_j(x) sigma_j, E(x) = sum_j F_j(x) sigma_j.
+ *  sol      dev [nrhs][n] (only the sigma part is read)
+ *  pts      dev [P][3]
+ *  on_panel dev [P] or NULL: >= 0 marks the point as that panel's centroid and
+ *           returns the limit from the eps+ side (principal value + sigma n / 2);
+ *           -1 = volume point (must not lie on a panel edge).
+ *  phi      dev [nrhs][P] or NULL;  E dev [nrhs][P][3]. */
+bem_status bem_eval_field(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t P, const double* pts,
+                          const int32_t* on_panel, double* phi, double* E);
+
+/* Field lines dx/ds = direction * E/|E| by classical RK4 with step h, all
+ * lines in one persistent launch.  A step whose segment [x_n, x_{n+1}]
+ * intersects a panel is discarded and the line stops with that panel's kind
+ * (smallest segment parameter wins, then the lowest panel index).
+ *  line_rhs dev [L] or NULL (all lines use load case 0): which sol row drives line l
+ *  starts   dev [L][3]
+ *  n_steps, stop_code  dev [L]
+ *  path     dev [L][max_steps+1][3] or NULL: x_0..x_{n_steps}; later slots untouched. */
+bem_status bem_trace_lines(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                           const double* starts, const bem_trace_params* tp, int32_t* n_steps,
+                           int32_t* stop_code, double* path);
+
+/* Streamer-inception integral of Eq. Breakdowncrit along each field line,
+ * integral[l] = int alpha_eff(|E|) ds, carried as an extra RK4 state
+ * (h/6 (a1 + 2 a2 + 2 a3 + a4) per accepted step from the stage fields).
+ *  integral dev [L]; exceeds dev [L] (uint8, integral > k_str) or NULL. */
+bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t L,
+                                 const int32_t* line_rhs, const double* starts, const bem_trace_params* tp,
+                                 double* integral, int32_t* n_steps, int32_t* stop_code, uint8_t* exceeds);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * each launch while enabled.  Names: "geometry", "far_assemble", "near_mask_csr",
+ * "near_assemble", "finalize", "gemv", "gmres_ortho", "eval_far", "eval_near", "trace". */
+bem_status bem_set_profiling(bem_ctx* ctx, int32_t enable);
+bem_status bem_kernel_stats(bem_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
+bem_status bem_reset_stats(bem_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H */

@@ -1,0 +1,198 @@
+"""MI355X (gfx950) indirect single-layer collocation BEM.
+
+Python binding of the C ABI in include/bem.h.  Every numerical step runs in
+the HIP kernels of libbem.so; this module only marshals arguments.  torch
+supplies device memory and the stream.  There is no CPU fallback: without the
+built library or a gfx950 GPU every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+DIRICHLET, FLOATING, INTERFACE = 0, 1, 2
+FP64, MIXED = 0, 1
+STOP_NAMES = {0: "max_steps", 1: "dirichlet", 2: "floating", 3: "interface", 4: "weak_field", 5: "nonfinite"}
+
+
+class BemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_lib.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, lib):
+    if rc != 0:
+        raise BemError(rc, lib.bem_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def trace_params(h=1e-4, e_min=1e-3, max_steps=2000, direction=1, alpha_a=1e-3, alpha_e0=25.0, alpha_p=2.0,
+                 k_str=float("inf"), start_offset=1e-6) -> _lib.TraceParams:
+    return _lib.TraceParams(h, e_min, start_offset, max_steps, direction, alpha_a, alpha_e0, alpha_p, k_str)
+
+
+class Context:
+    """One assembled BEM problem on the current GPU (bem_create / bem_destroy)."""
+
+    def __init__(self, vert, tri, tri_body, body_kind, eps_plus, eps_minus, precision=FP64, eta=6.0, restart=100,
+                 constraint_form=0, stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._vert = np.ascontiguousarray(vert, dtype=np.float64)
+        self._tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self._tb = np.ascontiguousarray(tri_body, dtype=np.int32)
+        kinds = np.asarray(body_kind, dtype=np.int32)
+        ep = np.asarray(eps_plus, dtype=np.float64)
+        em = np.asarray(eps_minus, dtype=np.float64)
+        self.n_body = len(kinds)
+        bodies = (_lib.Body * self.n_body)(*[_lib.Body(int(k), float(a), float(b)) for k, a, b in zip(kinds, ep, em)])
+        opt = _lib.Options(int(precision), float(eta), int(restart), int(constraint_form))
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ctx = ctypes.c_void_p()
+        rc = self.lib.bem_create(len(self._vert), self._vert.ctypes.data, len(self._tri), self._tri.ctypes.data,
+                                 self._tb.ctypes.data, self.n_body, ctypes.addressof(bodies), ctypes.byref(opt),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx))
+        _check(rc, self.lib)
+        self.N = len(self._tri)
+        self.n = int(self.lib.bem_n_unknowns(self._ctx))
+        self.precision = int(precision)
+
+    @classmethod
+    def from_problem(cls, p, **kw):
+        return cls(p.vert, p.tri, p.tri_body, p.body_kind, p.eps_plus, p.eps_minus, **kw)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.bem_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ calls
+    def assemble(self):
+        _check(self.lib.bem_assemble(self._ctx), self.lib)
+
+    @property
+    def near_pairs(self) -> int:
+        return int(self.lib.bem_near_pairs(self._ctx))
+
+    def copy_rows(self, row0: int, n_rows: int):
+        torch = _torch()
+        out = torch.empty((n_rows, self.n), dtype=torch.float64, device=self.device)
+        _check(self.lib.bem_copy_rows(self._ctx, row0, n_rows, _dev_ptr(out)), self.lib)
+        return out
+
+    def rhs(self, body_V):
+        torch = _torch()
+        bv = np.ascontiguousarray(np.atleast_2d(body_V), dtype=np.float64)
+        out = torch.empty((bv.shape[0], self.n), dtype=torch.float64, device=self.device)
+        _check(self.lib.bem_rhs(self._ctx, bv.shape[0], bv.ctypes.data, _dev_ptr(out)), self.lib)
+        return out
+
+    def matvec(self, x, transpose=False):
+        torch = _torch()
+        x2 = x.reshape(-1, self.n).contiguous()
+        y = torch.empty_like(x2)
+        _check(self.lib.bem_matvec(self._ctx, x2.shape[0], _dev_ptr(x2), _dev_ptr(y), int(bool(transpose))), self.lib)
+        return y.reshape(x.shape)
+
+    def solve(self, body_V, tol=1e-10, max_iter=10000, raise_on_noconv=True):
+        """Returns (sol [nrhs, n] float64 on the GPU, info dict)."""
+        torch = _torch()
+        bv = np.ascontiguousarray(np.atleast_2d(body_V), dtype=np.float64)
+        sol = torch.empty((bv.shape[0], self.n), dtype=torch.float64, device=self.device)
+        info = _lib.SolveInfo()
+        rc = self.lib.bem_solve_gmres(self._ctx, bv.shape[0], bv.ctypes.data, float(tol), int(max_iter),
+                                      _dev_ptr(sol), ctypes.byref(info))
+        if rc != 0 and (rc != _lib.BEM_ERR_NOCONV or raise_on_noconv):
+            _check(rc, self.lib)
+        return sol, dict(iters=info.iters, rel_residual=info.rel_residual, refinements=info.refinements,
+                         converged=(rc == 0))
+
+    def eval_field(self, sol, pts, on_panel=None, want_phi=True):
+        torch = _torch()
+        sol2 = sol.reshape(-1, self.n).contiguous()
+        nrhs = sol2.shape[0]
+        pts = torch.as_tensor(pts, dtype=torch.float64, device=self.device).reshape(-1, 3).contiguous()
+        P = pts.shape[0]
+        op = None
+        if on_panel is not None:
+            op = torch.as_tensor(on_panel, dtype=torch.int32, device=self.device).contiguous()
+        phi = torch.empty((nrhs, P), dtype=torch.float64, device=self.device) if want_phi else None
+        E = torch.empty((nrhs, P, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.bem_eval_field(self._ctx, nrhs, _dev_ptr(sol2), P, _dev_ptr(pts), _dev_ptr(op),
+                                       _dev_ptr(phi), _dev_ptr(E)), self.lib)
+        return phi, E
+
+    def _line_args(self, sol, starts, line_rhs):
+        torch = _torch()
+        sol2 = sol.reshape(-1, self.n).contiguous()
+        starts = torch.as_tensor(starts, dtype=torch.float64, device=self.device).reshape(-1, 3).contiguous()
+        lr = None
+        if line_rhs is not None:
+            lr = torch.as_tensor(line_rhs, dtype=torch.int32, device=self.device).contiguous()
+        return sol2, starts, lr
+
+    def trace_lines(self, sol, starts, params=None, line_rhs=None, want_path=False):
+        torch = _torch()
+        params = params or trace_params()
+        sol2, starts, lr = self._line_args(sol, starts, line_rhs)
+        L = starts.shape[0]
+        ns = torch.empty(L, dtype=torch.int32, device=self.device)
+        st = torch.empty(L, dtype=torch.int32, device=self.device)
+        path = (torch.full((L, params.max_steps + 1, 3), float("nan"), dtype=torch.float64, device=self.device)
+                if want_path else None)
+        _check(self.lib.bem_trace_lines(self._ctx, sol2.shape[0], _dev_ptr(sol2), L, _dev_ptr(lr), _dev_ptr(starts),
+                                        ctypes.byref(params), _dev_ptr(ns), _dev_ptr(st), _dev_ptr(path)), self.lib)
+        return ns, st, path
+
+    def streamer_integral(self, sol, starts, params=None, line_rhs=None):
+        torch = _torch()
+        params = params or trace_params()
+        sol2, starts, lr = self._line_args(sol, starts, line_rhs)
+        L = starts.shape[0]
+        I = torch.empty(L, dtype=torch.float64, device=self.device)
+        ns = torch.empty(L, dtype=torch.int32, device=self.device)
+        st = torch.empty(L, dtype=torch.int32, device=self.device)
+        ex = torch.empty(L, dtype=torch.uint8, device=self.device)
+        _check(self.lib.bem_streamer_integral(self._ctx, sol2.shape[0], _dev_ptr(sol2), L, _dev_ptr(lr),
+                                              _dev_ptr(starts), ctypes.byref(params), _dev_ptr(I), _dev_ptr(ns),
+                                              _dev_ptr(st), _dev_ptr(ex)), self.lib)
+        return I, ns, st, ex
+
+    # -------------------------------------------------------------- profiling
+    def set_profiling(self, on=True):
+        _check(self.lib.bem_set_profiling(self._ctx, int(bool(on))), self.lib)
+
+    def kernel_stats(self, name: str):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(self.lib.bem_kernel_stats(self._ctx, name.encode(), ctypes.byref(n), ctypes.byref(ms)), self.lib)
+        return int(n.value), float(ms.value)
+
+    def reset_stats(self):
+        _check(self.lib.bem_reset_stats(self._ctx), self.lib)

@@ -1,0 +1,508 @@
+// C ABI of the library: validation, context lifetime, device buffers and the
+// order of the passes.  Nothing here computes the method itself; every
+// numerical step runs in the kernels of the other translation units.
+#include <algorithm>
+#include <memory>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+bem_status fail(bem_status s, const std::string& m) {
+    g_err = m;
+    return s;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define API_TRY try {
+#define API_CATCH                                                                  \
+    }                                                                              \
+    catch (const bem::Error& e) {                                                  \
+        return fail(e.code, e.what());                                             \
+    }                                                                              \
+    catch (const std::bad_alloc&) {                                                \
+        return fail(BEM_ERR_OOM, "host allocation failed");                        \
+    }                                                                              \
+    catch (const std::exception& e) {                                              \
+        return fail(BEM_ERR_HIP, e.what());                                        \
+    }
+
+template <class T>
+void upload(bem::DBuf& b, const T* h, size_t count, hipStream_t s) {
+    b.alloc(sizeof(T) * (count > 0 ? count : 1));
+    if (count) BEM_HIP(hipMemcpyAsync(b.p, h, sizeof(T) * count, hipMemcpyHostToDevice, s));
+}
+
+void check_assembled(const bem_ctx* c) {
+    if (!c->assembled) throw bem::Error(BEM_ERR_STATE, "bem_assemble has not been called");
+}
+
+std::vector<double> fetch_f64(const bem_ctx* c, const double* d, size_t count) {
+    std::vector<double> h(count);
+    if (count) {
+        BEM_HIP(hipMemcpyAsync(h.data(), d, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+        BEM_HIP(hipStreamSynchronize(c->stream));
+    }
+    return h;
+}
+
+std::vector<int32_t> fetch_i32(const bem_ctx* c, const int32_t* d, size_t count) {
+    std::vector<int32_t> h(count);
+    if (count) {
+        BEM_HIP(hipMemcpyAsync(h.data(), d, sizeof(int32_t) * count, hipMemcpyDeviceToHost, c->stream));
+        BEM_HIP(hipStreamSynchronize(c->stream));
+    }
+    return h;
+}
+
+void check_points(const bem_ctx* c, int64_t P, const double* pts) {
+    if (P < 0) throw bem::Error(BEM_ERR_INVALID, "negative point count");
+    if (P > 0 && !pts) throw bem::Error(BEM_ERR_INVALID, "points pointer is NULL");
+    auto h = fetch_f64(c, pts, (size_t)P * 3);
+    for (double v : h)
+        if (!std::isfinite(v)) throw bem::Error(BEM_ERR_INVALID, "non-finite point coordinate");
+}
+
+void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                 const double* starts, const bem_trace_params* tp) {
+    if (!tp) throw bem::Error(BEM_ERR_INVALID, "trace parameters are NULL");
+    if (nrhs < 1) throw bem::Error(BEM_ERR_INVALID, "nrhs must be >= 1");
+    if (!sol) throw bem::Error(BEM_ERR_INVALID, "solution pointer is NULL");
+    if (!(tp->h > 0.0) || !std::isfinite(tp->h)) throw bem::Error(BEM_ERR_INVALID, "step h must be finite and > 0");
+    if (!(tp->h < (c->opt.eta - 1.0) * c->min_R * (1.0 - 1e-9)))
+        throw bem::Error(BEM_ERR_INVALID,
+                         "step h must be < (eta - 1) * smallest circumradius so that every panel a step can "
+                         "reach is classified near");
+    if (tp->max_steps < 1 || tp->max_steps > 1000000) throw bem::Error(BEM_ERR_INVALID, "max_steps out of 1..1e6");
+    if (!(tp->e_min >= 0.0) || !std::isfinite(tp->e_min)) throw bem::Error(BEM_ERR_INVALID, "e_min must be >= 0");
+    if (!std::isfinite(tp->alpha_a) || !std::isfinite(tp->alpha_e0) || !std::isfinite(tp->alpha_p) ||
+        std::isnan(tp->k_str))
+        throw bem::Error(BEM_ERR_INVALID, "non-finite ionisation parameters");
+    if (L < 0 || L >= ((int64_t)1 << 31)) throw bem::Error(BEM_ERR_INVALID, "line count out of range");
+    check_points(c, L, starts);
+    if (line_rhs) {
+        auto h = fetch_i32(c, line_rhs, (size_t)L);
+        for (int32_t v : h)
+            if (v < 0 || v >= nrhs) throw bem::Error(BEM_ERR_INVALID, "line_rhs entry out of range");
+    }
+}
+
+}  // namespace
+
+namespace bem {
+
+KTimer::KTimer(bem_ctx* ctx, const char* nm) : c(ctx), name(nm) {
+    if (!c->profiling) return;
+    auto get = [&]() {
+        if (!c->event_pool.empty()) {
+            hipEvent_t e = c->event_pool.back();
+            c->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        BEM_HIP(hipEventCreate(&e));
+        return e;
+    };
+    a = get();
+    b = get();
+    BEM_HIP(hipEventRecord(a, c->stream));
+}
+
+KTimer::~KTimer() {
+    if (!a) return;
+    if (hipEventRecord(b, c->stream) != hipSuccess) return;
+    c->pending.push_back({name, {a, b}});
+    if (c->pending.size() > 4096) resolve_stats(c);
+}
+
+void resolve_stats(bem_ctx* c) {
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            auto& s = c->stats[p.first];
+            s.launches += 1;
+            s.ms += ms;
+        }
+        c->event_pool.push_back(p.second.first);
+        c->event_pool.push_back(p.second.second);
+    }
+    c->pending.clear();
+}
+
+}  // namespace bem
+
+extern "C" {
+
+const char* bem_last_error(void) { return g_err.c_str(); }
+
+bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const int32_t* tri, const int32_t* tri_body,
+                      int32_t n_body, const bem_body* bodies, const bem_options* opt, void* hip_stream,
+                      bem_ctx** out) {
+    if (!out) return fail(BEM_ERR_INVALID, "out pointer is NULL");
+    *out = nullptr;
+    if (!vert || !tri || !tri_body || !bodies) return fail(BEM_ERR_INVALID, "NULL mesh array");
+    if (n_vert < 3 || n_tri < 1 || n_body < 1)
+        return fail(BEM_ERR_INVALID, "mesh needs >= 3 vertices, >= 1 triangle, >= 1 body");
+    if (n_tri >= ((int64_t)1 << 31) || n_vert >= ((int64_t)1 << 31)) return fail(BEM_ERR_INVALID, "mesh too large");
+    bem_options o = {BEM_FP64, 6.0, 100, 0};
+    if (opt) o = *opt;
+    if (o.precision != BEM_FP64 && o.precision != BEM_MIXED) return fail(BEM_ERR_INVALID, "unknown precision");
+    if (!(o.eta >= 1.0) || !std::isfinite(o.eta)) return fail(BEM_ERR_INVALID, "eta must be finite and >= 1");
+    if (o.restart < 1 || o.restart > 1000) return fail(BEM_ERR_INVALID, "restart out of 1..1000");
+    if (o.constraint_form != 0 && o.constraint_form != 1) return fail(BEM_ERR_INVALID, "unknown constraint_form");
+    for (int64_t k = 0; k < 3 * n_vert; ++k)
+        if (!std::isfinite(vert[k])) return fail(BEM_ERR_INVALID, "non-finite vertex coordinate");
+    for (int32_t b = 0; b < n_body; ++b) {
+        const bem_body& bd = bodies[b];
+        if (bd.kind < BEM_DIRICHLET || bd.kind > BEM_INTERFACE) return fail(BEM_ERR_INVALID, "unknown body kind");
+        if (!(bd.eps_plus > 0.0) || !std::isfinite(bd.eps_plus)) return fail(BEM_ERR_INVALID, "eps_plus must be > 0");
+        if (bd.kind == BEM_INTERFACE && (!(bd.eps_minus > 0.0) || !std::isfinite(bd.eps_minus)))
+            return fail(BEM_ERR_INVALID, "eps_minus must be > 0 on an interface");
+    }
+    double min_R = INFINITY;
+    std::vector<int64_t> per_body(n_body, 0);
+    for (int64_t j = 0; j < n_tri; ++j) {
+        const int32_t* t = tri + 3 * j;
+        for (int k = 0; k < 3; ++k)
+            if (t[k] < 0 || t[k] >= n_vert) return fail(BEM_ERR_INVALID, "triangle vertex index out of range");
+        if (tri_body[j] < 0 || tri_body[j] >= n_body) return fail(BEM_ERR_INVALID, "triangle body index out of range");
+        per_body[tri_body[j]]++;
+        const double* a = vert + 3 * (int64_t)t[0];
+        const double* b = vert + 3 * (int64_t)t[1];
+        const double* c = vert + 3 * (int64_t)t[2];
+        double u[3], w[3], e[3];
+        for (int k = 0; k < 3; ++k) {
+            u[k] = b[k] - a[k];
+            w[k] = c[k] - a[k];
+            e[k] = c[k] - b[k];
+        }
+        const double cr0 = u[1] * w[2] - u[2] * w[1], cr1 = u[2] * w[0] - u[0] * w[2], cr2 = u[0] * w[1] - u[1] * w[0];
+        const double area = 0.5 * std::sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2);
+        const double lu = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        const double lw = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        const double le = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        const double lmax = std::max(lu, std::max(lw, le));
+        if (!(area > 1e-14 * lmax * lmax)) return fail(BEM_ERR_DEGENERATE, "degenerate triangle " + std::to_string(j));
+        min_R = std::min(min_R, lu * lw * le / (4.0 * area));
+    }
+    for (int32_t b = 0; b < n_body; ++b)
+        if (bodies[b].kind == BEM_FLOATING && per_body[b] == 0)
+            return fail(BEM_ERR_INVALID, "floating body without panels");
+
+    API_TRY
+    int dev = 0;
+    BEM_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    BEM_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        throw bem::Error(BEM_ERR_HIP, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+    std::unique_ptr<bem_ctx> c(new bem_ctx());
+    c->device = dev;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->opt = o;
+    c->N = n_tri;
+    c->n_vert = n_vert;
+    c->n_body = n_body;
+    c->min_R = min_R;
+    c->h_tri_body.assign(tri_body, tri_body + n_tri);
+    c->h_body_kind.resize(n_body);
+    c->h_epsp.resize(n_body);
+    c->h_epsm.resize(n_body);
+    c->h_body_fidx.assign(n_body, -1);
+    for (int32_t b = 0; b < n_body; ++b) {
+        c->h_body_kind[b] = bodies[b].kind;
+        c->h_epsp[b] = bodies[b].eps_plus;
+        c->h_epsm[b] = bodies[b].eps_minus;
+        if (bodies[b].kind == BEM_FLOATING) c->h_body_fidx[b] = c->n_float++;
+    }
+    c->n = c->N + c->n_float;
+    c->ld = (c->n + 31) / 32 * 32;
+    // row segments by kind (Sec. 4: rows grouped by type); floating rows sorted by
+    // (body, panel) so that each body's rows are contiguous
+    std::vector<int32_t> slot(n_tri, -1);
+    for (int64_t i = 0; i < n_tri; ++i) {
+        if (c->h_body_kind[tri_body[i]] == BEM_INTERFACE)
+            c->h_rows_int.push_back((int32_t)i);
+        else
+            c->h_rows_pot.push_back((int32_t)i);
+    }
+    for (int32_t f = 0; f < c->n_float; ++f)
+        for (int64_t i = 0; i < n_tri; ++i)
+            if (c->h_body_fidx[tri_body[i]] == f) {
+                slot[i] = (int32_t)c->h_rows_flt.size();
+                c->h_rows_flt.push_back((int32_t)i);
+            }
+    const int64_t Np = (c->N + 255) / 256 * 256;
+    hipStream_t s = c->stream;
+    c->host_stage.alloc(sizeof(double) * 4096);
+    upload(c->vert, vert, (size_t)(3 * n_vert), s);
+    upload(c->tri, tri, (size_t)(3 * n_tri), s);
+    upload(c->tri_body, tri_body, (size_t)n_tri, s);
+    upload(c->body_kind, c->h_body_kind.data(), (size_t)n_body, s);
+    upload(c->body_epsp, c->h_epsp.data(), (size_t)n_body, s);
+    upload(c->body_epsm, c->h_epsm.data(), (size_t)n_body, s);
+    upload(c->body_fidx, c->h_body_fidx.data(), (size_t)n_body, s);
+    upload(c->rows_pot, c->h_rows_pot.data(), c->h_rows_pot.size(), s);
+    upload(c->rows_int, c->h_rows_int.data(), c->h_rows_int.size(), s);
+    upload(c->rows_flt, c->h_rows_flt.data(), c->h_rows_flt.size(), s);
+    upload(c->row_slot, slot.data(), slot.size(), s);
+    // interface-row scales (eps+ - eps-) followed by ones for the K' rows of floating bodies
+    std::vector<double> scales;
+    for (int32_t i : c->h_rows_int) scales.push_back(c->h_epsp[tri_body[i]] - c->h_epsm[tri_body[i]]);
+    if (scales.empty()) scales.push_back(0.0);
+    for (size_t k = 0; k < c->h_rows_flt.size(); ++k) scales.push_back(1.0);
+    upload(c->gm_misc, scales.data(), scales.size(), s);
+    c->far64.alloc(sizeof(double) * bem::FAR_REC * Np);
+    c->far32.alloc(sizeof(float) * bem::FAR_REC * Np);
+    c->tri64.alloc(sizeof(double) * bem::TRI_REC * c->N);
+    bem::launch_geometry(c.get());
+    BEM_HIP(hipStreamSynchronize(s));   // host-side sources of the uploads are temporaries
+    *out = c.release();
+    return BEM_OK;
+    API_CATCH
+}
+
+void bem_destroy(bem_ctx* c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+int64_t bem_n_unknowns(const bem_ctx* c) { return c ? c->n : -1; }
+
+int64_t bem_near_pairs(const bem_ctx* c) { return c ? c->near_nnz : -1; }
+
+bem_status bem_assemble(bem_ctx* c) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    const bool mixed = c->opt.precision == BEM_MIXED;
+    const int64_t N = c->N, n = c->n, ld = c->ld;
+    const int64_t nblk = bem::ceil_div(N, 64);
+    const size_t nflt = c->h_rows_flt.size();
+    // device memory needed, checked before allocating anything large
+    size_t need = 0;
+    need += mixed ? sizeof(float) * (size_t)N * ld + sizeof(double) * (size_t)c->n_float * ld
+                  : sizeof(double) * (size_t)n * ld;
+    need += sizeof(uint64_t) * (size_t)nblk * N;                 // near masks
+    need += (size_t)N * 160 * (mixed ? 16 : 8);                   // near list, ~90-160 pairs per row
+    if (c->opt.constraint_form == 0) need += sizeof(double) * nflt * N;
+    size_t free_b = 0, total_b = 0;
+    BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t have = free_b + c->A64.bytes + c->A32.bytes + c->Kf.bytes + c->near_col.bytes + c->near_row.bytes +
+                        c->near_val.bytes;
+    if (need > have) throw bem::Error(BEM_ERR_OOM, "assembly needs " + std::to_string(need >> 20) + " MiB, " +
+                                                       std::to_string(have >> 20) + " MiB free");
+    c->assembled = false;
+    if (mixed) {
+        c->A64.release();
+        c->A32.alloc(sizeof(float) * (size_t)N * ld);
+        c->A64.alloc(sizeof(double) * (size_t)(c->n_float > 0 ? c->n_float : 1) * ld);
+    } else {
+        c->A32.release();
+        c->A64.alloc(sizeof(double) * (size_t)n * ld);
+    }
+    if (c->opt.constraint_form == 0 && nflt > 0) c->Kf.alloc(sizeof(double) * nflt * N);
+    c->nearmask.alloc(sizeof(uint64_t) * nblk * N);
+    c->diag.alloc(sizeof(double) * ld);
+    bem::launch_far_assemble(c);
+    bem::launch_near_csr(c, c->nearmask.as<uint64_t>(), N, c->near_ptr, c->near_row, c->near_col, &c->near_nnz,
+                         "near_mask_csr");
+    if (mixed) c->near_val.alloc(sizeof(double) * (c->near_nnz > 0 ? c->near_nnz : 1));
+    bem::launch_near_assemble(c);
+    bem::launch_finalize(c);
+    c->nearmask.release();
+    if (c->opt.constraint_form == 0) c->Kf.release();
+    BEM_HIP(hipStreamSynchronize(c->stream));
+    c->assembled = true;
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    check_assembled(c);
+    if (row0 < 0 || n_rows < 0 || row0 + n_rows > c->n) throw bem::Error(BEM_ERR_INVALID, "row range out of bounds");
+    if (n_rows == 0) return BEM_OK;
+    if (!out) throw bem::Error(BEM_ERR_INVALID, "out pointer is NULL");
+    bem::launch_copy_rows(c, row0, n_rows, out);
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_rhs(bem_ctx* c, int32_t nrhs, const double* body_V, double* b) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (nrhs < 1 || !body_V || !b) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL arrays required");
+    for (int64_t k = 0; k < (int64_t)nrhs * c->n_body; ++k)
+        if (!std::isfinite(body_V[k])) throw bem::Error(BEM_ERR_INVALID, "non-finite body potential");
+    upload(c->gm_b, body_V, (size_t)nrhs * c->n_body, c->stream);
+    bem::launch_rhs(c, nrhs, c->gm_b.as<double>(), b);
+    BEM_HIP(hipStreamSynchronize(c->stream));   // body_V staging buffer is reused
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_matvec(bem_ctx* c, int32_t nrhs, const double* x, double* y, int32_t transpose) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    check_assembled(c);
+    if (nrhs < 1 || !x || !y) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL vectors required");
+    if (transpose != 0 && transpose != 1) throw bem::Error(BEM_ERR_INVALID, "transpose must be 0 or 1");
+    c->gm_x.alloc(sizeof(double) * c->ld * 2);
+    double* xa = c->gm_x.as<double>();
+    double* ya = xa + c->ld;
+    for (int32_t r = 0; r < nrhs; ++r) {
+        BEM_HIP(hipMemcpyAsync(xa, x + (int64_t)r * c->n, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+        if (transpose)
+            bem::launch_matvec_t(c, xa, ya, c->stream);
+        else
+            bem::launch_matvec(c, xa, ya, c->stream);
+        BEM_HIP(hipMemcpyAsync(y + (int64_t)r * c->n, ya, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_solve_gmres(bem_ctx* c, int32_t nrhs, const double* body_V, double tol, int32_t max_iter, double* sol,
+                           bem_solve_info* info) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    check_assembled(c);
+    if (nrhs < 1 || !body_V || !sol) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL arrays required");
+    if (!(tol > 0.0) || !std::isfinite(tol)) throw bem::Error(BEM_ERR_INVALID, "tol must be finite and > 0");
+    if (max_iter < 1) throw bem::Error(BEM_ERR_INVALID, "max_iter must be >= 1");
+    for (int64_t k = 0; k < (int64_t)nrhs * c->n_body; ++k)
+        if (!std::isfinite(body_V[k])) throw bem::Error(BEM_ERR_INVALID, "non-finite body potential");
+    const int64_t n = c->n, ld = c->ld;
+    c->gm_b.alloc(sizeof(double) * (ld * 2 + (size_t)nrhs * c->n_body));
+    double* bvec = c->gm_b.as<double>();
+    double* xvec = bvec + ld;
+    double* dV = xvec + ld;
+    BEM_HIP(hipMemcpyAsync(dV, body_V, sizeof(double) * nrhs * c->n_body, hipMemcpyHostToDevice, c->stream));
+    int total_it = 0, total_ref = 0;
+    double worst = 0.0;
+    bool all_conv = true;
+    for (int32_t r = 0; r < nrhs; ++r) {
+        bem::launch_rhs(c, 1, dV + (int64_t)r * c->n_body, bvec);
+        int it = 0, ref = 0;
+        double rr = 0.0;
+        const int rc = bem::gmres_solve(c, bvec, xvec, tol, max_iter, &it, &rr, &ref);
+        BEM_HIP(hipMemcpyAsync(sol + (int64_t)r * n, xvec, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        total_it += it;
+        total_ref += ref;
+        worst = std::max(worst, rr);
+        if (rc != 0) all_conv = false;
+    }
+    BEM_HIP(hipStreamSynchronize(c->stream));
+    if (info) {
+        info->iters = total_it;
+        info->rel_residual = worst;
+        info->refinements = total_ref;
+    }
+    if (!all_conv)
+        return fail(BEM_ERR_NOCONV, "GMRES stopped at relative residual " + std::to_string(worst) + " after " +
+                                        std::to_string(total_it) + " iterations");
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_eval_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts,
+                          const int32_t* on_panel, double* phi, double* E) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (nrhs < 1 || !sol || (P > 0 && !E)) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL sol, E required");
+    check_points(c, P, pts);
+    if (on_panel) {
+        auto h = fetch_i32(c, on_panel, (size_t)P);
+        for (int32_t v : h)
+            if (v < -1 || v >= c->N) throw bem::Error(BEM_ERR_INVALID, "on_panel entry out of range");
+    }
+    for (int32_t r = 0; r < nrhs; ++r)
+        bem::launch_eval(c, sol + (int64_t)r * c->n, P, pts, on_panel, phi ? phi + (int64_t)r * P : nullptr,
+                         E + (int64_t)r * P * 3);
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_trace_lines(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                           const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                           double* path) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    check_trace(c, nrhs, sol, L, line_rhs, starts, tp);
+    if (L > 0 && (!n_steps || !stop_code)) throw bem::Error(BEM_ERR_INVALID, "n_steps and stop_code are required");
+    bem::launch_trace(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, nullptr, nullptr);
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_streamer_integral(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                                 const double* starts, const bem_trace_params* tp, double* integral, int32_t* n_steps,
+                                 int32_t* stop_code, uint8_t* exceeds) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    check_trace(c, nrhs, sol, L, line_rhs, starts, tp);
+    if (L > 0 && (!integral || !n_steps || !stop_code))
+        throw bem::Error(BEM_ERR_INVALID, "integral, n_steps and stop_code are required");
+    bem::launch_trace(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, nullptr, integral, exceeds);
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_set_profiling(bem_ctx* c, int32_t enable) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    c->profiling = enable != 0;
+    return BEM_OK;
+}
+
+bem_status bem_kernel_stats(bem_ctx* c, const char* name, int64_t* launches, double* total_ms) {
+    if (!c || !name || !launches || !total_ms) return fail(BEM_ERR_INVALID, "NULL argument");
+    DeviceGuard g(c->device);
+    API_TRY
+    bem::resolve_stats(c);
+    auto it = c->stats.find(name);
+    *launches = it == c->stats.end() ? 0 : it->second.launches;
+    *total_ms = it == c->stats.end() ? 0.0 : it->second.ms;
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_reset_stats(bem_ctx* c) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    bem::resolve_stats(c);
+    c->stats.clear();
+    return BEM_OK;
+    API_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Device-side building blocks shared by the gfx950 kernels: the Sec. 4
+// pair classification, the 7-point far-field sums and the closed-form
+// potential/field of a flat triangle with unit charge density.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+constexpr double INV4PI = 0.079577471545947667884;   // 1 / (4 pi)
+
+// native clang vectors (usable with the nontemporal load builtin)
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Sec. 4 classification: the pair (x, panel) is regular iff the squared
+// distance from x to the circumcentre exceeds (eta R)^2.  Written with
+// explicit fma so that every kernel makes the identical decision.
+__device__ __forceinline__ bool is_regular(double dx, double dy, double dz, double rr) {
+    double d2 = __fma_rn(dx, dx, __fma_rn(dy, dy, dz * dz));
+    return d2 > rr;
+}
+
+// Closed-form single-layer potential S and field F = -grad S of a flat
+// triangle with unit density at x (Wilton et al. 1984; Graglia 1993).  With
+// w the signed height of x over the plane, rho its foot point and, for each
+// edge a -> b with in-plane outward normal m, the edge abscissae s-, s+, the
+// in-plane distance t and the vertex distances R-, R+:
+//   f_e = ln((R+ + s+)/(R- + s-))      (ln((R- - s-)/(R+ - s+)) if s+ + s- <= 0)
+//   b_e = angle difference of (t s+, R0^2 + |w| R+) and (t s-, R0^2 + |w| R-)
+//   4 pi S = sum t f_e - |w| sum b_e,   4 pi F = sum m f_e + sign(w) n sum b_e.
+// The angle difference is taken with one atan2 (both angles lie in
+// [-pi/2, pi/2]).  inplane: x is the triangle's own centroid, so w = 0 and
+// sign(w) = 0 (principal value).  T is the 16-double exact-geometry record.
+template <bool WANT_S, bool WANT_F>
+__device__ __forceinline__ void flat_tri_SF(const double* __restrict__ T, double x0, double x1, double x2,
+                                            bool inplane, double& S, double& F0, double& F1, double& F2) {
+    const double n0 = T[TR_N + 0], n1 = T[TR_N + 1], n2 = T[TR_N + 2];
+    double w = inplane ? 0.0 : (x0 - T[0]) * n0 + (x1 - T[1]) * n1 + (x2 - T[2]) * n2;
+    const double r0 = x0 - w * n0, r1 = x1 - w * n1, r2 = x2 - w * n2;
+    const double aw = fabs(w), w2 = w * w;
+    // distances from x to the three vertices
+    double Rv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double d0 = x0 - T[3 * k], d1 = x1 - T[3 * k + 1], d2 = x2 - T[3 * k + 2];
+        Rv[k] = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    double st = 0.0, sb = 0.0, m0s = 0.0, m1s = 0.0, m2s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int b = (e + 1) % 3;
+        const double ax = T[3 * e], ay = T[3 * e + 1], az = T[3 * e + 2];
+        double l0 = T[3 * b] - ax, l1 = T[3 * b + 1] - ay, l2 = T[3 * b + 2] - az;
+        const double len = sqrt(l0 * l0 + l1 * l1 + l2 * l2);
+        const double il = 1.0 / len;
+        l0 *= il; l1 *= il; l2 *= il;
+        // m = l x n
+        const double m0 = l1 * n2 - l2 * n1, m1 = l2 * n0 - l0 * n2, m2 = l0 * n1 - l1 * n0;
+        const double q0 = ax - r0, q1 = ay - r1, q2 = az - r2;
+        const double sm = q0 * l0 + q1 * l1 + q2 * l2;
+        const double sp = sm + len;
+        const double t = q0 * m0 + q1 * m1 + q2 * m2;
+        const double Rm = Rv[e], Rp = Rv[b];
+        double f;
+        if (sp + sm > 0.0)
+            f = log((Rp + sp) / (Rm + sm));
+        else
+            f = log((Rm - sm) / (Rp - sp));
+        const double R02 = t * t + w2;
+        const double xp = R02 + aw * Rp, xm = R02 + aw * Rm;
+        const double yp = t * sp, ym = t * sm;
+        const double beta = atan2(yp * xm - ym * xp, xp * xm + yp * ym);
+        st += t * f;
+        sb += beta;
+        m0s += m0 * f;
+        m1s += m1 * f;
+        m2s += m2 * f;
+    }
+    if (WANT_S) S = (st - aw * sb) * INV4PI;
+    if (WANT_F) {
+        const double sg = (w > 0.0) ? sb : ((w < 0.0) ? -sb : 0.0);
+        F0 = (m0s + sg * n0) * INV4PI;
+        F1 = (m1s + sg * n1) * INV4PI;
+        F2 = (m2s + sg * n2) * INV4PI;
+    }
+}
+
+// ---- wave / block reductions (wave64) --------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+}  // namespace bem

@@ -1,0 +1,171 @@
+// Internal declarations of the gfx950 BEM library: context layout, device
+// buffers and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/bem.h"
+
+namespace bem {
+
+// ---- error plumbing -------------------------------------------------------
+struct Error : std::runtime_error {
+    bem_status code;
+    Error(bem_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define BEM_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::bem::Error(BEM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define BEM_CHECK_LAUNCH() BEM_HIP(hipGetLastError())
+
+// ---- device buffer with ownership -----------------------------------------
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        if (b == 0) return;
+        BEM_HIP(hipMalloc(&p, b));
+        bytes = b;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---- pinned host buffer (staging of small device-to-host reads) ----------
+struct HBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    HBuf() = default;
+    HBuf(const HBuf&) = delete;
+    HBuf& operator=(const HBuf&) = delete;
+    ~HBuf() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        BEM_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+        bytes = b;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---- layout constants ----------------------------------------------------
+// Far-field record of one panel (FP64 or FP32), 32 values:
+//   [0..6] node x, [7..13] node y, [14..20] node z, [21..27] weight * area / (4 pi),
+//   [28..30] circumcentre, [31] (eta * R)^2.
+constexpr int FAR_REC = 32;
+constexpr int FR_X = 0, FR_Y = 7, FR_Z = 14, FR_W = 21, FR_CC = 28, FR_RR = 31;
+// Exact-geometry record of one panel (FP64), 16 values:
+//   [0..8] v1 v2 v3, [9..11] unit normal, [12..14] centroid, [15] area.
+constexpr int TRI_REC = 16;
+constexpr int TR_V = 0, TR_N = 9, TR_C = 12, TR_A = 15;
+
+struct KStat {
+    int64_t launches = 0;
+    double ms = 0.0;
+};
+
+}  // namespace bem
+
+struct bem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bem_options opt{};
+    int64_t N = 0, n = 0, ld = 0, n_vert = 0;
+    int32_t n_body = 0, n_float = 0;
+    double shift[3] = {0, 0, 0};   // mesh translated by -shift on the device (FP32 accuracy)
+    double min_R = 0.0;
+
+    std::vector<int32_t> h_tri_body, h_body_kind, h_body_fidx;
+    std::vector<double> h_epsp, h_epsm;
+    std::vector<int32_t> h_rows_pot, h_rows_int, h_rows_flt;   // row segments by kind (Sec. 4)
+
+    bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx;
+    bem::DBuf far64, far32, tri64;
+    bem::DBuf rows_pot, rows_int, rows_flt, row_slot;
+    bem::DBuf A64, A32, Kf;                 // dense operator (FP64 or FP32) and the K' block of floating rows
+    bem::DBuf nearmask, near_ptr, near_row, near_col, near_val;
+    bem::DBuf diag;
+    int64_t near_nnz = 0;
+    bool assembled = false;
+
+    // scratch
+    bem::DBuf gm_V, gm_w, gm_z, gm_h, gm_part, gm_x, gm_r, gm_b, gm_misc;
+    bem::HBuf host_stage;
+    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue;
+
+    // profiling
+    bool profiling = false;
+    std::map<std::string, bem::KStat> stats;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> event_pool;
+
+    ~bem_ctx() {
+        for (auto& p : pending) {
+            (void)hipEventDestroy(p.second.first);
+            (void)hipEventDestroy(p.second.second);
+        }
+        for (auto e : event_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace bem {
+
+// RAII timer: records a pair of events on the context stream around a launch.
+struct KTimer {
+    bem_ctx* c;
+    const char* name;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(bem_ctx* ctx, const char* nm);
+    ~KTimer();
+};
+void resolve_stats(bem_ctx* c);
+
+// ---- launchers (one translation unit each) --------------------------------
+void launch_geometry(bem_ctx* c);                                  // geometry.hip
+void launch_far_assemble(bem_ctx* c);                              // assemble.hip
+void launch_near_csr(bem_ctx* c, const uint64_t* mask, int64_t n_targets, DBuf& ptr, DBuf& row, DBuf& col,
+                     int64_t* nnz, const char* tname);             // assemble.hip
+void launch_near_assemble(bem_ctx* c);                             // assemble.hip
+void launch_finalize(bem_ctx* c);                                  // assemble.hip
+void launch_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out);
+void launch_rhs(bem_ctx* c, int32_t nrhs, const double* d_bodyV, double* b);
+void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      // gemv.hip
+void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s);    // gemv.hip
+int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,
+                int* refinements);
+void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel,
+                 double* phi, double* E);                          // eval.hip
+void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                  const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                  double* path, double* integral, uint8_t* exceeds);   // trace.hip
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace bem
