@@ -180,6 +180,13 @@ bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, 
                                  const int32_t* line_rhs, const double* starts, const bem_trace_params* tp,
                                  double* integral, int32_t* n_steps, int32_t* stop_code, uint8_t* exceeds);
 
+/* Tuning knobs (no effect on results beyond summation order).
+ *  "trace_mode": 0 = choose by line count, 1 = all lines advance together
+ *                (one batched evaluation per RK4 stage, spread over the GPU),
+ *                2 = one persistent launch, one workgroup per line.
+ * Errors: INVALID for an unknown key or value. */
+bem_status bem_set_tuning(bem_ctx* ctx, const char* key, int64_t value);
+
 /* Per-kernel timing with HIP events recorded on the context stream around
  * each launch while enabled.  Names: "geometry", "far_assemble", "near_mask_csr",
  * "near_assemble", "finalize", "gemv", "gmres_ortho", "eval_far", "eval_near", "trace". */

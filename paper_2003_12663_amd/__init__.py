@@ -184,6 +184,9 @@ class Context:
                                               _dev_ptr(st), _dev_ptr(ex)), self.lib)
         return I, ns, st, ex
 
+    def set_tuning(self, key: str, value: int):
+        _check(self.lib.bem_set_tuning(self._ctx, key.encode(), int(value)), self.lib)
+
     # -------------------------------------------------------------- profiling
     def set_profiling(self, on=True):
         _check(self.lib.bem_set_profiling(self._ctx, int(bool(on))), self.lib)

@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "DEGENERATE", 3: "OOM", 4: "HIP", 5: "
 EXPORTS = [
     "bem_create", "bem_destroy", "bem_last_error", "bem_n_unknowns", "bem_assemble", "bem_copy_rows",
     "bem_near_pairs", "bem_rhs", "bem_matvec", "bem_solve_gmres", "bem_eval_field", "bem_trace_lines",
-    "bem_streamer_integral", "bem_set_profiling", "bem_kernel_stats", "bem_reset_stats",
+    "bem_streamer_integral", "bem_set_tuning", "bem_set_profiling", "bem_kernel_stats", "bem_reset_stats",
 ]
 
 
@@ -64,6 +64,7 @@ def load() -> ctypes.CDLL:
         "bem_eval_field": (i32, [P, i32, P, i64, P, P, P, P]),
         "bem_trace_lines": (i32, [P, i32, P, i64, P, P, P, P, P, P]),
         "bem_streamer_integral": (i32, [P, i32, P, i64, P, P, P, P, P, P, P]),
+        "bem_set_tuning": (i32, [P, ctypes.c_char_p, i64]),
         "bem_set_profiling": (i32, [P, i32]),
         "bem_kernel_stats": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(f64)]),
         "bem_reset_stats": (i32, [P]),

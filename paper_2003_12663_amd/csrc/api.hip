@@ -477,6 +477,16 @@ bem_status bem_streamer_integral(bem_ctx* c, int32_t nrhs, const double* sol, in
     API_CATCH
 }
 
+bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
+    if (!c || !key) return fail(BEM_ERR_INVALID, "NULL argument");
+    if (std::strcmp(key, "trace_mode") == 0) {
+        if (value < 0 || value > 2) return fail(BEM_ERR_INVALID, "trace_mode must be 0, 1 or 2");
+        c->trace_mode = (int32_t)value;
+        return BEM_OK;
+    }
+    return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
+}
+
 bem_status bem_set_profiling(bem_ctx* c, int32_t enable) {
     if (!c) return fail(BEM_ERR_INVALID, "NULL context");
     c->profiling = enable != 0;

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ far64, c
             for (int q = 0; q < 7; ++q) {
                 const R dx = x0 - qx[q], dy = x1 - qy[q], dz = x2 - qz[q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                s += qw[q] * rsqrt(r2);
+                s += qw[q] * rsqrt_pos(r2);
             }
             acc = s;
         } else {
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ far64, c
             for (int q = 0; q < 7; ++q) {
                 const R dx = x0 - qx[q], dy = x1 - qy[q], dz = x2 - qz[q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ir = rsqrt(r2);
+                const R ir = rsqrt_pos(r2);
                 const R t = qw[q] * ir * ir * ir;
                 f0 += t * dx;
                 f1 += t * dy;

@@ -31,26 +31,30 @@ __device__ __forceinline__ bool is_regular(double dx, double dy, double dz, doub
 // edge a -> b with in-plane outward normal m, the edge abscissae s-, s+, the
 // in-plane distance t and the vertex distances R-, R+:
 //   f_e = ln((R+ + s+)/(R- + s-))      (ln((R- - s-)/(R+ - s+)) if s+ + s- <= 0)
-//   b_e = angle difference of (t s+, R0^2 + |w| R+) and (t s-, R0^2 + |w| R-)
-//   4 pi S = sum t f_e - |w| sum b_e,   4 pi F = sum m f_e + sign(w) n sum b_e.
-// The angle difference is taken with one atan2 (both angles lie in
-// [-pi/2, pi/2]).  inplane: x is the triangle's own centroid, so w = 0 and
-// sign(w) = 0 (principal value).  T is the 16-double exact-geometry record.
+//   4 pi S = sum t f_e - |w| Omega,   4 pi F = sum m f_e + sign(w) n Omega,
+// where Omega, the sum of the three edge angles of those papers, is the solid
+// angle the triangle subtends at x, taken here in one step from the formula of
+// Van Oosterom & Strackee (1983): tan(Omega/2) = |[r1 r2 r3]| /
+// (R1 R2 R3 + (r1.r2) R3 + (r1.r3) R2 + (r2.r3) R1), r_k = v_k - x.
+// inplane: x is the triangle's own centroid, so w = 0 and sign(w) = 0
+// (principal value).  T is the 16-double exact-geometry record.
 template <bool WANT_S, bool WANT_F>
 __device__ __forceinline__ void flat_tri_SF(const double* __restrict__ T, double x0, double x1, double x2,
                                             bool inplane, double& S, double& F0, double& F1, double& F2) {
     const double n0 = T[TR_N + 0], n1 = T[TR_N + 1], n2 = T[TR_N + 2];
     double w = inplane ? 0.0 : (x0 - T[0]) * n0 + (x1 - T[1]) * n1 + (x2 - T[2]) * n2;
     const double r0 = x0 - w * n0, r1 = x1 - w * n1, r2 = x2 - w * n2;
-    const double aw = fabs(w), w2 = w * w;
-    // distances from x to the three vertices
-    double Rv[3];
+    const double aw = fabs(w);
+    // vectors and distances from x to the three vertices
+    double V[3][3], Rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double d0 = x0 - T[3 * k], d1 = x1 - T[3 * k + 1], d2 = x2 - T[3 * k + 2];
-        Rv[k] = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        V[k][0] = T[3 * k] - x0;
+        V[k][1] = T[3 * k + 1] - x1;
+        V[k][2] = T[3 * k + 2] - x2;
+        Rv[k] = sqrt(V[k][0] * V[k][0] + V[k][1] * V[k][1] + V[k][2] * V[k][2]);
     }
-    double st = 0.0, sb = 0.0, m0s = 0.0, m1s = 0.0, m2s = 0.0;
+    double st = 0.0, m0s = 0.0, m1s = 0.0, m2s = 0.0;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const int b = (e + 1) % 3;
@@ -71,24 +75,41 @@ __device__ __forceinline__ void flat_tri_SF(const double* __restrict__ T, double
             f = log((Rp + sp) / (Rm + sm));
         else
             f = log((Rm - sm) / (Rp - sp));
-        const double R02 = t * t + w2;
-        const double xp = R02 + aw * Rp, xm = R02 + aw * Rm;
-        const double yp = t * sp, ym = t * sm;
-        const double beta = atan2(yp * xm - ym * xp, xp * xm + yp * ym);
         st += t * f;
-        sb += beta;
         m0s += m0 * f;
         m1s += m1 * f;
         m2s += m2 * f;
     }
-    if (WANT_S) S = (st - aw * sb) * INV4PI;
+    double omega = 0.0;
+    if (!inplane) {
+        const double c0 = V[1][1] * V[2][2] - V[1][2] * V[2][1];
+        const double c1 = V[1][2] * V[2][0] - V[1][0] * V[2][2];
+        const double c2 = V[1][0] * V[2][1] - V[1][1] * V[2][0];
+        const double triple = V[0][0] * c0 + V[0][1] * c1 + V[0][2] * c2;
+        const double d01 = V[0][0] * V[1][0] + V[0][1] * V[1][1] + V[0][2] * V[1][2];
+        const double d02 = V[0][0] * V[2][0] + V[0][1] * V[2][1] + V[0][2] * V[2][2];
+        const double d12 = V[1][0] * V[2][0] + V[1][1] * V[2][1] + V[1][2] * V[2][2];
+        const double den = Rv[0] * Rv[1] * Rv[2] + d01 * Rv[2] + d02 * Rv[1] + d12 * Rv[0];
+        omega = 2.0 * atan2(fabs(triple), den);
+    }
+    if (WANT_S) S = (st - aw * omega) * INV4PI;
     if (WANT_F) {
-        const double sg = (w > 0.0) ? sb : ((w < 0.0) ? -sb : 0.0);
+        const double sg = (w > 0.0) ? omega : ((w < 0.0) ? -omega : 0.0);
         F0 = (m0s + sg * n0) * INV4PI;
         F1 = (m1s + sg * n1) * INV4PI;
         F2 = (m2s + sg * n2) * INV4PI;
     }
 }
+
+// 1/sqrt(x) for finite x > 0: the hardware estimate refined by one
+// third-order step of y <- y (1 - e)^(-1/2) = y (1 + e/2 + 3 e^2/8 + ...),
+// e = 1 - x y^2.  No special-value handling: callers mask x = 0 by select.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __fma_rn(-x * y, y, 1.0);
+    return __fma_rn(y * e, __fma_rn(e, 0.375, 0.5), y);
+}
+__device__ __forceinline__ float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // ---- wave / block reductions (wave64) --------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

@@ -118,7 +118,10 @@ struct bem_ctx {
     // scratch
     bem::DBuf gm_V, gm_w, gm_z, gm_h, gm_part, gm_x, gm_r, gm_b, gm_misc;
     bem::HBuf host_stage;
-    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue;
+    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part;
+
+    // tuning knobs (bem_set_tuning)
+    int32_t trace_mode = 0;   // 0 auto, 1 all lines together (batched passes), 2 persistent per-line workgroups
 
     // profiling
     bool profiling = false;
@@ -165,6 +168,9 @@ void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, 
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                   const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                   double* path, double* integral, uint8_t* exceeds);   // trace.hip
+void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                          const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                          double* path, double* integral, uint8_t* exceeds);   // trace_batched.hip
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_eval_far(const double* __restrict__ far
             for (int q = 0; q < 7; ++q) {
                 const R dx = xr0 - tq[pj][q], dy = xr1 - tq[pj][7 + q], dz = xr2 - tq[pj][14 + q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ir = rsqrt(r2);
+                const R ir = rsqrt_pos(r2);
                 const R t = tq[pj][21 + q] * ir;
                 sp += t;
                 const R t3 = t * ir * ir;

@@ -138,7 +138,7 @@ __device__ __forceinline__ void field_pass(const bool HIT, Shared<T>& sh, int& p
                     const R dy = pr1 - fy[q * Npi + j];
                     const R dz = pr2 - fz[q * Npi + j];
                     const R r2 = dx * dx + dy * dy + dz * dz;
-                    const R ir = rsqrt(r2);
+                    const R ir = rsqrt_pos(r2);
                     const R t = fw[q * Npi + j] * ir * ir * ir;
                     f0 += t * dx;
                     f1 += t * dy;
@@ -353,8 +353,15 @@ void launch_trace_T(bem_ctx* c, int64_t Np, const double* sol, int64_t L, const 
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                   const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code, double* path,
                   double* integral, uint8_t* exceeds) {
-    (void)nrhs;
     if (L == 0) return;
+    int cus = 0;
+    BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    // few lines cannot fill the GPU one workgroup per line: advance them together
+    const int mode = c->trace_mode != 0 ? c->trace_mode : (L <= 8 * (int64_t)cus ? 1 : 2);
+    if (mode == 1) {
+        launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds);
+        return;
+    }
     KTimer t(c, "trace");
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     TraceArgs a;
@@ -369,8 +376,6 @@ void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const 
     c->tr_queue.alloc(sizeof(int32_t) * 64);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, c->stream, c->tr_queue.as<int32_t>());
     BEM_CHECK_LAUNCH();
-    int cus = 0;
-    BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     // few lines: one wide workgroup per line; many lines: narrower workgroups, several per CU
     if (L <= (int64_t)cus) {
         launch_trace_T<512>(c, Np, sol, L, line_rhs, starts, a, n_steps, stop_code, path, integral, exceeds,

@@ -1,0 +1,483 @@
+// Field lines and the streamer integral with all lines advancing together
+// (Sec. 1, Eq. Breakdowncrit; RK4 on dx/ds = dir E/|E|).
+//
+// Every active line needs one field evaluation per RK4 stage, and a line's
+// stages depend on each other, so one line alone cannot fill the GPU.  Here
+// all active lines advance by one stage per pass, and a pass is one batched
+// evaluation spread over the whole GPU, in two launches:
+//  k_lb_far  - (line tile x panel chunk) blocks: a block stages a chunk of C
+//              panels in LDS (read by broadcast) and evaluates the regular
+//              pairs of 256 lines by the 7-point rule, one line per lane.
+//              Near pairs are not evaluated here (Sec. 4: near-singular pairs
+//              are marked and done after the regular ones); each lane records
+//              them in a bit mask.  Output per (chunk, line): partial field and
+//              near mask.
+//  k_lb_step - one block per active line: sums the partials in a fixed order,
+//              evaluates the line's near pairs with the closed forms (all 256
+//              threads, fixed-order sums, so runs are bitwise reproducible),
+//              tests them against the step's segment on end-of-step passes,
+//              advances the RK4 stage machine, accumulates the streamer
+//              integral, stops the line (hit, weak field, max steps,
+//              non-finite) and appends survivors to the next active list.
+// All lines start together, so every active line is in the same RK4 stage in
+// a given pass.  A panel that a step's segment can reach lies within R + h of
+// the step's end point, hence in its near set when h < (eta - 1) R_min.
+#include <climits>
+
+#include "bem_device.h"
+
+namespace bem {
+namespace {
+
+constexpr int LB_T = 256;        // lines per tile (one per lane)
+constexpr int LB_C = 32;         // panels per chunk
+constexpr int LB_NRHS_LDS = 64;  // load cases whose sigma chunk is staged in LDS
+
+struct LBArgs {
+    double h, e_min, dir, a, e0, p, k_str;
+    int32_t max_steps;
+};
+
+struct LBState {
+    double* x;      // [L][3] current point
+    double* y;      // [L][3] query point of the pass
+    double* ks;     // [L][3] k1 + 2 k2 + 2 k3 + k4 so far
+    double* asum;   // [L] alpha sum of the stages
+    double* I;      // [L] integral
+    int32_t* ns;    // [L] accepted steps
+};
+
+__device__ __noinline__ double lb_pow(double d, double p) { return pow(d, p); }
+
+__device__ __forceinline__ double lb_alpha(const LBArgs& a, double e) {
+    const double d = e - a.e0;
+    if (!(d > 0.0)) return 0.0;
+    return a.a * (a.p == 2.0 ? d * d : lb_pow(d, a.p));
+}
+
+// Moeller-Trumbore test of the closed segment q -> q + d against the closed
+// triangle T; t in [0,1], or -1 when there is no hit.
+__device__ __forceinline__ double lb_segment_tri(const double* __restrict__ T, double q0, double q1, double q2,
+                                                 double d0, double d1, double d2) {
+    const double a0 = T[3] - T[0], a1 = T[4] - T[1], a2 = T[5] - T[2];
+    const double b0 = T[6] - T[0], b1 = T[7] - T[1], b2 = T[8] - T[2];
+    const double pv0 = d1 * b2 - d2 * b1, pv1 = d2 * b0 - d0 * b2, pv2 = d0 * b1 - d1 * b0;
+    const double det = a0 * pv0 + a1 * pv1 + a2 * pv2;
+    if (det == 0.0) return -1.0;
+    const double inv = 1.0 / det;
+    const double t0 = q0 - T[0], t1 = q1 - T[1], t2 = q2 - T[2];
+    const double u = (t0 * pv0 + t1 * pv1 + t2 * pv2) * inv;
+    if (u < 0.0 || u > 1.0) return -1.0;
+    const double qv0 = t1 * a2 - t2 * a1, qv1 = t2 * a0 - t0 * a2, qv2 = t0 * a1 - t1 * a0;
+    const double v = (d0 * qv0 + d1 * qv1 + d2 * qv2) * inv;
+    if (v < 0.0 || u + v > 1.0) return -1.0;
+    const double t = (b0 * qv0 + b1 * qv1 + b2 * qv2) * inv;
+    if (t < 0.0 || t > 1.0) return -1.0;
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_lb_init(int64_t L, const double* __restrict__ starts, LBState s,
+                                                 int32_t* __restrict__ act, int32_t* __restrict__ count,
+                                                 double* __restrict__ path, int64_t pstride) {
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l == 0) count[0] = (int32_t)L;
+    if (l >= L) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = starts[3 * l + k];
+        s.x[3 * l + k] = v;
+        s.y[3 * l + k] = v;
+        s.ks[3 * l + k] = 0.0;
+        if (path) path[l * pstride + k] = v;
+    }
+    s.asum[l] = 0.0;
+    s.I[l] = 0.0;
+    s.ns[l] = 0;
+    act[l] = (int32_t)l;
+}
+
+// SPLIT = 1: 256 lines per block (4 waves), every lane walks the whole chunk.
+// SPLIT > 1: 64 lines per block (SPLIT waves); wave w walks panels
+// [w C/SPLIT, (w + 1) C/SPLIT) of the chunk and the partial fields are added
+// in wave order (for few lines: 1/SPLIT of the serial work per lane).
+template <typename R, int SPLIT>
+__global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : LB_T) void k_lb_far(const double* __restrict__ far64, const R* __restrict__ farR,
+                                                 int64_t Np, int64_t N, const double* __restrict__ sol, int64_t n,
+                                                 int32_t nrhs, const int32_t* __restrict__ line_rhs, int64_t L,
+                                                 const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+                                                 int32_t* __restrict__ count_next, const double* __restrict__ ys,
+                                                 double* __restrict__ part, uint32_t* __restrict__ pmask) {
+    constexpr int NT = SPLIT > 1 ? 64 * SPLIT : LB_T;   // threads per block
+    constexpr int TILE = SPLIT > 1 ? 64 : LB_T;         // lines per block
+    constexpr int PER = LB_C / SPLIT;
+    __shared__ R tq[LB_C][28];
+    __shared__ double tc[LB_C][4];
+    __shared__ double tsig[LB_NRHS_LDS][LB_C + 1];
+    __shared__ double wred[SPLIT > 1 ? SPLIT : 1][64][3];
+    __shared__ uint32_t wmask[SPLIT > 1 ? SPLIT : 1][64];
+
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) count_next[0] = 0;
+    const int32_t A = count[0];
+    const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+    if (tile0 >= A) return;   // uniform over the block
+    const int64_t j0 = (int64_t)blockIdx.y * LB_C;
+    const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
+    const bool sig_lds = nrhs <= LB_NRHS_LDS;
+    for (int e = threadIdx.x; e < LB_C * 32; e += NT) {
+        const int pj = e % LB_C, comp = e / LB_C;
+        const int64_t j = j0 + pj;   // < Np (Np is N rounded up to 256)
+        if (comp < 28)
+            tq[pj][comp] = farR[(int64_t)comp * Np + j];
+        else
+            tc[pj][comp - 28] = far64[(int64_t)comp * Np + j];
+    }
+    if (sig_lds)
+        for (int e = threadIdx.x; e < nrhs * LB_C; e += NT) {
+            const int r = e / LB_C, pj = e % LB_C;
+            tsig[r][pj] = (pj < nc) ? sol[(int64_t)r * n + j0 + pj] : 0.0;
+        }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = tile0 + (SPLIT > 1 ? lane : (int)threadIdx.x);
+    const bool live = t < A;
+    const int pj0 = SPLIT > 1 ? wv * PER : 0;
+    const int pj1 = SPLIT > 1 ? (pj0 + PER < nc ? pj0 + PER : nc) : nc;
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    uint32_t nmask = 0;
+    int64_t l = 0;
+    if (live) {
+        l = act[t];
+        const int32_t rhs = line_rhs ? line_rhs[l] : 0;
+        const double p0 = ys[3 * l], p1 = ys[3 * l + 1], p2 = ys[3 * l + 2];
+        const R pr0 = (R)p0, pr1 = (R)p1, pr2 = (R)p2;
+        for (int pj = pj0; pj < pj1; ++pj) {
+            if (!is_regular(p0 - tc[pj][0], p1 - tc[pj][1], p2 - tc[pj][2], tc[pj][3])) {
+                nmask |= 1u << pj;
+                continue;
+            }
+            R f0 = 0, f1 = 0, f2 = 0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const R dx = pr0 - tq[pj][q], dy = pr1 - tq[pj][7 + q], dz = pr2 - tq[pj][14 + q];
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ir = rsqrt_pos(r2);
+                const R tw = tq[pj][21 + q] * ir * ir * ir;
+                f0 += tw * dx;
+                f1 += tw * dy;
+                f2 += tw * dz;
+            }
+            const double sg = sig_lds ? tsig[rhs][pj] : sol[(int64_t)rhs * n + j0 + pj];
+            e0 = fma(sg, (double)f0, e0);
+            e1 = fma(sg, (double)f1, e1);
+            e2 = fma(sg, (double)f2, e2);
+        }
+    }
+    if (SPLIT > 1) {
+        wred[wv][lane][0] = e0;
+        wred[wv][lane][1] = e1;
+        wred[wv][lane][2] = e2;
+        wmask[wv][lane] = nmask;
+        __syncthreads();
+        if (wv != 0 || !live) return;
+        e0 = wred[0][lane][0];
+        e1 = wred[0][lane][1];
+        e2 = wred[0][lane][2];
+        nmask = wmask[0][lane];
+#pragma unroll
+        for (int w = 1; w < SPLIT; ++w) {
+            e0 += wred[w][lane][0];
+            e1 += wred[w][lane][1];
+            e2 += wred[w][lane][2];
+            nmask |= wmask[w][lane];
+        }
+    } else if (!live) {
+        return;
+    }
+    double* o = part + ((int64_t)blockIdx.y * L + l) * 3;
+    o[0] = e0;
+    o[1] = e1;
+    o[2] = e2;
+    pmask[(int64_t)blockIdx.y * L + l] = nmask;
+}
+
+constexpr int LB_Q = 1024;   // near pairs per round in k_lb_step
+
+// One block per active line: far partials + the line's near pairs (closed
+// forms, and the segment test on end-of-step passes) + the RK4 stage machine.
+__global__ __launch_bounds__(256) void k_lb_step(
+    int64_t L, int64_t KS, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+    int32_t* __restrict__ act_next, int32_t* __restrict__ count_next, const double* __restrict__ part,
+    const uint32_t* __restrict__ pmask, int phase, LBState s, LBArgs a, const double* __restrict__ tri64,
+    const double* __restrict__ sol, int64_t n, const int32_t* __restrict__ line_rhs,
+    const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind, int32_t* __restrict__ n_steps,
+    int32_t* __restrict__ stop_code, double* __restrict__ integral, uint8_t* __restrict__ exceeds,
+    double* __restrict__ path, int64_t pstride) {
+    __shared__ int32_t list[LB_Q];
+    __shared__ int32_t scan[4];
+    __shared__ double red[4][4];
+    __shared__ int32_t redj[4];
+    const int32_t A = count[0];
+    if ((int64_t)blockIdx.x >= A) return;
+    const int64_t l = act[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const double* sigma = sol + (line_rhs ? (int64_t)line_rhs[l] : 0) * n;
+    const double p0 = s.y[3 * l], p1 = s.y[3 * l + 1], p2 = s.y[3 * l + 2];
+    const double q0 = s.x[3 * l], q1 = s.x[3 * l + 1], q2 = s.x[3 * l + 2];
+    const bool hit_pass = (phase == 4);
+    // far partials, fixed order per thread
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    for (int64_t k = tid; k < KS; k += 256) {
+        const double* o = part + (k * L + l) * 3;
+        e0 += o[0];
+        e1 += o[1];
+        e2 += o[2];
+    }
+    // near pairs: count this thread's, exclusive scan over the block (wave scans + one barrier)
+    int cnt = 0;
+    for (int64_t k = tid; k < KS; k += 256) cnt += __popc(pmask[k * L + l]);
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) scan[wv] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wv; ++w) wbase += scan[w];
+    const int total = scan[0] + scan[1] + scan[2] + scan[3];
+    const int off = wbase + incl - cnt;
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0, bt = 2.0;
+    int bj = INT_MAX;
+    for (int base = 0; base < total; base += LB_Q) {
+        __syncthreads();
+        // this thread's pairs that fall in [base, base + LB_Q)
+        if (off + cnt > base && off < base + LB_Q) {
+            int pos = off;
+            for (int64_t k = tid; k < KS && pos < base + LB_Q; k += 256) {
+                uint32_t m = pmask[k * L + l];
+                while (m) {
+                    const int b = __builtin_ctz(m);
+                    m &= m - 1;
+                    if (pos >= base && pos < base + LB_Q) list[pos - base] = (int32_t)(k * LB_C + b);
+                    ++pos;
+                }
+            }
+        }
+        __syncthreads();
+        const int nq = (total - base) < LB_Q ? (total - base) : LB_Q;
+        for (int q = tid; q < nq; q += 256) {
+            const int j = list[q];
+            const double* Tj = tri64 + (int64_t)TRI_REC * j;
+            double S, F0, F1, F2;
+            flat_tri_SF<false, true>(Tj, p0, p1, p2, false, S, F0, F1, F2);
+            const double sg = sigma[j];
+            n0 = fma(sg, F0, n0);
+            n1 = fma(sg, F1, n1);
+            n2 = fma(sg, F2, n2);
+            if (hit_pass) {
+                const double th = lb_segment_tri(Tj, q0, q1, q2, p0 - q0, p1 - q1, p2 - q2);
+                if (th >= 0.0 && (th < bt || (th == bt && j < bj))) {
+                    bt = th;
+                    bj = j;
+                }
+            }
+        }
+    }
+    e0 = wave_sum(e0 + n0);
+    e1 = wave_sum(e1 + n1);
+    e2 = wave_sum(e2 + n2);
+    if (hit_pass) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double t2 = __shfl_xor(bt, o, 64);
+            const int j2 = __shfl_xor(bj, o, 64);
+            if (t2 < bt || (t2 == bt && j2 < bj)) {
+                bt = t2;
+                bj = j2;
+            }
+        }
+    }
+    if (lane == 0) {
+        red[wv][0] = e0;
+        red[wv][1] = e1;
+        red[wv][2] = e2;
+        red[wv][3] = bt;
+        redj[wv] = bj;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const double F0 = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    const double F1 = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    const double F2 = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
+    int hit = -1;
+    if (hit_pass) {
+        double tb = 2.0;
+        int jb = INT_MAX;
+        for (int w = 0; w < 4; ++w)
+            if (red[w][3] < tb || (red[w][3] == tb && redj[w] < jb)) {
+                tb = red[w][3];
+                jb = redj[w];
+            }
+        hit = (jb != INT_MAX) ? jb : -1;
+    }
+    const double h = a.h;
+    double x0 = q0, x1 = q1, x2 = q2;
+    int32_t ns = s.ns[l];
+    int code = -1;   // -1: the line goes on
+    if (hit_pass) {
+        if (hit >= 0) {
+            const int32_t k = body_kind[tri_body[hit]];
+            code = (k == BEM_DIRICHLET) ? BEM_STOP_DIRICHLET
+                                        : ((k == BEM_FLOATING) ? BEM_STOP_FLOATING : BEM_STOP_INTERFACE);
+        } else {
+            s.I[l] += h / 6.0 * s.asum[l];
+            x0 = p0;
+            x1 = p1;
+            x2 = p2;
+            s.x[3 * l] = x0;
+            s.x[3 * l + 1] = x1;
+            s.x[3 * l + 2] = x2;
+            ++ns;
+            s.ns[l] = ns;
+            if (path) {
+                path[l * pstride + 3 * ns + 0] = x0;
+                path[l * pstride + 3 * ns + 1] = x1;
+                path[l * pstride + 3 * ns + 2] = x2;
+            }
+            if (ns >= a.max_steps) code = BEM_STOP_MAXSTEPS;
+        }
+    }
+    if (code < 0) {
+        const double m = sqrt(F0 * F0 + F1 * F1 + F2 * F2);
+        const double k0 = a.dir * F0 / m, k1 = a.dir * F1 / m, k2 = a.dir * F2 / m;
+        double* ks = s.ks + 3 * l;
+        double* y = s.y + 3 * l;
+        if (phase == 0 || phase == 4) {
+            if (!isfinite(m))
+                code = BEM_STOP_NONFINITE;
+            else if (m < a.e_min)
+                code = BEM_STOP_WEAK;
+            else {
+                ks[0] = k0;
+                ks[1] = k1;
+                ks[2] = k2;
+                s.asum[l] = lb_alpha(a, m);
+                y[0] = x0 + 0.5 * h * k0;
+                y[1] = x1 + 0.5 * h * k1;
+                y[2] = x2 + 0.5 * h * k2;
+            }
+        } else if (phase < 3) {
+            ks[0] += 2.0 * k0;
+            ks[1] += 2.0 * k1;
+            ks[2] += 2.0 * k2;
+            s.asum[l] += 2.0 * lb_alpha(a, m);
+            const double c = (phase == 1) ? 0.5 * h : h;
+            y[0] = x0 + c * k0;
+            y[1] = x1 + c * k1;
+            y[2] = x2 + c * k2;
+        } else {
+            ks[0] += k0;
+            ks[1] += k1;
+            ks[2] += k2;
+            s.asum[l] += lb_alpha(a, m);
+            y[0] = x0 + h / 6.0 * ks[0];
+            y[1] = x1 + h / 6.0 * ks[1];
+            y[2] = x2 + h / 6.0 * ks[2];
+            if (!(isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]))) code = BEM_STOP_NONFINITE;
+        }
+    }
+    if (code >= 0) {
+        n_steps[l] = ns;
+        stop_code[l] = code;
+        if (integral) integral[l] = s.I[l];
+        if (exceeds) exceeds[l] = (s.I[l] > a.k_str) ? 1 : 0;
+    } else {
+        act_next[atomicAdd(count_next, 1)] = (int32_t)l;
+    }
+}
+
+}  // namespace
+
+void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                          const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                          double* path, double* integral, uint8_t* exceeds) {
+    if (L == 0) return;
+    KTimer t(c, "trace");
+    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
+    const int64_t N = c->N;
+    const int64_t KS = ceil_div(N, LB_C);
+    const int64_t pstride = 3 * ((int64_t)tp->max_steps + 1);
+    LBArgs a;
+    a.h = tp->h;
+    a.e_min = tp->e_min;
+    a.dir = tp->direction >= 0 ? 1.0 : -1.0;
+    a.a = tp->alpha_a;
+    a.e0 = tp->alpha_e0;
+    a.p = tp->alpha_p;
+    a.k_str = tp->k_str;
+    a.max_steps = tp->max_steps;
+    // state: x, y, ks (3 each), asum, I; ns; two active lists and two counters
+    const size_t dbl = (size_t)L * 11;
+    c->lb_state.alloc(sizeof(double) * dbl + sizeof(int32_t) * ((size_t)L * 3 + 64));
+    c->lb_part.alloc(sizeof(double) * 3 * (size_t)KS * L + sizeof(uint32_t) * (size_t)KS * L);
+    double* base = c->lb_state.as<double>();
+    LBState s;
+    s.x = base;
+    s.y = base + 3 * L;
+    s.ks = base + 6 * L;
+    s.asum = base + 9 * L;
+    s.I = base + 10 * L;
+    int32_t* ib = reinterpret_cast<int32_t*>(base + dbl);
+    s.ns = ib;
+    int32_t* act[2] = {ib + L, ib + 2 * L};
+    int32_t* cnt[2] = {ib + 3 * L, ib + 3 * L + 16};
+    double* part = c->lb_part.as<double>();
+    uint32_t* pmask = reinterpret_cast<uint32_t*>(part + 3 * (size_t)KS * L);
+    hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, starts, s, act[0],
+                       cnt[0], path, pstride);
+    BEM_CHECK_LAUNCH();
+    const bool fp64 = c->opt.precision == BEM_FP64;
+    const int64_t max_pass = 4 * (int64_t)tp->max_steps + 1;
+    int cur = 0;
+    int32_t* host = c->host_stage.as<int32_t>();
+    int64_t known_active = L;   // upper bound on the active count (refreshed every 32 passes)
+    for (int64_t pass = 0; pass < max_pass; ++pass) {
+        const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
+        const bool split = known_active <= 64;
+        // blocks of tiles past the active count would only launch and exit: size the grids by
+        // the last known active count (an upper bound, the count only falls)
+        dim3 g1((unsigned)ceil_div(known_active, split ? 64 : LB_T), (unsigned)KS);
+#define BEM_LB_FAR(R, SP, FR)                                                                                     \
+    hipLaunchKernelGGL((k_lb_far<R, SP>), g1, dim3(SP > 1 ? 64 * SP : LB_T), 0, c->stream, c->far64.as<double>(), FR, Np, N, sol,     \
+                       c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask)
+        if (fp64) {
+            if (split)
+                BEM_LB_FAR(double, 8, c->far64.as<double>());
+            else
+                BEM_LB_FAR(double, 1, c->far64.as<double>());
+        } else {
+            if (split)
+                BEM_LB_FAR(float, 8, c->far32.as<float>());
+            else
+                BEM_LB_FAR(float, 1, c->far32.as<float>());
+        }
+#undef BEM_LB_FAR
+        BEM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, KS, act[cur], cnt[cur],
+                           act[cur ^ 1], cnt[cur ^ 1], part, pmask, phase, s, a, c->tri64.as<double>(), sol, c->n,
+                           line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,
+                           integral, exceeds, path, pstride);
+        BEM_CHECK_LAUNCH();
+        cur ^= 1;
+        if ((pass & 31) == 31 || pass == max_pass - 1) {
+            BEM_HIP(hipMemcpyAsync(host, cnt[cur], sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            BEM_HIP(hipStreamSynchronize(c->stream));
+            if (host[0] == 0) break;
+            known_active = host[0];
+        }
+    }
+}
+
+}  // namespace bem

@@ -1,0 +1,95 @@
+"""Parity at the benchmark's full size (coax, ~20k panels, 256 field lines),
+in the launch configuration the benchmark times, on outputs the oracle can
+compute one by one: sampled matrix rows, the residual of the GPU solution
+against sampled oracle rows, the field at sampled points, and sampled lines
+of the 256-line launch."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import coax_problem_for_size, electrode_line_starts, gap_eval_points
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-fullsize] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_12663_amd as bem
+    p = coax_problem_for_size(20000)
+    _say(f"coax N={p.n_tri}: assemble + solve")
+    c = bem.Context.from_problem(p)
+    c.assemble()
+    sol, info = c.solve(p.body_V, tol=1e-12, max_iter=5000)
+    o = oracle.Oracle(p)
+    yield bem, p, c, o, sol, info
+    c.close()
+
+
+def test_sampled_rows(setup):
+    bem, p, c, o, sol, info = setup
+    rng = np.random.default_rng(21)
+    N = p.n_tri
+    kinds = p.body_kind[p.tri_body]
+    rows = np.concatenate([rng.choice(np.nonzero(kinds == k)[0], 8, replace=False) for k in (0, 1, 2)]
+                          + [np.array([0, N - 1, N])])          # first, last panel row and the constraint row
+    rows = np.unique(rows)
+    _say(f"rows {len(rows)}")
+    A = o.assemble_rows(rows)
+    G = np.stack([c.copy_rows(int(r), 1).cpu().numpy()[0] for r in rows])
+    err = (np.abs(G - A) / np.abs(A).max(axis=1, keepdims=True)).max()
+    assert err <= 1e-12, err
+    # the GPU solution satisfies the oracle's equations on these rows
+    x = sol[0].cpu().numpy()
+    b = o.rhs(p.body_V)[rows]
+    r = A @ x - b
+    bn = np.linalg.norm(o.rhs(p.body_V))
+    assert np.abs(r).max() <= 1e-9 * max(np.abs(b).max(), bn / np.sqrt(len(x)))
+    assert info["converged"] and info["rel_residual"] <= 1e-12
+
+
+def test_sampled_field(setup):
+    bem, p, c, o, sol, info = setup
+    x = sol[0].cpu().numpy()
+    pts = gap_eval_points(1000, seed=3)
+    _, E = c.eval_field(sol, pts)
+    idx = np.arange(0, 1000, 25)
+    _say(f"field at {len(idx)} of 1000 points")
+    _, E_o = o.eval(x, pts[idx])
+    Eg = E[0].cpu().numpy()[idx]
+    assert np.abs(np.linalg.norm(Eg, axis=1) - np.linalg.norm(E_o, axis=1)).max() <= \
+        1e-10 * np.linalg.norm(E_o, axis=1).max()
+    # surface field at sampled centroids (exterior limit), as the benchmark computes it for all
+    N = p.n_tri
+    cen = p.vert[p.tri].mean(axis=1)
+    on = np.arange(N, dtype=np.int32)
+    _, Es = c.eval_field(sol, cen, on_panel=on, want_phi=False)
+    sel = np.arange(0, N, 997)
+    _, Es_o = o.eval(x, cen[sel], on_panel=sel)
+    assert np.abs(Es[0].cpu().numpy()[sel] - Es_o).max() <= 1e-10 * np.abs(Es_o).max()
+
+
+def test_sampled_lines_of_full_launch(setup):
+    bem, p, c, o, sol, info = setup
+    x = sol[0].cpu().numpy()
+    starts, _, _ = electrode_line_starts(p, 256, seed=2)
+    tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-3)
+    I, ns, st, _ = c.streamer_integral(sol, starts, tp)
+    I, ns, st = I.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
+    # the shortest line of each stop kind plus two fixed ones (oracle cost grows with length)
+    pick = {int(np.argmin(np.where(st == k, ns, 10 ** 9))) for k in np.unique(st)} | {0, 17}
+    pick = np.array(sorted(pick))
+    _say(f"oracle lines {pick.tolist()} steps {ns[pick].tolist()}")
+    nso, sto, Io = o.trace(x, starts[pick], oracle.trace_params(h=1e-4, max_steps=2000, e_min=1e-3))
+    assert np.array_equal(ns[pick], nso) and np.array_equal(st[pick], sto)
+    assert np.abs(I[pick] - Io).max() <= 1e-10 * max(np.abs(Io).max(), 1e-300)

@@ -195,20 +195,24 @@ def _trace_compare(bem, c, o, x, starts, params_kw, L_check=None):
     return I, ns, st
 
 
-def test_sphere_trace(bem):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_sphere_trace(bem, mode):
     p = sphere_problem(3, V0=50.0)
-    _say("sphere trace")
+    _say(f"sphere trace mode {mode}")
     c, o, x, x_ref = _sigma_case(bem, p)
+    c.set_tuning("trace_mode", mode)
     starts, _, _ = electrode_line_starts(p, 8, seed=6)
     I, ns, st = _trace_compare(bem, c, o, x, starts, dict(h=1e-4, max_steps=300))
     assert np.all(ns == 300) and np.all(st == 0) and np.all(I > 0)
     c.close()
 
 
-def test_coax_trace_stop_codes(bem):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_coax_trace_stop_codes(bem, mode):
     p = coax_problem(0.012)
-    _say("coax trace")
+    _say(f"coax trace mode {mode}")
     c, o, x, x_ref = _sigma_case(bem, p)
+    c.set_tuning("trace_mode", mode)
     starts, _, _ = electrode_line_starts(p, 12, seed=2)
     # h = 1e-3 keeps the oracle fast; lines reach the shell, ring or disc
     I, ns, st = _trace_compare(bem, c, o, x, starts, dict(h=1e-3, max_steps=200))
@@ -217,10 +221,12 @@ def test_coax_trace_stop_codes(bem):
     c.close()
 
 
-def test_trace_edge_cases(bem):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_trace_edge_cases(bem, mode):
     p = sphere_problem(2)
-    _say("trace edge cases")
+    _say(f"trace edge cases mode {mode}")
     c, o, x, x_ref = _sigma_case(bem, p)
+    c.set_tuning("trace_mode", mode)
     sol = torch.tensor(x, device="cuda")
     starts, _, _ = electrode_line_starts(p, 3, seed=1)
     # one step
@@ -310,4 +316,28 @@ def test_multi_rhs_linearity(bem):
     sol, info = c.solve(bv, tol=1e-12)
     s = sol.cpu().numpy()
     assert rel(s[0], 0.5 * s[1]) <= 1e-10 and rel(s[2], 2.0 * s[1]) <= 1e-10
+    c.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_trace_multi_rhs_lines(bem, mode):
+    # lines driven by different load cases (line_rhs), both trace layouts
+    p = coax_problem(0.012)
+    _say(f"multi-rhs lines mode {mode}")
+    c = _ctx(bem, p)
+    c.set_tuning("trace_mode", mode)
+    bv = np.tile(p.body_V, (3, 1))
+    bv[:, 1] = [0.7, 1.0, 1.6]
+    sol, info = c.solve(bv, tol=1e-13, max_iter=20000)
+    starts, _, _ = electrode_line_starts(p, 9, seed=11)
+    line_rhs = np.array([0, 1, 2] * 3, dtype=np.int32)
+    tp = bem.trace_params(h=1e-3, max_steps=60)
+    I, ns, st, _ = c.streamer_integral(sol, starts, tp, line_rhs=line_rhs)
+    o = oracle.Oracle(p)
+    s_h = sol.cpu().numpy()
+    for r in range(3):
+        sel = np.nonzero(line_rhs == r)[0]
+        nso, sto, Io = o.trace(s_h[r], starts[sel], oracle.trace_params(h=1e-3, max_steps=60))
+        assert np.array_equal(ns.cpu().numpy()[sel], nso) and np.array_equal(st.cpu().numpy()[sel], sto)
+        assert np.abs(I.cpu().numpy()[sel] - Io).max() <= 1e-10 * max(np.abs(Io).max(), 1e-300)
     c.close()
