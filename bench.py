@@ -9,10 +9,11 @@ integral, all from inputs already resident in GPU memory.
 
 Prints one JSON line.  value = panel-pair evaluations per second over the
 whole step (matrix entries + surface-field pairs + field-line pairs).
-The roofline entry is for the field-line kernel (the dominant kernel):
-algorithmic FP64 flops per launch / its average duration measured with HIP
-events on the stream it runs on.  cpu_baseline times the plain FP64 CPU
-oracle on a bounded sample of the same workload.
+The roofline entry is for the dominant kernel, the far-field pass of the
+field-line tracer (k_lb_far, one launch per RK4 stage of all live lines):
+algorithmic FP64 flops per launch (regular pairs x 141 flop) / its average
+duration, measured with HIP events on the stream it runs on.  cpu_baseline
+times the plain FP64 CPU oracle on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -47,10 +48,59 @@ def parse():
     ap.add_argument("--lines", type=int, default=256)
     ap.add_argument("--max-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=256)
-    ap.add_argument("--cpu-sample-lines", type=int, default=2)
-    ap.add_argument("--cpu-sample-steps", type=int, default=25)
+    ap.add_argument("--cpu-sample-rows", type=int, default=19732)
+    ap.add_argument("--cpu-sample-lines", type=int, default=48)
+    ap.add_argument("--cpu-sample-steps", type=int, default=800)
+    ap.add_argument("--no-tts", action="store_true", help="skip the 64-load-case time-to-solve comparison")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 5 device-to-device copies of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": a.numel() * 8,
+                      "bytes_written_per_launch": a.numel() * 8, "launches": 5}))
+
+
+def time_to_solve(bem, torch, p, ctx64, nrhs=64, tol=1e-8):
+    """64 load cases (driven electrode U[0.5, 2], shell at 0) from the assembled state:
+    FP64 one by one, FP64 batched (FP64 matrix cores) and mixed batched (FP32 matrix cores
+    inside FP64 refinement).  Errors are max_j |s_j - s_ref_j| / max_j |s_ref_j| of sigma against
+    a batched FP64 solve to 1e-12."""
+    from workloads import rod_load_cases
+    bv = rod_load_cases(p, nrhs, seed=4)
+    N = p.n_tri
+    ref, _ = ctx64.solve(bv, tol=1e-12, max_iter=20000)
+    out = {"load_cases": nrhs, "tol": tol}
+
+    def timed(ctx, key):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol, info = ctx.solve(bv, tol=tol, max_iter=20000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = float(((sol[:, :N] - ref[:, :N]).abs().max() / ref[:, :N].abs().max()).item())
+        out[key] = {"s": dt, "iters": info["iters"], "refinements": info["refinements"], "sigma_rel_err": err}
+
+    ctx64.set_tuning("batched_solve", 0)
+    timed(ctx64, "fp64_one_by_one")
+    ctx64.set_tuning("batched_solve", 1)
+    timed(ctx64, "fp64_batched")
+    ctxm = bem.Context.from_problem(p, precision=bem.MIXED, eta=6.0, restart=100)
+    ctxm.assemble()
+    timed(ctxm, "mixed_batched")
+    ctxm.close()
+    out["speedup_mixed_vs_fp64_one_by_one"] = out["fp64_one_by_one"]["s"] / out["mixed_batched"]["s"]
+    out["speedup_mixed_vs_fp64_batched"] = out["fp64_batched"]["s"] / out["mixed_batched"]["s"]
+    return out
 
 
 def cpu_baseline(p, x, starts, args):
@@ -58,7 +108,7 @@ def cpu_baseline(p, x, starts, args):
     import oracle
     o = oracle.Oracle(p)
     rng = np.random.default_rng(12)
-    rows = np.sort(rng.choice(p.n_tri, size=args.cpu_sample_rows, replace=False))
+    rows = np.sort(rng.choice(p.n_tri, size=min(args.cpu_sample_rows, p.n_tri), replace=False))
     t0 = time.perf_counter()
     o.assemble_rows(rows)
     t_rows = time.perf_counter() - t0
@@ -76,6 +126,9 @@ def cpu_baseline(p, x, starts, args):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -131,16 +184,30 @@ def main():
     pairs = pairs_matrix + pairs_surface + pairs_lines
     stats = {k: ctx.kernel_stats(k) for k in ("geometry", "far_assemble", "near_mask_csr", "near_assemble",
                                                 "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
-                                                "eval_near_csr", "eval_far", "eval_near", "trace")}
+                                                "eval_near_csr", "eval_far", "eval_near", "trace", "trace_far",
+                                                "trace_step")}
+    near_line_pairs = ctx.counter("trace_near_pairs") / args.steps
     tr_n, tr_ms = stats["trace"]
     trace_ms = tr_ms / max(tr_n, 1)
-    trace_flops = pairs_lines * FLOP_FIELD_PAIR
-    achieved = trace_flops / (trace_ms * 1e-3) / 1e12
+    # dominant kernel: the far-field pass of the field-line tracer (k_lb_far), one launch per RK4 stage;
+    # the library times every 16th launch (a uniform sample of the passes)
+    tf_n, tf_ms = stats["trace_far"]
+    far_launches = ctx.counter("trace_far_launches") / args.steps
+    far_pairs = pairs_lines - near_line_pairs          # regular pairs: the ones k_lb_far evaluates
+    far_flop_per_launch = far_pairs * FLOP_FIELD_PAIR / far_launches
+    far_avg_ms = tf_ms / max(tf_n, 1)
+    achieved = far_flop_per_launch / (far_avg_ms * 1e-3) / 1e12
     gv_n, gv_ms = stats["gemv"]
     gemv_ms = gv_ms / max(gv_n, 1)
     gemv_gbs = (8.0 * n_unk * n_unk) / (gemv_ms * 1e-3) / 1e9
     fa_n, fa_ms = stats["far_assemble"]
     phases = {k: (v[1] / args.steps) for k, v in stats.items()}
+
+    tts = None
+    if not args.no_tts:
+        ctx.set_profiling(False)
+        print("[bench] time-to-solve, 64 load cases", file=sys.stderr, flush=True)
+        tts = time_to_solve(bem, torch, p, ctx)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -177,12 +244,15 @@ def main():
         "phase_ms_per_step": phases,
         "streamer_integral_sum": float(I.sum().item()),
         "stop_code_counts": {str(k): int(np.sum(st_h == k)) for k in range(6)},
-        "roofline": {"kernel": "k_trace (field lines + streamer integral)", "bound": "alu",
+        "roofline": {"kernel": "k_lb_far (far-field pass of the field-line tracer, FP64)", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-                     "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": pairs_lines,
-                     "avg_launch_ms": trace_ms},
+                     "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": far_pairs / far_launches,
+                     "launches_per_step": far_launches, "avg_launch_ms": far_avg_ms},
+        "trace_ms_per_step": trace_ms,
+        "trace_near_pairs": near_line_pairs,
         "cpu_baseline": cpu,
+        "time_to_solve_64_load_cases": tts,
     }
     print(json.dumps(out))
     ctx.close()

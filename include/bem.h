@@ -137,13 +137,16 @@ int64_t bem_near_pairs(const bem_ctx* ctx);
 bem_status bem_rhs(bem_ctx* ctx, int32_t nrhs, const double* body_V, double* b);
 
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1) for nrhs vectors,
- * x, y dev [nrhs][n], FP64 (the Krylov matvec of Sec. 3). */
+ * x, y dev [nrhs][n], FP64 (the Krylov matvec of Sec. 3).  With nrhs >= 2
+ * and "batched_solve" on, A x is one product of up to 64 vectors on the
+ * matrix cores with FP64 accumulation (MIXED: the FP32 far entries widened). */
 bem_status bem_matvec(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, int32_t transpose);
 
 /* Solve A sol = b(body_V) for nrhs load cases by restarted GMRES with the
  * diagonal (Jacobi) preconditioner applied on the right (Sec. 5.2), CGS2
- * orthogonalisation, zero initial guess, stopping at ||b - A x|| <= tol ||b||.
- * MIXED: GMRES on the mixed operator inside FP64 iterative refinement.
+ * orthogonalisation, zero initial guess, stopping at ||b - A x|| <= tol ||b||
+ * for every load case.  MIXED: GMRES on the mixed operator inside FP64
+ * iterative refinement.  Several load cases: see "batched_solve" below.
  *  body_V host [nrhs][n_body]; sol dev [nrhs][n]; info host (may be NULL).
  * Errors: STATE (not assembled), INVALID, NOCONV (best iterate written). */
 bem_status bem_solve_gmres(bem_ctx* ctx, int32_t nrhs, const double* body_V, double tol,
@@ -184,15 +187,30 @@ bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, 
  *  "trace_mode": 0 = choose by line count, 1 = all lines advance together
  *                (one batched evaluation per RK4 stage, spread over the GPU),
  *                2 = one persistent launch, one workgroup per line.
+ *  "batched_solve": 1 (default) = bem_solve_gmres with nrhs >= 2 runs up to 64
+ *                independent GMRES recurrences together, one multi-right-hand-
+ *                side matrix product per iteration on the matrix cores (FP64:
+ *                FP64 cores; MIXED: FP32 cores inside FP64 iterative
+ *                refinement); 0 = one right-hand side after another.
  * Errors: INVALID for an unknown key or value. */
 bem_status bem_set_tuning(bem_ctx* ctx, const char* key, int64_t value);
 
 /* Per-kernel timing with HIP events recorded on the context stream around
  * each launch while enabled.  Names: "geometry", "far_assemble", "near_mask_csr",
- * "near_assemble", "finalize", "gemv", "gmres_ortho", "eval_far", "eval_near", "trace". */
+ * "near_assemble", "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
+ * "eval_near_csr", "eval_far", "eval_near", "trace" (a whole field-line call),
+ * "trace_far" and "trace_step" (the two kernels of a batched pass; every 16th
+ * pass is timed, so their launch counts are a sample and total_ms covers that
+ * sample), "gemm_f32", "gemm_f64", "bgmres_iter". */
 bem_status bem_set_profiling(bem_ctx* ctx, int32_t enable);
 bem_status bem_kernel_stats(bem_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
-bem_status bem_reset_stats(bem_ctx* ctx);
+bem_status bem_reset_stats(bem_ctx* ctx);   /* also zeroes the counters below */
+
+/* Work counters since creation or the last bem_reset_stats:
+ * "trace_near_pairs"   = (point, panel) pairs of field-line evaluations that
+ *                        took the closed-form (near) path in the batched layout;
+ * "trace_far_launches" = far-field pass launches of the batched layout. */
+bem_status bem_get_counter(bem_ctx* ctx, const char* name, int64_t* value);
 
 #ifdef __cplusplus
 }

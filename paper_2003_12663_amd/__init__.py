@@ -199,3 +199,8 @@ class Context:
 
     def reset_stats(self):
         _check(self.lib.bem_reset_stats(self._ctx), self.lib)
+
+    def counter(self, name: str) -> int:
+        v = ctypes.c_int64(0)
+        _check(self.lib.bem_get_counter(self._ctx, name.encode(), ctypes.byref(v)), self.lib)
+        return int(v.value)

@@ -108,8 +108,8 @@ void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, c
 
 namespace bem {
 
-KTimer::KTimer(bem_ctx* ctx, const char* nm) : c(ctx), name(nm) {
-    if (!c->profiling) return;
+KTimer::KTimer(bem_ctx* ctx, const char* nm, bool enabled) : c(ctx), name(nm) {
+    if (!c->profiling || !enabled) return;
     auto get = [&]() {
         if (!c->event_pool.empty()) {
             hipEvent_t e = c->event_pool.back();
@@ -273,6 +273,8 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     c->far64.alloc(sizeof(double) * bem::FAR_REC * Np);
     c->far32.alloc(sizeof(float) * bem::FAR_REC * Np);
     c->tri64.alloc(sizeof(double) * bem::TRI_REC * c->N);
+    c->counters.alloc(sizeof(uint64_t) * 8);
+    BEM_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(uint64_t) * 8, s));
     bem::launch_geometry(c.get());
     BEM_HIP(hipStreamSynchronize(s));   // host-side sources of the uploads are temporaries
     *out = c.release();
@@ -372,6 +374,12 @@ bem_status bem_matvec(bem_ctx* c, int32_t nrhs, const double* x, double* y, int3
     check_assembled(c);
     if (nrhs < 1 || !x || !y) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL vectors required");
     if (transpose != 0 && transpose != 1) throw bem::Error(BEM_ERR_INVALID, "transpose must be 0 or 1");
+    if (nrhs >= 2 && !transpose && c->batched_solve) {
+        for (int32_t r0 = 0; r0 < nrhs; r0 += 64)
+            bem::batched_apply_exact(c, (int)std::min<int32_t>(64, nrhs - r0), x + (int64_t)r0 * c->n,
+                                     y + (int64_t)r0 * c->n);
+        return BEM_OK;
+    }
     c->gm_x.alloc(sizeof(double) * c->ld * 2);
     double* xa = c->gm_x.as<double>();
     double* ya = xa + c->ld;
@@ -407,16 +415,40 @@ bem_status bem_solve_gmres(bem_ctx* c, int32_t nrhs, const double* body_V, doubl
     int total_it = 0, total_ref = 0;
     double worst = 0.0;
     bool all_conv = true;
-    for (int32_t r = 0; r < nrhs; ++r) {
-        bem::launch_rhs(c, 1, dV + (int64_t)r * c->n_body, bvec);
-        int it = 0, ref = 0;
-        double rr = 0.0;
-        const int rc = bem::gmres_solve(c, bvec, xvec, tol, max_iter, &it, &rr, &ref);
-        BEM_HIP(hipMemcpyAsync(sol + (int64_t)r * n, xvec, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-        total_it += it;
-        total_ref += ref;
-        worst = std::max(worst, rr);
-        if (rc != 0) all_conv = false;
+    if (nrhs >= 2 && c->batched_solve) {
+        // groups of up to 64 load cases, one shared matrix product per iteration
+        for (int32_t r0 = 0; r0 < nrhs; r0 += 64) {
+            const int nr = (int)std::min<int32_t>(64, nrhs - r0);
+            c->bg_B.alloc(sizeof(double) * 64 * ld);
+            c->bg_X.alloc(sizeof(double) * 64 * ld);
+            double* B = c->bg_B.as<double>();
+            double* X = c->bg_X.as<double>();
+            for (int r = 0; r < nr; ++r)
+                bem::launch_rhs(c, 1, dV + (int64_t)(r0 + r) * c->n_body, B + (int64_t)r * ld);
+            int it = 0, ref = 0;
+            double rr = 0.0;
+            const int rc = bem::gmres_solve_batched(c, nr, B, X, tol, max_iter, &it, &rr, &ref);
+            for (int r = 0; r < nr; ++r)
+                BEM_HIP(hipMemcpyAsync(sol + (int64_t)(r0 + r) * n, X + (int64_t)r * ld, sizeof(double) * n,
+                                       hipMemcpyDeviceToDevice, c->stream));
+            total_it += it;
+            total_ref += ref;
+            worst = std::max(worst, rr);
+            if (rc != 0) all_conv = false;
+        }
+    } else {
+        for (int32_t r = 0; r < nrhs; ++r) {
+            bem::launch_rhs(c, 1, dV + (int64_t)r * c->n_body, bvec);
+            int it = 0, ref = 0;
+            double rr = 0.0;
+            const int rc = bem::gmres_solve(c, bvec, xvec, tol, max_iter, &it, &rr, &ref);
+            BEM_HIP(hipMemcpyAsync(sol + (int64_t)r * n, xvec, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                                   c->stream));
+            total_it += it;
+            total_ref += ref;
+            worst = std::max(worst, rr);
+            if (rc != 0) all_conv = false;
+        }
     }
     BEM_HIP(hipStreamSynchronize(c->stream));
     if (info) {
@@ -484,6 +516,11 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         c->trace_mode = (int32_t)value;
         return BEM_OK;
     }
+    if (std::strcmp(key, "batched_solve") == 0) {
+        if (value < 0 || value > 1) return fail(BEM_ERR_INVALID, "batched_solve must be 0 or 1");
+        c->batched_solve = (int32_t)value;
+        return BEM_OK;
+    }
     return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
 }
 
@@ -511,6 +548,28 @@ bem_status bem_reset_stats(bem_ctx* c) {
     API_TRY
     bem::resolve_stats(c);
     c->stats.clear();
+    c->trace_far_launches = 0;
+    BEM_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(uint64_t) * 8, c->stream));
+    BEM_HIP(hipStreamSynchronize(c->stream));
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_get_counter(bem_ctx* c, const char* name, int64_t* value) {
+    if (!c || !name || !value) return fail(BEM_ERR_INVALID, "NULL argument");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (std::strcmp(name, "trace_far_launches") == 0) {
+        *value = c->trace_far_launches;
+        return BEM_OK;
+    }
+    int idx = -1;
+    if (std::strcmp(name, "trace_near_pairs") == 0) idx = 0;
+    if (idx < 0) throw bem::Error(BEM_ERR_INVALID, std::string("unknown counter ") + name);
+    uint64_t v = 0;
+    BEM_HIP(hipMemcpyAsync(&v, c->counters.as<uint64_t>() + idx, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    BEM_HIP(hipStreamSynchronize(c->stream));
+    *value = (int64_t)v;
     return BEM_OK;
     API_CATCH
 }

@@ -120,8 +120,15 @@ struct bem_ctx {
     bem::HBuf host_stage;
     bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part;
 
+    bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X;   // batched GMRES
+
+    // device counters (bem_get_counter): [0] near pairs evaluated by the batched field-line passes
+    bem::DBuf counters;
+    int64_t trace_far_launches = 0;   // host-side count of batched field-line passes (bem_get_counter)
+
     // tuning knobs (bem_set_tuning)
     int32_t trace_mode = 0;   // 0 auto, 1 all lines together (batched passes), 2 persistent per-line workgroups
+    int32_t batched_solve = 1;   // several right-hand sides: 1 one batched solve (shared matrix products), 0 one by one
 
     // profiling
     bool profiling = false;
@@ -141,11 +148,12 @@ struct bem_ctx {
 namespace bem {
 
 // RAII timer: records a pair of events on the context stream around a launch.
+// enabled = false skips this launch (used to time a fixed sample of very frequent launches).
 struct KTimer {
     bem_ctx* c;
     const char* name;
     hipEvent_t a = nullptr, b = nullptr;
-    KTimer(bem_ctx* ctx, const char* nm);
+    KTimer(bem_ctx* ctx, const char* nm, bool enabled = true);
     ~KTimer();
 };
 void resolve_stats(bem_ctx* c);
@@ -163,6 +171,9 @@ void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      
 void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s);    // gemv.hip
 int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,
                 int* refinements);
+int gmres_solve_batched(bem_ctx* c, int nr, const double* B, double* X, double tol, int max_iter, int* iters,
+                        double* relres, int* refinements);   // gmres_batched.hip: nr <= 64, rows of stride ld
+void batched_apply_exact(bem_ctx* c, int nr, const double* X, double* Y);   // rows of stride n
 void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel,
                  double* phi, double* E);                          // eval.hip
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,

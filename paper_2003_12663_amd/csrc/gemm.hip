@@ -1,0 +1,168 @@
+// Dense products with many right-hand sides: Y = A Z for up to 64 load cases
+// at once (the matvec of a batched Krylov solve), on the MFMA matrix cores.
+//
+// A is the row-major system matrix (FP32 far matrix of the mixed mode, or the
+// FP64 matrix); Z holds the 64 input vectors.  Each A row is streamed from
+// HBM once per product and multiplied with all 64 vectors, so the product is
+// bound by the matrix cores rather than by HBM (2 flop x 64 per A entry).
+//
+//  k_gemm_f32: v_mfma_f32_32x32x2f32, FP32 operands and FP32 accumulation.
+//     A wave owns 32 rows x 64 columns (two 32x32 accumulators) over a
+//     quarter of K; the block's four waves cover all of K for the same rows
+//     and their partial tiles are added in LDS in a fixed order.
+//  k_gemm_f64: v_mfma_f64_16x16x4f64, FP64 accumulation, A either FP64 or
+//     FP32 widened exactly (FP32 values are FP64 numbers), so for the FP32
+//     far matrix it is the exact FP64-accumulated product of the mixed
+//     operator.  A wave owns 16 rows x 64 columns over a quarter of K.
+// Operand k-order: lane (r, h) of a 32-lane half feeds A[row r][k0 + 16h + s]
+// and Z[col][k0 + 16h + s] at step s; any order of k that is the same for both
+// operands gives the same sum.
+// Z layout: Zt[col][k] (vector-major), row stride ldz >= K, zero beyond the
+// true length; K is a multiple of 32 (rows of A are padded with zeros).
+#include "bem_device.h"
+
+namespace bem {
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int GM_WAVES = 4;   // K split over the waves of a block
+
+__global__ __launch_bounds__(64 * GM_WAVES) void k_gemm_f32(const float* __restrict__ A, int64_t lda, int64_t M,
+                                                            int64_t K, const float* __restrict__ Zt, int64_t ldz,
+                                                            int ncols, double* __restrict__ Y, int64_t ldy,
+                                                            int accumulate) {
+    __shared__ float part[GM_WAVES][64][33];   // partial tiles, [wave][col][row] (+1 pad)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int64_t row0 = (int64_t)blockIdx.x * 32;
+    const int64_t arow = row0 + r < M ? row0 + r : M - 1;
+    const float* __restrict__ Ap = A + arow * lda;
+    const float* __restrict__ Z0 = Zt + (int64_t)r * ldz;
+    const float* __restrict__ Z1 = Zt + (int64_t)(32 + r) * ldz;
+    // this wave's K range: a multiple of 32
+    const int64_t kblocks = K / 32;
+    const int64_t kb0 = kblocks * wv / GM_WAVES, kb1 = kblocks * (wv + 1) / GM_WAVES;
+    f16v acc0 = {0}, acc1 = {0};
+    for (int64_t kb = kb0; kb < kb1; ++kb) {
+        const int64_t k = kb * 32 + 16 * h;
+        f4v a[4], b0[4], b1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k) + q);
+            b0[q] = reinterpret_cast<const f4v*>(Z0 + k)[q];
+            b1[q] = reinterpret_cast<const f4v*>(Z1 + k)[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q][e], b0[q][e], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q][e], b1[q][e], acc1, 0, 0, 0);
+            }
+        }
+    }
+    // accumulator element v of lane (r, h): row 8 (v / 4) + 4 h + v % 4, column r (+32)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = 8 * (v >> 2) + 4 * h + (v & 3);
+        part[wv][r][row] = acc0[v];
+        part[wv][32 + r][row] = acc1[v];
+    }
+    __syncthreads();
+    // 256 threads add the 4 partial tiles (64 cols x 32 rows) in wave order
+    for (int e = threadIdx.x; e < 64 * 32; e += 64 * GM_WAVES) {
+        const int col = e >> 5, row = e & 31;
+        const int64_t i = row0 + row;
+        if (i >= M || col >= ncols) continue;
+        const float s = ((part[0][col][row] + part[1][col][row]) + part[2][col][row]) + part[3][col][row];
+        double* y = Y + (int64_t)col * ldy + i;
+        *y = accumulate ? *y + (double)s : (double)s;
+    }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(64 * GM_WAVES) void k_gemm_f64(const TA* __restrict__ A, int64_t lda, int64_t M,
+                                                            int64_t K, const double* __restrict__ Zt, int64_t ldz,
+                                                            int ncols, double* __restrict__ Y, int64_t ldy,
+                                                            int accumulate, double alpha) {
+    __shared__ double part[GM_WAVES][64][17];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, q4 = lane >> 4;   // row (A) / column (B) within 16, k group 0..3
+    const int64_t row0 = (int64_t)blockIdx.x * 16;
+    const int64_t arow = row0 + r < M ? row0 + r : M - 1;
+    const TA* __restrict__ Ap = A + arow * lda;
+    const int64_t kblocks = K / 16;
+    const int64_t kb0 = kblocks * wv / GM_WAVES, kb1 = kblocks * (wv + 1) / GM_WAVES;
+    d4v acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = (d4v){0.0, 0.0, 0.0, 0.0};
+    for (int64_t kb = kb0; kb < kb1; ++kb) {
+        const int64_t k = kb * 16 + 4 * q4;   // this lane's 4 consecutive k
+        double a[4];
+        if (sizeof(TA) == 4) {
+            const f4v av = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k));
+            a[0] = av[0]; a[1] = av[1]; a[2] = av[2]; a[3] = av[3];
+        } else {
+            const d2v a0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k));
+            const d2v a1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k) + 1);
+            a[0] = a0[0]; a[1] = a0[1]; a[2] = a1[0]; a[3] = a1[1];
+        }
+        double b[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double* zp = Zt + (int64_t)(16 * c + r) * ldz + k;
+            const d2v z0 = reinterpret_cast<const d2v*>(zp)[0];
+            const d2v z1 = reinterpret_cast<const d2v*>(zp)[1];
+            b[c][0] = z0[0]; b[c][1] = z0[1]; b[c][2] = z1[0]; b[c][3] = z1[1];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[c][s], acc[c], 0, 0, 0);
+    }
+    // accumulator element v of lane (r, q4): row 4 v + q4, column r (+16 c)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[wv][16 * c + r][4 * v + q4] = acc[c][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 16; e += 64 * GM_WAVES) {
+        const int col = e >> 4, row = e & 15;
+        const int64_t i = row0 + row;
+        if (i >= M || col >= ncols) continue;
+        const double s = alpha * (((part[0][col][row] + part[1][col][row]) + part[2][col][row]) + part[3][col][row]);
+        double* y = Y + (int64_t)col * ldy + i;
+        *y = accumulate ? *y + s : s;
+    }
+}
+
+}  // namespace
+
+// Y[c][0..M) (+)= A[0..M)[0..K) Zt[c][0..K) for c < ncols (<= 64); Zt has 64 rows.
+void launch_gemm_f32(bem_ctx* c, const float* A, int64_t lda, int64_t M, int64_t K, const float* Zt, int64_t ldz,
+                     int ncols, double* Y, int64_t ldy, bool accumulate) {
+    if (M <= 0) return;
+    if (K % 32 != 0 || ldz % 4 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f32 shape not padded");
+    KTimer t(c, "gemm_f32");
+    hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)ceil_div(M, 32)), dim3(64 * GM_WAVES), 0, c->stream, A, lda, M, K,
+                       Zt, ldz, ncols, Y, ldy, (int)accumulate);
+    BEM_CHECK_LAUNCH();
+}
+
+void launch_gemm_f64(bem_ctx* c, const void* A, bool a_is_f32, int64_t lda, int64_t M, int64_t K, const double* Zt,
+                     int64_t ldz, int ncols, double* Y, int64_t ldy, bool accumulate, double alpha) {
+    if (M <= 0) return;
+    if (K % 16 != 0 || ldz % 2 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f64 shape not padded");
+    KTimer t(c, "gemm_f64");
+    if (a_is_f32)
+        hipLaunchKernelGGL((k_gemm_f64<float>), dim3((unsigned)ceil_div(M, 16)), dim3(64 * GM_WAVES), 0, c->stream,
+                           (const float*)A, lda, M, K, Zt, ldz, ncols, Y, ldy, (int)accumulate, alpha);
+    else
+        hipLaunchKernelGGL((k_gemm_f64<double>), dim3((unsigned)ceil_div(M, 16)), dim3(64 * GM_WAVES), 0, c->stream,
+                           (const double*)A, lda, M, K, Zt, ldz, ncols, Y, ldy, (int)accumulate, alpha);
+    BEM_CHECK_LAUNCH();
+}
+
+}  // namespace bem

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
     const double* __restrict__ sol, int64_t n, const int32_t* __restrict__ line_rhs,
     const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind, int32_t* __restrict__ n_steps,
     int32_t* __restrict__ stop_code, double* __restrict__ integral, uint8_t* __restrict__ exceeds,
-    double* __restrict__ path, int64_t pstride) {
+    double* __restrict__ path, int64_t pstride, unsigned long long* __restrict__ near_count) {
     __shared__ int32_t list[LB_Q];
     __shared__ int32_t scan[4];
     __shared__ double red[4][4];
@@ -248,6 +248,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
     for (int w = 0; w < wv; ++w) wbase += scan[w];
     const int total = scan[0] + scan[1] + scan[2] + scan[3];
     const int off = wbase + incl - cnt;
+    if (tid == 0 && near_count) atomicAdd(near_count, (unsigned long long)total);
     double n0 = 0.0, n1 = 0.0, n2 = 0.0, bt = 2.0;
     int bj = INT_MAX;
     for (int base = 0; base < total; base += LB_Q) {
@@ -438,6 +439,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, starts, s, act[0],
                        cnt[0], path, pstride);
     BEM_CHECK_LAUNCH();
+    unsigned long long* near_count = reinterpret_cast<unsigned long long*>(c->counters.p);
     const bool fp64 = c->opt.precision == BEM_FP64;
     const int64_t max_pass = 4 * (int64_t)tp->max_steps + 1;
     int cur = 0;
@@ -446,6 +448,9 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
         const bool split = known_active <= 64;
+        {
+        // every 16th pass is timed: the event records would otherwise cost more than the short launches
+        KTimer tf(c, "trace_far", (pass & 15) == 0);
         // blocks of tiles past the active count would only launch and exit: size the grids by
         // the last known active count (an upper bound, the count only falls)
         dim3 g1((unsigned)ceil_div(known_active, split ? 64 : LB_T), (unsigned)KS);
@@ -465,11 +470,16 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         }
 #undef BEM_LB_FAR
         BEM_CHECK_LAUNCH();
+        ++c->trace_far_launches;
+        }
+        {
+        KTimer ts(c, "trace_step", (pass & 15) == 0);
         hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, KS, act[cur], cnt[cur],
                            act[cur ^ 1], cnt[cur ^ 1], part, pmask, phase, s, a, c->tri64.as<double>(), sol, c->n,
                            line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,
-                           integral, exceeds, path, pstride);
+                           integral, exceeds, path, pstride, near_count);
         BEM_CHECK_LAUNCH();
+        }
         cur ^= 1;
         if ((pass & 31) == 31 || pass == max_pass - 1) {
             BEM_HIP(hipMemcpyAsync(host, cnt[cur], sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));

@@ -341,3 +341,54 @@ def test_trace_multi_rhs_lines(bem, mode):
         assert np.array_equal(ns.cpu().numpy()[sel], nso) and np.array_equal(st.cpu().numpy()[sel], sto)
         assert np.abs(I.cpu().numpy()[sel] - Io).max() <= 1e-10 * max(np.abs(Io).max(), 1e-300)
     c.close()
+
+
+def test_batched_matvec_mfma(bem):
+    # the multi-vector product on the matrix cores against the oracle matrix
+    for prec in (bem.FP64, bem.MIXED):
+        p = coax_problem(0.012)
+        _say(f"batched matvec precision {prec}")
+        o = oracle.Oracle(p)
+        A = o.assemble()
+        c = _ctx(bem, p, precision=prec)
+        rng = np.random.default_rng(5)
+        X = rng.standard_normal((37, c.n))
+        Y = c.matvec(torch.tensor(X, device="cuda")).cpu().numpy()
+        if prec == bem.FP64:
+            assert rel(Y, X @ A.T) <= 1e-12
+        else:
+            G = c.copy_rows(0, c.n).cpu().numpy()       # the mixed operator itself
+            assert rel(Y, X @ G.T) <= 1e-12
+            assert rel(Y, X @ A.T) <= 1e-6
+        c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_solve_many_rhs(bem, prec):
+    p = coax_problem(0.012)
+    _say(f"batched solve {prec}")
+    o = oracle.Oracle(p)
+    A = o.assemble()
+    rng = np.random.default_rng(4)
+    nr = 70                                     # two groups: 64 + 6
+    bv = np.tile(p.body_V, (nr, 1))
+    bv[:, 1] = rng.uniform(0.5, 2.0, nr)        # rod potential
+    bv[::3, 0] = rng.uniform(-0.5, 0.5, len(bv[::3]))   # some load cases also drive the shell (rank 2)
+    X_ref = np.linalg.solve(A, np.stack([o.rhs(v) for v in bv]).T).T
+    kw = dict(precision=bem.FP64) if prec == "fp64" else dict(precision=bem.MIXED)
+    c = _ctx(bem, p, **kw)
+    tol = 1e-13 if prec == "fp64" else 1e-8
+    sol, info = c.solve(bv, tol=tol, max_iter=20000)
+    assert info["converged"] and info["rel_residual"] <= tol
+    S = sol.cpu().numpy()
+    N = p.n_tri
+    for r in range(nr):
+        e = rel(S[r, :N], X_ref[r, :N])
+        assert e <= (1e-10 if prec == "fp64" else 1e-5), (r, e)
+    if prec == "mixed":
+        assert info["refinements"] >= 1
+    # the batched and one-by-one solvers agree
+    c.set_tuning("batched_solve", 0)
+    sol1, _ = c.solve(bv[:3], tol=tol, max_iter=20000)
+    assert rel(sol1.cpu().numpy()[:, :N], S[:3, :N]) <= (1e-10 if prec == "fp64" else 1e-5)
+    c.close()
