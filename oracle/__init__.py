@@ -15,17 +15,20 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_DUAL = os.path.join(_HERE, "oracle_dual.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 DIRICHLET, FLOATING, INTERFACE = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oracle.c and oracle_dual.c into liboracle.so (gcc, -O2, no FMA contraction)."""
+    stale = (not os.path.exists(_LIB)
+             or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_DUAL)))
+    if force or stale:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-march=x86-64-v2", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_DUAL, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -147,6 +150,28 @@ class Oracle:
         self.lib.orc_trace(ctypes.byref(self.p), _ptr(sigma), ctypes.c_int64(L), _ptr(starts), ctypes.byref(params),
                            _ptr(ns), _ptr(st), _ptr(I), _ptr(path))
         return (ns, st, I, path) if want_path else (ns, st, I)
+
+    def dual_streamer(self, dvert, body_V, dbody_V, start_panel, start_bary, params: TraceParams, n_steps,
+                      tol=1e-13):
+        """Forward-mode derivative of the streamer integrals along (dvert, dbody_V), with the
+        classification and the per-line step counts n_steps held fixed.  Line l starts at
+        sum_k bary_k v_k + params.start_offset * n of its panel.  Returns (I, dI, u, du, rc)."""
+        dv = _f64(dvert, (-1, 3)) if dvert is not None else None
+        bv = _f64(body_V)
+        dbv = _f64(dbody_V) if dbody_V is not None else None
+        sp = _i32(start_panel)
+        sb = _f64(start_bary, (-1, 3))
+        ns = _i32(n_steps)
+        L = len(sp)
+        I = np.empty(L)
+        dI = np.empty(L)
+        u = np.empty(self.n)
+        du = np.empty(self.n)
+        rc = self.lib.orc_dual_streamer(ctypes.byref(self.p), _ptr(dv), _ptr(bv), _ptr(dbv), ctypes.c_int64(L),
+                                        _ptr(sp), _ptr(sb), ctypes.c_double(params.start_offset),
+                                        ctypes.byref(params), _ptr(ns), ctypes.c_double(tol), _ptr(u), _ptr(du),
+                                        _ptr(I), _ptr(dI))
+        return I, dI, u, du, int(rc)
 
 
 def gmres(A, b, tol=1e-13, restart=100, max_iter=10000):
