@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--cpu-sample-lines", type=int, default=48)
     ap.add_argument("--cpu-sample-steps", type=int, default=800)
     ap.add_argument("--no-tts", action="store_true", help="skip the 64-load-case time-to-solve comparison")
+    ap.add_argument("--tts-only", action="store_true", help="only the 64-load-case time-to-solve comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -150,6 +151,11 @@ def main():
     tp = bem.trace_params(h=1e-4, max_steps=args.max_steps, e_min=1e-3)
     ctx = bem.Context.from_problem(p, precision=bem.FP64, eta=6.0, restart=100)
     print(f"[bench] coax N={N} lines={args.lines}", file=sys.stderr, flush=True)
+    if args.tts_only:
+        ctx.assemble()
+        print(json.dumps({"time_to_solve_64_load_cases": time_to_solve(bem, torch, p, ctx)}))
+        ctx.close()
+        return
 
     def step():
         ctx.assemble()

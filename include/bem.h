@@ -61,9 +61,11 @@ typedef struct {
 } bem_body;
 
 typedef struct {
-    int32_t precision;       /* bem_precision.  FP64: dense FP64 matrix.  MIXED: dense FP32 far
-                                field (near slots zero) + FP64 near CSR, FP64 Krylov vectors and
-                                iterative refinement. */
+    int32_t precision;       /* bem_precision.  FP64: dense FP64 matrix.  MIXED: far entries in a
+                                dense FP32 matrix; each near entry v is stored as its FP32 head
+                                h = fl32(v) in the dense slot plus the exact FP64 remainder v - h in
+                                a near CSR list, so the operator is FP32 far + FP64 near; FP64
+                                Krylov vectors and iterative refinement. */
     double eta;              /* Sec. 4 classification: (point, triangle) regular iff D > eta*R with
                                 D the distance to the circumcentre, R the circumradius.  >= 1.
                                 Regular pairs use the 7-point rule, the others closed forms. */
@@ -82,7 +84,8 @@ typedef struct {
 typedef struct {
     double h;             /* RK4 arc-length step; must be < (eta - 1) * min circumradius */
     double e_min;         /* stop (code 4) when |E| < e_min at the start of a step */
-    double start_offset;  /* informational (starts are given as points) */
+    double start_offset;  /* offset of line starts along the panel normal; used by bem_streamer_grad
+                             when starts move with their panels, informational elsewhere */
     int32_t max_steps;    /* stop (code 0) after this many accepted steps, 1..1e6 */
     int32_t direction;    /* +1: follow E, -1: follow -E */
     double alpha_a, alpha_e0, alpha_p; /* alpha_eff(E) = alpha_a * max(E - alpha_e0, 0)^alpha_p */
@@ -183,6 +186,34 @@ bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, 
                                  const int32_t* line_rhs, const double* starts, const bem_trace_params* tp,
                                  double* integral, int32_t* n_steps, int32_t* stop_code, uint8_t* exceeds);
 
+/* Gradient of J = sum_l dJ_dI[l] * integral[l] (the streamer integrals above) with
+ * respect to the mesh vertices and the body potentials, by reverse mode through
+ * the whole method: the field lines (adjoint RK4 with the field Jacobian at every
+ * stage point), the field of every panel (quadrature nodes and weights for regular
+ * pairs, the closed forms for the others), the solve (one adjoint GMRES with A^T
+ * per load case) and the collocation system of Eqs. Final1-Final4 (collocation
+ * points, normals, areas of the constraint rows).  The regular/near classification
+ * of Sec. 4 and each line's step count and stop reason are held at their values
+ * for the given state (the derivative of the piecewise-smooth map on its piece).
+ *  sol          dev [nrhs][n]: the solution for body_V (as from bem_solve_gmres; the
+ *               gradient assumes it solves the assembled system)
+ *  line_rhs, starts: as for bem_streamer_integral (the forward run is redone inside)
+ *  start_panel  dev [L] or NULL: line l starts on that panel and moves with it,
+ *               starts[l] = sum_k start_bary[l][k] v_k + start_offset n (vertices in
+ *               the panel's own order); NULL = starts fixed in space
+ *  start_bary   dev [L][3] (required with start_panel)
+ *  dJ_dI        dev [L]
+ *  tol          relative residual of the adjoint solves
+ *  dJ_dvert     dev [n_vert][3] (written)
+ *  dJ_dV        dev [nrhs][n_body] (written; 0 for non-conductor bodies)
+ *  dJ_dstart    dev [L][3] or NULL: dJ/d starts[l] at fixed mesh
+ * FP64 precision only; alpha_p >= 1.  Errors: STATE (not assembled), INVALID,
+ * NOCONV (an adjoint solve missed tol), OOM, HIP. */
+bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t L,
+                             const int32_t* line_rhs, const double* starts, const int32_t* start_panel,
+                             const double* start_bary, const bem_trace_params* tp, const double* dJ_dI,
+                             double tol, double* dJ_dvert, double* dJ_dV, double* dJ_dstart);
+
 /* Tuning knobs (no effect on results beyond summation order).
  *  "trace_mode": 0 = choose by line count, 1 = all lines advance together
  *                (one batched evaluation per RK4 stage, spread over the GPU),
@@ -192,8 +223,30 @@ bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, 
  *                side matrix product per iteration on the matrix cores (FP64:
  *                FP64 cores; MIXED: FP32 cores inside FP64 iterative
  *                refinement); 0 = one right-hand side after another.
+ *  Tile shapes (set by bem_autotune, or by hand):
+ *  "far_rows":    collocation rows per block of the far-field assembly (32, 64, 128; default 64)
+ *  "gemv_rows":   matrix rows per block of the GMRES matvec (2, 4, 8; default 4)
+ *  "gemm_blocks": minimum blocks of the FP32 multi-vector product, by K ranges (64..65536; 1024)
+ *  "eval_blocks": target blocks of the field evaluation, by panel ranges (64..65536; 2048)
+ *  "trace_split": live-line count at or below which a field-line pass splits each panel chunk
+ *                 over eight waves (0..4096; default 64)
  * Errors: INVALID for an unknown key or value. */
 bem_status bem_set_tuning(bem_ctx* ctx, const char* key, int64_t value);
+
+/* Current value of a tuning knob (keys as for bem_set_tuning).  Errors: INVALID. */
+bem_status bem_get_tuning(const bem_ctx* ctx, const char* key, int64_t* value);
+
+/* Autotuner for the tile shapes above: times each candidate on this context's
+ * assembled problem (HIP events, best of three after a warm-up; ties to the
+ * first candidate) and sets the fastest.  cache_path (host string, or NULL for
+ * no cache): a JSON file keyed by device architecture, panel and unknown
+ * counts, precision and eta; an entry for this key is used without timing,
+ * otherwise the new choice is added and the file rewritten.  Tuning re-runs
+ * the assembly (the timed candidates overwrite the matrix); results change at
+ * most in summation order.  from_cache (host, may be NULL): 1 if the cache
+ * supplied the choice.  Errors: STATE (not assembled), INVALID (unreadable or
+ * invalid cache entry, unwritable file), HIP, OOM. */
+bem_status bem_autotune(bem_ctx* ctx, const char* cache_path, int32_t* from_cache);
 
 /* Per-kernel timing with HIP events recorded on the context stream around
  * each launch while enabled.  Names: "geometry", "far_assemble", "near_mask_csr",

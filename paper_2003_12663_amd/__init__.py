@@ -184,8 +184,41 @@ class Context:
                                               _dev_ptr(st), _dev_ptr(ex)), self.lib)
         return I, ns, st, ex
 
+    def streamer_grad(self, sol, starts, dJ_dI, params=None, line_rhs=None, start_panel=None, start_bary=None,
+                      tol=1e-12, want_dstart=False):
+        """Gradient of J = sum_l dJ_dI[l] * I_l (bem_streamer_grad).  Returns
+        (dJ_dvert [n_vert, 3], dJ_dV [nrhs, n_body], dJ_dstart [L, 3] or None), float64 on the GPU."""
+        torch = _torch()
+        params = params or trace_params()
+        sol2, starts, lr = self._line_args(sol, starts, line_rhs)
+        L = starts.shape[0]
+        g = torch.as_tensor(dJ_dI, dtype=torch.float64, device=self.device).reshape(L).contiguous()
+        sp = sb = None
+        if start_panel is not None:
+            sp = torch.as_tensor(start_panel, dtype=torch.int32, device=self.device).reshape(L).contiguous()
+            sb = torch.as_tensor(start_bary, dtype=torch.float64, device=self.device).reshape(L, 3).contiguous()
+        dvert = torch.empty((len(self._vert), 3), dtype=torch.float64, device=self.device)
+        dV = torch.empty((sol2.shape[0], self.n_body), dtype=torch.float64, device=self.device)
+        dstart = torch.empty((L, 3), dtype=torch.float64, device=self.device) if want_dstart else None
+        _check(self.lib.bem_streamer_grad(self._ctx, sol2.shape[0], _dev_ptr(sol2), L, _dev_ptr(lr), _dev_ptr(starts),
+                                          _dev_ptr(sp), _dev_ptr(sb), ctypes.byref(params), _dev_ptr(g),
+                                          float(tol), _dev_ptr(dvert), _dev_ptr(dV), _dev_ptr(dstart)), self.lib)
+        return dvert, dV, dstart
+
     def set_tuning(self, key: str, value: int):
         _check(self.lib.bem_set_tuning(self._ctx, key.encode(), int(value)), self.lib)
+
+    def get_tuning(self, key: str) -> int:
+        v = ctypes.c_int64(0)
+        _check(self.lib.bem_get_tuning(self._ctx, key.encode(), ctypes.byref(v)), self.lib)
+        return int(v.value)
+
+    def autotune(self, cache_path=None) -> bool:
+        """Time the tile-shape candidates (or load them from the JSON cache); True if cached."""
+        fc = ctypes.c_int32(0)
+        path = cache_path.encode() if cache_path is not None else None
+        _check(self.lib.bem_autotune(self._ctx, path, ctypes.byref(fc)), self.lib)
+        return bool(fc.value)
 
     # -------------------------------------------------------------- profiling
     def set_profiling(self, on=True):
@@ -204,3 +237,65 @@ class Context:
         v = ctypes.c_int64(0)
         _check(self.lib.bem_get_counter(self._ctx, name.encode(), ctypes.byref(v)), self.lib)
         return int(v.value)
+
+
+def line_starts(vert, tri, start_panel, start_bary, offset):
+    """Line starts that sit on panels: sum_k bary_k v_k + offset * n of panel start_panel[l]
+    (torch, differentiable; the same placement bem_streamer_grad assumes)."""
+    torch = _torch()
+    t = torch.as_tensor(np.asarray(tri)[np.asarray(start_panel)], dtype=torch.long, device=vert.device)
+    a, b, c = vert[t[:, 0]], vert[t[:, 1]], vert[t[:, 2]]
+    bary = torch.as_tensor(start_bary, dtype=vert.dtype, device=vert.device)
+    nrm = torch.linalg.cross(b - a, c - a)
+    nrm = nrm / torch.linalg.norm(nrm, dim=1, keepdim=True)
+    return bary[:, :1] * a + bary[:, 1:2] * b + bary[:, 2:3] * c + offset * nrm
+
+
+def _streamer_function():
+    torch = _torch()
+
+    class StreamerIntegral(torch.autograd.Function):
+        """I = streamer integrals of the field lines of the BEM solution for vertex
+        positions `vert` (tensor [n_vert, 3]) and body potentials `body_V` (tensor
+        [n_body]), lines starting on panels (start_panel, start_bary, params.start_offset).
+        Forward: assemble, GMRES, bem_streamer_integral.  Backward: bem_streamer_grad."""
+
+        @staticmethod
+        def forward(ctx, vert, body_V, problem, start_panel, start_bary, params, solve_tol, eta, constraint_form):
+            v = vert.detach().cpu().numpy()
+            bv = body_V.detach().cpu().numpy()
+            bctx = Context(v, problem.tri, problem.tri_body, problem.body_kind, problem.eps_plus, problem.eps_minus,
+                           precision=FP64, eta=eta, constraint_form=constraint_form)
+            bctx.assemble()
+            sol, _ = bctx.solve(bv, tol=solve_tol, max_iter=100000)
+            starts = line_starts(vert.detach().to(bctx.device), problem.tri, start_panel, start_bary,
+                                 params.start_offset)
+            I, ns, st, _ = bctx.streamer_integral(sol, starts, params)
+            ctx.bctx, ctx.sol, ctx.starts, ctx.params = bctx, sol, starts, params
+            ctx.start_panel, ctx.start_bary = start_panel, start_bary
+            ctx.dev_in = vert.device
+            return I.to(vert.device)
+
+        @staticmethod
+        def backward(ctx, gI):
+            bctx = ctx.bctx
+            dvert, dV, _ = bctx.streamer_grad(ctx.sol, ctx.starts, gI.detach().to(bctx.device, torch.float64),
+                                              ctx.params, start_panel=ctx.start_panel, start_bary=ctx.start_bary)
+            bctx.close()
+            return dvert.to(ctx.dev_in), dV[0].to(ctx.dev_in), None, None, None, None, None, None, None
+
+    return StreamerIntegral
+
+
+_SI = None
+
+
+def streamer_integral(vert, body_V, problem, start_panel, start_bary, params=None, solve_tol=1e-12, eta=6.0,
+                      constraint_form=0):
+    """Differentiable streamer integrals (torch.autograd): see _streamer_function."""
+    global _SI
+    if _SI is None:
+        _SI = _streamer_function()
+    return _SI.apply(vert, body_V, problem, np.asarray(start_panel, dtype=np.int32),
+                     np.asarray(start_bary, dtype=np.float64), params or trace_params(), solve_tol, eta,
+                     constraint_form)

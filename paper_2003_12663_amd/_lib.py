@@ -15,7 +15,7 @@ EXPORTS = [
     "bem_create", "bem_destroy", "bem_last_error", "bem_n_unknowns", "bem_assemble", "bem_copy_rows",
     "bem_near_pairs", "bem_rhs", "bem_matvec", "bem_solve_gmres", "bem_eval_field", "bem_trace_lines",
     "bem_streamer_integral", "bem_set_tuning", "bem_set_profiling", "bem_kernel_stats", "bem_reset_stats",
-    "bem_get_counter",
+    "bem_get_counter", "bem_streamer_grad", "bem_get_tuning", "bem_autotune",
 ]
 
 
@@ -70,6 +70,9 @@ def load() -> ctypes.CDLL:
         "bem_kernel_stats": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(f64)]),
         "bem_reset_stats": (i32, [P]),
         "bem_get_counter": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i64)]),
+        "bem_streamer_grad": (i32, [P, i32, P, i64, P, P, P, P, P, P, f64, P, P, P]),
+        "bem_get_tuning": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i64)]),
+        "bem_autotune": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

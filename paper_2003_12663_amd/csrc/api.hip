@@ -222,6 +222,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     c->n_vert = n_vert;
     c->n_body = n_body;
     c->min_R = min_R;
+    c->h_tri.assign(tri, tri + 3 * n_tri);
     c->h_tri_body.assign(tri_body, tri_body + n_tri);
     c->h_body_kind.resize(n_body);
     c->h_epsp.resize(n_body);
@@ -509,6 +510,32 @@ bem_status bem_streamer_integral(bem_ctx* c, int32_t nrhs, const double* sol, in
     API_CATCH
 }
 
+bem_status bem_streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                             const double* starts, const int32_t* start_panel, const double* start_bary,
+                             const bem_trace_params* tp, const double* dJ_dI, double tol, double* dJ_dvert,
+                             double* dJ_dV, double* dJ_dstart) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (!c->assembled) throw bem::Error(BEM_ERR_STATE, "assemble the system first");
+    if (c->opt.precision != BEM_FP64) throw bem::Error(BEM_ERR_INVALID, "the gradient needs precision FP64");
+    check_trace(c, nrhs, sol, L, line_rhs, starts, tp);
+    if (!(tp->alpha_p >= 1.0)) throw bem::Error(BEM_ERR_INVALID, "the gradient needs alpha_p >= 1");
+    if (!(tol > 0.0) || !(tol < 1.0)) throw bem::Error(BEM_ERR_INVALID, "tol must be in (0, 1)");
+    if (!dJ_dvert || !dJ_dV) throw bem::Error(BEM_ERR_INVALID, "dJ_dvert and dJ_dV are required");
+    if (L > 0 && !dJ_dI) throw bem::Error(BEM_ERR_INVALID, "dJ_dI is required");
+    if (start_panel) {
+        if (L > 0 && !start_bary) throw bem::Error(BEM_ERR_INVALID, "start_bary is required with start_panel");
+        auto h = fetch_i32(c, start_panel, (size_t)L);
+        for (int32_t v : h)
+            if (v < 0 || v >= c->N) throw bem::Error(BEM_ERR_INVALID, "start_panel entry out of range");
+    }
+    bem::streamer_grad(c, nrhs, sol, L, line_rhs, starts, start_panel, start_bary, tp, dJ_dI, tol, dJ_dvert, dJ_dV,
+                       dJ_dstart);
+    return BEM_OK;
+    API_CATCH
+}
+
 bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return fail(BEM_ERR_INVALID, "NULL argument");
     if (std::strcmp(key, "trace_mode") == 0) {
@@ -521,7 +548,49 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         c->batched_solve = (int32_t)value;
         return BEM_OK;
     }
+    struct Knob {
+        const char* name;
+        int32_t bem_ctx::*field;
+        int64_t lo, hi;
+        bool pow2_choice;
+    };
+    static const Knob knobs[] = {
+        {"far_rows", &bem_ctx::tune_far_rows, 32, 128, true},     {"gemv_rows", &bem_ctx::tune_gemv_rows, 2, 8, true},
+        {"gemm_blocks", &bem_ctx::tune_gemm_blocks, 64, 65536, false},
+        {"eval_blocks", &bem_ctx::tune_eval_blocks, 64, 65536, false},
+        {"trace_split", &bem_ctx::tune_trace_split, 0, 4096, false},
+    };
+    for (const Knob& k : knobs)
+        if (std::strcmp(key, k.name) == 0) {
+            const bool ok = value >= k.lo && value <= k.hi && (!k.pow2_choice || (value & (value - 1)) == 0);
+            if (!ok) return fail(BEM_ERR_INVALID, std::string("value out of range for ") + key);
+            c->*(k.field) = (int32_t)value;
+            return BEM_OK;
+        }
     return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
+}
+
+bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
+    if (!c || !key || !value) return fail(BEM_ERR_INVALID, "NULL argument");
+    if (std::strcmp(key, "trace_mode") == 0) *value = c->trace_mode;
+    else if (std::strcmp(key, "batched_solve") == 0) *value = c->batched_solve;
+    else if (std::strcmp(key, "far_rows") == 0) *value = c->tune_far_rows;
+    else if (std::strcmp(key, "gemv_rows") == 0) *value = c->tune_gemv_rows;
+    else if (std::strcmp(key, "gemm_blocks") == 0) *value = c->tune_gemm_blocks;
+    else if (std::strcmp(key, "eval_blocks") == 0) *value = c->tune_eval_blocks;
+    else if (std::strcmp(key, "trace_split") == 0) *value = c->tune_trace_split;
+    else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
+    return BEM_OK;
+}
+
+bem_status bem_autotune(bem_ctx* c, const char* cache_path, int32_t* from_cache) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    const int r = bem::autotune(c, cache_path);
+    if (from_cache) *from_cache = r;
+    return BEM_OK;
+    API_CATCH
 }
 
 bem_status bem_set_profiling(bem_ctx* c, int32_t enable) {

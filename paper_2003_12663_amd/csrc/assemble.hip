@@ -18,7 +18,6 @@
 namespace bem {
 namespace {
 
-constexpr int FAR_ROWS_PER_BLOCK = 64;
 
 // MODE 0: potential rows S_ij = sum_q w_q / |x_i - y_q|
 // MODE 1: normal-derivative rows K'_ij = n_i . sum_q w_q (x_i - y_q) / |x_i - y_q|^3,
@@ -28,7 +27,7 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ far64, c
                                              const double* __restrict__ tri64, int64_t N,
                                              const int32_t* __restrict__ rows, int64_t n_rows,
                                              const double* __restrict__ row_scale, R* __restrict__ out, int64_t ld,
-                                             int out_by_slot, uint64_t* __restrict__ mask) {
+                                             int out_by_slot, uint64_t* __restrict__ mask, int rows_per_block) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;   // < Np always
     const bool valid = j < N;
     const double ccx = far64[(int64_t)(FR_CC + 0) * Np + j];
@@ -43,8 +42,8 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ far64, c
         qz[q] = farR[(int64_t)(FR_Z + q) * Np + j];
         qw[q] = farR[(int64_t)(FR_W + q) * Np + j];
     }
-    const int64_t r0 = (int64_t)blockIdx.y * FAR_ROWS_PER_BLOCK;
-    const int64_t r1 = r0 + FAR_ROWS_PER_BLOCK < n_rows ? r0 + FAR_ROWS_PER_BLOCK : n_rows;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+    const int64_t r1 = r0 + rows_per_block < n_rows ? r0 + rows_per_block : n_rows;
     const bool wave_live = ((j & ~(int64_t)63) < N);
     for (int64_t r = r0; r < r1; ++r) {
         const int64_t i = rows[r];
@@ -145,8 +144,9 @@ __global__ __launch_bounds__(256) void k_near(const double* __restrict__ tri64, 
                                               const double* __restrict__ epsp, const double* __restrict__ epsm,
                                               const int32_t* __restrict__ row_slot, int64_t nnz,
                                               const int32_t* __restrict__ nrow, const int32_t* __restrict__ ncol,
-                                              double* __restrict__ A64, int64_t ld, double* __restrict__ nval,
-                                              double* __restrict__ Kf, int64_t N, double* __restrict__ diag) {
+                                              double* __restrict__ A64, float* __restrict__ A32, int64_t ld,
+                                              double* __restrict__ nval, double* __restrict__ Kf, int64_t N,
+                                              double* __restrict__ diag) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= nnz) return;
     const int64_t i = nrow[k], j = ncol[k];
@@ -164,7 +164,13 @@ __global__ __launch_bounds__(256) void k_near(const double* __restrict__ tri64, 
     else
         v = S;
     if (A64) A64[i * ld + j] = v;
-    if (nval) nval[k] = v;
+    if (A32) {
+        // mixed operator: FP32 head in the dense slot, exact FP64 remainder in the near list, so that
+        // head + remainder == v exactly and a pure FP32 product sees every entry to FP32 accuracy
+        const float hi = (float)v;
+        A32[i * ld + j] = hi;
+        nval[k] = v - (double)hi;
+    }
     if (self) diag[i] = (v != 0.0) ? v : 1.0;
     if (Kf && kind == BEM_FLOATING) Kf[(int64_t)row_slot[i] * N + j] = kp;
 }
@@ -276,26 +282,27 @@ void launch_far_assemble(bem_ctx* c) {
     auto launch = [&](int mode, const bem::DBuf& rows, int64_t nr, const double* scale, bool by_slot, bool with_mask,
                       void* out, int64_t ld, bool fp32) {
         if (nr == 0) return;
-        dim3 grid((unsigned)(Np / 256), (unsigned)ceil_div(nr, FAR_ROWS_PER_BLOCK));
+        const int rpb = c->tune_far_rows;
+        dim3 grid((unsigned)(Np / 256), (unsigned)ceil_div(nr, rpb));
         uint64_t* m = with_mask ? mask : nullptr;
         if (!fp32) {
             if (mode == 0)
                 hipLaunchKernelGGL((k_far<0, double>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
                                    c->far64.as<double>(), Np, c->tri64.as<double>(), c->N, rows.as<int32_t>(), nr,
-                                   scale, (double*)out, ld, (int)by_slot, m);
+                                   scale, (double*)out, ld, (int)by_slot, m, rpb);
             else
                 hipLaunchKernelGGL((k_far<1, double>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
                                    c->far64.as<double>(), Np, c->tri64.as<double>(), c->N, rows.as<int32_t>(), nr,
-                                   scale, (double*)out, ld, (int)by_slot, m);
+                                   scale, (double*)out, ld, (int)by_slot, m, rpb);
         } else {
             if (mode == 0)
                 hipLaunchKernelGGL((k_far<0, float>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
                                    c->far32.as<float>(), Np, c->tri64.as<double>(), c->N, rows.as<int32_t>(), nr,
-                                   scale, (float*)out, ld, (int)by_slot, m);
+                                   scale, (float*)out, ld, (int)by_slot, m, rpb);
             else
                 hipLaunchKernelGGL((k_far<1, float>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
                                    c->far32.as<float>(), Np, c->tri64.as<double>(), c->N, rows.as<int32_t>(), nr,
-                                   scale, (float*)out, ld, (int)by_slot, m);
+                                   scale, (float*)out, ld, (int)by_slot, m, rpb);
         }
         BEM_CHECK_LAUNCH();
     };
@@ -342,7 +349,8 @@ void launch_near_assemble(bem_ctx* c) {
                        c->tri64.as<double>(), c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(),
                        c->body_epsp.as<double>(), c->body_epsm.as<double>(), c->row_slot.as<int32_t>(), c->near_nnz,
                        c->near_row.as<int32_t>(), c->near_col.as<int32_t>(), mixed ? nullptr : c->A64.as<double>(),
-                       c->ld, mixed ? c->near_val.as<double>() : nullptr, Kf, c->N,
+                       mixed ? c->A32.as<float>() : nullptr, c->ld, mixed ? c->near_val.as<double>() : nullptr, Kf,
+                       c->N,
                        c->diag.as<double>());
     BEM_CHECK_LAUNCH();
 }

@@ -102,7 +102,7 @@ struct bem_ctx {
     double shift[3] = {0, 0, 0};   // mesh translated by -shift on the device (FP32 accuracy)
     double min_R = 0.0;
 
-    std::vector<int32_t> h_tri_body, h_body_kind, h_body_fidx;
+    std::vector<int32_t> h_tri, h_tri_body, h_body_kind, h_body_fidx;
     std::vector<double> h_epsp, h_epsm;
     std::vector<int32_t> h_rows_pot, h_rows_int, h_rows_flt;   // row segments by kind (Sec. 4)
 
@@ -120,7 +120,11 @@ struct bem_ctx {
     bem::HBuf host_stage;
     bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part;
 
-    bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X;   // batched GMRES
+    bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part;   // batched GMRES
+
+    // gradient of the streamer integrals
+    bem::DBuf ad_state, ad_part, ad_mask, ad_cnt, ad_self, ad_ppart, ad_list, ad_path, ad_stage, ad_geo, ad_seg,
+        ad_vptr, ad_vcorner;
 
     // device counters (bem_get_counter): [0] near pairs evaluated by the batched field-line passes
     bem::DBuf counters;
@@ -129,6 +133,12 @@ struct bem_ctx {
     // tuning knobs (bem_set_tuning)
     int32_t trace_mode = 0;   // 0 auto, 1 all lines together (batched passes), 2 persistent per-line workgroups
     int32_t batched_solve = 1;   // several right-hand sides: 1 one batched solve (shared matrix products), 0 one by one
+    // tile shapes (bem_set_tuning / bem_autotune); none changes a result beyond summation order
+    int32_t tune_far_rows = 64;       // collocation rows per block of the far-field assembly
+    int32_t tune_gemv_rows = 4;       // matrix rows per block of the GMRES matvec (2, 4, 8)
+    int32_t tune_gemm_blocks = 1024;  // minimum blocks of the FP32 multi-vector product (K ranges)
+    int32_t tune_eval_blocks = 2048;  // target blocks of the field evaluation (panel-range split)
+    int32_t tune_trace_split = 64;    // live-line count at or below which field-line passes split chunks
 
     // profiling
     bool profiling = false;
@@ -176,12 +186,21 @@ int gmres_solve_batched(bem_ctx* c, int nr, const double* B, double* X, double t
 void batched_apply_exact(bem_ctx* c, int nr, const double* X, double* Y);   // rows of stride n
 void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel,
                  double* phi, double* E);                          // eval.hip
+// Sec. 4 classification of (point, panel) pairs as ballot masks mask[(j >> 6) * P + p] (bit j & 63 set:
+// not regular, or j == on_panel[p]); ceil(N / 64) * P words.
+void launch_point_mask(bem_ctx* c, int64_t P, const double* pts, const int32_t* on_panel, uint64_t* mask);
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                   const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                   double* path, double* integral, uint8_t* exceeds);   // trace.hip
 void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                           const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                           double* path, double* integral, uint8_t* exceeds);   // trace_batched.hip
+
+int autotune(bem_ctx* c, const char* cache_path);   // autotune.hip; 1 = loaded from the cache
+void streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                   const double* starts, const int32_t* start_panel, const double* start_bary,
+                   const bem_trace_params* tp, const double* gI, double tol, double* dvert, double* dV,
+                   double* dstart);   // adjoint_panel.hip
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

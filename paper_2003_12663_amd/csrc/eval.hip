@@ -145,6 +145,15 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ 
 
 }  // namespace
 
+void launch_point_mask(bem_ctx* c, int64_t P, const double* pts, const int32_t* on_panel, uint64_t* mask) {
+    if (P == 0) return;
+    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
+    dim3 grid((unsigned)(Np / 256), (unsigned)ceil_div(P, EV_MASK_PTS));
+    hipLaunchKernelGGL(k_eval_mask, grid, dim3(256), 0, c->stream, c->far64.as<double>(), Np, c->N, P, pts, on_panel,
+                       mask);
+    BEM_CHECK_LAUNCH();
+}
+
 void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel, double* phi,
                  double* E) {
     if (P == 0) return;
@@ -161,9 +170,9 @@ void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, 
     }
     int64_t nnz = 0;
     launch_near_csr(c, c->ev_mask.as<uint64_t>(), P, c->ev_ptr, c->ev_row, c->ev_col, &nnz, "eval_near_csr");
-    // split the panel range so that the grid has about 2048 blocks
+    // split the panel range so that the grid has about the tuned number of blocks (default 2048)
     const int64_t pb = ceil_div(P, 256);
-    int64_t KS = 2048 / pb;
+    int64_t KS = c->tune_eval_blocks / pb;
     if (KS < 1) KS = 1;
     if (KS > ceil_div(N, EV_TILE)) KS = ceil_div(N, EV_TILE);
     const int64_t span = ceil_div(ceil_div(N, KS), EV_TILE) * EV_TILE;

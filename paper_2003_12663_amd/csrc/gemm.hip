@@ -6,10 +6,8 @@
 // HBM once per product and multiplied with all 64 vectors, so the product is
 // bound by the matrix cores rather than by HBM (2 flop x 64 per A entry).
 //
-//  k_gemm_f32: v_mfma_f32_32x32x2f32, FP32 operands and FP32 accumulation.
-//     A wave owns 32 rows x 64 columns (two 32x32 accumulators) over a
-//     quarter of K; the block's four waves cover all of K for the same rows
-//     and their partial tiles are added in LDS in a fixed order.
+//  k_gemm_f32: v_mfma_f32_32x32x2f32, FP32 operands and FP32 accumulation
+//     within a K range; A and Z tiles staged in LDS (see the kernel).
 //  k_gemm_f64: v_mfma_f64_16x16x4f64, FP64 accumulation, A either FP64 or
 //     FP32 widened exactly (FP32 values are FP64 numbers), so for the FP32
 //     far matrix it is the exact FP64-accumulated product of the mixed
@@ -19,6 +17,8 @@
 // operands gives the same sum.
 // Z layout: Zt[col][k] (vector-major), row stride ldz >= K, zero beyond the
 // true length; K is a multiple of 32 (rows of A are padded with zeros).
+#include <algorithm>
+
 #include "bem_device.h"
 
 namespace bem {
@@ -29,30 +29,66 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int GM_WAVES = 4;   // K split over the waves of a block
 
-__global__ __launch_bounds__(64 * GM_WAVES) void k_gemm_f32(const float* __restrict__ A, int64_t lda, int64_t M,
-                                                            int64_t K, const float* __restrict__ Zt, int64_t ldz,
-                                                            int ncols, double* __restrict__ Y, int64_t ldy,
-                                                            int accumulate) {
-    __shared__ float part[GM_WAVES][64][33];   // partial tiles, [wave][col][row] (+1 pad)
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// FP32 product, LDS-staged: a block owns 128 rows (32 per wave) x 64 columns over
+// one K range (blockIdx.y); per step it stages a 128 x 32 tile of A and a
+// 64 x 32 tile of Z in LDS with row-contiguous 16-byte loads (8 lanes cover a
+// 128-byte row segment), prefetching the next step into registers, and each
+// wave runs 32 MFMAs from LDS.  Partial tiles of the K ranges go to Ypart
+// [ks][col][row] and k_gemm_f32_sum adds them in K-range order.
+constexpr int G32_ROWS = 128, G32_KC = 32, G32_PAD = 36;
+
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ A, int64_t lda, int64_t M, int64_t K,
+                                                    const float* __restrict__ Zt, int64_t ldz, int64_t kb_per,
+                                                    float* __restrict__ Ypart) {
+    __shared__ __attribute__((aligned(16))) float As[G32_ROWS][G32_PAD];
+    __shared__ __attribute__((aligned(16))) float Bs[64][G32_PAD];
+    __shared__ float Ct[64][G32_ROWS + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 31, h = lane >> 5;
-    const int64_t row0 = (int64_t)blockIdx.x * 32;
-    const int64_t arow = row0 + r < M ? row0 + r : M - 1;
-    const float* __restrict__ Ap = A + arow * lda;
-    const float* __restrict__ Z0 = Zt + (int64_t)r * ldz;
-    const float* __restrict__ Z1 = Zt + (int64_t)(32 + r) * ldz;
-    // this wave's K range: a multiple of 32
-    const int64_t kblocks = K / 32;
-    const int64_t kb0 = kblocks * wv / GM_WAVES, kb1 = kblocks * (wv + 1) / GM_WAVES;
+    const int64_t row0 = (int64_t)blockIdx.x * G32_ROWS;
+    const int64_t kblocks = K / G32_KC;
+    const int64_t kb0 = (int64_t)blockIdx.y * kb_per;
+    const int64_t kb1 = kb0 + kb_per < kblocks ? kb0 + kb_per : kblocks;
+    // this thread's staging slots: A rows (tid >> 3) + 32 i, Z column (tid >> 3) + 32 i, 16 bytes at 4 (tid & 7)
+    const int sr = tid >> 3, sc = 4 * (tid & 7);
+    const float* Ap[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int64_t rr = row0 + sr + 32 * i;
+        if (rr >= M) rr = M - 1;   // rows past the end are read from the last row and never stored
+        Ap[i] = A + rr * lda + sc;
+    }
+    const float* Zp0 = Zt + (int64_t)sr * ldz + sc;
+    const float* Zp1 = Zt + (int64_t)(sr + 32) * ldz + sc;
     f16v acc0 = {0}, acc1 = {0};
+    f4v ra[4], rz[2];
+    if (kb0 < kb1) {
+        const int64_t k = kb0 * G32_KC;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ra[i] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap[i] + k));
+        rz[0] = *reinterpret_cast<const f4v*>(Zp0 + k);
+        rz[1] = *reinterpret_cast<const f4v*>(Zp1 + k);
+    }
     for (int64_t kb = kb0; kb < kb1; ++kb) {
-        const int64_t k = kb * 32 + 16 * h;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *reinterpret_cast<f4v*>(&As[sr + 32 * i][sc]) = ra[i];
+        *reinterpret_cast<f4v*>(&Bs[sr][sc]) = rz[0];
+        *reinterpret_cast<f4v*>(&Bs[sr + 32][sc]) = rz[1];
+        __syncthreads();
+        if (kb + 1 < kb1) {
+            const int64_t k = (kb + 1) * G32_KC;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap[i] + k));
+            rz[0] = *reinterpret_cast<const f4v*>(Zp0 + k);
+            rz[1] = *reinterpret_cast<const f4v*>(Zp1 + k);
+        }
         f4v a[4], b0[4], b1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            a[q] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k) + q);
-            b0[q] = reinterpret_cast<const f4v*>(Z0 + k)[q];
-            b1[q] = reinterpret_cast<const f4v*>(Z1 + k)[q];
+            a[q] = *reinterpret_cast<const f4v*>(&As[32 * wv + r][16 * h + 4 * q]);
+            b0[q] = *reinterpret_cast<const f4v*>(&Bs[r][16 * h + 4 * q]);
+            b1[q] = *reinterpret_cast<const f4v*>(&Bs[32 + r][16 * h + 4 * q]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -63,23 +99,32 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gemm_f32(const float* __restr
             }
         }
     }
-    // accumulator element v of lane (r, h): row 8 (v / 4) + 4 h + v % 4, column r (+32)
+    // accumulator element v of lane (r, h): row 8 (v / 4) + 4 h + v % 4 (+32 wv), column r (+32)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int row = 8 * (v >> 2) + 4 * h + (v & 3);
-        part[wv][r][row] = acc0[v];
-        part[wv][32 + r][row] = acc1[v];
+        const int row = 32 * wv + 8 * (v >> 2) + 4 * h + (v & 3);
+        Ct[r][row] = acc0[v];
+        Ct[32 + r][row] = acc1[v];
     }
     __syncthreads();
-    // 256 threads add the 4 partial tiles (64 cols x 32 rows) in wave order
-    for (int e = threadIdx.x; e < 64 * 32; e += 64 * GM_WAVES) {
-        const int col = e >> 5, row = e & 31;
+    float* out = Ypart + (int64_t)blockIdx.y * 64 * M;
+    for (int e = tid; e < 64 * G32_ROWS; e += 256) {
+        const int col = e / G32_ROWS, row = e % G32_ROWS;
         const int64_t i = row0 + row;
-        if (i >= M || col >= ncols) continue;
-        const float s = ((part[0][col][row] + part[1][col][row]) + part[2][col][row]) + part[3][col][row];
-        double* y = Y + (int64_t)col * ldy + i;
-        *y = accumulate ? *y + (double)s : (double)s;
+        if (i < M) out[(int64_t)col * M + i] = Ct[col][row];
     }
+}
+
+// Y[col][i] (+)= sum over the K ranges of Ypart[ks][col][i] (FP64 sum, fixed order)
+__global__ __launch_bounds__(256) void k_gemm_f32_sum(const float* __restrict__ Ypart, int KS, int64_t M, int ncols,
+                                                      double* __restrict__ Y, int64_t ldy, int accumulate) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int col = blockIdx.y;
+    if (i >= M || col >= ncols) return;
+    double s = 0.0;
+    for (int k = 0; k < KS; ++k) s += (double)Ypart[((int64_t)k * 64 + col) * M + i];
+    double* y = Y + (int64_t)col * ldy + i;
+    *y = accumulate ? *y + s : s;
 }
 
 template <typename TA>
@@ -144,10 +189,20 @@ __global__ __launch_bounds__(64 * GM_WAVES) void k_gemm_f64(const TA* __restrict
 void launch_gemm_f32(bem_ctx* c, const float* A, int64_t lda, int64_t M, int64_t K, const float* Zt, int64_t ldz,
                      int ncols, double* Y, int64_t ldy, bool accumulate) {
     if (M <= 0) return;
-    if (K % 32 != 0 || ldz % 4 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f32 shape not padded");
+    if (K % G32_KC != 0 || ldz % 4 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f32 shape not padded");
     KTimer t(c, "gemm_f32");
-    hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)ceil_div(M, 32)), dim3(64 * GM_WAVES), 0, c->stream, A, lda, M, K,
-                       Zt, ldz, ncols, Y, ldy, (int)accumulate);
+    const int64_t rb = ceil_div(M, G32_ROWS);
+    const int64_t kblocks = K / G32_KC;
+    // K ranges so that the grid has at least the tuned number of blocks (default 1024: 2 per CU)
+    int64_t KS = std::max<int64_t>(1, std::min<int64_t>(ceil_div(c->tune_gemm_blocks, rb), kblocks));
+    const int64_t kb_per = ceil_div(kblocks, KS);
+    KS = ceil_div(kblocks, kb_per);
+    c->gemm_part.alloc(sizeof(float) * (size_t)KS * 64 * M);
+    hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)rb, (unsigned)KS), dim3(256), 0, c->stream, A, lda, M, K, Zt, ldz,
+                       kb_per, c->gemm_part.as<float>());
+    BEM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_gemm_f32_sum, dim3((unsigned)ceil_div(M, 256), (unsigned)ncols), dim3(256), 0, c->stream,
+                       c->gemm_part.as<float>(), (int)KS, M, ncols, Y, ldy, (int)accumulate);
     BEM_CHECK_LAUNCH();
 }
 

@@ -5,9 +5,9 @@
 // k_gemv64: a 256-thread block owns RB consecutive rows; each thread reads
 // 16-byte column pairs of all RB rows per step, so one x load feeds RB
 // multiply-adds and each row segment read by the block is 4 KB contiguous.
-// k_gemv32: the same for the FP32 far matrix of the mixed mode (float4
-// loads, FP64 accumulation), with the FP64 near CSR entries of the block's
-// rows added by the same block.
+// k_gemv32: the same for the FP32 matrix of the mixed mode (float4 loads,
+// FP64 accumulation), with the FP64 remainders of the near entries (near list
+// of the block's rows) added by the same block.
 // k_gemvT64: y = A^T x, column pairs per thread over a slab of rows; slabs
 // are summed by a second kernel in a fixed order (deterministic).
 #include "bem_device.h"
@@ -15,7 +15,6 @@
 namespace bem {
 namespace {
 
-constexpr int GEMV_RB = 4;
 
 template <int RB>
 __device__ __forceinline__ void block_reduce_rows(double (&acc)[RB], double* __restrict__ y, int64_t row0,
@@ -170,23 +169,32 @@ __global__ __launch_bounds__(256) void k_sum_slabs(const double* __restrict__ pa
 
 }  // namespace
 
-// y = A x for the assembled operator (FP64 or mixed)
-void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s) {
-    KTimer t(c, "gemv");
+template <int RB>
+void matvec_rb(bem_ctx* c, const double* x, double* y, hipStream_t s) {
     const int64_t n = c->n, N = c->N, ld = c->ld;
     if (c->opt.precision == BEM_FP64) {
-        hipLaunchKernelGGL((k_gemv64<GEMV_RB>), dim3((unsigned)ceil_div(n, GEMV_RB)), dim3(256), 0, s,
-                           c->A64.as<double>(), ld, n, n, x, y);
+        hipLaunchKernelGGL((k_gemv64<RB>), dim3((unsigned)ceil_div(n, RB)), dim3(256), 0, s, c->A64.as<double>(), ld,
+                           n, n, x, y);
         BEM_CHECK_LAUNCH();
         return;
     }
-    hipLaunchKernelGGL((k_gemv32<GEMV_RB>), dim3((unsigned)ceil_div(N, GEMV_RB)), dim3(256), 0, s, c->A32.as<float>(),
-                       ld, N, n, x, c->near_ptr.as<int64_t>(), c->near_col.as<int32_t>(), c->near_val.as<double>(), y);
+    hipLaunchKernelGGL((k_gemv32<RB>), dim3((unsigned)ceil_div(N, RB)), dim3(256), 0, s, c->A32.as<float>(), ld, N, n,
+                       x, c->near_ptr.as<int64_t>(), c->near_col.as<int32_t>(), c->near_val.as<double>(), y);
     BEM_CHECK_LAUNCH();
     if (n > N) {
-        hipLaunchKernelGGL((k_gemv64<GEMV_RB>), dim3((unsigned)ceil_div(n - N, GEMV_RB)), dim3(256), 0, s,
-                           c->A64.as<double>(), ld, n - N, n, x, y + N);
+        hipLaunchKernelGGL((k_gemv64<RB>), dim3((unsigned)ceil_div(n - N, RB)), dim3(256), 0, s, c->A64.as<double>(),
+                           ld, n - N, n, x, y + N);
         BEM_CHECK_LAUNCH();
+    }
+}
+
+// y = A x for the assembled operator (FP64 or mixed); rows per block from the tuning
+void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s) {
+    KTimer t(c, "gemv");
+    switch (c->tune_gemv_rows) {
+        case 2: matvec_rb<2>(c, x, y, s); break;
+        case 8: matvec_rb<8>(c, x, y, s); break;
+        default: matvec_rb<4>(c, x, y, s); break;
     }
 }
 

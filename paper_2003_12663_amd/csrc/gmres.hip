@@ -104,6 +104,7 @@ struct Work {
     double *V, *w, *z, *h, *part, *Hcol, *misc;
     double* host;    // pinned host staging
     hipStream_t s;
+    bool transpose = false;   // solve with A^T (same Jacobi diagonal)
     dim3 g1() const { return dim3((unsigned)ceil_div(n, 256)); }
 };
 
@@ -147,7 +148,10 @@ int gmres_core(Work& W, const double* b, double* x, double tol, int max_iter, in
     }
     for (;;) {
         // r = b - A x into V[0]
-        launch_matvec(c, x, W.w, W.s);
+        if (W.transpose)
+            launch_matvec_t(c, x, W.w, W.s);
+        else
+            launch_matvec(c, x, W.w, W.s);
         hipLaunchKernelGGL(k_residual, W.g1(), dim3(256), 0, W.s, b, W.w, n, W.V);
         BEM_CHECK_LAUNCH();
         const double beta = host_norm(W, W.V);
@@ -168,7 +172,10 @@ int gmres_core(Work& W, const double* b, double* x, double tol, int max_iter, in
             double* Vj = W.V + (int64_t)j * W.vs;
             hipLaunchKernelGGL(k_div_diag, W.g1(), dim3(256), 0, W.s, Vj, d, n, W.z);
             BEM_CHECK_LAUNCH();
-            launch_matvec(c, W.z, W.w, W.s);
+            if (W.transpose)
+                launch_matvec_t(c, W.z, W.w, W.s);
+            else
+                launch_matvec(c, W.z, W.w, W.s);
             {
                 KTimer to(c, "gmres_ortho");
                 for (int pass = 0; pass < 2; ++pass) {
@@ -225,10 +232,7 @@ int gmres_core(Work& W, const double* b, double* x, double tol, int max_iter, in
 
 }  // namespace
 
-int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,
-                int* refinements_out) {
-    *refinements_out = 0;
-    Work W;
+static void setup_work(bem_ctx* c, Work& W) {
     W.c = c;
     W.n = c->n;
     W.vs = c->ld;
@@ -249,6 +253,22 @@ int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter
     W.part = c->gm_part.as<double>();
     W.misc = c->gm_r.as<double>() + 2 * W.vs;
     W.host = c->host_stage.as<double>();
+}
+
+// A^T x = b (FP64 operator only): the adjoint solve of the gradient.
+int gmres_solve_t(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres) {
+    if (c->opt.precision != BEM_FP64) throw Error(BEM_ERR_INVALID, "the adjoint solve needs precision FP64");
+    Work W;
+    setup_work(c, W);
+    W.transpose = true;
+    return gmres_core(W, b, x, tol, max_iter, iters, relres, false);
+}
+
+int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,
+                int* refinements_out) {
+    *refinements_out = 0;
+    Work W;
+    setup_work(c, W);
     if (c->opt.precision == BEM_FP64) return gmres_core(W, b, x, tol, max_iter, iters, relres, false);
 
     // Mixed mode: FP64 iterative refinement around GMRES on the mixed operator.

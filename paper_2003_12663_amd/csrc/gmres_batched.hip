@@ -4,12 +4,12 @@
 // the matrix is read once per iteration for all load cases.
 //
 // FP64 mode: the product uses the FP64 matrix on the FP64 matrix cores.
-// Mixed mode: the inner product uses the FP32 far matrix on the FP32 matrix
-// cores (FP32 operands and accumulation) plus the FP64 near CSR and FP64
-// constraint rows; an outer FP64 iterative refinement recomputes the
-// residual with the exact FP64-accumulated product of the same mixed
-// operator, so the FP32 rounding of the inner products does not limit the
-// final residual.
+// Mixed mode: the inner product is the FP32 matrix (far entries and the FP32
+// heads of the near entries) on the FP32 matrix cores, FP32 operands and
+// accumulation, plus the FP64 constraint rows; an outer FP64 iterative
+// refinement recomputes the residual with the exact FP64-accumulated product
+// of the mixed operator (FP32 matrix widened + FP64 near remainders), so the
+// FP32 rounding of the inner products does not limit the final residual.
 //
 // Each recurrence keeps its own basis, Hessenberg matrix and rotations
 // (independent, not block, Krylov spaces: identical or proportional
@@ -161,19 +161,21 @@ void apply(BW& w, const double* src, int64_t sstride, const double* d, bool exac
     const bool mixed = c->opt.precision == BEM_MIXED;
     const bool f32 = mixed && !exact;
     hipLaunchKernelGGL(k_b_prep, dim3((unsigned)ceil_div(w.ld, 256), BR), dim3(256), 0, w.s, src, sstride, w.nr, w.n,
-                       w.ld, d, f32 ? w.zt32 : nullptr, f32 ? nullptr : w.zt64, mixed ? w.zn64 : nullptr);
+                       w.ld, d, f32 ? w.zt32 : nullptr, f32 ? nullptr : w.zt64, (mixed && !f32) ? w.zn64 : nullptr);
     BEM_CHECK_LAUNCH();
     if (!mixed) {
         launch_gemm_f64(c, c->A64.p, false, w.ld, w.n, w.ld, w.zt64, w.ld, w.nr, w.W, w.ld, false, 1.0);
         return;
     }
-    if (f32)
+    if (f32) {
         launch_gemm_f32(c, c->A32.as<float>(), w.ld, w.N, w.ld, w.zt32, w.ld, w.nr, w.W, w.ld, false);
-    else
+    } else {
         launch_gemm_f64(c, c->A32.p, true, w.ld, w.N, w.ld, w.zt64, w.ld, w.nr, w.W, w.ld, false, 1.0);
-    hipLaunchKernelGGL(k_b_near, dim3((unsigned)ceil_div(w.N, 4)), dim3(256), 0, w.s, c->near_ptr.as<int64_t>(),
-                       c->near_col.as<int32_t>(), c->near_val.as<double>(), w.N, w.zn64, w.nr, w.W, w.ld);
-    BEM_CHECK_LAUNCH();
+        // FP64 remainders of the near entries
+        hipLaunchKernelGGL(k_b_near, dim3((unsigned)ceil_div(w.N, 4)), dim3(256), 0, w.s, c->near_ptr.as<int64_t>(),
+                           c->near_col.as<int32_t>(), c->near_val.as<double>(), w.N, w.zn64, w.nr, w.W, w.ld);
+        BEM_CHECK_LAUNCH();
+    }
     if (w.n > w.N) {
         // constraint rows (FP64) need the FP64 vectors
         if (f32) {
@@ -185,11 +187,18 @@ void apply(BW& w, const double* src, int64_t sstride, const double* d, bool exac
     }
 }
 
+// blocks per dot product: about 2048 blocks per launch in total, each at least a few waves of work
+int dot_split(const BW& w, int ndots) {
+    const int64_t g = 2048 / std::max(ndots, 1);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, w.G));
+}
+
 // norms of the nr vectors v[r * ld] into dst[r * dstride] (device); with `out`, also to the host
 void norms(BW& w, const double* v, double* dst, int dstride, std::vector<double>* out) {
-    hipLaunchKernelGGL(k_b_dots, dim3(w.G, 1, w.nr), dim3(256), 0, w.s, v, 1, w.ld, w.n, v, w.part, w.G);
+    const int G = dot_split(w, w.nr);
+    hipLaunchKernelGGL(k_b_dots, dim3(G, 1, w.nr), dim3(256), 0, w.s, v, 1, w.ld, w.n, v, w.part, G);
     BEM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_b_reduce, dim3((unsigned)ceil_div(w.nr, 64)), dim3(64), 0, w.s, w.part, w.G, 1, 1, w.nr, dst,
+    hipLaunchKernelGGL(k_b_reduce, dim3((unsigned)ceil_div(w.nr, 64)), dim3(64), 0, w.s, w.part, G, 1, 1, w.nr, dst,
                        dstride, (double*)nullptr, 0, 1);
     BEM_CHECK_LAUNCH();
     if (out) {
@@ -239,12 +248,13 @@ int bgmres(BW& w, const double* B, double* X, double tol, int max_iter, bool exa
             KTimer tj(c, "bgmres_iter");
             // W = A (V[:, j] / d)
             apply(w, w.V + (int64_t)j * w.ld, (int64_t)m1 * w.ld, d, exact_apply);
+            const int G = dot_split(w, (j + 1) * nr);
             for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(k_b_dots, dim3(w.G, j + 1, nr), dim3(256), 0, w.s, w.V, m1, w.ld, w.n, w.W,
-                                   w.part, w.G);
+                hipLaunchKernelGGL(k_b_dots, dim3(G, j + 1, nr), dim3(256), 0, w.s, w.V, m1, w.ld, w.n, w.W, w.part,
+                                   G);
                 BEM_CHECK_LAUNCH();
                 hipLaunchKernelGGL(k_b_reduce, dim3((unsigned)ceil_div((j + 1) * nr, 64)), dim3(64), 0, w.s, w.part,
-                                   w.G, m1, j + 1, nr, w.h, hs, w.Hcol, pass, 0);
+                                   G, m1, j + 1, nr, w.h, hs, w.Hcol, pass, 0);
                 BEM_CHECK_LAUNCH();
                 hipLaunchKernelGGL(k_b_orth, w.gv(), dim3(256), 0, w.s, w.V, m1, w.ld, w.n, j + 1, w.h, hs, w.W);
                 BEM_CHECK_LAUNCH();
@@ -391,9 +401,11 @@ int gmres_solve_batched(bem_ctx* c, int nr, const double* B, double* X, double t
                 worst = std::max(worst, rel[r]);
             }
             if (worst <= tol || iters >= max_iter || refinements >= 20) break;
-            // inner solve of A D = R to a few digits on the FP32 cores
+            // inner solve of A D = R on the FP32 cores to the digits still missing, but not below 1e-4:
+            // FP32-accumulated products over ~10^4 terms carry ~1e-6..1e-5 relative noise, and an
+            // inner target near that floor stalls GMRES
             std::vector<double> rr(nr);
-            const double inner = std::max(1e-4, 0.5 * tol / std::max(worst, 1e-300));
+            const double inner = std::min(0.1, std::max(1e-4, 0.3 * tol / std::max(worst, 1e-300)));
             iters += bgmres(w, R, D, inner, max_iter - iters, false, rr, rn);
             hipLaunchKernelGGL(k_b_add, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, w.s, X, D, total);
             BEM_CHECK_LAUNCH();

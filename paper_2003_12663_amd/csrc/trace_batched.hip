@@ -22,6 +22,7 @@
 // All lines start together, so every active line is in the same RK4 stage in
 // a given pass.  A panel that a step's segment can reach lies within R + h of
 // the step's end point, hence in its near set when h < (eta - 1) R_min.
+#include <algorithm>
 #include <climits>
 
 #include "bem_device.h"
@@ -401,6 +402,68 @@ __global__ __launch_bounds__(256) void k_lb_step(
 
 }  // namespace
 
+namespace {
+__global__ void k_lb_iota(int32_t* __restrict__ act, int32_t* __restrict__ count, int64_t L) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < L) act[i] = (int32_t)i;
+    if (i == 0) count[0] = (int32_t)L;
+}
+}  // namespace
+
+// Duration (ms, best of 3 after a warm-up) of one far-field pass over L lines at the points pts
+// (FP64 or FP32 by the context's precision), split or not: used by the autotuner.
+double time_far_pass(bem_ctx* c, int64_t L, bool split, const double* pts, const double* sol) {
+    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
+    const int64_t N = c->N;
+    const int64_t KS = ceil_div(N, LB_C);
+    c->lb_state.alloc(sizeof(double) * (size_t)L * 11 + sizeof(int32_t) * ((size_t)L * 3 + 64));
+    c->lb_part.alloc(sizeof(double) * 3 * (size_t)KS * L + sizeof(uint32_t) * (size_t)KS * L);
+    int32_t* ib = reinterpret_cast<int32_t*>(c->lb_state.as<double>() + (size_t)L * 11);
+    int32_t* act = ib + L;
+    int32_t* cnt = ib + 3 * L;
+    double* part = c->lb_part.as<double>();
+    uint32_t* pmask = reinterpret_cast<uint32_t*>(part + 3 * (size_t)KS * L);
+    hipLaunchKernelGGL(k_lb_iota, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, act, cnt, L);
+    BEM_CHECK_LAUNCH();
+    const bool fp64 = c->opt.precision == BEM_FP64;
+    dim3 g1((unsigned)ceil_div(L, split ? 64 : LB_T), (unsigned)KS);
+    auto run = [&] {
+#define BEM_LB_FAR(R, SP, FR)                                                                                     \
+    hipLaunchKernelGGL((k_lb_far<R, SP>), g1, dim3(SP > 1 ? 64 * SP : LB_T), 0, c->stream, c->far64.as<double>(), FR, \
+                       Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask)
+        if (fp64) {
+            if (split)
+                BEM_LB_FAR(double, 8, c->far64.as<double>());
+            else
+                BEM_LB_FAR(double, 1, c->far64.as<double>());
+        } else {
+            if (split)
+                BEM_LB_FAR(float, 8, c->far32.as<float>());
+            else
+                BEM_LB_FAR(float, 1, c->far32.as<float>());
+        }
+#undef BEM_LB_FAR
+        BEM_CHECK_LAUNCH();
+    };
+    hipEvent_t a, b;
+    BEM_HIP(hipEventCreate(&a));
+    BEM_HIP(hipEventCreate(&b));
+    run();
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+        BEM_HIP(hipEventRecord(a, c->stream));
+        run();
+        BEM_HIP(hipEventRecord(b, c->stream));
+        BEM_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        BEM_HIP(hipEventElapsedTime(&ms, a, b));
+        best = std::min(best, (double)ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
 void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                           const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                           double* path, double* integral, uint8_t* exceeds) {
@@ -447,7 +510,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     int64_t known_active = L;   // upper bound on the active count (refreshed every 32 passes)
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
-        const bool split = known_active <= 64;
+        const bool split = known_active <= c->tune_trace_split;
         {
         // every 16th pass is timed: the event records would otherwise cost more than the short launches
         KTimer tf(c, "trace_far", (pass & 15) == 0);
