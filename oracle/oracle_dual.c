@@ -172,7 +172,10 @@ static void dquad7(const dl x[3], const dl* v, dl area, dl* S, dl F[3])
  *   beta_e = atan2(t s+, t^2 + w^2 + |w| R+) - atan2(t s-, t^2 + w^2 + |w| R-),
  *   4 pi S = sum t f_e - |w| sum beta_e,  4 pi F = sum m f_e + sign(w) n sum beta_e.
  * on_plane: x is the triangle's own centroid (principal value; w and sign(w)
- * are zero and stay zero when the triangle moves). */
+ * are zero and stay zero when the triangle moves).  A point in the plane of the
+ * triangle but outside it (coplanar panels) has w = 0 with a sum of angles that
+ * vanishes like |w|: sign(w) sum beta and |w| sum beta are smooth in w there, and
+ * their derivative is the one-sided one, taken by treating w as +0. */
 static void danalytic(const dl x[3], const dl* v, int on_plane, dl* S, dl F[3])
 {
     dl e1[3], e2[3], cr[3], n[3];
@@ -187,6 +190,11 @@ static void danalytic(const dl x[3], const dl* v, int on_plane, dl* S, dl F[3])
     dl rho[3];
     for (int k = 0; k < 3; ++k) rho[k] = sub(x[k], mul(w, n[k]));
     dl aw = dabs(w);
+    double s = sgn(w.v);
+    if (!on_plane && w.v == 0.0) {
+        aw = w;
+        s = 1.0;
+    }
     dl sum_tf = cst(0.0), sum_beta = cst(0.0), mf[3] = {cst(0.0), cst(0.0), cst(0.0)};
     for (int e = 0; e < 3; ++e) {
         const dl* a = v + 3 * e;
@@ -214,7 +222,6 @@ static void danalytic(const dl x[3], const dl* v, int on_plane, dl* S, dl F[3])
         sum_beta = add(sum_beta, beta);
         for (int k = 0; k < 3; ++k) mf[k] = add(mf[k], mul(m[k], f));
     }
-    double s = sgn(w.v);
     *S = scl(sub(sum_tf, mul(aw, sum_beta)), 1.0 / (4.0 * ORC_PI));
     for (int k = 0; k < 3; ++k) F[k] = scl(add(mf[k], scl(mul(n[k], sum_beta), s)), 1.0 / (4.0 * ORC_PI));
 }
