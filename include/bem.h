@@ -228,8 +228,11 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
  *  "gemv_rows":   matrix rows per block of the GMRES matvec (2, 4, 8; default 4)
  *  "gemm_blocks": minimum blocks of the FP32 multi-vector product, by K ranges (64..65536; 1024)
  *  "eval_blocks": target blocks of the field evaluation, by panel ranges (64..65536; 2048)
+ *  "trace_tile":  lines per block of an unsplit field-line pass (64, 128, 256; default 256)
  *  "trace_split": live-line count at or below which a field-line pass splits each panel chunk
  *                 over eight waves (0..4096; default 64)
+ *  "grad_batch":  points per batch of the pair passes of bem_streamer_grad (64..2^24; default
+ *                 131072; bounds scratch memory)
  * Errors: INVALID for an unknown key or value. */
 bem_status bem_set_tuning(bem_ctx* ctx, const char* key, int64_t value);
 

@@ -3,8 +3,10 @@
 // field of a flat triangle written over them, so that one evaluation gives the
 // value and its derivatives along three coordinates (of the field point, or of
 // one triangle vertex).  The formulas are those of flat_tri_SF (Wilton et al.
-// 1984 edge terms, Van Oosterom & Strackee 1983 solid angle); here the normal
-// is recomputed from the (possibly perturbed) vertices.
+// 1984 edge terms, Van Oosterom & Strackee 1983 solid angle), with the solid
+// angle carried signed so that the derivative is right for points in the plane
+// of the triangle but outside it; the normal is recomputed from the (possibly
+// perturbed) vertices.
 #pragma once
 
 #include "bem_device.h"
@@ -43,11 +45,6 @@ __device__ __forceinline__ D3 datan2(D3 y, D3 x) {
     const double iv = 1.0 / (x.v * x.v + y.v * y.v);
     return {atan2(y.v, x.v), (x.v * y.d0 - y.v * x.d0) * iv, (x.v * y.d1 - y.v * x.d1) * iv,
             (x.v * y.d2 - y.v * x.d2) * iv};
-}
-// |a| with slope sign(a) (0 at 0)
-__device__ __forceinline__ D3 dabs(D3 a) {
-    const double s = a.v > 0.0 ? 1.0 : (a.v < 0.0 ? -1.0 : 0.0);
-    return a * s;
 }
 
 // S and F = -grad_x S of a flat triangle (vertices V[k][c]) with unit density at X.
@@ -92,7 +89,10 @@ __device__ __forceinline__ void tri_SF_d3(const D3 (&V)[3][3], const D3 (&X)[3],
         m1s = m1s + m1 * f;
         m2s = m2s + m2 * f;
     }
-    D3 omega = d3(0.0);
+    // signed solid angle Omega_s = sign(w) Omega = 2 atan2(-[r1 r2 r3], den): the triple product
+    // equals -2 a w for a flat triangle, so this is smooth across the plane outside the triangle
+    // (coplanar panels, w = 0) and sign(w) / |w| are not needed: |w| Omega = w Omega_s
+    D3 omega_s = d3(0.0);
     if (!inplane) {
         const D3 x0 = P[1][1] * P[2][2] - P[1][2] * P[2][1];
         const D3 x1 = P[1][2] * P[2][0] - P[1][0] * P[2][2];
@@ -102,13 +102,12 @@ __device__ __forceinline__ void tri_SF_d3(const D3 (&V)[3][3], const D3 (&X)[3],
         const D3 d02 = P[0][0] * P[2][0] + P[0][1] * P[2][1] + P[0][2] * P[2][2];
         const D3 d12 = P[1][0] * P[2][0] + P[1][1] * P[2][1] + P[1][2] * P[2][2];
         const D3 den = Rv[0] * Rv[1] * Rv[2] + d01 * Rv[2] + d02 * Rv[1] + d12 * Rv[0];
-        omega = datan2(dabs(triple), den) * 2.0;
+        omega_s = datan2(-triple, den) * 2.0;
     }
-    S = (st - dabs(w) * omega) * INV4PI;
-    const double sg = w.v > 0.0 ? 1.0 : (w.v < 0.0 ? -1.0 : 0.0);
-    F[0] = (m0s + omega * n0 * sg) * INV4PI;
-    F[1] = (m1s + omega * n1 * sg) * INV4PI;
-    F[2] = (m2s + omega * n2 * sg) * INV4PI;
+    S = (st - w * omega_s) * INV4PI;
+    F[0] = (m0s + omega_s * n0) * INV4PI;
+    F[1] = (m1s + omega_s * n1) * INV4PI;
+    F[2] = (m2s + omega_s * n2) * INV4PI;
 }
 
 // Field F and its Jacobian dF/dx (Jac[a][b] = dF_a/dx_b) at the point x of the

@@ -474,7 +474,7 @@ void launch_rows_EH(bem_ctx* c, const double* sigma, int64_t P, const double* pt
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t KS = ceil_div(N, LA_C);
-    const int64_t B = std::min<int64_t>(P, 8192);   // points per batch (bounds the partial buffer)
+    const int64_t B = std::min<int64_t>(P, std::min<int64_t>(8192, c->grad_batch));   // bounds the partial buffer
     c->ad_part.alloc(sizeof(double) * LA_NC * (size_t)KS * B + sizeof(uint32_t) * (size_t)KS * B);
     double* part = c->ad_part.as<double>();
     uint32_t* pmask = reinterpret_cast<uint32_t*>(part + LA_NC * (size_t)KS * B);

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(64) void k_pm_fill(const uint64_t* __restrict__ mas
 __global__ __launch_bounds__(256) void k_pan_far_adj(const double* __restrict__ far64, int64_t Np, int64_t N,
                                                      int64_t P, int64_t span, const double* __restrict__ pts,
                                                      const double* __restrict__ aw, const double* __restrict__ cw,
-                                                     int self_mode, double* __restrict__ part) {
+                                                     int self_mode, int64_t p_off, double* __restrict__ part) {
     __shared__ double tp[PA_TILE][7];
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = j < N;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_pan_far_adj(const double* __restrict__ 
         if (!valid) continue;
         for (int pi = 0; pi < cnt; ++pi) {
             const double x0 = tp[pi][0], x1 = tp[pi][1], x2 = tp[pi][2];
-            if (self_mode && t0 + pi == j) continue;
+            if (self_mode && t0 + pi + p_off == j) continue;
             if (!is_regular(x0 - cc0, x1 - cc1, x2 - cc2, rr)) continue;
             const double a = tp[pi][3], c0 = tp[pi][4], c1 = tp[pi][5], c2 = tp[pi][6];
 #pragma unroll
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_pan_reduce(const double* __restrict__ p
 __global__ __launch_bounds__(256) void k_pan_near_adj(const int64_t* __restrict__ ptr, const int32_t* __restrict__ list,
                                                       int64_t N, const double* __restrict__ tri64,
                                                       const double* __restrict__ pts, const double* __restrict__ aw,
-                                                      const double* __restrict__ cw, int self_mode,
+                                                      const double* __restrict__ cw, int self_mode, int64_t p_off,
                                                       double* __restrict__ acc) {
     const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_pan_near_adj(const int64_t* __restrict_
     for (int c = 0; c < 9; ++c) g[c] = 0.0;
     for (int64_t e = ptr[j] + lane; e < ptr[j + 1]; e += 64) {
         const int64_t p = list[e];
-        const bool self = self_mode && p == j;
+        const bool self = self_mode && p + p_off == j;
         const double a = aw ? aw[p] : 0.0;
         // the constant zero K'_ii of the own panel carries no derivative: no field term for self
         const double c0 = self ? 0.0 : cw[3 * p], c1 = self ? 0.0 : cw[3 * p + 1], c2 = self ? 0.0 : cw[3 * p + 2];
@@ -494,13 +494,13 @@ void zero(bem_ctx* c, double* p, int64_t n) {
 
 // Panel-side pair terms over a point set: acc += (T_far, T_near, corner derivatives) of
 // sum_p [a_p S_j(x_p) + c_p . F_j(x_p)] for every panel j.  self_mode: point p is the
-// centroid of panel p (the point moves with its panel).
+// centroid of panel p (the point moves with its panel).  Points go in batches of grad_batch.
 void panel_side(bem_ctx* c, int64_t P, const double* pts, const double* aw, const double* cw, bool self_mode,
                 double* acc) {
     const int64_t N = c->N;
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t nblk = ceil_div(N, 64);
-    const int64_t B = std::min<int64_t>(P, 131072);   // points per batch
+    const int64_t B = std::min<int64_t>(P, c->grad_batch);   // points per batch
     c->ad_mask.alloc(sizeof(uint64_t) * (size_t)nblk * B);
     const int PB = 32;
     c->ad_cnt.alloc(sizeof(int32_t) * (size_t)PB * N + sizeof(int64_t) * (N + 2));   // + alignment pad
@@ -523,7 +523,7 @@ void panel_side(bem_ctx* c, int64_t P, const double* pts, const double* aw, cons
             KS = ceil_div(nb, span);
             c->ad_ppart.alloc(sizeof(double) * 10 * (size_t)KS * N);
             hipLaunchKernelGGL(k_pan_far_adj, dim3((unsigned)pb, (unsigned)KS), dim3(256), 0, c->stream,
-                               c->far64.as<double>(), Np, N, nb, span, bp, ba, bc, (int)(self_mode && b0 == 0),
+                               c->far64.as<double>(), Np, N, nb, span, bp, ba, bc, (int)self_mode, b0,
                                c->ad_ppart.as<double>());
             BEM_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_pan_reduce, dim3((unsigned)pb), dim3(256), 0, c->stream, c->ad_ppart.as<double>(), KS,
@@ -535,9 +535,8 @@ void panel_side(bem_ctx* c, int64_t P, const double* pts, const double* aw, cons
             KTimer t(c, "grad_panel_near");
             const int32_t* op = nullptr;
             if (self_mode) {
-                if (b0 != 0) throw Error(BEM_ERR_INVALID, "centroid point sets are processed in one batch");
-                std::vector<int32_t> iota(nb);
-                for (int64_t i = 0; i < nb; ++i) iota[i] = (int32_t)i;
+                std::vector<int32_t> iota(nb);   // point i of the batch is the centroid of panel b0 + i
+                for (int64_t i = 0; i < nb; ++i) iota[i] = (int32_t)(b0 + i);
                 BEM_HIP(hipMemcpyAsync(c->ad_self.p, iota.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice,
                                        c->stream));
                 BEM_HIP(hipStreamSynchronize(c->stream));
@@ -560,7 +559,7 @@ void panel_side(bem_ctx* c, int64_t P, const double* pts, const double* aw, cons
                                nb, N, chunk, cnt, ptr, c->ad_list.as<int32_t>());
             BEM_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_pan_near_adj, dim3((unsigned)ceil_div(N, 4)), dim3(256), 0, c->stream, ptr,
-                               c->ad_list.as<int32_t>(), N, c->tri64.as<double>(), bp, ba, bc, (int)self_mode, acc);
+                               c->ad_list.as<int32_t>(), N, c->tri64.as<double>(), bp, ba, bc, (int)self_mode, b0, acc);
             BEM_CHECK_LAUNCH();
         }
     }

@@ -559,6 +559,8 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"gemm_blocks", &bem_ctx::tune_gemm_blocks, 64, 65536, false},
         {"eval_blocks", &bem_ctx::tune_eval_blocks, 64, 65536, false},
         {"trace_split", &bem_ctx::tune_trace_split, 0, 4096, false},
+        {"trace_tile", &bem_ctx::tune_trace_tile, 64, 256, true},
+        {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
     for (const Knob& k : knobs)
         if (std::strcmp(key, k.name) == 0) {
@@ -579,6 +581,8 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     else if (std::strcmp(key, "gemm_blocks") == 0) *value = c->tune_gemm_blocks;
     else if (std::strcmp(key, "eval_blocks") == 0) *value = c->tune_eval_blocks;
     else if (std::strcmp(key, "trace_split") == 0) *value = c->tune_trace_split;
+    else if (std::strcmp(key, "grad_batch") == 0) *value = c->grad_batch;
+    else if (std::strcmp(key, "trace_tile") == 0) *value = c->tune_trace_tile;
     else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
     return BEM_OK;
 }

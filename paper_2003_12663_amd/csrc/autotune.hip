@@ -6,6 +6,7 @@
 //   gemv_rows    matrix rows per block of the GMRES matvec             {2, 4, 8}
 //   gemm_blocks  minimum blocks of the FP32 multi-vector product       {512, 1024, 2048} (MIXED)
 //   eval_blocks  target blocks of the field evaluation                 {1024, 2048, 4096}
+//   trace_tile   lines per block of an unsplit field-line pass            {64, 128, 256} (at 256 lines)
 //   trace_split  live-line count at or below which a field-line pass splits each panel chunk over
 //                eight waves; the largest of {0, 32, 64, 128, 256} at which the split pass is faster
 // Each candidate runs once to warm up and is then timed three times with HIP
@@ -27,7 +28,7 @@ namespace bem {
 
 void launch_gemm_f32(bem_ctx* c, const float* A, int64_t lda, int64_t M, int64_t K, const float* Zt, int64_t ldz,
                      int ncols, double* Y, int64_t ldy, bool accumulate);
-double time_far_pass(bem_ctx* c, int64_t L, bool split, const double* pts, const double* sol);
+double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, const double* pts, const double* sol);
 
 namespace {
 
@@ -84,7 +85,8 @@ int pick(bem_ctx* c, const std::vector<int>& cand, Set&& set_and_run) {
     return best;
 }
 
-const char* KNOBS[] = {"far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_split"};
+constexpr int NKNOB = 6;
+const char* KNOBS[NKNOB] = {"far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile", "trace_split"};
 
 int32_t* knob(bem_ctx* c, int k) {
     switch (k) {
@@ -92,6 +94,7 @@ int32_t* knob(bem_ctx* c, int k) {
         case 1: return &c->tune_gemv_rows;
         case 2: return &c->tune_gemm_blocks;
         case 3: return &c->tune_eval_blocks;
+        case 4: return &c->tune_trace_tile;
         default: return &c->tune_trace_split;
     }
 }
@@ -108,13 +111,13 @@ std::string cache_key(bem_ctx* c) {
 }
 
 // lines of the cache file: `"<key>": {"far_rows": 64, ...},`
-bool parse_line(const std::string& line, std::string& key, int (&vals)[5]) {
+bool parse_line(const std::string& line, std::string& key, int (&vals)[NKNOB]) {
     const size_t q0 = line.find('"');
     if (q0 == std::string::npos) return false;
     const size_t q1 = line.find('"', q0 + 1);
     if (q1 == std::string::npos || line.find('{', q1) == std::string::npos) return false;
     key = line.substr(q0 + 1, q1 - q0 - 1);
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < NKNOB; ++k) {
         const std::string pat = std::string("\"") + KNOBS[k] + "\":";
         const size_t p = line.find(pat, q1);
         if (p == std::string::npos) return false;
@@ -129,6 +132,7 @@ bool valid_value(int k, int v) {
         case 1: return v == 2 || v == 4 || v == 8;
         case 2: return v >= 64 && v <= 65536;
         case 3: return v >= 64 && v <= 65536;
+        case 4: return v == 64 || v == 128 || v == 256;
         default: return v >= 0 && v <= 4096;
     }
 }
@@ -145,15 +149,15 @@ int autotune(bem_ctx* c, const char* cache_path) {
         std::string line;
         while (std::getline(in, line)) {
             std::string k;
-            int v[5];
-            if (parse_line(line, k, v)) entries.push_back({k, std::vector<int>(v, v + 5)});
+            int v[NKNOB];
+            if (parse_line(line, k, v)) entries.push_back({k, std::vector<int>(v, v + NKNOB)});
         }
         for (auto& e : entries)
             if (e.first == key) {
                 bool ok = true;
-                for (int k = 0; k < 5; ++k) ok = ok && valid_value(k, e.second[k]);
+                for (int k = 0; k < NKNOB; ++k) ok = ok && valid_value(k, e.second[k]);
                 if (!ok) throw Error(BEM_ERR_INVALID, std::string("invalid tuning cache entry in ") + cache_path);
-                for (int k = 0; k < 5; ++k) *knob(c, k) = e.second[k];
+                for (int k = 0; k < NKNOB; ++k) *knob(c, k) = e.second[k];
                 return 1;
             }
     }
@@ -203,13 +207,24 @@ int autotune(bem_ctx* c, const char* cache_path) {
         c->tune_eval_blocks = v;
         launch_eval(c, x.as<double>(), N, pts.as<double>(), nullptr, nullptr, y.as<double>());
     });
-    // field-line pass: split or not, at 32..256 live lines
+    // field-line pass: lines per block at 256 live lines, then split or not at 32..256 live lines
     {
+        const int64_t Lt = std::min<int64_t>(N, 256);
+        int best_tile = 256;
+        double tb = 1e30;
+        for (int tile : {64, 128, 256}) {
+            const double t = time_far_pass(c, Lt, false, tile, pts.as<double>(), x.as<double>());
+            if (t < tb) {
+                tb = t;
+                best_tile = tile;
+            }
+        }
+        c->tune_trace_tile = best_tile;
         int thr = 0;
         for (int64_t L : {32, 64, 128, 256}) {
             if (L > N) break;
-            const double t_split = time_far_pass(c, L, true, pts.as<double>(), x.as<double>());
-            const double t_full = time_far_pass(c, L, false, pts.as<double>(), x.as<double>());
+            const double t_split = time_far_pass(c, L, true, 64, pts.as<double>(), x.as<double>());
+            const double t_full = time_far_pass(c, L, false, best_tile, pts.as<double>(), x.as<double>());
             if (t_split < t_full) thr = (int)L;
         }
         c->tune_trace_split = thr;
@@ -219,8 +234,8 @@ int autotune(bem_ctx* c, const char* cache_path) {
     const bem_status rs = bem_assemble(c);
     if (rs != BEM_OK) throw Error(rs, "re-assembly after tuning failed");
     if (cache_path) {
-        std::vector<int> mine(5);
-        for (int k = 0; k < 5; ++k) mine[k] = *knob(c, k);
+        std::vector<int> mine(NKNOB);
+        for (int k = 0; k < NKNOB; ++k) mine[k] = *knob(c, k);
         bool found = false;
         for (auto& e : entries)
             if (e.first == key) {
@@ -232,7 +247,8 @@ int autotune(bem_ctx* c, const char* cache_path) {
         os << "{\n";
         for (size_t i = 0; i < entries.size(); ++i) {
             os << "\"" << entries[i].first << "\": {";
-            for (int k = 0; k < 5; ++k) os << (k ? ", " : "") << "\"" << KNOBS[k] << "\": " << entries[i].second[k];
+            for (int k = 0; k < NKNOB; ++k)
+                os << (k ? ", " : "") << "\"" << KNOBS[k] << "\": " << entries[i].second[k];
             os << "}" << (i + 1 < entries.size() ? "," : "") << "\n";
         }
         os << "}\n";

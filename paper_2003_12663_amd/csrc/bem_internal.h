@@ -139,6 +139,8 @@ struct bem_ctx {
     int32_t tune_gemm_blocks = 1024;  // minimum blocks of the FP32 multi-vector product (K ranges)
     int32_t tune_eval_blocks = 2048;  // target blocks of the field evaluation (panel-range split)
     int32_t tune_trace_split = 64;    // live-line count at or below which field-line passes split chunks
+    int32_t tune_trace_tile = 256;    // lines per block of an unsplit field-line pass (64, 128, 256)
+    int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
     // profiling
     bool profiling = false;

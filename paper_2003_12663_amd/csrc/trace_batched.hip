@@ -30,7 +30,6 @@
 namespace bem {
 namespace {
 
-constexpr int LB_T = 256;        // lines per tile (one per lane)
 constexpr int LB_C = 32;         // panels per chunk
 constexpr int LB_NRHS_LDS = 64;  // load cases whose sigma chunk is staged in LDS
 
@@ -97,19 +96,20 @@ __global__ __launch_bounds__(256) void k_lb_init(int64_t L, const double* __rest
     act[l] = (int32_t)l;
 }
 
-// SPLIT = 1: 256 lines per block (4 waves), every lane walks the whole chunk.
+// SPLIT = 1: TILE_LINES (64, 128 or 256) lines per block, one per lane, every lane
+// walks the whole chunk.
 // SPLIT > 1: 64 lines per block (SPLIT waves); wave w walks panels
 // [w C/SPLIT, (w + 1) C/SPLIT) of the chunk and the partial fields are added
 // in wave order (for few lines: 1/SPLIT of the serial work per lane).
-template <typename R, int SPLIT>
-__global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : LB_T) void k_lb_far(const double* __restrict__ far64, const R* __restrict__ farR,
+template <typename R, int SPLIT, int TILE_LINES>
+__global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(const double* __restrict__ far64, const R* __restrict__ farR,
                                                  int64_t Np, int64_t N, const double* __restrict__ sol, int64_t n,
                                                  int32_t nrhs, const int32_t* __restrict__ line_rhs, int64_t L,
                                                  const int32_t* __restrict__ act, const int32_t* __restrict__ count,
                                                  int32_t* __restrict__ count_next, const double* __restrict__ ys,
                                                  double* __restrict__ part, uint32_t* __restrict__ pmask) {
-    constexpr int NT = SPLIT > 1 ? 64 * SPLIT : LB_T;   // threads per block
-    constexpr int TILE = SPLIT > 1 ? 64 : LB_T;         // lines per block
+    constexpr int NT = SPLIT > 1 ? 64 * SPLIT : TILE_LINES;   // threads per block
+    constexpr int TILE = SPLIT > 1 ? 64 : TILE_LINES;         // lines per block
     constexpr int PER = LB_C / SPLIT;
     __shared__ R tq[LB_C][28];
     __shared__ double tc[LB_C][4];
@@ -201,7 +201,8 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : LB_T) void k_lb_far(const 
     pmask[(int64_t)blockIdx.y * L + l] = nmask;
 }
 
-constexpr int LB_Q = 1024;   // near pairs per round in k_lb_step
+constexpr int LB_Q = 1024;    // near pairs per round in k_lb_step
+constexpr int LB_MREG = 8;    // near masks per thread held in registers by k_lb_step (KS <= 2048)
 
 // One block per active line: far partials + the line's near pairs (closed
 // forms, and the segment test on end-of-step passes) + the RK4 stage machine.
@@ -226,17 +227,37 @@ __global__ __launch_bounds__(256) void k_lb_step(
     const double p0 = s.y[3 * l], p1 = s.y[3 * l + 1], p2 = s.y[3 * l + 2];
     const double q0 = s.x[3 * l], q1 = s.x[3 * l + 1], q2 = s.x[3 * l + 2];
     const bool hit_pass = (phase == 4);
-    // far partials, fixed order per thread
+    // the line's stage-machine state, read early so that its latency overlaps the sums below
+    const int32_t ns0 = s.ns[l];
+    const double asum0 = s.asum[l], I0 = s.I[l];
+    const double ks0 = s.ks[3 * l], ks1 = s.ks[3 * l + 1], ks2 = s.ks[3 * l + 2];
+    // far partials (fixed order per thread) and near masks in one sweep; the first LB_MREG masks
+    // of each thread stay in registers for the list fill below
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    for (int64_t k = tid; k < KS; k += 256) {
+    uint32_t mreg[LB_MREG];
+    int cnt = 0;
+#pragma unroll
+    for (int t = 0; t < LB_MREG; ++t) {
+        const int64_t k = tid + 256 * t;
+        uint32_t m = 0;
+        if (k < KS) {
+            const double* o = part + (k * L + l) * 3;
+            e0 += o[0];
+            e1 += o[1];
+            e2 += o[2];
+            m = pmask[k * L + l];
+        }
+        mreg[t] = m;
+        cnt += __popc(m);
+    }
+    for (int64_t k = tid + 256 * LB_MREG; k < KS; k += 256) {
         const double* o = part + (k * L + l) * 3;
         e0 += o[0];
         e1 += o[1];
         e2 += o[2];
+        cnt += __popc(pmask[k * L + l]);
     }
-    // near pairs: count this thread's, exclusive scan over the block (wave scans + one barrier)
-    int cnt = 0;
-    for (int64_t k = tid; k < KS; k += 256) cnt += __popc(pmask[k * L + l]);
+    // near pairs: exclusive scan of the per-thread counts over the block (wave scans + one barrier)
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -257,7 +278,18 @@ __global__ __launch_bounds__(256) void k_lb_step(
         // this thread's pairs that fall in [base, base + LB_Q)
         if (off + cnt > base && off < base + LB_Q) {
             int pos = off;
-            for (int64_t k = tid; k < KS && pos < base + LB_Q; k += 256) {
+#pragma unroll
+            for (int t = 0; t < LB_MREG; ++t) {
+                uint32_t m = mreg[t];
+                const int64_t k = tid + 256 * t;
+                while (m) {
+                    const int b = __builtin_ctz(m);
+                    m &= m - 1;
+                    if (pos >= base && pos < base + LB_Q) list[pos - base] = (int32_t)(k * LB_C + b);
+                    ++pos;
+                }
+            }
+            for (int64_t k = tid + 256 * LB_MREG; k < KS && pos < base + LB_Q; k += 256) {
                 uint32_t m = pmask[k * L + l];
                 while (m) {
                     const int b = __builtin_ctz(m);
@@ -326,7 +358,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
     }
     const double h = a.h;
     double x0 = q0, x1 = q1, x2 = q2;
-    int32_t ns = s.ns[l];
+    int32_t ns = ns0;
     int code = -1;   // -1: the line goes on
     if (hit_pass) {
         if (hit >= 0) {
@@ -334,7 +366,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
             code = (k == BEM_DIRICHLET) ? BEM_STOP_DIRICHLET
                                         : ((k == BEM_FLOATING) ? BEM_STOP_FLOATING : BEM_STOP_INTERFACE);
         } else {
-            s.I[l] += h / 6.0 * s.asum[l];
+            s.I[l] = I0 + h / 6.0 * asum0;
             x0 = p0;
             x1 = p1;
             x2 = p2;
@@ -371,30 +403,32 @@ __global__ __launch_bounds__(256) void k_lb_step(
                 y[2] = x2 + 0.5 * h * k2;
             }
         } else if (phase < 3) {
-            ks[0] += 2.0 * k0;
-            ks[1] += 2.0 * k1;
-            ks[2] += 2.0 * k2;
-            s.asum[l] += 2.0 * lb_alpha(a, m);
+            ks[0] = ks0 + 2.0 * k0;
+            ks[1] = ks1 + 2.0 * k1;
+            ks[2] = ks2 + 2.0 * k2;
+            s.asum[l] = asum0 + 2.0 * lb_alpha(a, m);
             const double c = (phase == 1) ? 0.5 * h : h;
             y[0] = x0 + c * k0;
             y[1] = x1 + c * k1;
             y[2] = x2 + c * k2;
         } else {
-            ks[0] += k0;
-            ks[1] += k1;
-            ks[2] += k2;
-            s.asum[l] += lb_alpha(a, m);
-            y[0] = x0 + h / 6.0 * ks[0];
-            y[1] = x1 + h / 6.0 * ks[1];
-            y[2] = x2 + h / 6.0 * ks[2];
+            const double t0 = ks0 + k0, t1 = ks1 + k1, t2 = ks2 + k2;
+            ks[0] = t0;
+            ks[1] = t1;
+            ks[2] = t2;
+            s.asum[l] = asum0 + lb_alpha(a, m);
+            y[0] = x0 + h / 6.0 * t0;
+            y[1] = x1 + h / 6.0 * t1;
+            y[2] = x2 + h / 6.0 * t2;
             if (!(isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]))) code = BEM_STOP_NONFINITE;
         }
     }
     if (code >= 0) {
         n_steps[l] = ns;
         stop_code[l] = code;
-        if (integral) integral[l] = s.I[l];
-        if (exceeds) exceeds[l] = (s.I[l] > a.k_str) ? 1 : 0;
+        const double Iend = (hit_pass && hit < 0) ? I0 + h / 6.0 * asum0 : I0;
+        if (integral) integral[l] = Iend;
+        if (exceeds) exceeds[l] = (Iend > a.k_str) ? 1 : 0;
     } else {
         act_next[atomicAdd(count_next, 1)] = (int32_t)l;
     }
@@ -411,8 +445,9 @@ __global__ void k_lb_iota(int32_t* __restrict__ act, int32_t* __restrict__ count
 }  // namespace
 
 // Duration (ms, best of 3 after a warm-up) of one far-field pass over L lines at the points pts
-// (FP64 or FP32 by the context's precision), split or not: used by the autotuner.
-double time_far_pass(bem_ctx* c, int64_t L, bool split, const double* pts, const double* sol) {
+// (FP64 or FP32 by the context's precision), split, or not with tile_lines lines per block:
+// used by the autotuner.
+double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, const double* pts, const double* sol) {
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t KS = ceil_div(N, LB_C);
@@ -426,22 +461,27 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, const double* pts, const
     hipLaunchKernelGGL(k_lb_iota, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, act, cnt, L);
     BEM_CHECK_LAUNCH();
     const bool fp64 = c->opt.precision == BEM_FP64;
-    dim3 g1((unsigned)ceil_div(L, split ? 64 : LB_T), (unsigned)KS);
+    const int tile = split ? 64 : tile_lines;
+    dim3 g1((unsigned)ceil_div(L, tile), (unsigned)KS);
     auto run = [&] {
-#define BEM_LB_FAR(R, SP, FR)                                                                                     \
-    hipLaunchKernelGGL((k_lb_far<R, SP>), g1, dim3(SP > 1 ? 64 * SP : LB_T), 0, c->stream, c->far64.as<double>(), FR, \
-                       Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask)
+#define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
+    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
+                       FR, Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask)
+#define BEM_LB_FAR_ALL(R, FR)                      \
+    if (split)                                     \
+        BEM_LB_FAR(R, 8, 64, FR);                  \
+    else if (tile == 64)                           \
+        BEM_LB_FAR(R, 1, 64, FR);                  \
+    else if (tile == 128)                          \
+        BEM_LB_FAR(R, 1, 128, FR);                 \
+    else                                           \
+        BEM_LB_FAR(R, 1, 256, FR)
         if (fp64) {
-            if (split)
-                BEM_LB_FAR(double, 8, c->far64.as<double>());
-            else
-                BEM_LB_FAR(double, 1, c->far64.as<double>());
+            BEM_LB_FAR_ALL(double, c->far64.as<double>());
         } else {
-            if (split)
-                BEM_LB_FAR(float, 8, c->far32.as<float>());
-            else
-                BEM_LB_FAR(float, 1, c->far32.as<float>());
+            BEM_LB_FAR_ALL(float, c->far32.as<float>());
         }
+#undef BEM_LB_FAR_ALL
 #undef BEM_LB_FAR
         BEM_CHECK_LAUNCH();
     };
@@ -516,21 +556,26 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         KTimer tf(c, "trace_far", (pass & 15) == 0);
         // blocks of tiles past the active count would only launch and exit: size the grids by
         // the last known active count (an upper bound, the count only falls)
-        dim3 g1((unsigned)ceil_div(known_active, split ? 64 : LB_T), (unsigned)KS);
-#define BEM_LB_FAR(R, SP, FR)                                                                                     \
-    hipLaunchKernelGGL((k_lb_far<R, SP>), g1, dim3(SP > 1 ? 64 * SP : LB_T), 0, c->stream, c->far64.as<double>(), FR, Np, N, sol,     \
-                       c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask)
+        const int tile = split ? 64 : c->tune_trace_tile;
+        dim3 g1((unsigned)ceil_div(known_active, tile), (unsigned)KS);
+#define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
+    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
+                       FR, Np, N, sol, c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask)
+#define BEM_LB_FAR_ALL(R, FR)                      \
+    if (split)                                     \
+        BEM_LB_FAR(R, 8, 64, FR);                  \
+    else if (tile == 64)                           \
+        BEM_LB_FAR(R, 1, 64, FR);                  \
+    else if (tile == 128)                          \
+        BEM_LB_FAR(R, 1, 128, FR);                 \
+    else                                           \
+        BEM_LB_FAR(R, 1, 256, FR)
         if (fp64) {
-            if (split)
-                BEM_LB_FAR(double, 8, c->far64.as<double>());
-            else
-                BEM_LB_FAR(double, 1, c->far64.as<double>());
+            BEM_LB_FAR_ALL(double, c->far64.as<double>());
         } else {
-            if (split)
-                BEM_LB_FAR(float, 8, c->far32.as<float>());
-            else
-                BEM_LB_FAR(float, 1, c->far32.as<float>());
+            BEM_LB_FAR_ALL(float, c->far32.as<float>());
         }
+#undef BEM_LB_FAR_ALL
 #undef BEM_LB_FAR
         BEM_CHECK_LAUNCH();
         ++c->trace_far_launches;

@@ -27,11 +27,13 @@ def bem():
     return bem
 
 
-def _case(bem, oracle_mod, p, L, steps, h, cf=0, seed=6, nrhs=1):
+def _case(bem, oracle_mod, p, L, steps, h, cf=0, seed=6, nrhs=1, batch=None):
     import torch
     dev = torch.device("cuda", 0)
     starts, panel, bary = electrode_line_starts(p, L, seed=seed)
     ctx = bem.Context.from_problem(p, precision=bem.FP64, eta=6.0, constraint_form=cf)
+    if batch is not None:
+        ctx.set_tuning("grad_batch", batch)
     ctx.assemble()
     bv = np.stack([p.body_V * (1.0 + 0.25 * r) for r in range(nrhs)])
     sol, info = ctx.solve(bv, tol=1e-13, max_iter=20000)
@@ -89,6 +91,41 @@ def test_gradient_matches_oracle_dual(bem, oracle_mod, name, make, L, steps, h, 
     c["ctx"].close()
 
 
+def _check_dirs(oracle_mod, p, c, cf=0, trials=2):
+    rng = np.random.default_rng(8)
+    nrhs = c["bv"].shape[0]
+    for trial in range(trials):
+        dv = rng.standard_normal(p.vert.shape)
+        dV = rng.standard_normal((nrhs, p.n_body))
+        _, dJ = _oracle_dir(oracle_mod, p, c, dv, dV, cf)
+        gpu = float(np.sum(c["dvert"] * dv) + np.sum(c["dV"] * dV))
+        scale = np.linalg.norm(c["dvert"]) * np.linalg.norm(dv) + np.linalg.norm(c["dV"]) * np.linalg.norm(dV)
+        assert abs(gpu - dJ) <= REL * scale, (trial, gpu, dJ, scale)
+
+
+def test_gradient_small_batches(bem, oracle_mod):
+    """Point batches smaller than the panel count (stage points and collocation points)."""
+    p = sphere_problem(2, V0=50.0)
+    c = _case(bem, oracle_mod, p, 6, 40, 1e-2, nrhs=2, batch=100)
+    _check_dirs(oracle_mod, p, c)
+    c["ctx"].close()
+
+
+@pytest.mark.parametrize("L,steps", [(4, 2000), (80, 150)], ids=["4_full_lines", "80_short_lines"])
+def test_gradient_coarse_coax(bem, oracle_mod, L, steps):
+    """Coax with all body kinds (grounded shell, driven rod, floating torus, eps_r = 4 spacer),
+    coarse mesh; lines hit the shell (first case) or run out of steps (second)."""
+    from workloads import coax_problem
+    p = coax_problem(0.012)
+    print(f"[grad] coarse coax N={p.n_tri} L={L} steps={steps}", flush=True)
+    c = _case(bem, oracle_mod, p, L, steps, 1e-4, seed=7)
+    assert np.all(c["I"] >= 0.0) and c["I"].sum() > 0.0
+    _check_dirs(oracle_mod, p, c, trials=1)
+    G = c["dvert"]
+    assert np.linalg.norm(G.sum(axis=0)) <= 1e-9 * np.abs(G).sum()
+    c["ctx"].close()
+
+
 def test_gradient_body_potential_only(bem, oracle_mod):
     """dJ/dV alone (vertex direction zero) on a floating-shell case."""
     p = floating_shell_problem(1, V0=50.0)
@@ -102,16 +139,18 @@ def test_gradient_body_potential_only(bem, oracle_mod):
 
 
 def test_gradient_line_starts(bem, oracle_mod):
-    """dJ/dstarts (mesh fixed) against central differences of the oracle trace."""
+    """dJ/dstarts (mesh fixed) against central differences of the oracle trace (step 1e-8: the
+    starts sit 1e-6 above their panels, a larger step could move one through the surface)."""
     p = sphere_problem(1, V0=50.0)
     c = _case(bem, oracle_mod, p, 4, 60, 1e-2)
     o = oracle_mod.Oracle(p)
     u = c["sol"][0].cpu().numpy()
     tp = oracle_mod.trace_params(h=1e-2, max_steps=60, e_min=1e-3)
     ds = np.random.default_rng(9).standard_normal(c["starts"].shape)
-    hfd = 1e-6
-    _, _, Ip = o.trace(u[:p.n_tri], c["starts"] + hfd * ds, tp)
-    _, _, Im = o.trace(u[:p.n_tri], c["starts"] - hfd * ds, tp)
+    hfd = 1e-8
+    nsp, _, Ip = o.trace(u[:p.n_tri], c["starts"] + hfd * ds, tp)
+    nsm, _, Im = o.trace(u[:p.n_tri], c["starts"] - hfd * ds, tp)
+    assert np.array_equal(nsp, c["ns"]) and np.array_equal(nsm, c["ns"])
     fd = float(np.dot(c["g"], (Ip - Im) / (2 * hfd)))
     gpu = float(np.sum(c["dstart"] * ds))
     assert abs(gpu - fd) <= 1e-6 * np.linalg.norm(c["dstart"]) * np.linalg.norm(ds)

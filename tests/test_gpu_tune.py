@@ -11,7 +11,8 @@ from workloads import sphere_eval_points, sphere_problem
 pytestmark = pytest.mark.gpu
 
 CANDIDATES = {"far_rows": {32, 64, 128}, "gemv_rows": {2, 4, 8}, "gemm_blocks": {512, 1024, 2048},
-              "eval_blocks": {1024, 2048, 4096}, "trace_split": {0, 32, 64, 128, 256}}
+              "eval_blocks": {1024, 2048, 4096}, "trace_tile": {64, 128, 256},
+              "trace_split": {0, 32, 64, 128, 256}}
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +65,8 @@ def test_autotune_cache_and_results(bem, tmp_path, precision):
 def test_tuning_knob_validation(bem):
     p = sphere_problem(1)
     ctx = bem.Context.from_problem(p)
-    for key, bad in (("far_rows", 48), ("gemv_rows", 3), ("eval_blocks", 10), ("trace_split", -1), ("nope", 1)):
+    for key, bad in (("far_rows", 48), ("gemv_rows", 3), ("eval_blocks", 10), ("trace_split", -1),
+                     ("trace_tile", 96), ("grad_batch", 8), ("nope", 1)):
         with pytest.raises(bem.BemError):
             ctx.set_tuning(key, bad)
     ctx.set_tuning("gemv_rows", 8)
