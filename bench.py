@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=800)
     ap.add_argument("--no-tts", action="store_true", help="skip the 64-load-case time-to-solve comparison")
     ap.add_argument("--tts-only", action="store_true", help="only the 64-load-case time-to-solve comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the gradient and the 64-load-case x 64-line runs")
+    ap.add_argument("--extras-only", action="store_true", help="only the gradient and 4096-line runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -101,6 +104,60 @@ def time_to_solve(bem, torch, p, ctx64, nrhs=64, tol=1e-8):
     ctxm.close()
     out["speedup_mixed_vs_fp64_one_by_one"] = out["fp64_one_by_one"]["s"] / out["mixed_batched"]["s"]
     out["speedup_mixed_vs_fp64_batched"] = out["fp64_batched"]["s"] / out["mixed_batched"]["s"]
+    return out
+
+
+def gradient_run(bem, torch, p, ctx):
+    """Gradient of J = sum of the streamer integrals of 128 lines (seed 7) at V0 = 1 with respect to
+    all vertex coordinates and body potentials (bem_streamer_grad), after one forward run."""
+    from workloads import electrode_line_starts
+    starts, panel, bary = electrode_line_starts(p, 128, seed=7)
+    st = torch.tensor(starts, device="cuda")
+    tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-3)
+    sol, _ = ctx.solve(p.body_V, tol=1e-12, max_iter=20000)
+    g = torch.ones(128, dtype=torch.float64, device="cuda")
+    ctx.streamer_grad(sol, st, g, tp, start_panel=panel, start_bary=bary)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    I, ns, stc, _ = ctx.streamer_integral(sol, st, tp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dvert, dV, _ = ctx.streamer_grad(sol, st, g, tp, start_panel=panel, start_bary=bary)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    G = dvert.cpu().numpy()
+    return {"lines": 128, "J": float(I.sum().item()), "forward_s": t1 - t0, "gradient_s": t2 - t1,
+            "gradient_over_forward": (t2 - t1) / (t1 - t0), "dJ_dV_rod": float(dV[0, 1].item()),
+            "translation_residual_rel": float(np.linalg.norm(G.sum(axis=0)) / np.abs(G).sum())}
+
+
+def cases_by_lines_run(bem, torch, p, ctx):
+    """64 load cases (rod U[0.5, 2], seed 4) solved together, then 64 lines per case (seed 5):
+    4096 field lines with streamer integrals in one call, both line layouts timed."""
+    from workloads import electrode_line_starts, rod_load_cases
+    bv = rod_load_cases(p, 64, seed=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol, info = ctx.solve(bv, tol=1e-10, max_iter=20000)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    starts, _, _ = electrode_line_starts(p, 4096, seed=5)
+    st = torch.tensor(starts, device="cuda")
+    lr = np.repeat(np.arange(64, dtype=np.int32), 64)
+    tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-3)
+    out = {"load_cases": 64, "lines": 4096, "solve_s": t_solve, "solve_iters": info["iters"]}
+    for mode, name in ((1, "all_lines_together"), (2, "persistent_per_line")):
+        ctx.set_tuning("trace_mode", mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        I, ns, stc, _ = ctx.streamer_integral(sol, st, tp, line_rhs=lr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ns_h = ns.cpu().numpy()
+        passes = int(np.sum(1 + 4 * ns_h + 4 * (stc.cpu().numpy() != 0)))
+        out[name] = {"s": dt, "field_evals": passes, "pairs_per_s": passes * p.n_tri / dt,
+                     "integral_sum": float(I.sum().item())}
+    ctx.set_tuning("trace_mode", 0)
     return out
 
 
@@ -156,6 +213,18 @@ def main():
         print(json.dumps({"time_to_solve_64_load_cases": time_to_solve(bem, torch, p, ctx)}))
         ctx.close()
         return
+    if args.extras_only:
+        ctx.assemble()
+        ctx.autotune(None)
+        print(json.dumps({"gradient_coax_128_lines": gradient_run(bem, torch, p, ctx),
+                          "cases_64_x_lines_64": cases_by_lines_run(bem, torch, p, ctx)}))
+        ctx.close()
+        return
+    # tile shapes for this problem, timed before the timed region (tuning re-assembles)
+    ctx.assemble()
+    ctx.autotune(None)
+    tuning = {k: ctx.get_tuning(k) for k in ("far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile",
+                                              "trace_splitk", "trace_split", "trace_few")}
 
     def step():
         ctx.assemble()
@@ -209,6 +278,13 @@ def main():
     fa_n, fa_ms = stats["far_assemble"]
     phases = {k: (v[1] / args.steps) for k, v in stats.items()}
 
+    extras = {}
+    if not args.no_extras:
+        ctx.set_profiling(False)
+        print("[bench] gradient and 64 x 64 lines", file=sys.stderr, flush=True)
+        extras["gradient_coax_128_lines"] = gradient_run(bem, torch, p, ctx)
+        extras["cases_64_x_lines_64"] = cases_by_lines_run(bem, torch, p, ctx)
+
     tts = None
     if not args.no_tts:
         ctx.set_profiling(False)
@@ -259,7 +335,9 @@ def main():
         "trace_near_pairs": near_line_pairs,
         "cpu_baseline": cpu,
         "time_to_solve_64_load_cases": tts,
+        "tuning": tuning,
     }
+    out.update(extras)
     print(json.dumps(out))
     ctx.close()
 

@@ -229,6 +229,9 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
  *  "gemm_blocks": minimum blocks of the FP32 multi-vector product, by K ranges (64..65536; 1024)
  *  "eval_blocks": target blocks of the field evaluation, by panel ranges (64..65536; 2048)
  *  "trace_tile":  lines per block of an unsplit field-line pass (64, 128, 256; default 256)
+ *  "trace_splitk": waves splitting each panel chunk in a split field-line pass (2, 4, 8; default 8)
+ *  "trace_few":   live-line count at or below which a field-line pass is panel-stationary (one
+ *                 lane per panel, all live lines per lane; 0..32; default 16)
  *  "trace_split": live-line count at or below which a field-line pass splits each panel chunk
  *                 over eight waves (0..4096; default 64)
  *  "grad_batch":  points per batch of the pair passes of bem_streamer_grad (64..2^24; default

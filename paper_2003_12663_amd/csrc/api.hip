@@ -560,6 +560,8 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"eval_blocks", &bem_ctx::tune_eval_blocks, 64, 65536, false},
         {"trace_split", &bem_ctx::tune_trace_split, 0, 4096, false},
         {"trace_tile", &bem_ctx::tune_trace_tile, 64, 256, true},
+        {"trace_few", &bem_ctx::tune_trace_few, 0, 32, false},
+        {"trace_splitk", &bem_ctx::tune_trace_splitk, 2, 8, true},
         {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
     for (const Knob& k : knobs)
@@ -583,6 +585,8 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     else if (std::strcmp(key, "trace_split") == 0) *value = c->tune_trace_split;
     else if (std::strcmp(key, "grad_batch") == 0) *value = c->grad_batch;
     else if (std::strcmp(key, "trace_tile") == 0) *value = c->tune_trace_tile;
+    else if (std::strcmp(key, "trace_few") == 0) *value = c->tune_trace_few;
+    else if (std::strcmp(key, "trace_splitk") == 0) *value = c->tune_trace_splitk;
     else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
     return BEM_OK;
 }

@@ -7,8 +7,11 @@
 //   gemm_blocks  minimum blocks of the FP32 multi-vector product       {512, 1024, 2048} (MIXED)
 //   eval_blocks  target blocks of the field evaluation                 {1024, 2048, 4096}
 //   trace_tile   lines per block of an unsplit field-line pass            {64, 128, 256} (at 256 lines)
+//   trace_splitk waves splitting each panel chunk in a split field-line pass {2, 4, 8} (at 256 lines)
 //   trace_split  live-line count at or below which a field-line pass splits each panel chunk over
 //                eight waves; the largest of {0, 32, 64, 128, 256} at which the split pass is faster
+//   trace_few    live-line count at or below which the panel-stationary pass is used: the largest
+//                of {0, 2, 4, 8, 16, 32} at which it beats the other passes
 // Each candidate runs once to warm up and is then timed three times with HIP
 // events on the context stream; the fastest (minimum) wins, ties to the first
 // candidate.  Cache: a JSON object keyed by "<arch> N=<panels> n=<unknowns>
@@ -28,7 +31,8 @@ namespace bem {
 
 void launch_gemm_f32(bem_ctx* c, const float* A, int64_t lda, int64_t M, int64_t K, const float* Zt, int64_t ldz,
                      int ncols, double* Y, int64_t ldy, bool accumulate);
-double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, const double* pts, const double* sol);
+double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int splitk, const double* pts,
+                     const double* sol);
 
 namespace {
 
@@ -85,8 +89,9 @@ int pick(bem_ctx* c, const std::vector<int>& cand, Set&& set_and_run) {
     return best;
 }
 
-constexpr int NKNOB = 6;
-const char* KNOBS[NKNOB] = {"far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile", "trace_split"};
+constexpr int NKNOB = 8;
+const char* KNOBS[NKNOB] = {"far_rows",   "gemv_rows",    "gemm_blocks", "eval_blocks",
+                            "trace_tile", "trace_splitk", "trace_split", "trace_few"};
 
 int32_t* knob(bem_ctx* c, int k) {
     switch (k) {
@@ -95,7 +100,9 @@ int32_t* knob(bem_ctx* c, int k) {
         case 2: return &c->tune_gemm_blocks;
         case 3: return &c->tune_eval_blocks;
         case 4: return &c->tune_trace_tile;
-        default: return &c->tune_trace_split;
+        case 5: return &c->tune_trace_splitk;
+        case 6: return &c->tune_trace_split;
+        default: return &c->tune_trace_few;
     }
 }
 
@@ -133,7 +140,9 @@ bool valid_value(int k, int v) {
         case 2: return v >= 64 && v <= 65536;
         case 3: return v >= 64 && v <= 65536;
         case 4: return v == 64 || v == 128 || v == 256;
-        default: return v >= 0 && v <= 4096;
+        case 5: return v == 2 || v == 4 || v == 8;
+        case 6: return v >= 0 && v <= 4096;
+        default: return v >= 0 && v <= 32;
     }
 }
 
@@ -213,21 +222,41 @@ int autotune(bem_ctx* c, const char* cache_path) {
         int best_tile = 256;
         double tb = 1e30;
         for (int tile : {64, 128, 256}) {
-            const double t = time_far_pass(c, Lt, false, tile, pts.as<double>(), x.as<double>());
+            const double t = time_far_pass(c, Lt, false, tile, 8, pts.as<double>(), x.as<double>());
             if (t < tb) {
                 tb = t;
                 best_tile = tile;
             }
         }
         c->tune_trace_tile = best_tile;
+        int best_k = 8;
+        tb = 1e30;
+        for (int k : {2, 4, 8}) {
+            const double t = time_far_pass(c, Lt, true, 64, k, pts.as<double>(), x.as<double>());
+            if (t < tb) {
+                tb = t;
+                best_k = k;
+            }
+        }
+        c->tune_trace_splitk = best_k;
         int thr = 0;
         for (int64_t L : {32, 64, 128, 256}) {
             if (L > N) break;
-            const double t_split = time_far_pass(c, L, true, 64, pts.as<double>(), x.as<double>());
-            const double t_full = time_far_pass(c, L, false, best_tile, pts.as<double>(), x.as<double>());
+            const double t_split = time_far_pass(c, L, true, 64, best_k, pts.as<double>(), x.as<double>());
+            const double t_full = time_far_pass(c, L, false, best_tile, best_k, pts.as<double>(), x.as<double>());
             if (t_split < t_full) thr = (int)L;
         }
         c->tune_trace_split = thr;
+        int few = 0;
+        for (int64_t L : {2, 4, 8, 16, 32}) {
+            if (L > N) break;
+            const double t_few = time_far_pass(c, L, false, 0, best_k, pts.as<double>(), x.as<double>());
+            const bool use_split = L <= thr;
+            const double t_other =
+                time_far_pass(c, L, use_split, best_tile, best_k, pts.as<double>(), x.as<double>());
+            if (t_few < t_other) few = (int)L;
+        }
+        c->tune_trace_few = few;
     }
     BEM_HIP(hipStreamSynchronize(s));
     // the far-assembly candidates overwrote the matrix without its near entries: assemble again

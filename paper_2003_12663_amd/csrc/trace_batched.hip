@@ -201,13 +201,100 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     pmask[(int64_t)blockIdx.y * L + l] = nmask;
 }
 
+
+// Few live lines (the tail of a run, when most lines have stopped): a
+// panel-stationary pass.  One lane per panel (256 per block) loads its panel's
+// record once and evaluates the regular pairs of all A <= LB_FEW lines; the
+// per-line sums are reduced over the block (fixed order), so there are
+// ceil(N/256) partial rows instead of one per 32-panel chunk, and the near bits
+// come from ballots in the same (chunk, line) mask layout as k_lb_far.
+constexpr int LB_FEW = 32;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ far64, const R* __restrict__ farR,
+                                                    int64_t Np, int64_t N, const double* __restrict__ sol, int64_t n,
+                                                    const int32_t* __restrict__ line_rhs, int64_t L,
+                                                    const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ count_next, const double* __restrict__ ys,
+                                                    double* __restrict__ part, uint32_t* __restrict__ pmask) {
+    __shared__ double lp[LB_FEW][3];
+    __shared__ int32_t lrow[LB_FEW];
+    __shared__ double wred[4][3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) count_next[0] = 0;
+    const int32_t A = count[0] < LB_FEW ? count[0] : LB_FEW;   // the launcher guarantees count <= LB_FEW
+    if (threadIdx.x < A) {
+        const int64_t l = act[threadIdx.x];
+        lrow[threadIdx.x] = (int32_t)l;
+        lp[threadIdx.x][0] = ys[3 * l];
+        lp[threadIdx.x][1] = ys[3 * l + 1];
+        lp[threadIdx.x][2] = ys[3 * l + 2];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;   // < Np (grid covers N rounded up to 256)
+    const bool valid = j < N;
+    R qx[7], qy[7], qz[7], qw[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        qx[q] = farR[(int64_t)(FR_X + q) * Np + j];
+        qy[q] = farR[(int64_t)(FR_Y + q) * Np + j];
+        qz[q] = farR[(int64_t)(FR_Z + q) * Np + j];
+        qw[q] = farR[(int64_t)(FR_W + q) * Np + j];
+    }
+    const double ccx = far64[(int64_t)(FR_CC + 0) * Np + j], ccy = far64[(int64_t)(FR_CC + 1) * Np + j];
+    const double ccz = far64[(int64_t)(FR_CC + 2) * Np + j], rr = far64[(int64_t)FR_RR * Np + j];
+    for (int t = 0; t < A; ++t) {
+        const int64_t l = lrow[t];
+        const double p0 = lp[t][0], p1 = lp[t][1], p2 = lp[t][2];
+        const bool reg = valid && is_regular(p0 - ccx, p1 - ccy, p2 - ccz, rr);
+        const uint64_t near = __ballot(valid && !reg);
+        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+        if (reg) {
+            const R pr0 = (R)p0, pr1 = (R)p1, pr2 = (R)p2;
+            R f0 = 0, f1 = 0, f2 = 0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const R dx = pr0 - qx[q], dy = pr1 - qy[q], dz = pr2 - qz[q];
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ir = rsqrt_pos(r2);
+                const R tw = qw[q] * ir * ir * ir;
+                f0 += tw * dx;
+                f1 += tw * dy;
+                f2 += tw * dz;
+            }
+            const double sg = sol[(line_rhs ? (int64_t)line_rhs[l] : 0) * n + j];
+            e0 = sg * (double)f0;
+            e1 = sg * (double)f1;
+            e2 = sg * (double)f2;
+        }
+        // near bits: lanes 0..31 and 32..63 of the wave are two 32-panel chunks
+        const int64_t c0 = (j - lane) / LB_C;
+        if (lane == 0 && ((j - lane) < N)) pmask[c0 * L + l] = (uint32_t)near;
+        if (lane == 32 && ((j - lane + 32) < N)) pmask[(c0 + 1) * L + l] = (uint32_t)(near >> 32);
+        e0 = wave_sum(e0);
+        e1 = wave_sum(e1);
+        e2 = wave_sum(e2);
+        __syncthreads();
+        if (lane == 0) {
+            wred[wv][0] = e0;
+            wred[wv][1] = e1;
+            wred[wv][2] = e2;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int c = threadIdx.x;
+            part[((int64_t)blockIdx.x * L + l) * 3 + c] = (wred[0][c] + wred[1][c]) + (wred[2][c] + wred[3][c]);
+        }
+    }
+}
+
 constexpr int LB_Q = 1024;    // near pairs per round in k_lb_step
 constexpr int LB_MREG = 8;    // near masks per thread held in registers by k_lb_step (KS <= 2048)
 
 // One block per active line: far partials + the line's near pairs (closed
 // forms, and the segment test on end-of-step passes) + the RK4 stage machine.
 __global__ __launch_bounds__(256) void k_lb_step(
-    int64_t L, int64_t KS, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+    int64_t L, int64_t KS, int64_t KSP, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
     int32_t* __restrict__ act_next, int32_t* __restrict__ count_next, const double* __restrict__ part,
     const uint32_t* __restrict__ pmask, int phase, LBState s, LBArgs a, const double* __restrict__ tri64,
     const double* __restrict__ sol, int64_t n, const int32_t* __restrict__ line_rhs,
@@ -240,22 +327,24 @@ __global__ __launch_bounds__(256) void k_lb_step(
     for (int t = 0; t < LB_MREG; ++t) {
         const int64_t k = tid + 256 * t;
         uint32_t m = 0;
-        if (k < KS) {
+        if (k < KSP) {
             const double* o = part + (k * L + l) * 3;
             e0 += o[0];
             e1 += o[1];
             e2 += o[2];
-            m = pmask[k * L + l];
         }
+        if (k < KS) m = pmask[k * L + l];
         mreg[t] = m;
         cnt += __popc(m);
     }
-    for (int64_t k = tid + 256 * LB_MREG; k < KS; k += 256) {
-        const double* o = part + (k * L + l) * 3;
-        e0 += o[0];
-        e1 += o[1];
-        e2 += o[2];
-        cnt += __popc(pmask[k * L + l]);
+    for (int64_t k = tid + 256 * LB_MREG; k < KS || k < KSP; k += 256) {
+        if (k < KSP) {
+            const double* o = part + (k * L + l) * 3;
+            e0 += o[0];
+            e1 += o[1];
+            e2 += o[2];
+        }
+        if (k < KS) cnt += __popc(pmask[k * L + l]);
     }
     // near pairs: exclusive scan of the per-thread counts over the block (wave scans + one barrier)
     int incl = cnt;
@@ -445,9 +534,11 @@ __global__ void k_lb_iota(int32_t* __restrict__ act, int32_t* __restrict__ count
 }  // namespace
 
 // Duration (ms, best of 3 after a warm-up) of one far-field pass over L lines at the points pts
-// (FP64 or FP32 by the context's precision), split, or not with tile_lines lines per block:
+// (FP64 or FP32 by the context's precision), split, or not with tile_lines lines per block
+// (tile_lines = 0: the panel-stationary few-line pass); splitk waves per chunk when split:
 // used by the autotuner.
-double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, const double* pts, const double* sol) {
+double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int splitk, const double* pts,
+                     const double* sol) {
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t KS = ceil_div(N, LB_C);
@@ -461,14 +552,32 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, const do
     hipLaunchKernelGGL(k_lb_iota, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, act, cnt, L);
     BEM_CHECK_LAUNCH();
     const bool fp64 = c->opt.precision == BEM_FP64;
-    const int tile = split ? 64 : tile_lines;
+    const int tile = split ? 64 : (tile_lines > 0 ? tile_lines : 256);
     dim3 g1((unsigned)ceil_div(L, tile), (unsigned)KS);
+    const bool few = !split && tile_lines == 0;
+    if (few && L > LB_FEW) throw Error(BEM_ERR_INVALID, "few-line pass timed above its line limit");
     auto run = [&] {
+        if (few) {
+            if (fp64)
+                hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)(Np / 256)), dim3(256), 0, c->stream,
+                                   c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n,
+                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask);
+            else
+                hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)(Np / 256)), dim3(256), 0, c->stream,
+                                   c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n,
+                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask);
+            BEM_CHECK_LAUNCH();
+            return;
+        }
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
                        FR, Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask)
 #define BEM_LB_FAR_ALL(R, FR)                      \
-    if (split)                                     \
+    if (split && splitk == 2)                      \
+        BEM_LB_FAR(R, 2, 64, FR);                  \
+    else if (split && splitk == 4)                 \
+        BEM_LB_FAR(R, 4, 64, FR);                  \
+    else if (split)                                \
         BEM_LB_FAR(R, 8, 64, FR);                  \
     else if (tile == 64)                           \
         BEM_LB_FAR(R, 1, 64, FR);                  \
@@ -550,19 +659,26 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     int64_t known_active = L;   // upper bound on the active count (refreshed every 32 passes)
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
+        const bool few = known_active <= std::min<int64_t>(c->tune_trace_few, LB_FEW);
         const bool split = known_active <= c->tune_trace_split;
+        int64_t KSP = KS;   // partial rows the step kernel sums
         {
         // every 16th pass is timed: the event records would otherwise cost more than the short launches
         KTimer tf(c, "trace_far", (pass & 15) == 0);
         // blocks of tiles past the active count would only launch and exit: size the grids by
         // the last known active count (an upper bound, the count only falls)
         const int tile = split ? 64 : c->tune_trace_tile;
+        const int splitk = c->tune_trace_splitk;
         dim3 g1((unsigned)ceil_div(known_active, tile), (unsigned)KS);
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
                        FR, Np, N, sol, c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask)
 #define BEM_LB_FAR_ALL(R, FR)                      \
-    if (split)                                     \
+    if (split && splitk == 2)                      \
+        BEM_LB_FAR(R, 2, 64, FR);                  \
+    else if (split && splitk == 4)                 \
+        BEM_LB_FAR(R, 4, 64, FR);                  \
+    else if (split)                                \
         BEM_LB_FAR(R, 8, 64, FR);                  \
     else if (tile == 64)                           \
         BEM_LB_FAR(R, 1, 64, FR);                  \
@@ -570,7 +686,17 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         BEM_LB_FAR(R, 1, 128, FR);                 \
     else                                           \
         BEM_LB_FAR(R, 1, 256, FR)
-        if (fp64) {
+        if (few) {
+            KSP = Np / 256;
+            if (fp64)
+                hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)KSP), dim3(256), 0, c->stream,
+                                   c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n, line_rhs, L, act[cur],
+                                   cnt[cur], cnt[cur ^ 1], s.y, part, pmask);
+            else
+                hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)KSP), dim3(256), 0, c->stream,
+                                   c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n, line_rhs, L, act[cur],
+                                   cnt[cur], cnt[cur ^ 1], s.y, part, pmask);
+        } else if (fp64) {
             BEM_LB_FAR_ALL(double, c->far64.as<double>());
         } else {
             BEM_LB_FAR_ALL(float, c->far32.as<float>());
@@ -582,7 +708,8 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         }
         {
         KTimer ts(c, "trace_step", (pass & 15) == 0);
-        hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, KS, act[cur], cnt[cur],
+        hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, KS, KSP, act[cur],
+                           cnt[cur],
                            act[cur ^ 1], cnt[cur ^ 1], part, pmask, phase, s, a, c->tri64.as<double>(), sol, c->n,
                            line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,
                            integral, exceeds, path, pstride, near_count);
