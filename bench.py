@@ -35,6 +35,13 @@ if ROOT not in sys.path:
 #   sigma_j * F accumulation 6  -> field-only pair 141
 #   potential-only pair (assembly of S rows): 9 + 7 x (3 + 5 + 1 + 2) = 86
 FLOP_FIELD_PAIR = 141
+# HBM traffic of one k_lb_far launch (this workload, FP64, 8 waves per chunk): rocprofv3 FETCH_SIZE and
+# WRITE_SIZE per dispatch, averaged over the 5060 chunked passes of one step, scaled by the device-copy
+# calibration (FETCH x 2, WRITE x 1); see profiles/hbm_counters_coax20k.md.  Re-measure when the
+# kernel changes.
+K_LB_FAR_FETCH_KIB = 2601.5
+K_LB_FAR_WRITE_KIB = 3113.8
+K_LB_FAR_TRAFFIC_BYTES = (2.0 * K_LB_FAR_FETCH_KIB + 1.0 * K_LB_FAR_WRITE_KIB) * 1024.0
 FLOP_POT_PAIR = 86
 FP64_VALU_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -268,7 +275,7 @@ def main():
     # the library times every 16th launch (a uniform sample of the passes)
     tf_n, tf_ms = stats["trace_far"]
     far_launches = ctx.counter("trace_far_launches") / args.steps
-    far_pairs = pairs_lines - near_line_pairs          # regular pairs: the ones k_lb_far evaluates
+    far_pairs = ctx.counter("trace_far_pairs") / args.steps   # regular pairs of the far passes
     far_flop_per_launch = far_pairs * FLOP_FIELD_PAIR / far_launches
     far_avg_ms = tf_ms / max(tf_n, 1)
     achieved = far_flop_per_launch / (far_avg_ms * 1e-3) / 1e12
@@ -328,7 +335,8 @@ def main():
         "stop_code_counts": {str(k): int(np.sum(st_h == k)) for k in range(6)},
         "roofline": {"kernel": "k_lb_far (far-field pass of the field-line tracer, FP64)", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": K_LB_FAR_TRAFFIC_BYTES,
+                     "traffic_unit": "bytes per launch (HBM, counters)",
                      "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": far_pairs / far_launches,
                      "launches_per_step": far_launches, "avg_launch_ms": far_avg_ms},
         "trace_ms_per_step": trace_ms,

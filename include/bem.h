@@ -167,7 +167,7 @@ bem_status bem_eval_field(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t
                           const int32_t* on_panel, double* phi, double* E);
 
 /* Field lines dx/ds = direction * E/|E| by classical RK4 with step h, all
- * lines in one persistent launch.  A step whose segment [x_n, x_{n+1}]
+ * lines in one call ("trace_mode" picks the layout).  A step whose segment [x_n, x_{n+1}]
  * intersects a panel is discarded and the line stops with that panel's kind
  * (smallest segment parameter wins, then the lowest panel index).
  *  line_rhs dev [L] or NULL (all lines use load case 0): which sol row drives line l
@@ -215,9 +215,9 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
                              double tol, double* dJ_dvert, double* dJ_dV, double* dJ_dstart);
 
 /* Tuning knobs (no effect on results beyond summation order).
- *  "trace_mode": 0 = choose by line count, 1 = all lines advance together
- *                (one batched evaluation per RK4 stage, spread over the GPU),
- *                2 = one persistent launch, one workgroup per line.
+ *  "trace_mode": 0 (default) or 1 = all lines advance together (one batched
+ *                evaluation per RK4 stage, spread over the GPU), 2 = one
+ *                persistent launch, one workgroup per line.
  *  "batched_solve": 1 (default) = bem_solve_gmres with nrhs >= 2 runs up to 64
  *                independent GMRES recurrences together, one multi-right-hand-
  *                side matrix product per iteration on the matrix cores (FP64:
@@ -231,7 +231,7 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
  *  "trace_tile":  lines per block of an unsplit field-line pass (64, 128, 256; default 256)
  *  "trace_splitk": waves splitting each panel chunk in a split field-line pass (2, 4, 8; default 8)
  *  "trace_few":   live-line count at or below which a field-line pass is panel-stationary (one
- *                 lane per panel, all live lines per lane; 0..32; default 16)
+ *                 lane per panel, all live lines per lane; 0..16; default 8)
  *  "trace_split": live-line count at or below which a field-line pass splits each panel chunk
  *                 over eight waves (0..4096; default 64)
  *  "grad_batch":  points per batch of the pair passes of bem_streamer_grad (64..2^24; default
@@ -243,8 +243,9 @@ bem_status bem_set_tuning(bem_ctx* ctx, const char* key, int64_t value);
 bem_status bem_get_tuning(const bem_ctx* ctx, const char* key, int64_t* value);
 
 /* Autotuner for the tile shapes above: times each candidate on this context's
- * assembled problem (HIP events, best of three after a warm-up; ties to the
- * first candidate) and sets the fastest.  cache_path (host string, or NULL for
+ * assembled problem (HIP events, best of three after a warm-up) and sets the
+ * fastest; a candidate replaces the default only when it is more than 3 %
+ * faster, so that timing noise does not flip the choice between runs.  cache_path (host string, or NULL for
  * no cache): a JSON file keyed by device architecture, panel and unknown
  * counts, precision and eta; an entry for this key is used without timing,
  * otherwise the new choice is added and the file rewritten.  Tuning re-runs
@@ -260,7 +261,8 @@ bem_status bem_autotune(bem_ctx* ctx, const char* cache_path, int32_t* from_cach
  * "eval_near_csr", "eval_far", "eval_near", "trace" (a whole field-line call),
  * "trace_far" and "trace_step" (the two kernels of a batched pass; every 16th
  * pass is timed, so their launch counts are a sample and total_ms covers that
- * sample), "gemm_f32", "gemm_f64", "bgmres_iter". */
+ * sample), "gemm_f32", "gemm_f64", "bgmres_iter", "grad", "grad_reverse", "grad_rows_EH",
+ * "grad_panel_far", "grad_panel_near", "gemvT". */
 bem_status bem_set_profiling(bem_ctx* ctx, int32_t enable);
 bem_status bem_kernel_stats(bem_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
 bem_status bem_reset_stats(bem_ctx* ctx);   /* also zeroes the counters below */
@@ -268,7 +270,11 @@ bem_status bem_reset_stats(bem_ctx* ctx);   /* also zeroes the counters below */
 /* Work counters since creation or the last bem_reset_stats:
  * "trace_near_pairs"   = (point, panel) pairs of field-line evaluations that
  *                        took the closed-form (near) path in the batched layout;
- * "trace_far_launches" = far-field pass launches of the batched layout. */
+ * "trace_far_pairs"    = regular (7-point rule) pairs evaluated by the chunked
+ *                        far-field passes (k_lb_far) of the batched layout;
+ * "trace_far_launches" = launches of those chunked passes ("trace_far" times
+ *                        a sample of them); the panel-stationary few-line
+ *                        passes are in neither. */
 bem_status bem_get_counter(bem_ctx* ctx, const char* name, int64_t* value);
 
 #ifdef __cplusplus

@@ -560,7 +560,7 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"eval_blocks", &bem_ctx::tune_eval_blocks, 64, 65536, false},
         {"trace_split", &bem_ctx::tune_trace_split, 0, 4096, false},
         {"trace_tile", &bem_ctx::tune_trace_tile, 64, 256, true},
-        {"trace_few", &bem_ctx::tune_trace_few, 0, 32, false},
+        {"trace_few", &bem_ctx::tune_trace_few, 0, 16, false},
         {"trace_splitk", &bem_ctx::tune_trace_splitk, 2, 8, true},
         {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
@@ -642,6 +642,7 @@ bem_status bem_get_counter(bem_ctx* c, const char* name, int64_t* value) {
     }
     int idx = -1;
     if (std::strcmp(name, "trace_near_pairs") == 0) idx = 0;
+    if (std::strcmp(name, "trace_far_pairs") == 0) idx = 1;
     if (idx < 0) throw bem::Error(BEM_ERR_INVALID, std::string("unknown counter ") + name);
     uint64_t v = 0;
     BEM_HIP(hipMemcpyAsync(&v, c->counters.as<uint64_t>() + idx, sizeof(v), hipMemcpyDeviceToHost, c->stream));

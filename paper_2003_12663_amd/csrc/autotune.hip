@@ -11,10 +11,10 @@
 //   trace_split  live-line count at or below which a field-line pass splits each panel chunk over
 //                eight waves; the largest of {0, 32, 64, 128, 256} at which the split pass is faster
 //   trace_few    live-line count at or below which the panel-stationary pass is used: the largest
-//                of {0, 2, 4, 8, 16, 32} at which it beats the other passes
+//                of {0, 2, 4, 8, 16} at which its far part beats the other far passes
 // Each candidate runs once to warm up and is then timed three times with HIP
-// events on the context stream; the fastest (minimum) wins, ties to the first
-// candidate.  Cache: a JSON object keyed by "<arch> N=<panels> n=<unknowns>
+// events on the context stream (best of three); a candidate replaces the
+// default only when it is more than 3 % faster.  Cache: a JSON object keyed by "<arch> N=<panels> n=<unknowns>
 // precision=<0|1> eta=<eta>", one entry per line, read and rewritten whole.
 #include <algorithm>
 #include <cstdio>
@@ -75,18 +75,29 @@ double time_ms(bem_ctx* c, F&& f) {
     return best;
 }
 
-template <typename Set>
-int pick(bem_ctx* c, const std::vector<int>& cand, Set&& set_and_run) {
-    int best = cand[0];
-    double tb = 1e30;
-    for (int v : cand) {
-        const double t = time_ms(c, [&] { set_and_run(v); });
-        if (t < tb) {
-            tb = t;
-            best = v;
+// A candidate replaces the default only when it is faster by more than 3 %, so that timing
+// noise does not flip the choice between runs.
+constexpr double HYST = 0.97;
+
+int choose(const std::vector<int>& cand, const std::vector<double>& t, int dflt) {
+    double td = 1e30;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (cand[i] == dflt) td = t[i];
+    int best = dflt;
+    double tb = td;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (t[i] < HYST * td && t[i] < tb) {
+            tb = t[i];
+            best = cand[i];
         }
-    }
     return best;
+}
+
+template <typename Set>
+int pick(bem_ctx* c, const std::vector<int>& cand, int dflt, Set&& set_and_run) {
+    std::vector<double> t;
+    for (int v : cand) t.push_back(time_ms(c, [&] { set_and_run(v); }));
+    return choose(cand, t, dflt);
 }
 
 constexpr int NKNOB = 8;
@@ -142,7 +153,7 @@ bool valid_value(int k, int v) {
         case 4: return v == 64 || v == 128 || v == 256;
         case 5: return v == 2 || v == 4 || v == 8;
         case 6: return v >= 0 && v <= 4096;
-        default: return v >= 0 && v <= 32;
+        default: return v >= 0 && v <= 16;
     }
 }
 
@@ -186,13 +197,13 @@ int autotune(bem_ctx* c, const char* cache_path) {
         const int64_t nblk = ceil_div(N, 64);
         c->nearmask.alloc(sizeof(uint64_t) * nblk * N);
         if (c->opt.constraint_form == 0 && !c->h_rows_flt.empty()) c->Kf.alloc(sizeof(double) * c->h_rows_flt.size() * N);
-        c->tune_far_rows = pick(c, {32, 64, 128}, [&](int v) {
+        c->tune_far_rows = pick(c, {32, 64, 128}, 64, [&](int v) {
             c->tune_far_rows = v;
             launch_far_assemble(c);
         });
     }
     // matvec
-    c->tune_gemv_rows = pick(c, {2, 4, 8}, [&](int v) {
+    c->tune_gemv_rows = pick(c, {2, 4, 8}, 4, [&](int v) {
         c->tune_gemv_rows = v;
         launch_matvec(c, x.as<double>(), y.as<double>(), s);
     });
@@ -202,7 +213,7 @@ int autotune(bem_ctx* c, const char* cache_path) {
         hipLaunchKernelGGL(k_tune_fill_f, dim3((unsigned)ceil_div(64 * ld, 256)), dim3(256), 0, s, z.as<float>(),
                            64 * ld, 1.0f);
         BEM_CHECK_LAUNCH();
-        c->tune_gemm_blocks = pick(c, {512, 1024, 2048}, [&](int v) {
+        c->tune_gemm_blocks = pick(c, {512, 1024, 2048}, 1024, [&](int v) {
             c->tune_gemm_blocks = v;
             launch_gemm_f32(c, c->A32.as<float>(), ld, N, ld, z.as<float>(), ld, 64, y.as<double>(), ld, false);
         });
@@ -212,32 +223,20 @@ int autotune(bem_ctx* c, const char* cache_path) {
     hipLaunchKernelGGL(k_tune_points, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, c->tri64.as<double>(), N,
                        pts.as<double>());
     BEM_CHECK_LAUNCH();
-    c->tune_eval_blocks = pick(c, {1024, 2048, 4096}, [&](int v) {
+    c->tune_eval_blocks = pick(c, {1024, 2048, 4096}, 2048, [&](int v) {
         c->tune_eval_blocks = v;
         launch_eval(c, x.as<double>(), N, pts.as<double>(), nullptr, nullptr, y.as<double>());
     });
     // field-line pass: lines per block at 256 live lines, then split or not at 32..256 live lines
     {
         const int64_t Lt = std::min<int64_t>(N, 256);
-        int best_tile = 256;
-        double tb = 1e30;
-        for (int tile : {64, 128, 256}) {
-            const double t = time_far_pass(c, Lt, false, tile, 8, pts.as<double>(), x.as<double>());
-            if (t < tb) {
-                tb = t;
-                best_tile = tile;
-            }
-        }
+        std::vector<double> tt;
+        for (int tile : {64, 128, 256}) tt.push_back(time_far_pass(c, Lt, false, tile, 8, pts.as<double>(), x.as<double>()));
+        const int best_tile = choose({64, 128, 256}, tt, 256);
         c->tune_trace_tile = best_tile;
-        int best_k = 8;
-        tb = 1e30;
-        for (int k : {2, 4, 8}) {
-            const double t = time_far_pass(c, Lt, true, 64, k, pts.as<double>(), x.as<double>());
-            if (t < tb) {
-                tb = t;
-                best_k = k;
-            }
-        }
+        tt.clear();
+        for (int k : {2, 4, 8}) tt.push_back(time_far_pass(c, Lt, true, 64, k, pts.as<double>(), x.as<double>()));
+        const int best_k = choose({2, 4, 8}, tt, 8);
         c->tune_trace_splitk = best_k;
         int thr = 0;
         for (int64_t L : {32, 64, 128, 256}) {
@@ -248,7 +247,7 @@ int autotune(bem_ctx* c, const char* cache_path) {
         }
         c->tune_trace_split = thr;
         int few = 0;
-        for (int64_t L : {2, 4, 8, 16, 32}) {
+        for (int64_t L : {2, 4, 8, 16}) {
             if (L > N) break;
             const double t_few = time_far_pass(c, L, false, 0, best_k, pts.as<double>(), x.as<double>());
             const bool use_split = L <= thr;

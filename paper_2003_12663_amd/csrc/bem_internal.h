@@ -141,7 +141,7 @@ struct bem_ctx {
     int32_t tune_trace_split = 64;    // live-line count at or below which field-line passes split chunks
     int32_t tune_trace_tile = 256;    // lines per block of an unsplit field-line pass (64, 128, 256)
     int32_t tune_trace_splitk = 8;    // waves that split a panel chunk in a split field-line pass (2, 4, 8)
-    int32_t tune_trace_few = 16;      // live-line count at or below which the panel-stationary pass is used (<= 32)
+    int32_t tune_trace_few = 8;       // live-line count at or below which the panel-stationary pass is used (<= 16)
     int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
     // profiling

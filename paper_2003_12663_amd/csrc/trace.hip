@@ -356,8 +356,9 @@ void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const 
     if (L == 0) return;
     int cus = 0;
     BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-    // few lines cannot fill the GPU one workgroup per line: advance them together
-    const int mode = c->trace_mode != 0 ? c->trace_mode : (L <= 8 * (int64_t)cus ? 1 : 2);
+    // default: all lines advance together (measured faster than one workgroup per line for
+    // 4 to 4096 lines; the per-line layout is bound by per-CU load bandwidth)
+    const int mode = c->trace_mode != 0 ? c->trace_mode : 1;
     if (mode == 1) {
         launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds);
         return;

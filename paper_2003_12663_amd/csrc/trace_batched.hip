@@ -107,7 +107,8 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
                                                  int32_t nrhs, const int32_t* __restrict__ line_rhs, int64_t L,
                                                  const int32_t* __restrict__ act, const int32_t* __restrict__ count,
                                                  int32_t* __restrict__ count_next, const double* __restrict__ ys,
-                                                 double* __restrict__ part, uint32_t* __restrict__ pmask) {
+                                                 double* __restrict__ part, uint32_t* __restrict__ pmask,
+                                                 int32_t tiles, int64_t KS) {
     constexpr int NT = SPLIT > 1 ? 64 * SPLIT : TILE_LINES;   // threads per block
     constexpr int TILE = SPLIT > 1 ? 64 : TILE_LINES;         // lines per block
     constexpr int PER = LB_C / SPLIT;
@@ -117,11 +118,16 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     __shared__ double wred[SPLIT > 1 ? SPLIT : 1][64][3];
     __shared__ uint32_t wmask[SPLIT > 1 ? SPLIT : 1][64];
 
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) count_next[0] = 0;
+    // XCD-aware order: blocks are dealt to the 8 XCDs round-robin by linear id, so the tiles of
+    // one panel chunk get ids that are equal mod 8 and share one XCD's L2 for the chunk's records
+    const int64_t bid = blockIdx.x, xcd = bid & 7, m = bid >> 3;
+    const int64_t tile = m % tiles, chunk = 8 * (m / tiles) + xcd;
+    if (bid == 0 && threadIdx.x == 0) count_next[0] = 0;
+    if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
     const int32_t A = count[0];
-    const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+    const int64_t tile0 = tile * TILE;
     if (tile0 >= A) return;   // uniform over the block
-    const int64_t j0 = (int64_t)blockIdx.y * LB_C;
+    const int64_t j0 = chunk * LB_C;
     const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
     const bool sig_lds = nrhs <= LB_NRHS_LDS;
     for (int e = threadIdx.x; e < LB_C * 32; e += NT) {
@@ -194,11 +200,11 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     } else if (!live) {
         return;
     }
-    double* o = part + ((int64_t)blockIdx.y * L + l) * 3;
+    double* o = part + (chunk * L + l) * 3;
     o[0] = e0;
     o[1] = e1;
     o[2] = e2;
-    pmask[(int64_t)blockIdx.y * L + l] = nmask;
+    pmask[chunk * L + l] = nmask;
 }
 
 
@@ -294,7 +300,7 @@ constexpr int LB_MREG = 8;    // near masks per thread held in registers by k_lb
 // One block per active line: far partials + the line's near pairs (closed
 // forms, and the segment test on end-of-step passes) + the RK4 stage machine.
 __global__ __launch_bounds__(256) void k_lb_step(
-    int64_t L, int64_t KS, int64_t KSP, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+    int64_t L, int64_t N, int64_t KS, int64_t KSP, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
     int32_t* __restrict__ act_next, int32_t* __restrict__ count_next, const double* __restrict__ part,
     const uint32_t* __restrict__ pmask, int phase, LBState s, LBArgs a, const double* __restrict__ tri64,
     const double* __restrict__ sol, int64_t n, const int32_t* __restrict__ line_rhs,
@@ -359,7 +365,12 @@ __global__ __launch_bounds__(256) void k_lb_step(
     for (int w = 0; w < wv; ++w) wbase += scan[w];
     const int total = scan[0] + scan[1] + scan[2] + scan[3];
     const int off = wbase + incl - cnt;
-    if (tid == 0 && near_count) atomicAdd(near_count, (unsigned long long)total);
+    if (tid == 0 && near_count) {
+        atomicAdd(near_count, (unsigned long long)total);
+        // every other panel of this line was a regular pair of the chunked far pass (k_lb_far);
+        // the panel-stationary few-line pass (KSP != KS) is not counted
+        if (KSP == KS) atomicAdd(near_count + 1, (unsigned long long)(N - total));
+    }
     double n0 = 0.0, n1 = 0.0, n2 = 0.0, bt = 2.0;
     int bj = INT_MAX;
     for (int base = 0; base < total; base += LB_Q) {
@@ -553,7 +564,8 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
     BEM_CHECK_LAUNCH();
     const bool fp64 = c->opt.precision == BEM_FP64;
     const int tile = split ? 64 : (tile_lines > 0 ? tile_lines : 256);
-    dim3 g1((unsigned)ceil_div(L, tile), (unsigned)KS);
+    const int32_t ntile = (int32_t)ceil_div(L, tile);
+    dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
     const bool few = !split && tile_lines == 0;
     if (few && L > LB_FEW) throw Error(BEM_ERR_INVALID, "few-line pass timed above its line limit");
     auto run = [&] {
@@ -571,7 +583,8 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
         }
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
-                       FR, Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask)
+                       FR, Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, \
+                       ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -664,15 +677,17 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         int64_t KSP = KS;   // partial rows the step kernel sums
         {
         // every 16th pass is timed: the event records would otherwise cost more than the short launches
-        KTimer tf(c, "trace_far", (pass & 15) == 0);
+        KTimer tf(c, "trace_far", !few && (pass & 15) == 0);
         // blocks of tiles past the active count would only launch and exit: size the grids by
         // the last known active count (an upper bound, the count only falls)
         const int tile = split ? 64 : c->tune_trace_tile;
         const int splitk = c->tune_trace_splitk;
-        dim3 g1((unsigned)ceil_div(known_active, tile), (unsigned)KS);
+        const int32_t ntile = (int32_t)ceil_div(known_active, tile);
+        dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
-                       FR, Np, N, sol, c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask)
+                       FR, Np, N, sol, c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask, \
+                       ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -704,11 +719,11 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
 #undef BEM_LB_FAR_ALL
 #undef BEM_LB_FAR
         BEM_CHECK_LAUNCH();
-        ++c->trace_far_launches;
+        if (!few) ++c->trace_far_launches;
         }
         {
         KTimer ts(c, "trace_step", (pass & 15) == 0);
-        hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, KS, KSP, act[cur],
+        hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, N, KS, KSP, act[cur],
                            cnt[cur],
                            act[cur ^ 1], cnt[cur ^ 1], part, pmask, phase, s, a, c->tri64.as<double>(), sol, c->n,
                            line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,

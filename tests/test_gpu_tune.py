@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 CANDIDATES = {"far_rows": {32, 64, 128}, "gemv_rows": {2, 4, 8}, "gemm_blocks": {512, 1024, 2048},
               "eval_blocks": {1024, 2048, 4096}, "trace_tile": {64, 128, 256}, "trace_splitk": {2, 4, 8},
-              "trace_split": {0, 32, 64, 128, 256}, "trace_few": {0, 2, 4, 8, 16, 32}}
+              "trace_split": {0, 32, 64, 128, 256}, "trace_few": {0, 2, 4, 8, 16}}
 
 
 @pytest.fixture(scope="module")
