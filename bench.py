@@ -168,6 +168,40 @@ def cases_by_lines_run(bem, torch, p, ctx):
     return out
 
 
+def c3_run(bem, torch):
+    """Coax at ~60k panels: single-right-hand-side solve in FP64 (to 1e-10) and in the mixed mode
+    (FP64 refinement to 1e-8) from the assembled state, and the mixed errors on sigma and on |E|
+    at 1000 air-gap points (seed 3) against FP64."""
+    from workloads import coax_problem_for_size, gap_eval_points
+    p = coax_problem_for_size(60000)
+    N = p.n_tri
+    pts = torch.tensor(gap_eval_points(1000, seed=3), device="cuda")
+    out = {"panels": N}
+    res = {}
+    for name, prec, tol in (("fp64", bem.FP64, 1e-10), ("mixed", bem.MIXED, 1e-8)):
+        ctx = bem.Context.from_problem(p, precision=prec, eta=6.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.assemble()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sol, info = ctx.solve(p.body_V, tol=tol, max_iter=20000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, E = ctx.eval_field(sol, pts, want_phi=False)
+        res[name] = (sol[0, :N].clone(), torch.linalg.norm(E[0], dim=1))
+        out[name] = {"assemble_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"],
+                     "refinements": info["refinements"], "rel_residual": info["rel_residual"]}
+        ctx.close()
+        torch.cuda.empty_cache()
+    s64, e64 = res["fp64"]
+    sm, em = res["mixed"]
+    out["mixed_sigma_rel_err"] = float((sm - s64).abs().max() / s64.abs().max())
+    out["mixed_E_rel_err"] = float((em - e64).abs().max() / e64.abs().max())
+    out["solve_speedup_mixed_vs_fp64"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    return out
+
+
 def cpu_baseline(p, x, starts, args):
     """The oracle on a bounded sample: a block of matrix rows and a few short lines."""
     import oracle
@@ -224,7 +258,8 @@ def main():
         ctx.assemble()
         ctx.autotune(None)
         print(json.dumps({"gradient_coax_128_lines": gradient_run(bem, torch, p, ctx),
-                          "cases_64_x_lines_64": cases_by_lines_run(bem, torch, p, ctx)}))
+                          "cases_64_x_lines_64": cases_by_lines_run(bem, torch, p, ctx),
+                          "coax_60k_mixed_vs_fp64": c3_run(bem, torch)}))
         ctx.close()
         return
     # tile shapes for this problem, timed before the timed region (tuning re-assembles)
@@ -291,6 +326,7 @@ def main():
         print("[bench] gradient and 64 x 64 lines", file=sys.stderr, flush=True)
         extras["gradient_coax_128_lines"] = gradient_run(bem, torch, p, ctx)
         extras["cases_64_x_lines_64"] = cases_by_lines_run(bem, torch, p, ctx)
+        extras["coax_60k_mixed_vs_fp64"] = c3_run(bem, torch)
 
     tts = None
     if not args.no_tts:
