@@ -36,11 +36,11 @@ if ROOT not in sys.path:
 #   potential-only pair (assembly of S rows): 9 + 7 x (3 + 5 + 1 + 2) = 86
 FLOP_FIELD_PAIR = 141
 # HBM traffic of one k_lb_far launch (this workload, FP64, 8 waves per chunk): rocprofv3 FETCH_SIZE and
-# WRITE_SIZE per dispatch, averaged over the 5060 chunked passes of one step, scaled by the device-copy
+# WRITE_SIZE per dispatch, averaged over the 5024 chunked passes of one step, scaled by the device-copy
 # calibration (FETCH x 2, WRITE x 1); see profiles/hbm_counters_coax20k.md.  Re-measure when the
 # kernel changes.
-K_LB_FAR_FETCH_KIB = 2601.5
-K_LB_FAR_WRITE_KIB = 3113.8
+K_LB_FAR_FETCH_KIB = 5057.6
+K_LB_FAR_WRITE_KIB = 2852.8
 K_LB_FAR_TRAFFIC_BYTES = (2.0 * K_LB_FAR_FETCH_KIB + 1.0 * K_LB_FAR_WRITE_KIB) * 1024.0
 FLOP_POT_PAIR = 86
 FP64_VALU_PEAK_TFLOPS = 78.6
@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the gradient and the 64-load-case x 64-line runs")
     ap.add_argument("--extras-only", action="store_true", help="only the gradient and 4096-line runs")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (JSON): reuse one tile choice across runs, e.g. for counter runs")
+    ap.add_argument("--trace-groups", type=int, default=None,
+                    help="line groups of the field-line tracer (1..4; default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -264,9 +268,11 @@ def main():
         return
     # tile shapes for this problem, timed before the timed region (tuning re-assembles)
     ctx.assemble()
-    ctx.autotune(None)
+    ctx.autotune(args.tune_cache)
+    if args.trace_groups is not None:
+        ctx.set_tuning("trace_groups", args.trace_groups)
     tuning = {k: ctx.get_tuning(k) for k in ("far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile",
-                                              "trace_splitk", "trace_split", "trace_few")}
+                                              "trace_splitk", "trace_split", "trace_few", "trace_groups")}
 
     def step():
         ctx.assemble()

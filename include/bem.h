@@ -12,9 +12,11 @@
  *  - "host" pointers are CPU memory; "dev" pointers are device memory of the
  *    context's GPU (e.g. a torch tensor's data_ptr()).  The caller owns every
  *    array; no call keeps a caller pointer after it returns.
- *  - All device work is enqueued on the stream given to bem_create.  Calls
+ *  - All device work is ordered on the stream given to bem_create.  Calls
  *    that return host-side results (bem_solve_gmres's info, counts) wait for
- *    that stream.
+ *    that stream.  The batched field-line tracer also runs kernels on a second
+ *    stream of its own, ordered after the work already on the context stream
+ *    and joined back into it before the call returns.
  *  - Every call returns a bem_status; on failure bem_last_error() gives a
  *    thread-local message.  Inputs are validated before any kernel launch.
  *  - One context per host thread at a time; contexts are independent.
@@ -234,6 +236,14 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
  *                 lane per panel, all live lines per lane; 0..16; default 8)
  *  "trace_split": live-line count at or below which a field-line pass splits each panel chunk
  *                 over eight waves (0..4096; default 64)
+ *  "trace_groups": line groups of a batched field-line run (1 or 2; default 1): lines are cut
+ *                 into two contiguous halves that advance on two streams (the context stream
+ *                 and a second one the library owns), so that one group's step kernel overlaps
+ *                 the other group's far-field pass; the groups are folded into one once the live
+ *                 lines fit one 64-line tile.  Each group picks its pass layout
+ *                 ("trace_few", "trace_split") by its own live count, which can change the
+ *                 summation order of a line's far field; with the layout fixed (trace_few 0,
+ *                 trace_split 0 or above the line count) results do not depend on the grouping
  *  "grad_batch":  points per batch of the pair passes of bem_streamer_grad (64..2^24; default
  *                 131072; bounds scratch memory)
  * Errors: INVALID for an unknown key or value. */
@@ -255,8 +265,9 @@ bem_status bem_get_tuning(const bem_ctx* ctx, const char* key, int64_t* value);
  * invalid cache entry, unwritable file), HIP, OOM. */
 bem_status bem_autotune(bem_ctx* ctx, const char* cache_path, int32_t* from_cache);
 
-/* Per-kernel timing with HIP events recorded on the context stream around
- * each launch while enabled.  Names: "geometry", "far_assemble", "near_mask_csr",
+/* Per-kernel timing with HIP events recorded around each launch while
+ * enabled, on the stream of the launch (the context stream, or the tracer's
+ * second stream for its line groups).  Names: "geometry", "far_assemble", "near_mask_csr",
  * "near_assemble", "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
  * "eval_near_csr", "eval_far", "eval_near", "trace" (a whole field-line call),
  * "trace_far" and "trace_step" (the two kernels of a batched pass; every 16th

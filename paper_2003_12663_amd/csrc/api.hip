@@ -108,7 +108,8 @@ void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, c
 
 namespace bem {
 
-KTimer::KTimer(bem_ctx* ctx, const char* nm, bool enabled) : c(ctx), name(nm) {
+KTimer::KTimer(bem_ctx* ctx, const char* nm, bool enabled, hipStream_t st)
+    : c(ctx), name(nm), s(st ? st : ctx->stream) {
     if (!c->profiling || !enabled) return;
     auto get = [&]() {
         if (!c->event_pool.empty()) {
@@ -122,12 +123,12 @@ KTimer::KTimer(bem_ctx* ctx, const char* nm, bool enabled) : c(ctx), name(nm) {
     };
     a = get();
     b = get();
-    BEM_HIP(hipEventRecord(a, c->stream));
+    BEM_HIP(hipEventRecord(a, s));
 }
 
 KTimer::~KTimer() {
     if (!a) return;
-    if (hipEventRecord(b, c->stream) != hipSuccess) return;
+    if (hipEventRecord(b, s) != hipSuccess) return;
     c->pending.push_back({name, {a, b}});
     if (c->pending.size() > 4096) resolve_stats(c);
 }
@@ -273,6 +274,8 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     upload(c->gm_misc, scales.data(), scales.size(), s);
     c->far64.alloc(sizeof(double) * bem::FAR_REC * Np);
     c->far32.alloc(sizeof(float) * bem::FAR_REC * Np);
+    c->pan64.alloc(sizeof(double) * bem::FAR_REC * Np);
+    c->pan32.alloc(sizeof(float) * bem::FAR_REC * Np);
     c->tri64.alloc(sizeof(double) * bem::TRI_REC * c->N);
     c->counters.alloc(sizeof(uint64_t) * 8);
     BEM_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(uint64_t) * 8, s));
@@ -287,6 +290,7 @@ void bem_destroy(bem_ctx* c) {
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->aux_stream) (void)hipStreamSynchronize(c->aux_stream);
     delete c;
 }
 
@@ -562,6 +566,7 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"trace_tile", &bem_ctx::tune_trace_tile, 64, 256, true},
         {"trace_few", &bem_ctx::tune_trace_few, 0, 16, false},
         {"trace_splitk", &bem_ctx::tune_trace_splitk, 2, 8, true},
+        {"trace_groups", &bem_ctx::tune_trace_groups, 1, 2, false},
         {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
     for (const Knob& k : knobs)
@@ -587,6 +592,7 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     else if (std::strcmp(key, "trace_tile") == 0) *value = c->tune_trace_tile;
     else if (std::strcmp(key, "trace_few") == 0) *value = c->tune_trace_few;
     else if (std::strcmp(key, "trace_splitk") == 0) *value = c->tune_trace_splitk;
+    else if (std::strcmp(key, "trace_groups") == 0) *value = c->tune_trace_groups;
     else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
     return BEM_OK;
 }

@@ -79,6 +79,9 @@ struct HBuf {
 // Far-field record of one panel (FP64 or FP32), 32 values:
 //   [0..6] node x, [7..13] node y, [14..20] node z, [21..27] weight * area / (4 pi),
 //   [28..30] circumcentre, [31] (eta * R)^2.
+// Held component-major (far64/far32: value c of panel j at c * Np + j, for coalesced
+// one-panel-per-lane reads) and panel-major (pan64/pan32: at FAR_REC * j + c, for reads of a
+// whole record at a wave-uniform address through the scalar cache).
 constexpr int FAR_REC = 32;
 constexpr int FR_X = 0, FR_Y = 7, FR_Z = 14, FR_W = 21, FR_CC = 28, FR_RR = 31;
 // Exact-geometry record of one panel (FP64), 16 values:
@@ -96,6 +99,10 @@ struct KStat {
 struct bem_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream of the field-line tracer (line groups advance on both streams) and the
+    // events that order it after / before the context stream; created on first use
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     bem_options opt{};
     int64_t N = 0, n = 0, ld = 0, n_vert = 0;
     int32_t n_body = 0, n_float = 0;
@@ -108,6 +115,7 @@ struct bem_ctx {
 
     bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx;
     bem::DBuf far64, far32, tri64;
+    bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;
     bem::DBuf A64, A32, Kf;                 // dense operator (FP64 or FP32) and the K' block of floating rows
     bem::DBuf nearmask, near_ptr, near_row, near_col, near_val;
@@ -142,6 +150,7 @@ struct bem_ctx {
     int32_t tune_trace_tile = 256;    // lines per block of an unsplit field-line pass (64, 128, 256)
     int32_t tune_trace_splitk = 8;    // waves that split a panel chunk in a split field-line pass (2, 4, 8)
     int32_t tune_trace_few = 8;       // live-line count at or below which the panel-stationary pass is used (<= 16)
+    int32_t tune_trace_groups = 1;    // line groups of a field-line run, each on its own stream (1 or 2)
     int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
     // profiling
@@ -156,6 +165,9 @@ struct bem_ctx {
             (void)hipEventDestroy(p.second.second);
         }
         for (auto e : event_pool) (void)hipEventDestroy(e);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
+        if (aux_stream) (void)hipStreamDestroy(aux_stream);
     }
 };
 
@@ -166,8 +178,10 @@ namespace bem {
 struct KTimer {
     bem_ctx* c;
     const char* name;
+    hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    KTimer(bem_ctx* ctx, const char* nm, bool enabled = true);
+    // records on stream st (nullptr: the context stream)
+    KTimer(bem_ctx* ctx, const char* nm, bool enabled = true, hipStream_t st = nullptr);
     ~KTimer();
 };
 void resolve_stats(bem_ctx* c);

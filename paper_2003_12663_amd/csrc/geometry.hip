@@ -9,7 +9,8 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_geometry(const double* __restrict__ vert, const int32_t* __restrict__ tri,
                                                   int64_t N, int64_t Np, double eta, double* __restrict__ far64,
-                                                  float* __restrict__ far32, double* __restrict__ tri64) {
+                                                  float* __restrict__ far32, double* __restrict__ tri64,
+                                                  double* __restrict__ pan64, float* __restrict__ pan32) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Np) return;
     if (j >= N) {
@@ -19,6 +20,8 @@ __global__ __launch_bounds__(256) void k_geometry(const double* __restrict__ ver
             double v = (c == FR_RR) ? -1.0 : ((c < FR_W || c >= FR_CC) ? 1.0e30 : 0.0);
             far64[(int64_t)c * Np + j] = v;
             far32[(int64_t)c * Np + j] = (float)((c == FR_RR) ? -1.0 : ((c < FR_W || c >= FR_CC) ? 1.0e30 : 0.0));
+            pan64[FAR_REC * j + c] = v;
+            pan32[FAR_REC * j + c] = far32[(int64_t)c * Np + j];
         }
         return;
     }
@@ -84,6 +87,13 @@ __global__ __launch_bounds__(256) void k_geometry(const double* __restrict__ ver
     // the FP32 copy is never used to classify: kernels classify in FP64 or
     // with this value widened, so it only needs to be conservative
     far32[(int64_t)FR_RR * Np + j] = (float)rr;
+    // the same records panel-major (one 32-value record per panel), for kernels that read a
+    // panel's whole record at a wave-uniform address
+#pragma unroll
+    for (int c = 0; c < FAR_REC; ++c) {
+        pan64[FAR_REC * j + c] = far64[(int64_t)c * Np + j];
+        pan32[FAR_REC * j + c] = far32[(int64_t)c * Np + j];
+    }
 
     double* T = tri64 + (int64_t)TRI_REC * j;
 #pragma unroll
@@ -105,7 +115,8 @@ void launch_geometry(bem_ctx* c) {
     const int64_t Np = c->far64.bytes / (sizeof(double) * FAR_REC);
     dim3 grid((unsigned)ceil_div(Np, 256));
     hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, c->stream, c->vert.as<double>(), c->tri.as<int32_t>(), c->N, Np,
-                       c->opt.eta, c->far64.as<double>(), c->far32.as<float>(), c->tri64.as<double>());
+                       c->opt.eta, c->far64.as<double>(), c->far32.as<float>(), c->tri64.as<double>(),
+                       c->pan64.as<double>(), c->pan32.as<float>());
     BEM_CHECK_LAUNCH();
 }
 

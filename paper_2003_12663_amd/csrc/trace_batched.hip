@@ -5,13 +5,15 @@
 // stages depend on each other, so one line alone cannot fill the GPU.  Here
 // all active lines advance by one stage per pass, and a pass is one batched
 // evaluation spread over the whole GPU, in two launches:
-//  k_lb_far  - (line tile x panel chunk) blocks: a block stages a chunk of C
-//              panels in LDS (read by broadcast) and evaluates the regular
-//              pairs of 256 lines by the 7-point rule, one line per lane.
+//  k_lb_far  - (line tile x panel chunk) blocks: a block walks a chunk of C
+//              panels (each record read at a wave-uniform address into scalar
+//              registers) and evaluates the regular pairs of its lines by the
+//              7-point rule, one line per lane.
 //              Near pairs are not evaluated here (Sec. 4: near-singular pairs
 //              are marked and done after the regular ones); each lane records
-//              them in a bit mask.  Output per (chunk, line): partial field and
-//              near mask.
+//              them in a bit mask.  Output per (line, chunk): partial field and
+//              near mask, line-major (a line's KS partials are contiguous, so
+//              the step kernel reads them coalesced).
 //  k_lb_step - one block per active line: sums the partials in a fixed order,
 //              evaluates the line's near pairs with the closed forms (all 256
 //              threads, fixed-order sums, so runs are bitwise reproducible),
@@ -31,7 +33,6 @@ namespace bem {
 namespace {
 
 constexpr int LB_C = 32;         // panels per chunk
-constexpr int LB_NRHS_LDS = 64;  // load cases whose sigma chunk is staged in LDS
 
 struct LBArgs {
     double h, e_min, dir, a, e0, p, k_str;
@@ -76,11 +77,13 @@ __device__ __forceinline__ double lb_segment_tri(const double* __restrict__ T, d
     return t;
 }
 
-__global__ __launch_bounds__(256) void k_lb_init(int64_t L, const double* __restrict__ starts, LBState s,
+// Lines [g L / G, (g + 1) L / G) form group g; its active count is count[32 g] (the
+// identity list act[l] = l is every group's first active list at once).
+__global__ __launch_bounds__(256) void k_lb_init(int64_t L, int32_t G, const double* __restrict__ starts, LBState s,
                                                  int32_t* __restrict__ act, int32_t* __restrict__ count,
                                                  double* __restrict__ path, int64_t pstride) {
     const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (l == 0) count[0] = (int32_t)L;
+    if (l < G) count[32 * l] = (int32_t)((l + 1) * L / G - l * L / G);
     if (l >= L) return;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -101,27 +104,30 @@ __global__ __launch_bounds__(256) void k_lb_init(int64_t L, const double* __rest
 // SPLIT > 1: 64 lines per block (SPLIT waves); wave w walks panels
 // [w C/SPLIT, (w + 1) C/SPLIT) of the chunk and the partial fields are added
 // in wave order (for few lines: 1/SPLIT of the serial work per lane).
+// A wave walks its panels in step, so each panel's record (panel-major, pan64 /
+// panR) is read at a wave-uniform address: it comes through the scalar cache
+// into scalar registers, which the FP64 (or FP32) arithmetic takes as operands
+// directly; nothing is staged in LDS and no lane reads a record of its own.
 template <typename R, int SPLIT, int TILE_LINES>
-__global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(const double* __restrict__ far64, const R* __restrict__ farR,
-                                                 int64_t Np, int64_t N, const double* __restrict__ sol, int64_t n,
-                                                 int32_t nrhs, const int32_t* __restrict__ line_rhs, int64_t L,
+__global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(const double* __restrict__ pan64, const R* __restrict__ panR,
+                                                 int64_t N, const double* __restrict__ sol, int64_t n,
+                                                 const int32_t* __restrict__ line_rhs, int64_t L,
                                                  const int32_t* __restrict__ act, const int32_t* __restrict__ count,
                                                  int32_t* __restrict__ count_next, const double* __restrict__ ys,
                                                  double* __restrict__ part, uint32_t* __restrict__ pmask,
                                                  int32_t tiles, int64_t KS) {
-    constexpr int NT = SPLIT > 1 ? 64 * SPLIT : TILE_LINES;   // threads per block
     constexpr int TILE = SPLIT > 1 ? 64 : TILE_LINES;         // lines per block
     constexpr int PER = LB_C / SPLIT;
-    __shared__ R tq[LB_C][28];
-    __shared__ double tc[LB_C][4];
-    __shared__ double tsig[LB_NRHS_LDS][LB_C + 1];
     __shared__ double wred[SPLIT > 1 ? SPLIT : 1][64][3];
     __shared__ uint32_t wmask[SPLIT > 1 ? SPLIT : 1][64];
 
-    // XCD-aware order: blocks are dealt to the 8 XCDs round-robin by linear id, so the tiles of
-    // one panel chunk get ids that are equal mod 8 and share one XCD's L2 for the chunk's records
+    // XCD-aware order: blocks are dealt to the 8 XCDs round-robin by linear id; XCD x takes the
+    // contiguous chunk range [x CPX, (x + 1) CPX) (CPX = ceil(KS / 8)), all tiles of each.  So the
+    // tiles of one chunk share one XCD's L2 for the chunk's records, and each line's partials
+    // from one XCD form one contiguous run of its line-major row (whole cache lines written back)
     const int64_t bid = blockIdx.x, xcd = bid & 7, m = bid >> 3;
-    const int64_t tile = m % tiles, chunk = 8 * (m / tiles) + xcd;
+    const int64_t CPX = (KS + 7) >> 3;
+    const int64_t tile = m % tiles, chunk = xcd * CPX + m / tiles;
     if (bid == 0 && threadIdx.x == 0) count_next[0] = 0;
     if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
     const int32_t A = count[0];
@@ -129,22 +135,8 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     if (tile0 >= A) return;   // uniform over the block
     const int64_t j0 = chunk * LB_C;
     const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
-    const bool sig_lds = nrhs <= LB_NRHS_LDS;
-    for (int e = threadIdx.x; e < LB_C * 32; e += NT) {
-        const int pj = e % LB_C, comp = e / LB_C;
-        const int64_t j = j0 + pj;   // < Np (Np is N rounded up to 256)
-        if (comp < 28)
-            tq[pj][comp] = farR[(int64_t)comp * Np + j];
-        else
-            tc[pj][comp - 28] = far64[(int64_t)comp * Np + j];
-    }
-    if (sig_lds)
-        for (int e = threadIdx.x; e < nrhs * LB_C; e += NT) {
-            const int r = e / LB_C, pj = e % LB_C;
-            tsig[r][pj] = (pj < nc) ? sol[(int64_t)r * n + j0 + pj] : 0.0;
-        }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int64_t t = tile0 + (SPLIT > 1 ? lane : (int)threadIdx.x);
     const bool live = t < A;
     const int pj0 = SPLIT > 1 ? wv * PER : 0;
@@ -154,26 +146,32 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     int64_t l = 0;
     if (live) {
         l = act[t];
-        const int32_t rhs = line_rhs ? line_rhs[l] : 0;
+        const double* sig = sol + (line_rhs ? (int64_t)line_rhs[l] * n : 0);
         const double p0 = ys[3 * l], p1 = ys[3 * l + 1], p2 = ys[3 * l + 2];
         const R pr0 = (R)p0, pr1 = (R)p1, pr2 = (R)p2;
         for (int pj = pj0; pj < pj1; ++pj) {
-            if (!is_regular(p0 - tc[pj][0], p1 - tc[pj][1], p2 - tc[pj][2], tc[pj][3])) {
+            const int64_t j = j0 + pj;
+            const double* c64 = pan64 + FAR_REC * j;
+            const R* cq = panR + FAR_REC * j;
+            R qv[FR_CC];
+#pragma unroll
+            for (int k = 0; k < FR_CC; ++k) qv[k] = cq[k];
+            if (!is_regular(p0 - c64[FR_CC], p1 - c64[FR_CC + 1], p2 - c64[FR_CC + 2], c64[FR_RR])) {
                 nmask |= 1u << pj;
                 continue;
             }
             R f0 = 0, f1 = 0, f2 = 0;
 #pragma unroll
             for (int q = 0; q < 7; ++q) {
-                const R dx = pr0 - tq[pj][q], dy = pr1 - tq[pj][7 + q], dz = pr2 - tq[pj][14 + q];
+                const R dx = pr0 - qv[FR_X + q], dy = pr1 - qv[FR_Y + q], dz = pr2 - qv[FR_Z + q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
                 const R ir = rsqrt_pos(r2);
-                const R tw = tq[pj][21 + q] * ir * ir * ir;
+                const R tw = qv[FR_W + q] * ir * ir * ir;
                 f0 += tw * dx;
                 f1 += tw * dy;
                 f2 += tw * dz;
             }
-            const double sg = sig_lds ? tsig[rhs][pj] : sol[(int64_t)rhs * n + j0 + pj];
+            const double sg = sig[j];
             e0 = fma(sg, (double)f0, e0);
             e1 = fma(sg, (double)f1, e1);
             e2 = fma(sg, (double)f2, e2);
@@ -200,11 +198,11 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     } else if (!live) {
         return;
     }
-    double* o = part + (chunk * L + l) * 3;
+    double* o = part + (l * KS + chunk) * 3;
     o[0] = e0;
     o[1] = e1;
     o[2] = e2;
-    pmask[chunk * L + l] = nmask;
+    pmask[l * KS + chunk] = nmask;
 }
 
 
@@ -213,7 +211,7 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
 // record once and evaluates the regular pairs of all A <= LB_FEW lines; the
 // per-line sums are reduced over the block (fixed order), so there are
 // ceil(N/256) partial rows instead of one per 32-panel chunk, and the near bits
-// come from ballots in the same (chunk, line) mask layout as k_lb_far.
+// come from ballots in the same (line, chunk) mask layout as k_lb_far.
 constexpr int LB_FEW = 32;
 
 template <typename R>
@@ -222,7 +220,7 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
                                                     const int32_t* __restrict__ line_rhs, int64_t L,
                                                     const int32_t* __restrict__ act, const int32_t* __restrict__ count,
                                                     int32_t* __restrict__ count_next, const double* __restrict__ ys,
-                                                    double* __restrict__ part, uint32_t* __restrict__ pmask) {
+                                                    double* __restrict__ part, uint32_t* __restrict__ pmask, int64_t KS) {
     __shared__ double lp[LB_FEW][3];
     __shared__ int32_t lrow[LB_FEW];
     __shared__ double wred[4][3];
@@ -275,8 +273,8 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
         }
         // near bits: lanes 0..31 and 32..63 of the wave are two 32-panel chunks
         const int64_t c0 = (j - lane) / LB_C;
-        if (lane == 0 && ((j - lane) < N)) pmask[c0 * L + l] = (uint32_t)near;
-        if (lane == 32 && ((j - lane + 32) < N)) pmask[(c0 + 1) * L + l] = (uint32_t)(near >> 32);
+        if (lane == 0 && ((j - lane) < N)) pmask[l * KS + c0] = (uint32_t)near;
+        if (lane == 32 && ((j - lane + 32) < N)) pmask[l * KS + c0 + 1] = (uint32_t)(near >> 32);
         e0 = wave_sum(e0);
         e1 = wave_sum(e1);
         e2 = wave_sum(e2);
@@ -289,7 +287,7 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
         __syncthreads();
         if (threadIdx.x < 3) {
             const int c = threadIdx.x;
-            part[((int64_t)blockIdx.x * L + l) * 3 + c] = (wred[0][c] + wred[1][c]) + (wred[2][c] + wred[3][c]);
+            part[(l * KS + (int64_t)blockIdx.x) * 3 + c] = (wred[0][c] + wred[1][c]) + (wred[2][c] + wred[3][c]);
         }
     }
 }
@@ -334,23 +332,23 @@ __global__ __launch_bounds__(256) void k_lb_step(
         const int64_t k = tid + 256 * t;
         uint32_t m = 0;
         if (k < KSP) {
-            const double* o = part + (k * L + l) * 3;
+            const double* o = part + (l * KS + k) * 3;
             e0 += o[0];
             e1 += o[1];
             e2 += o[2];
         }
-        if (k < KS) m = pmask[k * L + l];
+        if (k < KS) m = pmask[l * KS + k];
         mreg[t] = m;
         cnt += __popc(m);
     }
     for (int64_t k = tid + 256 * LB_MREG; k < KS || k < KSP; k += 256) {
         if (k < KSP) {
-            const double* o = part + (k * L + l) * 3;
+            const double* o = part + (l * KS + k) * 3;
             e0 += o[0];
             e1 += o[1];
             e2 += o[2];
         }
-        if (k < KS) cnt += __popc(pmask[k * L + l]);
+        if (k < KS) cnt += __popc(pmask[l * KS + k]);
     }
     // near pairs: exclusive scan of the per-thread counts over the block (wave scans + one barrier)
     int incl = cnt;
@@ -390,7 +388,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
                 }
             }
             for (int64_t k = tid + 256 * LB_MREG; k < KS && pos < base + LB_Q; k += 256) {
-                uint32_t m = pmask[k * L + l];
+                uint32_t m = pmask[l * KS + k];
                 while (m) {
                     const int b = __builtin_ctz(m);
                     m &= m - 1;
@@ -537,6 +535,20 @@ __global__ __launch_bounds__(256) void k_lb_step(
 }  // namespace
 
 namespace {
+// Folds group 1's active list into group 0's (one block): group 0 keeps its n0 entries and
+// takes group 1's n1 after them.  The launcher calls it only when n0 + n1 fits group 0's
+// slice [0, lo1), so the destination [n0, n0 + n1) lies below the source [lo1, lo1 + n1).
+__global__ __launch_bounds__(256) void k_lb_merge(int32_t* __restrict__ act, int32_t* __restrict__ cnt0,
+                                                  int32_t* __restrict__ cnt1, int64_t lo1) {
+    const int32_t n0 = cnt0[0], n1 = cnt1[0];
+    __syncthreads();   // every thread has read the counts before thread 0 rewrites them
+    for (int32_t i = threadIdx.x; i < n1; i += 256) act[n0 + i] = act[lo1 + i];
+    if (threadIdx.x == 0) {
+        cnt0[0] = n0 + n1;
+        cnt1[0] = 0;
+    }
+}
+
 __global__ void k_lb_iota(int32_t* __restrict__ act, int32_t* __restrict__ count, int64_t L) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < L) act[i] = (int32_t)i;
@@ -573,18 +585,17 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
             if (fp64)
                 hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)(Np / 256)), dim3(256), 0, c->stream,
                                    c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n,
-                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask);
+                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, KS);
             else
                 hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)(Np / 256)), dim3(256), 0, c->stream,
                                    c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n,
-                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask);
+                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, KS);
             BEM_CHECK_LAUNCH();
             return;
         }
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
-    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
-                       FR, Np, N, sol, c->n, 1, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, \
-                       ntile, KS)
+    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->pan64.as<double>(), \
+                       FR, N, sol, c->n, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -599,9 +610,9 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
     else                                           \
         BEM_LB_FAR(R, 1, 256, FR)
         if (fp64) {
-            BEM_LB_FAR_ALL(double, c->far64.as<double>());
+            BEM_LB_FAR_ALL(double, c->pan64.as<double>());
         } else {
-            BEM_LB_FAR_ALL(float, c->far32.as<float>());
+            BEM_LB_FAR_ALL(float, c->pan32.as<float>());
         }
 #undef BEM_LB_FAR_ALL
 #undef BEM_LB_FAR
@@ -644,9 +655,16 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     a.p = tp->alpha_p;
     a.k_str = tp->k_str;
     a.max_steps = tp->max_steps;
-    // state: x, y, ks (3 each), asum, I; ns; two active lists and two counters
+    // Line groups: two contiguous ranges of lines, each with its own active lists and counters and
+    // its own stream.  A group's pass is its own far launch and step launch, so while one group's
+    // step kernel (a short chain of dependent loads over a few hundred blocks) runs, the other
+    // group's far pass fills the rest of the GPU.  State, partials and masks are indexed by line,
+    // so the groups share them without overlap.  Once the live lines fit one 64-line tile the
+    // groups are folded into one (two part-empty tiles would cost twice the blocks of one).
+    const int32_t G = (int32_t)std::min<int64_t>(c->tune_trace_groups, L);
+    // state: x, y, ks (3 each), asum, I; ns; two active lists; two counters per group
     const size_t dbl = (size_t)L * 11;
-    c->lb_state.alloc(sizeof(double) * dbl + sizeof(int32_t) * ((size_t)L * 3 + 64));
+    c->lb_state.alloc(sizeof(double) * dbl + sizeof(int32_t) * ((size_t)L * 3 + 32 * 4));
     c->lb_part.alloc(sizeof(double) * 3 * (size_t)KS * L + sizeof(uint32_t) * (size_t)KS * L);
     double* base = c->lb_state.as<double>();
     LBState s;
@@ -657,36 +675,82 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     s.I = base + 10 * L;
     int32_t* ib = reinterpret_cast<int32_t*>(base + dbl);
     s.ns = ib;
-    int32_t* act[2] = {ib + L, ib + 2 * L};
-    int32_t* cnt[2] = {ib + 3 * L, ib + 3 * L + 16};
+    int32_t* cnt0 = ib + 3 * L;
     double* part = c->lb_part.as<double>();
     uint32_t* pmask = reinterpret_cast<uint32_t*>(part + 3 * (size_t)KS * L);
-    hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, starts, s, act[0],
-                       cnt[0], path, pstride);
+    hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, G, starts, s, ib + L,
+                       cnt0, path, pstride);
     BEM_CHECK_LAUNCH();
+    struct Group {
+        int64_t lo, size, known;   // known: upper bound on the active count (refreshed every 32 passes)
+        int32_t* act[2];
+        int32_t* cnt[2];
+        hipStream_t st;
+    };
+    if (G > 1 && !c->aux_stream) {
+        BEM_HIP(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+        BEM_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        BEM_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    Group grp[2];
+    for (int32_t g = 0; g < G; ++g) {
+        Group& q = grp[g];
+        q.lo = g * L / G;
+        q.size = (g + 1) * L / G - q.lo;
+        q.known = q.size;
+        q.act[0] = ib + L + q.lo;
+        q.act[1] = ib + 2 * L + q.lo;
+        q.cnt[0] = cnt0 + 32 * g;
+        q.cnt[1] = cnt0 + 32 * g + 16;
+        q.st = (g & 1) ? c->aux_stream : c->stream;
+    }
+    if (G > 1) {   // the second stream starts after everything enqueued so far (init included)
+        BEM_HIP(hipEventRecord(c->fork_ev, c->stream));
+        BEM_HIP(hipStreamWaitEvent(c->aux_stream, c->fork_ev, 0));
+    }
+    // join on every exit (an error thrown by a launch included): later context-stream work sees
+    // everything the second stream wrote
+    struct Join {
+        bem_ctx* c;
+        bool on;
+        ~Join() {
+            if (on && hipEventRecord(c->join_ev, c->aux_stream) == hipSuccess)
+                (void)hipStreamWaitEvent(c->stream, c->join_ev, 0);
+        }
+    } join{c, G > 1};
     unsigned long long* near_count = reinterpret_cast<unsigned long long*>(c->counters.p);
     const bool fp64 = c->opt.precision == BEM_FP64;
     const int64_t max_pass = 4 * (int64_t)tp->max_steps + 1;
     int cur = 0;
     int32_t* host = c->host_stage.as<int32_t>();
-    int64_t known_active = L;   // upper bound on the active count (refreshed every 32 passes)
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
-        const bool few = known_active <= std::min<int64_t>(c->tune_trace_few, LB_FEW);
-        const bool split = known_active <= c->tune_trace_split;
-        int64_t KSP = KS;   // partial rows the step kernel sums
-        {
-        // every 16th pass is timed: the event records would otherwise cost more than the short launches
-        KTimer tf(c, "trace_far", !few && (pass & 15) == 0);
-        // blocks of tiles past the active count would only launch and exit: size the grids by
-        // the last known active count (an upper bound, the count only falls)
-        const int tile = split ? 64 : c->tune_trace_tile;
-        const int splitk = c->tune_trace_splitk;
-        const int32_t ntile = (int32_t)ceil_div(known_active, tile);
-        dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
-#define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
-    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->far64.as<double>(), \
-                       FR, Np, N, sol, c->n, nrhs, line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask, \
+        // every 16th pass is timed (the event records would otherwise cost more than the short
+        // launches); with two live groups that pass runs its launches one after another, so the
+        // timed far launches measure the kernel alone rather than its overlap with the other group
+        const bool timed = (pass & 15) == 0;
+        const bool serial = timed && G > 1 && grp[0].known > 0 && grp[1].known > 0;
+        for (int32_t g = 0; g < G; ++g) {
+            Group& q = grp[g];
+            if (q.known == 0) continue;
+            if (serial) {   // wait for everything enqueued on the other stream
+                BEM_HIP(hipEventRecord(c->fork_ev, grp[g ^ 1].st));
+                BEM_HIP(hipStreamWaitEvent(q.st, c->fork_ev, 0));
+            }
+            const bool few = q.known <= std::min<int64_t>(c->tune_trace_few, LB_FEW);
+            const bool split = q.known <= c->tune_trace_split;
+            int64_t KSP = KS;   // partial rows the step kernel sums
+            {
+            KTimer tf(c, "trace_far", !few && timed, q.st);
+            // blocks of tiles past the active count would only launch and exit: size the grids by
+            // the last known active count (an upper bound, the count only falls)
+            const int tile = split ? 64 : c->tune_trace_tile;
+            const int splitk = c->tune_trace_splitk;
+            const int32_t ntile = (int32_t)ceil_div(q.known, tile);
+            dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
+#define BEM_LB_FAR(R, SP, TL, FR)                                                                            \
+    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, c->pan64.as<double>(), \
+                       FR, N, sol, c->n, line_rhs, L, q.act[cur], q.cnt[cur], q.cnt[cur ^ 1], s.y, part, pmask,  \
                        ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
@@ -701,41 +765,59 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         BEM_LB_FAR(R, 1, 128, FR);                 \
     else                                           \
         BEM_LB_FAR(R, 1, 256, FR)
-        if (few) {
-            KSP = Np / 256;
-            if (fp64)
-                hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)KSP), dim3(256), 0, c->stream,
-                                   c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n, line_rhs, L, act[cur],
-                                   cnt[cur], cnt[cur ^ 1], s.y, part, pmask);
-            else
-                hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)KSP), dim3(256), 0, c->stream,
-                                   c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n, line_rhs, L, act[cur],
-                                   cnt[cur], cnt[cur ^ 1], s.y, part, pmask);
-        } else if (fp64) {
-            BEM_LB_FAR_ALL(double, c->far64.as<double>());
-        } else {
-            BEM_LB_FAR_ALL(float, c->far32.as<float>());
-        }
+            if (few) {
+                KSP = Np / 256;
+                if (fp64)
+                    hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)KSP), dim3(256), 0, q.st,
+                                       c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n, line_rhs, L,
+                                       q.act[cur], q.cnt[cur], q.cnt[cur ^ 1], s.y, part, pmask, KS);
+                else
+                    hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)KSP), dim3(256), 0, q.st,
+                                       c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n, line_rhs, L,
+                                       q.act[cur], q.cnt[cur], q.cnt[cur ^ 1], s.y, part, pmask, KS);
+            } else if (fp64) {
+                BEM_LB_FAR_ALL(double, c->pan64.as<double>());
+            } else {
+                BEM_LB_FAR_ALL(float, c->pan32.as<float>());
+            }
 #undef BEM_LB_FAR_ALL
 #undef BEM_LB_FAR
-        BEM_CHECK_LAUNCH();
-        if (!few) ++c->trace_far_launches;
-        }
-        {
-        KTimer ts(c, "trace_step", (pass & 15) == 0);
-        hipLaunchKernelGGL(k_lb_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, N, KS, KSP, act[cur],
-                           cnt[cur],
-                           act[cur ^ 1], cnt[cur ^ 1], part, pmask, phase, s, a, c->tri64.as<double>(), sol, c->n,
-                           line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,
-                           integral, exceeds, path, pstride, near_count);
-        BEM_CHECK_LAUNCH();
+            BEM_CHECK_LAUNCH();
+            if (!few) ++c->trace_far_launches;
+            }
+            {
+            KTimer ts(c, "trace_step", timed, q.st);
+            hipLaunchKernelGGL(k_lb_step, dim3((unsigned)q.known), dim3(256), 0, q.st, L, N, KS, KSP, q.act[cur],
+                               q.cnt[cur], q.act[cur ^ 1], q.cnt[cur ^ 1], part, pmask, phase, s, a,
+                               c->tri64.as<double>(), sol, c->n, line_rhs, c->tri_body.as<int32_t>(),
+                               c->body_kind.as<int32_t>(), n_steps, stop_code, integral, exceeds, path, pstride,
+                               near_count);
+            BEM_CHECK_LAUNCH();
+            }
         }
         cur ^= 1;
         if ((pass & 31) == 31 || pass == max_pass - 1) {
-            BEM_HIP(hipMemcpyAsync(host, cnt[cur], sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-            BEM_HIP(hipStreamSynchronize(c->stream));
-            if (host[0] == 0) break;
-            known_active = host[0];
+            int64_t live = 0;
+            for (int32_t g = 0; g < G; ++g)
+                if (grp[g].known > 0)
+                    BEM_HIP(hipMemcpyAsync(host + g, grp[g].cnt[cur], sizeof(int32_t), hipMemcpyDeviceToHost,
+                                           grp[g].st));
+            for (int32_t g = 0; g < G; ++g)
+                if (grp[g].known > 0) {
+                    BEM_HIP(hipStreamSynchronize(grp[g].st));
+                    grp[g].known = host[g];
+                    live += host[g];
+                }
+            if (live == 0) break;
+            // fold group 1 into group 0 once all live lines fit one tile and group 0's slice (both
+            // streams are idle here: the counts above were read after synchronising them)
+            if (G > 1 && grp[1].known > 0 && live <= std::min<int64_t>(64, grp[1].lo)) {
+                hipLaunchKernelGGL(k_lb_merge, dim3(1), dim3(256), 0, grp[0].st, grp[0].act[cur], grp[0].cnt[cur],
+                                   grp[1].cnt[cur], grp[1].lo);
+                BEM_CHECK_LAUNCH();
+                grp[0].known = live;
+                grp[1].known = 0;
+            }
         }
     }
 }

@@ -343,6 +343,48 @@ def test_trace_multi_rhs_lines(bem, mode):
     c.close()
 
 
+def test_trace_line_groups(bem):
+    """Lines cut into two groups on two streams, folded into one when few lines remain.  With
+    the pass layout fixed (chunked, or split, at every live count) a line's arithmetic does not
+    depend on the grouping, so step counts, stop codes, integrals and paths are bitwise equal to
+    the one-group run.  With the layout switching by live count, each group switches by its own
+    count, which moves only the summation order: those runs are checked against the oracle."""
+    p = coax_problem(0.012)
+    _say("line groups")
+    c, o, x, x_ref = _sigma_case(bem, p)
+    sol = torch.tensor(x, device="cuda")
+    starts, _, _ = electrode_line_starts(p, 37, seed=4)
+    params = dict(h=1e-3, max_steps=120)
+    tp = bem.trace_params(**params)
+    nso, sto, Io, patho = o.trace(x, starts, oracle.trace_params(**params), want_path=True)
+    assert len(set(sto.tolist())) >= 2, "the case must stop lines in more than one way"
+
+    def run(groups, few, split):
+        c.set_tuning("trace_groups", groups)
+        c.set_tuning("trace_few", few)
+        c.set_tuning("trace_split", split)
+        assert c.get_tuning("trace_groups") == groups
+        I, ns, st, _ = c.streamer_integral(sol, starts, tp)
+        ns2, st2, path = c.trace_lines(sol, starts, tp, want_path=True)
+        got = [t.cpu().numpy() for t in (I, ns, st, ns2, st2, path)]
+        assert np.array_equal(got[1], nso) and np.array_equal(got[2], sto), (groups, few, split)
+        assert np.array_equal(got[3], nso) and np.array_equal(got[4], sto), (groups, few, split)
+        assert np.abs(got[0] - Io).max() <= 1e-10 * np.abs(Io).max(), (groups, few, split)
+        for l in range(len(starts)):
+            m = nso[l] + 1
+            assert np.abs(got[5][l, :m] - patho[l, :m]).max() <= 1e-9 * np.abs(patho[l, :m]).max()
+        return got
+
+    for split in (0, 4096):   # always chunked, always split
+        ref = run(1, 0, split)
+        got = run(2, 0, split)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b, equal_nan=True), split   # paths are NaN past a line's end
+    for groups, few, split in [(2, 8, 16), (2, 16, 64), (2, 0, 64), (1, 8, 16)]:
+        run(groups, few, split)
+    c.close()
+
+
 def test_batched_matvec_mfma(bem):
     # the multi-vector product on the matrix cores against the oracle matrix
     for prec in (bem.FP64, bem.MIXED):

@@ -66,7 +66,7 @@ def test_tuning_knob_validation(bem):
     p = sphere_problem(1)
     ctx = bem.Context.from_problem(p)
     for key, bad in (("far_rows", 48), ("gemv_rows", 3), ("eval_blocks", 10), ("trace_split", -1),
-                     ("trace_tile", 96), ("grad_batch", 8), ("nope", 1)):
+                     ("trace_tile", 96), ("trace_groups", 0), ("trace_groups", 3), ("grad_batch", 8), ("nope", 1)):
         with pytest.raises(bem.BemError):
             ctx.set_tuning(key, bad)
     ctx.set_tuning("gemv_rows", 8)
