@@ -39,14 +39,23 @@ struct LBArgs {
     int32_t max_steps;
 };
 
+// One buffer of slot-indexed line state.  A live line sits in slot s of the current buffer
+// (slots [0, count) are live); each pass moves every line that goes on to the slot it draws in
+// the other buffer, so every kernel indexes by slot and nothing waits on an active-list lookup.
 struct LBState {
-    double* x;      // [L][3] current point
-    double* y;      // [L][3] query point of the pass
-    double* ks;     // [L][3] k1 + 2 k2 + 2 k3 + k4 so far
-    double* asum;   // [L] alpha sum of the stages
-    double* I;      // [L] integral
-    int32_t* ns;    // [L] accepted steps
+    double* x;       // [slots][3] current point
+    double* y;       // [slots][3] query point of the pass
+    double* ks;      // [slots][3] k1 + 2 k2 + 2 k3 + k4 so far
+    double* asum;    // [slots] alpha sum of the stages
+    double* I;       // [slots] integral
+    int32_t* ns;     // [slots] accepted steps
+    int32_t* line;   // [slots] line id held by the slot
 };
+
+// the same buffer seen from slot lo on (a line group's slot range)
+inline LBState lb_shift(LBState s, int64_t lo) {
+    return {s.x + 3 * lo, s.y + 3 * lo, s.ks + 3 * lo, s.asum + lo, s.I + lo, s.ns + lo, s.line + lo};
+}
 
 __device__ __noinline__ double lb_pow(double d, double p) { return pow(d, p); }
 
@@ -77,11 +86,11 @@ __device__ __forceinline__ double lb_segment_tri(const double* __restrict__ T, d
     return t;
 }
 
-// Lines [g L / G, (g + 1) L / G) form group g; its active count is count[32 g] (the
-// identity list act[l] = l is every group's first active list at once).
+// Lines [g L / G, (g + 1) L / G) form group g, in slots [g L / G, (g + 1) L / G) of buffer 0
+// at the start; its live count is count[32 g].
 __global__ __launch_bounds__(256) void k_lb_init(int64_t L, int32_t G, const double* __restrict__ starts, LBState s,
-                                                 int32_t* __restrict__ act, int32_t* __restrict__ count,
-                                                 double* __restrict__ path, int64_t pstride) {
+                                                 int32_t* __restrict__ count, double* __restrict__ path,
+                                                 int64_t pstride) {
     const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (l < G) count[32 * l] = (int32_t)((l + 1) * L / G - l * L / G);
     if (l >= L) return;
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(256) void k_lb_init(int64_t L, int32_t G, const dou
     s.asum[l] = 0.0;
     s.I[l] = 0.0;
     s.ns[l] = 0;
-    act[l] = (int32_t)l;
+    s.line[l] = (int32_t)l;
 }
 
 // SPLIT = 1: TILE_LINES (64, 128 or 256) lines per block, one per lane, every lane
@@ -111,11 +120,11 @@ __global__ __launch_bounds__(256) void k_lb_init(int64_t L, int32_t G, const dou
 template <typename R, int SPLIT, int TILE_LINES>
 __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(const double* __restrict__ pan64, const R* __restrict__ panR,
                                                  int64_t N, const double* __restrict__ sol, int64_t n,
-                                                 const int32_t* __restrict__ line_rhs, int64_t L,
-                                                 const int32_t* __restrict__ act, const int32_t* __restrict__ count,
-                                                 int32_t* __restrict__ count_next, const double* __restrict__ ys,
-                                                 double* __restrict__ part, uint32_t* __restrict__ pmask,
-                                                 int32_t tiles, int64_t KS) {
+                                                 const int32_t* __restrict__ line_rhs,
+                                                 const int32_t* __restrict__ line_of, int64_t cap,
+                                                 const int32_t* __restrict__ count, int32_t* __restrict__ count_next,
+                                                 const double* __restrict__ ys, double* __restrict__ part,
+                                                 uint32_t* __restrict__ pmask, int32_t tiles, int64_t KS) {
     constexpr int TILE = SPLIT > 1 ? 64 : TILE_LINES;         // lines per block
     constexpr int PER = LB_C / SPLIT;
     __shared__ double wred[SPLIT > 1 ? SPLIT : 1][64][3];
@@ -130,24 +139,25 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     const int64_t tile = m % tiles, chunk = xcd * CPX + m / tiles;
     if (bid == 0 && threadIdx.x == 0) count_next[0] = 0;
     if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
-    const int32_t A = count[0];
     const int64_t tile0 = tile * TILE;
-    if (tile0 >= A) return;   // uniform over the block
-    const int64_t j0 = chunk * LB_C;
-    const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int64_t t = tile0 + (SPLIT > 1 ? lane : (int)threadIdx.x);
+    // the slot's query point is read together with the live count (slot index clamped into the
+    // group's cap slots; a slot past the count is never used)
+    const int64_t tc = t < cap ? t : cap - 1;
+    const double p0 = ys[3 * tc], p1 = ys[3 * tc + 1], p2 = ys[3 * tc + 2];
+    const int32_t A = count[0];
+    if (tile0 >= A) return;   // uniform over the block
+    const int64_t j0 = chunk * LB_C;
+    const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
     const bool live = t < A;
     const int pj0 = SPLIT > 1 ? wv * PER : 0;
     const int pj1 = SPLIT > 1 ? (pj0 + PER < nc ? pj0 + PER : nc) : nc;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     uint32_t nmask = 0;
-    int64_t l = 0;
     if (live) {
-        l = act[t];
-        const double* sig = sol + (line_rhs ? (int64_t)line_rhs[l] * n : 0);
-        const double p0 = ys[3 * l], p1 = ys[3 * l + 1], p2 = ys[3 * l + 2];
+        const double* sig = sol + (line_rhs ? (int64_t)line_rhs[line_of[t]] * n : 0);
         const R pr0 = (R)p0, pr1 = (R)p1, pr2 = (R)p2;
         for (int pj = pj0; pj < pj1; ++pj) {
             const int64_t j = j0 + pj;
@@ -198,11 +208,11 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     } else if (!live) {
         return;
     }
-    double* o = part + (l * KS + chunk) * 3;
+    double* o = part + (t * KS + chunk) * 3;
     o[0] = e0;
     o[1] = e1;
     o[2] = e2;
-    pmask[l * KS + chunk] = nmask;
+    pmask[t * KS + chunk] = nmask;
 }
 
 
@@ -217,22 +227,24 @@ constexpr int LB_FEW = 32;
 template <typename R>
 __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ far64, const R* __restrict__ farR,
                                                     int64_t Np, int64_t N, const double* __restrict__ sol, int64_t n,
-                                                    const int32_t* __restrict__ line_rhs, int64_t L,
-                                                    const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+                                                    const int32_t* __restrict__ line_rhs,
+                                                    const int32_t* __restrict__ line_of, int64_t cap,
+                                                    const int32_t* __restrict__ count,
                                                     int32_t* __restrict__ count_next, const double* __restrict__ ys,
                                                     double* __restrict__ part, uint32_t* __restrict__ pmask, int64_t KS) {
     __shared__ double lp[LB_FEW][3];
-    __shared__ int32_t lrow[LB_FEW];
-    __shared__ double wred[4][3];
+    __shared__ int32_t lrhs[LB_FEW];
+    __shared__ double wred[4][LB_FEW][3];
     if (blockIdx.x == 0 && threadIdx.x == 0) count_next[0] = 0;
-    const int32_t A = count[0] < LB_FEW ? count[0] : LB_FEW;   // the launcher guarantees count <= LB_FEW
-    if (threadIdx.x < A) {
-        const int64_t l = act[threadIdx.x];
-        lrow[threadIdx.x] = (int32_t)l;
-        lp[threadIdx.x][0] = ys[3 * l];
-        lp[threadIdx.x][1] = ys[3 * l + 1];
-        lp[threadIdx.x][2] = ys[3 * l + 2];
+    if (threadIdx.x < LB_FEW) {   // slot query points, read together with the live count
+        const int64_t t = threadIdx.x < cap ? threadIdx.x : cap - 1;
+        lp[threadIdx.x][0] = ys[3 * t];
+        lp[threadIdx.x][1] = ys[3 * t + 1];
+        lp[threadIdx.x][2] = ys[3 * t + 2];
     }
+    const int32_t A = count[0] < LB_FEW ? count[0] : LB_FEW;   // the launcher guarantees count <= LB_FEW
+    // a slot's line id is valid only below the live count
+    if (threadIdx.x < A) lrhs[threadIdx.x] = line_rhs ? line_rhs[line_of[threadIdx.x]] : 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;   // < Np (grid covers N rounded up to 256)
@@ -248,7 +260,6 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
     const double ccx = far64[(int64_t)(FR_CC + 0) * Np + j], ccy = far64[(int64_t)(FR_CC + 1) * Np + j];
     const double ccz = far64[(int64_t)(FR_CC + 2) * Np + j], rr = far64[(int64_t)FR_RR * Np + j];
     for (int t = 0; t < A; ++t) {
-        const int64_t l = lrow[t];
         const double p0 = lp[t][0], p1 = lp[t][1], p2 = lp[t][2];
         const bool reg = valid && is_regular(p0 - ccx, p1 - ccy, p2 - ccz, rr);
         const uint64_t near = __ballot(valid && !reg);
@@ -266,64 +277,65 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
                 f1 += tw * dy;
                 f2 += tw * dz;
             }
-            const double sg = sol[(line_rhs ? (int64_t)line_rhs[l] : 0) * n + j];
+            const double sg = sol[(int64_t)lrhs[t] * n + j];
             e0 = sg * (double)f0;
             e1 = sg * (double)f1;
             e2 = sg * (double)f2;
         }
         // near bits: lanes 0..31 and 32..63 of the wave are two 32-panel chunks
         const int64_t c0 = (j - lane) / LB_C;
-        if (lane == 0 && ((j - lane) < N)) pmask[l * KS + c0] = (uint32_t)near;
-        if (lane == 32 && ((j - lane + 32) < N)) pmask[l * KS + c0 + 1] = (uint32_t)(near >> 32);
+        if (lane == 0 && ((j - lane) < N)) pmask[t * KS + c0] = (uint32_t)near;
+        if (lane == 32 && ((j - lane + 32) < N)) pmask[t * KS + c0 + 1] = (uint32_t)(near >> 32);
         e0 = wave_sum(e0);
         e1 = wave_sum(e1);
         e2 = wave_sum(e2);
-        __syncthreads();
-        if (lane == 0) {
-            wred[wv][0] = e0;
-            wred[wv][1] = e1;
-            wred[wv][2] = e2;
+        if (lane == 0) {   // one slot per (wave, line): no barrier inside the line loop
+            wred[wv][t][0] = e0;
+            wred[wv][t][1] = e1;
+            wred[wv][t][2] = e2;
         }
-        __syncthreads();
-        if (threadIdx.x < 3) {
-            const int c = threadIdx.x;
-            part[(l * KS + (int64_t)blockIdx.x) * 3 + c] = (wred[0][c] + wred[1][c]) + (wred[2][c] + wred[3][c]);
-        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 * A) {
+        const int t = threadIdx.x / 3, c = threadIdx.x % 3;
+        part[((int64_t)t * KS + blockIdx.x) * 3 + c] = (wred[0][t][c] + wred[1][t][c]) + (wred[2][t][c] + wred[3][t][c]);
     }
 }
 
 constexpr int LB_Q = 1024;    // near pairs per round in k_lb_step
 constexpr int LB_MREG = 8;    // near masks per thread held in registers by k_lb_step (KS <= 2048)
 
-// One block per active line: far partials + the line's near pairs (closed
-// forms, and the segment test on end-of-step passes) + the RK4 stage machine.
+// One block per live slot: far partials + the line's near pairs (closed forms, and the
+// segment test on end-of-step passes) + the RK4 stage machine.  Everything the block needs
+// first (the live count, the slot's state, its partial row and masks) is indexed by the slot
+// alone, so those loads go out together; a line that goes on is written whole to the slot it
+// draws in the next buffer.
 __global__ __launch_bounds__(256) void k_lb_step(
-    int64_t L, int64_t N, int64_t KS, int64_t KSP, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
-    int32_t* __restrict__ act_next, int32_t* __restrict__ count_next, const double* __restrict__ part,
-    const uint32_t* __restrict__ pmask, int phase, LBState s, LBArgs a, const double* __restrict__ tri64,
-    const double* __restrict__ sol, int64_t n, const int32_t* __restrict__ line_rhs,
-    const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind, int32_t* __restrict__ n_steps,
-    int32_t* __restrict__ stop_code, double* __restrict__ integral, uint8_t* __restrict__ exceeds,
-    double* __restrict__ path, int64_t pstride, unsigned long long* __restrict__ near_count) {
+    int64_t N, int64_t KS, int64_t KSP, const int32_t* __restrict__ count, int32_t* __restrict__ count_next,
+    const double* __restrict__ part, const uint32_t* __restrict__ pmask, int phase, LBState cur, LBState nxt,
+    LBArgs a, const double* __restrict__ tri64, const double* __restrict__ sol, int64_t n,
+    const int32_t* __restrict__ line_rhs, const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind,
+    int32_t* __restrict__ n_steps, int32_t* __restrict__ stop_code, double* __restrict__ integral,
+    uint8_t* __restrict__ exceeds, double* __restrict__ path, int64_t pstride,
+    unsigned long long* __restrict__ near_count) {
     __shared__ int32_t list[LB_Q];
     __shared__ int32_t scan[4];
     __shared__ double red[4][4];
     __shared__ int32_t redj[4];
-    const int32_t A = count[0];
-    if ((int64_t)blockIdx.x >= A) return;
-    const int64_t l = act[blockIdx.x];
+    const int64_t b = blockIdx.x;   // < the group's slot count (the grid is sized by an upper bound)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    const double* sigma = sol + (line_rhs ? (int64_t)line_rhs[l] : 0) * n;
-    const double p0 = s.y[3 * l], p1 = s.y[3 * l + 1], p2 = s.y[3 * l + 2];
-    const double q0 = s.x[3 * l], q1 = s.x[3 * l + 1], q2 = s.x[3 * l + 2];
-    const bool hit_pass = (phase == 4);
-    // the line's stage-machine state, read early so that its latency overlaps the sums below
-    const int32_t ns0 = s.ns[l];
-    const double asum0 = s.asum[l], I0 = s.I[l];
-    const double ks0 = s.ks[3 * l], ks1 = s.ks[3 * l + 1], ks2 = s.ks[3 * l + 2];
-    // far partials (fixed order per thread) and near masks in one sweep; the first LB_MREG masks
-    // of each thread stay in registers for the list fill below
+    // slot state (a slot past the live count holds stale values that are never used)
+    const int64_t l = cur.line[b];
+    const double p0 = cur.y[3 * b], p1 = cur.y[3 * b + 1], p2 = cur.y[3 * b + 2];
+    const double q0 = cur.x[3 * b], q1 = cur.x[3 * b + 1], q2 = cur.x[3 * b + 2];
+    const int32_t ns0 = cur.ns[b];
+    const double asum0 = cur.asum[b], I0 = cur.I[b];
+    const double ks0 = cur.ks[3 * b], ks1 = cur.ks[3 * b + 1], ks2 = cur.ks[3 * b + 2];
+    // far partials (fixed order per thread) and near masks in one sweep of the slot's contiguous
+    // row; the first LB_MREG masks of each thread stay in registers for the list fill below
+    const double* prow = part + b * KS * 3;
+    const uint32_t* mrow = pmask + b * KS;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     uint32_t mreg[LB_MREG];
     int cnt = 0;
@@ -332,24 +344,26 @@ __global__ __launch_bounds__(256) void k_lb_step(
         const int64_t k = tid + 256 * t;
         uint32_t m = 0;
         if (k < KSP) {
-            const double* o = part + (l * KS + k) * 3;
-            e0 += o[0];
-            e1 += o[1];
-            e2 += o[2];
+            e0 += prow[3 * k];
+            e1 += prow[3 * k + 1];
+            e2 += prow[3 * k + 2];
         }
-        if (k < KS) m = pmask[l * KS + k];
+        if (k < KS) m = mrow[k];
         mreg[t] = m;
         cnt += __popc(m);
     }
     for (int64_t k = tid + 256 * LB_MREG; k < KS || k < KSP; k += 256) {
         if (k < KSP) {
-            const double* o = part + (l * KS + k) * 3;
-            e0 += o[0];
-            e1 += o[1];
-            e2 += o[2];
+            e0 += prow[3 * k];
+            e1 += prow[3 * k + 1];
+            e2 += prow[3 * k + 2];
         }
-        if (k < KS) cnt += __popc(pmask[l * KS + k]);
+        if (k < KS) cnt += __popc(mrow[k]);
     }
+    const int32_t A = count[0];
+    if (b >= A) return;   // uniform over the block
+    const double* sigma = sol + (line_rhs ? (int64_t)line_rhs[l] : 0) * n;
+    const bool hit_pass = (phase == 4);
     // near pairs: exclusive scan of the per-thread counts over the block (wave scans + one barrier)
     int incl = cnt;
 #pragma unroll
@@ -381,18 +395,18 @@ __global__ __launch_bounds__(256) void k_lb_step(
                 uint32_t m = mreg[t];
                 const int64_t k = tid + 256 * t;
                 while (m) {
-                    const int b = __builtin_ctz(m);
+                    const int bb = __builtin_ctz(m);
                     m &= m - 1;
-                    if (pos >= base && pos < base + LB_Q) list[pos - base] = (int32_t)(k * LB_C + b);
+                    if (pos >= base && pos < base + LB_Q) list[pos - base] = (int32_t)(k * LB_C + bb);
                     ++pos;
                 }
             }
             for (int64_t k = tid + 256 * LB_MREG; k < KS && pos < base + LB_Q; k += 256) {
-                uint32_t m = pmask[l * KS + k];
+                uint32_t m = mrow[k];
                 while (m) {
-                    const int b = __builtin_ctz(m);
+                    const int bb = __builtin_ctz(m);
                     m &= m - 1;
-                    if (pos >= base && pos < base + LB_Q) list[pos - base] = (int32_t)(k * LB_C + b);
+                    if (pos >= base && pos < base + LB_Q) list[pos - base] = (int32_t)(k * LB_C + bb);
                     ++pos;
                 }
             }
@@ -455,7 +469,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
         hit = (jb != INT_MAX) ? jb : -1;
     }
     const double h = a.h;
-    double x0 = q0, x1 = q1, x2 = q2;
+    double x0 = q0, x1 = q1, x2 = q2, I = I0;
     int32_t ns = ns0;
     int code = -1;   // -1: the line goes on
     if (hit_pass) {
@@ -463,16 +477,12 @@ __global__ __launch_bounds__(256) void k_lb_step(
             const int32_t k = body_kind[tri_body[hit]];
             code = (k == BEM_DIRICHLET) ? BEM_STOP_DIRICHLET
                                         : ((k == BEM_FLOATING) ? BEM_STOP_FLOATING : BEM_STOP_INTERFACE);
-        } else {
-            s.I[l] = I0 + h / 6.0 * asum0;
+        } else {   // the step is accepted: its end point becomes the line's point
+            I = I0 + h / 6.0 * asum0;
             x0 = p0;
             x1 = p1;
             x2 = p2;
-            s.x[3 * l] = x0;
-            s.x[3 * l + 1] = x1;
-            s.x[3 * l + 2] = x2;
             ++ns;
-            s.ns[l] = ns;
             if (path) {
                 path[l * pstride + 3 * ns + 0] = x0;
                 path[l * pstride + 3 * ns + 1] = x1;
@@ -481,78 +491,99 @@ __global__ __launch_bounds__(256) void k_lb_step(
             if (ns >= a.max_steps) code = BEM_STOP_MAXSTEPS;
         }
     }
+    double k0 = 0.0, k1 = 0.0, k2 = 0.0, asum = 0.0, y0 = 0.0, y1 = 0.0, y2 = 0.0;
     if (code < 0) {
         const double m = sqrt(F0 * F0 + F1 * F1 + F2 * F2);
-        const double k0 = a.dir * F0 / m, k1 = a.dir * F1 / m, k2 = a.dir * F2 / m;
-        double* ks = s.ks + 3 * l;
-        double* y = s.y + 3 * l;
+        const double d0 = a.dir * F0 / m, d1 = a.dir * F1 / m, d2 = a.dir * F2 / m;
         if (phase == 0 || phase == 4) {
             if (!isfinite(m))
                 code = BEM_STOP_NONFINITE;
             else if (m < a.e_min)
                 code = BEM_STOP_WEAK;
             else {
-                ks[0] = k0;
-                ks[1] = k1;
-                ks[2] = k2;
-                s.asum[l] = lb_alpha(a, m);
-                y[0] = x0 + 0.5 * h * k0;
-                y[1] = x1 + 0.5 * h * k1;
-                y[2] = x2 + 0.5 * h * k2;
+                k0 = d0;
+                k1 = d1;
+                k2 = d2;
+                asum = lb_alpha(a, m);
+                y0 = x0 + 0.5 * h * d0;
+                y1 = x1 + 0.5 * h * d1;
+                y2 = x2 + 0.5 * h * d2;
             }
         } else if (phase < 3) {
-            ks[0] = ks0 + 2.0 * k0;
-            ks[1] = ks1 + 2.0 * k1;
-            ks[2] = ks2 + 2.0 * k2;
-            s.asum[l] = asum0 + 2.0 * lb_alpha(a, m);
+            k0 = ks0 + 2.0 * d0;
+            k1 = ks1 + 2.0 * d1;
+            k2 = ks2 + 2.0 * d2;
+            asum = asum0 + 2.0 * lb_alpha(a, m);
             const double c = (phase == 1) ? 0.5 * h : h;
-            y[0] = x0 + c * k0;
-            y[1] = x1 + c * k1;
-            y[2] = x2 + c * k2;
+            y0 = x0 + c * d0;
+            y1 = x1 + c * d1;
+            y2 = x2 + c * d2;
         } else {
-            const double t0 = ks0 + k0, t1 = ks1 + k1, t2 = ks2 + k2;
-            ks[0] = t0;
-            ks[1] = t1;
-            ks[2] = t2;
-            s.asum[l] = asum0 + lb_alpha(a, m);
-            y[0] = x0 + h / 6.0 * t0;
-            y[1] = x1 + h / 6.0 * t1;
-            y[2] = x2 + h / 6.0 * t2;
-            if (!(isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]))) code = BEM_STOP_NONFINITE;
+            k0 = ks0 + d0;
+            k1 = ks1 + d1;
+            k2 = ks2 + d2;
+            asum = asum0 + lb_alpha(a, m);
+            y0 = x0 + h / 6.0 * k0;
+            y1 = x1 + h / 6.0 * k1;
+            y2 = x2 + h / 6.0 * k2;
+            if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) code = BEM_STOP_NONFINITE;
         }
     }
     if (code >= 0) {
         n_steps[l] = ns;
         stop_code[l] = code;
-        const double Iend = (hit_pass && hit < 0) ? I0 + h / 6.0 * asum0 : I0;
-        if (integral) integral[l] = Iend;
-        if (exceeds) exceeds[l] = (Iend > a.k_str) ? 1 : 0;
+        if (integral) integral[l] = I;
+        if (exceeds) exceeds[l] = (I > a.k_str) ? 1 : 0;
     } else {
-        act_next[atomicAdd(count_next, 1)] = (int32_t)l;
+        const int32_t sn = atomicAdd(count_next, 1);
+        nxt.x[3 * sn] = x0;
+        nxt.x[3 * sn + 1] = x1;
+        nxt.x[3 * sn + 2] = x2;
+        nxt.y[3 * sn] = y0;
+        nxt.y[3 * sn + 1] = y1;
+        nxt.y[3 * sn + 2] = y2;
+        nxt.ks[3 * sn] = k0;
+        nxt.ks[3 * sn + 1] = k1;
+        nxt.ks[3 * sn + 2] = k2;
+        nxt.asum[sn] = asum;
+        nxt.I[sn] = I;
+        nxt.ns[sn] = ns;
+        nxt.line[sn] = (int32_t)l;
     }
 }
 
 }  // namespace
 
 namespace {
-// Folds group 1's active list into group 0's (one block): group 0 keeps its n0 entries and
-// takes group 1's n1 after them.  The launcher calls it only when n0 + n1 fits group 0's
-// slice [0, lo1), so the destination [n0, n0 + n1) lies below the source [lo1, lo1 + n1).
-__global__ __launch_bounds__(256) void k_lb_merge(int32_t* __restrict__ act, int32_t* __restrict__ cnt0,
-                                                  int32_t* __restrict__ cnt1, int64_t lo1) {
+// Folds group 1's live slots into group 0's (one block): group 0 keeps its n0 slots and takes
+// group 1's n1 after them, whole states moved.  The launcher calls it only when n0 + n1 fits
+// group 0's slot range [0, lo1), so the destination [n0, n0 + n1) lies below the source
+// [lo1, lo1 + n1).
+__global__ __launch_bounds__(256) void k_lb_merge(LBState s, int32_t* __restrict__ cnt0, int32_t* __restrict__ cnt1,
+                                                  int64_t lo1) {
     const int32_t n0 = cnt0[0], n1 = cnt1[0];
     __syncthreads();   // every thread has read the counts before thread 0 rewrites them
-    for (int32_t i = threadIdx.x; i < n1; i += 256) act[n0 + i] = act[lo1 + i];
+    for (int32_t i = threadIdx.x; i < n1; i += 256) {
+        const int64_t d = n0 + i, r = lo1 + i;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s.x[3 * d + k] = s.x[3 * r + k];
+            s.y[3 * d + k] = s.y[3 * r + k];
+            s.ks[3 * d + k] = s.ks[3 * r + k];
+        }
+        s.asum[d] = s.asum[r];
+        s.I[d] = s.I[r];
+        s.ns[d] = s.ns[r];
+        s.line[d] = s.line[r];
+    }
     if (threadIdx.x == 0) {
         cnt0[0] = n0 + n1;
         cnt1[0] = 0;
     }
 }
 
-__global__ void k_lb_iota(int32_t* __restrict__ act, int32_t* __restrict__ count, int64_t L) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < L) act[i] = (int32_t)i;
-    if (i == 0) count[0] = (int32_t)L;
+__global__ void k_lb_set_count(int32_t* __restrict__ count, int32_t v) {
+    if (threadIdx.x == 0) count[0] = v;
 }
 }  // namespace
 
@@ -565,14 +596,13 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t KS = ceil_div(N, LB_C);
-    c->lb_state.alloc(sizeof(double) * (size_t)L * 11 + sizeof(int32_t) * ((size_t)L * 3 + 64));
+    // the points are the query points of slots 0..L-1, all live
+    c->lb_state.alloc(sizeof(double) * (size_t)L * 22 + sizeof(int32_t) * ((size_t)L * 4 + 32 * 4));
     c->lb_part.alloc(sizeof(double) * 3 * (size_t)KS * L + sizeof(uint32_t) * (size_t)KS * L);
-    int32_t* ib = reinterpret_cast<int32_t*>(c->lb_state.as<double>() + (size_t)L * 11);
-    int32_t* act = ib + L;
-    int32_t* cnt = ib + 3 * L;
+    int32_t* cnt = reinterpret_cast<int32_t*>(c->lb_state.as<double>() + (size_t)L * 22) + (size_t)L * 4;
     double* part = c->lb_part.as<double>();
     uint32_t* pmask = reinterpret_cast<uint32_t*>(part + 3 * (size_t)KS * L);
-    hipLaunchKernelGGL(k_lb_iota, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, act, cnt, L);
+    hipLaunchKernelGGL(k_lb_set_count, dim3(1), dim3(64), 0, c->stream, cnt, (int32_t)L);
     BEM_CHECK_LAUNCH();
     const bool fp64 = c->opt.precision == BEM_FP64;
     const int tile = split ? 64 : (tile_lines > 0 ? tile_lines : 256);
@@ -585,17 +615,20 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
             if (fp64)
                 hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)(Np / 256)), dim3(256), 0, c->stream,
                                    c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n,
-                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, KS);
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, L, cnt, cnt + 16, pts, part,
+                                   pmask, KS);
             else
                 hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)(Np / 256)), dim3(256), 0, c->stream,
                                    c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n,
-                                   (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, KS);
+                                   (const int32_t*)nullptr, (const int32_t*)nullptr, L, cnt, cnt + 16, pts, part,
+                                   pmask, KS);
             BEM_CHECK_LAUNCH();
             return;
         }
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->pan64.as<double>(), \
-                       FR, N, sol, c->n, (const int32_t*)nullptr, L, act, cnt, cnt + 16, pts, part, pmask, ntile, KS)
+                       FR, N, sol, c->n, (const int32_t*)nullptr, (const int32_t*)nullptr, L, cnt, cnt + 16, pts, \
+                       part, pmask, ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -655,35 +688,34 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     a.p = tp->alpha_p;
     a.k_str = tp->k_str;
     a.max_steps = tp->max_steps;
-    // Line groups: two contiguous ranges of lines, each with its own active lists and counters and
-    // its own stream.  A group's pass is its own far launch and step launch, so while one group's
-    // step kernel (a short chain of dependent loads over a few hundred blocks) runs, the other
-    // group's far pass fills the rest of the GPU.  State, partials and masks are indexed by line,
-    // so the groups share them without overlap.  Once the live lines fit one 64-line tile the
-    // groups are folded into one (two part-empty tiles would cost twice the blocks of one).
+    // Line groups: two contiguous slot ranges of lines, each with its own counters and its own
+    // stream.  A group's pass is its own far launch and step launch, so while one group's step
+    // kernel (a short chain of dependent loads over a few hundred blocks) runs, the other group's
+    // far pass fills the rest of the GPU.  State, partials and masks are indexed by slot and a
+    // group's slots stay in its range, so the groups share the buffers without overlap.  Once the
+    // live lines fit one 64-line tile the groups are folded into one (two part-empty tiles would
+    // cost twice the blocks of one).
     const int32_t G = (int32_t)std::min<int64_t>(c->tune_trace_groups, L);
-    // state: x, y, ks (3 each), asum, I; ns; two active lists; two counters per group
-    const size_t dbl = (size_t)L * 11;
-    c->lb_state.alloc(sizeof(double) * dbl + sizeof(int32_t) * ((size_t)L * 3 + 32 * 4));
+    // two state buffers (x, y, ks: 3 doubles; asum, I: 1 double; ns, line: 1 int32 per slot)
+    // and two live counters per group
+    c->lb_state.alloc(sizeof(double) * (size_t)L * 22 + sizeof(int32_t) * ((size_t)L * 4 + 32 * 4));
     c->lb_part.alloc(sizeof(double) * 3 * (size_t)KS * L + sizeof(uint32_t) * (size_t)KS * L);
-    double* base = c->lb_state.as<double>();
-    LBState s;
-    s.x = base;
-    s.y = base + 3 * L;
-    s.ks = base + 6 * L;
-    s.asum = base + 9 * L;
-    s.I = base + 10 * L;
-    int32_t* ib = reinterpret_cast<int32_t*>(base + dbl);
-    s.ns = ib;
-    int32_t* cnt0 = ib + 3 * L;
+    double* dbase = c->lb_state.as<double>();
+    int32_t* ibase = reinterpret_cast<int32_t*>(dbase + (size_t)L * 22);
+    LBState buf[2];
+    for (int k = 0; k < 2; ++k) {
+        double* d = dbase + (size_t)L * 11 * k;
+        int32_t* i = ibase + (size_t)L * 2 * k;
+        buf[k] = {d, d + 3 * L, d + 6 * L, d + 9 * L, d + 10 * L, i, i + L};
+    }
+    int32_t* cnt0 = ibase + (size_t)L * 4;
     double* part = c->lb_part.as<double>();
     uint32_t* pmask = reinterpret_cast<uint32_t*>(part + 3 * (size_t)KS * L);
-    hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, G, starts, s, ib + L,
+    hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, G, starts, buf[0],
                        cnt0, path, pstride);
     BEM_CHECK_LAUNCH();
     struct Group {
-        int64_t lo, size, known;   // known: upper bound on the active count (refreshed every 32 passes)
-        int32_t* act[2];
+        int64_t lo, size, known;   // slot range [lo, lo + size); known: upper bound on the live count
         int32_t* cnt[2];
         hipStream_t st;
     };
@@ -698,8 +730,6 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         q.lo = g * L / G;
         q.size = (g + 1) * L / G - q.lo;
         q.known = q.size;
-        q.act[0] = ib + L + q.lo;
-        q.act[1] = ib + 2 * L + q.lo;
         q.cnt[0] = cnt0 + 32 * g;
         q.cnt[1] = cnt0 + 32 * g + 16;
         q.st = (g & 1) ? c->aux_stream : c->stream;
@@ -737,21 +767,24 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                 BEM_HIP(hipEventRecord(c->fork_ev, grp[g ^ 1].st));
                 BEM_HIP(hipStreamWaitEvent(q.st, c->fork_ev, 0));
             }
+            const LBState sc = lb_shift(buf[cur], q.lo), sn = lb_shift(buf[cur ^ 1], q.lo);
+            double* gpart = part + 3 * q.lo * KS;
+            uint32_t* gmask = pmask + q.lo * KS;
             const bool few = q.known <= std::min<int64_t>(c->tune_trace_few, LB_FEW);
             const bool split = q.known <= c->tune_trace_split;
             int64_t KSP = KS;   // partial rows the step kernel sums
             {
             KTimer tf(c, "trace_far", !few && timed, q.st);
-            // blocks of tiles past the active count would only launch and exit: size the grids by
-            // the last known active count (an upper bound, the count only falls)
+            // blocks of tiles past the live count would only launch and exit: size the grids by
+            // the last known live count (an upper bound, the count only falls)
             const int tile = split ? 64 : c->tune_trace_tile;
             const int splitk = c->tune_trace_splitk;
             const int32_t ntile = (int32_t)ceil_div(q.known, tile);
             dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                            \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, c->pan64.as<double>(), \
-                       FR, N, sol, c->n, line_rhs, L, q.act[cur], q.cnt[cur], q.cnt[cur ^ 1], s.y, part, pmask,  \
-                       ntile, KS)
+                       FR, N, sol, c->n, line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart,   \
+                       gmask, ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -769,12 +802,12 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                 KSP = Np / 256;
                 if (fp64)
                     hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)KSP), dim3(256), 0, q.st,
-                                       c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n, line_rhs, L,
-                                       q.act[cur], q.cnt[cur], q.cnt[cur ^ 1], s.y, part, pmask, KS);
+                                       c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n, line_rhs,
+                                       sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask, KS);
                 else
                     hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)KSP), dim3(256), 0, q.st,
-                                       c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n, line_rhs, L,
-                                       q.act[cur], q.cnt[cur], q.cnt[cur ^ 1], s.y, part, pmask, KS);
+                                       c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n, line_rhs,
+                                       sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask, KS);
             } else if (fp64) {
                 BEM_LB_FAR_ALL(double, c->pan64.as<double>());
             } else {
@@ -787,11 +820,10 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             }
             {
             KTimer ts(c, "trace_step", timed, q.st);
-            hipLaunchKernelGGL(k_lb_step, dim3((unsigned)q.known), dim3(256), 0, q.st, L, N, KS, KSP, q.act[cur],
-                               q.cnt[cur], q.act[cur ^ 1], q.cnt[cur ^ 1], part, pmask, phase, s, a,
-                               c->tri64.as<double>(), sol, c->n, line_rhs, c->tri_body.as<int32_t>(),
-                               c->body_kind.as<int32_t>(), n_steps, stop_code, integral, exceeds, path, pstride,
-                               near_count);
+            hipLaunchKernelGGL(k_lb_step, dim3((unsigned)q.known), dim3(256), 0, q.st, N, KS, KSP, q.cnt[cur],
+                               q.cnt[cur ^ 1], gpart, gmask, phase, sc, sn, a, c->tri64.as<double>(), sol, c->n,
+                               line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,
+                               integral, exceeds, path, pstride, near_count);
             BEM_CHECK_LAUNCH();
             }
         }
@@ -809,10 +841,10 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                     live += host[g];
                 }
             if (live == 0) break;
-            // fold group 1 into group 0 once all live lines fit one tile and group 0's slice (both
-            // streams are idle here: the counts above were read after synchronising them)
+            // fold group 1 into group 0 once all live lines fit one tile and group 0's slot range
+            // (both streams are idle here: the counts above were read after synchronising them)
             if (G > 1 && grp[1].known > 0 && live <= std::min<int64_t>(64, grp[1].lo)) {
-                hipLaunchKernelGGL(k_lb_merge, dim3(1), dim3(256), 0, grp[0].st, grp[0].act[cur], grp[0].cnt[cur],
+                hipLaunchKernelGGL(k_lb_merge, dim3(1), dim3(256), 0, grp[0].st, buf[cur], grp[0].cnt[cur],
                                    grp[1].cnt[cur], grp[1].lo);
                 BEM_CHECK_LAUNCH();
                 grp[0].known = live;
