@@ -65,6 +65,21 @@ __device__ __forceinline__ double lb_alpha(const LBArgs& a, double e) {
     return a.a * (a.p == 2.0 ? d * d : lb_pow(d, a.p));
 }
 
+// w / r^3 from r^2.  FP64: from the hardware estimate y of r^-1/2 (relative error about 2^-24),
+// e = 1 - r^2 y^2 and r^-3 = y^3 (1 - e)^(-3/2) = y^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)): seven
+// operations, truncation error below 2^-68.  FP32: the hardware estimate is the answer.
+__device__ __forceinline__ double lb_w_r3(double w, double r2) {
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double y2 = y * y;
+    const double e = __fma_rn(-r2, y2, 1.0);
+    const double wy3 = w * (y2 * y);
+    return __fma_rn(wy3 * e, __fma_rn(e, 1.875, 1.5), wy3);
+}
+__device__ __forceinline__ float lb_w_r3(float w, float r2) {
+    const float ir = rsqrt_pos(r2);
+    return w * ir * ir * ir;
+}
+
 // Moeller-Trumbore test of the closed segment q -> q + d against the closed
 // triangle T; t in [0,1], or -1 when there is no hit.
 __device__ __forceinline__ double lb_segment_tri(const double* __restrict__ T, double q0, double q1, double q2,
@@ -175,8 +190,7 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
             for (int q = 0; q < 7; ++q) {
                 const R dx = pr0 - qv[FR_X + q], dy = pr1 - qv[FR_Y + q], dz = pr2 - qv[FR_Z + q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ir = rsqrt_pos(r2);
-                const R tw = qv[FR_W + q] * ir * ir * ir;
+                const R tw = lb_w_r3(qv[FR_W + q], r2);
                 f0 += tw * dx;
                 f1 += tw * dy;
                 f2 += tw * dz;
