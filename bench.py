@@ -39,7 +39,7 @@ FLOP_FIELD_PAIR = 141
 # WRITE_SIZE per dispatch, averaged over the 5024 chunked passes of one step, scaled by the device-copy
 # calibration (FETCH x 2, WRITE x 1); see profiles/hbm_counters_coax20k.md.  Re-measure when the
 # kernel changes.
-K_LB_FAR_FETCH_KIB = 5057.6
+K_LB_FAR_FETCH_KIB = 5054.7
 K_LB_FAR_WRITE_KIB = 2852.8
 K_LB_FAR_TRAFFIC_BYTES = (2.0 * K_LB_FAR_FETCH_KIB + 1.0 * K_LB_FAR_WRITE_KIB) * 1024.0
 FLOP_POT_PAIR = 86

@@ -68,14 +68,25 @@ __device__ __forceinline__ double lb_alpha(const LBArgs& a, double e) {
 // w / r^3 from r^2.  FP64: from the hardware estimate y of r^-1/2 (relative error about 2^-24),
 // e = 1 - r^2 y^2 and r^-3 = y^3 (1 - e)^(-3/2) = y^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)): seven
 // operations, truncation error below 2^-68.  FP32: the hardware estimate is the answer.
-__device__ __forceinline__ double lb_w_r3(double w, double r2) {
+// The series coefficients come in as k.c15 = 1.5 and k.c1875 = 1.875, held in registers by the
+// caller (lb_series_consts): neither is an inline FP64 constant, and left as literals they are
+// rebuilt inside the pair loop at every use.
+struct LBSeries {
+    double c15, c1875;
+};
+__device__ __forceinline__ LBSeries lb_series_consts() {
+    LBSeries k{1.5, 1.875};
+    asm volatile("" : "+v"(k.c15), "+v"(k.c1875));   // opaque: stays in a register
+    return k;
+}
+__device__ __forceinline__ double lb_w_r3(double w, double r2, const LBSeries& k) {
     const double y = __builtin_amdgcn_rsq(r2);
     const double y2 = y * y;
     const double e = __fma_rn(-r2, y2, 1.0);
     const double wy3 = w * (y2 * y);
-    return __fma_rn(wy3 * e, __fma_rn(e, 1.875, 1.5), wy3);
+    return __fma_rn(wy3 * e, __fma_rn(e, k.c1875, k.c15), wy3);
 }
-__device__ __forceinline__ float lb_w_r3(float w, float r2) {
+__device__ __forceinline__ float lb_w_r3(float w, float r2, const LBSeries&) {
     const float ir = rsqrt_pos(r2);
     return w * ir * ir * ir;
 }
@@ -174,6 +185,7 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     if (live) {
         const double* sig = sol + (line_rhs ? (int64_t)line_rhs[line_of[t]] * n : 0);
         const R pr0 = (R)p0, pr1 = (R)p1, pr2 = (R)p2;
+        const LBSeries ks = lb_series_consts();
         for (int pj = pj0; pj < pj1; ++pj) {
             const int64_t j = j0 + pj;
             const double* c64 = pan64 + FAR_REC * j;
@@ -190,7 +202,7 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
             for (int q = 0; q < 7; ++q) {
                 const R dx = pr0 - qv[FR_X + q], dy = pr1 - qv[FR_Y + q], dz = pr2 - qv[FR_Z + q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                const R tw = lb_w_r3(qv[FR_W + q], r2);
+                const R tw = lb_w_r3(qv[FR_W + q], r2, ks);
                 f0 += tw * dx;
                 f1 += tw * dy;
                 f2 += tw * dz;
@@ -273,6 +285,7 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
     }
     const double ccx = far64[(int64_t)(FR_CC + 0) * Np + j], ccy = far64[(int64_t)(FR_CC + 1) * Np + j];
     const double ccz = far64[(int64_t)(FR_CC + 2) * Np + j], rr = far64[(int64_t)FR_RR * Np + j];
+    const LBSeries ks = lb_series_consts();
     for (int t = 0; t < A; ++t) {
         const double p0 = lp[t][0], p1 = lp[t][1], p2 = lp[t][2];
         const bool reg = valid && is_regular(p0 - ccx, p1 - ccy, p2 - ccz, rr);
@@ -285,8 +298,7 @@ __global__ __launch_bounds__(256) void k_lb_far_few(const double* __restrict__ f
             for (int q = 0; q < 7; ++q) {
                 const R dx = pr0 - qx[q], dy = pr1 - qy[q], dz = pr2 - qz[q];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ir = rsqrt_pos(r2);
-                const R tw = qw[q] * ir * ir * ir;
+                const R tw = lb_w_r3(qw[q], r2, ks);
                 f0 += tw * dx;
                 f1 += tw * dy;
                 f2 += tw * dz;
