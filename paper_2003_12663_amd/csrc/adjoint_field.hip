@@ -16,9 +16,10 @@
 // the charge and geometry terms.  Regular/near classification and the number
 // of accepted steps are those of the forward run.
 //
-//  k_la_far  - (line tile x panel chunk) blocks, LDS panel tiles: partial
-//              E and H of the regular pairs by the 7-point rule, near pairs
-//              as bit masks (as in the forward tracer).
+//  k_la_far  - (line tile x panel chunk) blocks, panel records read at
+//              wave-uniform addresses: partial E and H of the regular pairs by
+//              the 7-point rule, near pairs as bit masks, line-major partial
+//              rows (as in the forward tracer).
 //  k_la_step - one block per line: partial sums + near pairs by the closed
 //              forms differentiated with dual numbers, then the stage machine.
 //  k_rows_EH - one block per collocation point: E and H of all panels but the
@@ -65,33 +66,28 @@ __device__ __forceinline__ double la_dalpha(const LAArgs& a, double e) {
 
 template <int SPLIT>
 __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : LA_T) void k_la_far(
-    const double* __restrict__ far64, int64_t Np, int64_t N, const double* __restrict__ sol, int64_t n,
+    const double* __restrict__ pan64, int64_t N, const double* __restrict__ sol, int64_t n,
     const int32_t* __restrict__ line_rhs, int64_t L, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
     int32_t* __restrict__ count_next, const double* __restrict__ ys, double* __restrict__ part,
-    uint32_t* __restrict__ pmask) {
-    constexpr int NT = SPLIT > 1 ? 64 * SPLIT : LA_T;
+    uint32_t* __restrict__ pmask, int32_t tiles, int64_t KS) {
     constexpr int TILE = SPLIT > 1 ? 64 : LA_T;
     constexpr int PER = LA_C / SPLIT;
-    __shared__ double tq[LA_C][28];
-    __shared__ double tc[LA_C][4];
     __shared__ double wred[SPLIT > 1 ? SPLIT : 1][64][LA_NC];
     __shared__ uint32_t wmask[SPLIT > 1 ? SPLIT : 1][64];
 
-    if (count_next && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) count_next[0] = 0;
+    // XCD x takes the contiguous chunk range [x CPX, (x + 1) CPX), all tiles of each (blocks are
+    // dealt to the 8 XCDs round-robin by linear id): a chunk's tiles share one L2 and each
+    // point's partials from one XCD are one contiguous run of its row
+    const int64_t bid = blockIdx.x, xcd = bid & 7, m = bid >> 3;
+    const int64_t CPX = (KS + 7) >> 3;
+    const int64_t tile = m % tiles, chunk = xcd * CPX + m / tiles;
+    if (count_next && bid == 0 && threadIdx.x == 0) count_next[0] = 0;
+    if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
     const int32_t A = count ? count[0] : (int32_t)L;
-    const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+    const int64_t tile0 = tile * TILE;
     if (tile0 >= A) return;
-    const int64_t j0 = (int64_t)blockIdx.y * LA_C;
+    const int64_t j0 = chunk * LA_C;
     const int nc = (int)((N - j0) < LA_C ? (N - j0) : LA_C);
-    for (int e = threadIdx.x; e < LA_C * 32; e += NT) {
-        const int pj = e % LA_C, comp = e / LA_C;
-        const int64_t j = j0 + pj;
-        if (comp < 28)
-            tq[pj][comp] = far64[(int64_t)comp * Np + j];
-        else
-            tc[pj][comp - 28] = far64[(int64_t)comp * Np + j];
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t t = tile0 + (SPLIT > 1 ? lane : (int)threadIdx.x);
     const bool live = t < A;
@@ -107,18 +103,23 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : LA_T) void k_la_far(
         const double* sigma = sol + (line_rhs ? (int64_t)line_rhs[l] : 0) * n;
         const double p0 = ys[3 * l], p1 = ys[3 * l + 1], p2 = ys[3 * l + 2];
         for (int pj = pj0; pj < pj1; ++pj) {
-            if (!is_regular(p0 - tc[pj][0], p1 - tc[pj][1], p2 - tc[pj][2], tc[pj][3])) {
+            // the panel's record at a wave-uniform address: scalar registers, no LDS staging
+            const double* cr = pan64 + FAR_REC * (j0 + pj);
+            double qv[FR_CC];
+#pragma unroll
+            for (int k = 0; k < FR_CC; ++k) qv[k] = cr[k];
+            if (!is_regular(p0 - cr[FR_CC], p1 - cr[FR_CC + 1], p2 - cr[FR_CC + 2], cr[FR_RR])) {
                 nmask |= 1u << pj;
                 continue;
             }
             double f0 = 0, f1 = 0, f2 = 0, s3 = 0, hxx = 0, hyy = 0, hzz = 0, hxy = 0, hxz = 0, hyz = 0;
 #pragma unroll
             for (int q = 0; q < 7; ++q) {
-                const double dx = p0 - tq[pj][q], dy = p1 - tq[pj][7 + q], dz = p2 - tq[pj][14 + q];
+                const double dx = p0 - qv[FR_X + q], dy = p1 - qv[FR_Y + q], dz = p2 - qv[FR_Z + q];
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 const double ir = rsqrt_pos(r2);
                 const double ir2 = ir * ir;
-                const double t3 = tq[pj][21 + q] * ir * ir2;   // w / r^3
+                const double t3 = qv[FR_W + q] * ir * ir2;   // w / r^3
                 const double t5 = 3.0 * t3 * ir2;             // 3 w / r^5
                 f0 += t3 * dx;
                 f1 += t3 * dy;
@@ -161,10 +162,10 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : LA_T) void k_la_far(
     } else if (!live) {
         return;
     }
-    double* o = part + ((int64_t)blockIdx.y * L + l) * LA_NC;
+    double* o = part + (l * KS + chunk) * LA_NC;
 #pragma unroll
     for (int k = 0; k < LA_NC; ++k) o[k] = acc[k];
-    pmask[(int64_t)blockIdx.y * L + l] = nmask;
+    pmask[l * KS + chunk] = nmask;
 }
 
 // E and H at point p of line/point slot l, by the whole block: fixed-order sums of
@@ -179,12 +180,12 @@ __device__ void block_EH(int64_t L, int64_t KS, int64_t l, const double* __restr
 #pragma unroll
     for (int k = 0; k < LA_NC; ++k) acc[k] = 0.0;
     for (int64_t k = tid; k < KS; k += 256) {
-        const double* o = part + (k * L + l) * LA_NC;
+        const double* o = part + (l * KS + k) * LA_NC;
 #pragma unroll
         for (int c = 0; c < LA_NC; ++c) acc[c] += o[c];
     }
     int cnt = 0;
-    for (int64_t k = tid; k < KS; k += 256) cnt += __popc(pmask[k * L + l]);
+    for (int64_t k = tid; k < KS; k += 256) cnt += __popc(pmask[l * KS + k]);
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -202,7 +203,7 @@ __device__ void block_EH(int64_t L, int64_t KS, int64_t l, const double* __restr
         if (off + cnt > base && off < base + LA_Q) {
             int pos = off;
             for (int64_t k = tid; k < KS && pos < base + LA_Q; k += 256) {
-                uint32_t m = pmask[k * L + l];
+                uint32_t m = pmask[l * KS + k];
                 while (m) {
                     const int b = __builtin_ctz(m);
                     m &= m - 1;
@@ -407,7 +408,6 @@ void launch_reverse_sweep(bem_ctx* c, const double* sol, int64_t L, const int32_
                           const int64_t* sbase, int32_t max_ns, double* SX, double* SE, double* x0bar) {
     if (L == 0) return;
     KTimer t(c, "grad_reverse");
-    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t KS = ceil_div(N, LA_C);
     LAArgs a;
@@ -444,14 +444,17 @@ void launch_reverse_sweep(bem_ctx* c, const double* sol, int64_t L, const int32_
     int cur = 0;
     for (int64_t pass = 0; pass < max_pass && known_active > 0; ++pass) {
         const int phase = (int)(pass % 4);
-        const bool split = known_active <= 64;
-        dim3 g1((unsigned)ceil_div(known_active, split ? 64 : LA_T), (unsigned)KS);
+        // up to 256 live lines: 64-line tiles with each chunk split over 8 waves (a 256-line tile
+        // would leave lanes idle and give too few blocks to fill the GPU)
+        const bool split = known_active <= 256;
+        const int32_t ntile = (int32_t)ceil_div(known_active, split ? 64 : LA_T);
+        dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
         if (split)
-            hipLaunchKernelGGL((k_la_far<8>), g1, dim3(512), 0, c->stream, c->far64.as<double>(), Np, N, sol, c->n,
-                               line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask);
+            hipLaunchKernelGGL((k_la_far<8>), g1, dim3(512), 0, c->stream, c->pan64.as<double>(), N, sol, c->n,
+                               line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask, ntile, KS);
         else
-            hipLaunchKernelGGL((k_la_far<1>), g1, dim3(LA_T), 0, c->stream, c->far64.as<double>(), Np, N, sol, c->n,
-                               line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask);
+            hipLaunchKernelGGL((k_la_far<1>), g1, dim3(LA_T), 0, c->stream, c->pan64.as<double>(), N, sol, c->n,
+                               line_rhs, L, act[cur], cnt[cur], cnt[cur ^ 1], s.y, part, pmask, ntile, KS);
         BEM_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_la_step, dim3((unsigned)known_active), dim3(256), 0, c->stream, L, KS, act[cur],
                            cnt[cur], act[cur ^ 1], cnt[cur ^ 1], part, pmask, phase, s, a, c->tri64.as<double>(), sol,
@@ -471,7 +474,6 @@ void launch_reverse_sweep(bem_ctx* c, const double* sol, int64_t L, const int32_
 void launch_rows_EH(bem_ctx* c, const double* sigma, int64_t P, const double* pts, double* out) {
     if (P == 0) return;
     KTimer t(c, "grad_rows_EH");
-    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t KS = ceil_div(N, LA_C);
     const int64_t B = std::min<int64_t>(P, std::min<int64_t>(8192, c->grad_batch));   // bounds the partial buffer
@@ -480,10 +482,11 @@ void launch_rows_EH(bem_ctx* c, const double* sigma, int64_t P, const double* pt
     uint32_t* pmask = reinterpret_cast<uint32_t*>(part + LA_NC * (size_t)KS * B);
     for (int64_t p0 = 0; p0 < P; p0 += B) {
         const int64_t nb = std::min<int64_t>(B, P - p0);
-        dim3 g1((unsigned)ceil_div(nb, LA_T), (unsigned)KS);
-        hipLaunchKernelGGL((k_la_far<1>), g1, dim3(LA_T), 0, c->stream, c->far64.as<double>(), Np, N, sigma, (int64_t)0,
+        const int32_t ntile = (int32_t)ceil_div(nb, LA_T);
+        dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
+        hipLaunchKernelGGL((k_la_far<1>), g1, dim3(LA_T), 0, c->stream, c->pan64.as<double>(), N, sigma, (int64_t)0,
                            (const int32_t*)nullptr, nb, (const int32_t*)nullptr, (const int32_t*)nullptr,
-                           (int32_t*)nullptr, pts + 3 * p0, part, pmask);
+                           (int32_t*)nullptr, pts + 3 * p0, part, pmask, ntile, KS);
         BEM_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_rows_EH, dim3((unsigned)nb), dim3(256), 0, c->stream, nb, KS, p0, part, pmask,
                            c->tri64.as<double>(), sigma, pts + 3 * p0, out);
