@@ -163,39 +163,45 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     const int64_t bid = blockIdx.x, xcd = bid & 7, m = bid >> 3;
     const int64_t CPX = (KS + 7) >> 3;
     const int64_t tile = m % tiles, chunk = xcd * CPX + m / tiles;
-    if (bid == 0 && threadIdx.x == 0) count_next[0] = 0;
-    if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
     const int64_t tile0 = tile * TILE;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int64_t t = tile0 + (SPLIT > 1 ? lane : (int)threadIdx.x);
-    // the slot's query point is read together with the live count (slot index clamped into the
-    // group's cap slots; a slot past the count is never used)
+    const int64_t j0 = chunk * LB_C;
+    const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
+    const int pj0 = SPLIT > 1 ? wv * PER : 0;
+    const int pj1 = SPLIT > 1 ? (pj0 + PER < nc ? pj0 + PER : nc) : nc;
+    // Requested together and waited for once, before any exit: the live count, the slot's
+    // query point (slot clamped into the group's cap slots; a slot past the count is never
+    // used) and the wave's first panel record (index clamped to a real panel).  Left to
+    // itself the compiler issues each of these after the branch that precedes its first use,
+    // one round trip after another.
+    const int64_t jf = (j0 + pj0 < N) ? j0 + pj0 : N - 1;
+    R qf[FR_CC];
+    double cf[4];
+#pragma unroll
+    for (int k = 0; k < FR_CC; ++k) qf[k] = panR[FAR_REC * jf + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cf[k] = pan64[FAR_REC * jf + FR_CC + k];
     const int64_t tc = t < cap ? t : cap - 1;
     const double p0 = ys[3 * tc], p1 = ys[3 * tc + 1], p2 = ys[3 * tc + 2];
     const int32_t A = count[0];
-    if (tile0 >= A) return;   // uniform over the block
-    const int64_t j0 = chunk * LB_C;
-    const int nc = (int)((N - j0) < LB_C ? (N - j0) : LB_C);
+    asm volatile("" ::"s"(A), "v"(p0), "v"(p1), "v"(p2), "s"(qf[0]), "s"(qf[FR_CC - 1]), "s"(cf[0]), "s"(cf[3]));
+    if (bid == 0 && threadIdx.x == 0) count_next[0] = 0;
+    if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
+    if (tile0 >= A) return;    // uniform over the block
     const bool live = t < A;
-    const int pj0 = SPLIT > 1 ? wv * PER : 0;
-    const int pj1 = SPLIT > 1 ? (pj0 + PER < nc ? pj0 + PER : nc) : nc;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     uint32_t nmask = 0;
     if (live) {
         const double* sig = sol + (line_rhs ? (int64_t)line_rhs[line_of[t]] * n : 0);
         const R pr0 = (R)p0, pr1 = (R)p1, pr2 = (R)p2;
         const LBSeries ks = lb_series_consts();
-        for (int pj = pj0; pj < pj1; ++pj) {
-            const int64_t j = j0 + pj;
-            const double* c64 = pan64 + FAR_REC * j;
-            const R* cq = panR + FAR_REC * j;
-            R qv[FR_CC];
-#pragma unroll
-            for (int k = 0; k < FR_CC; ++k) qv[k] = cq[k];
-            if (!is_regular(p0 - c64[FR_CC], p1 - c64[FR_CC + 1], p2 - c64[FR_CC + 2], c64[FR_RR])) {
+        // one regular pair (the 7-point rule) or a near bit, for panel pj of the chunk
+        auto pair = [&](int pj, const R (&qv)[FR_CC], const double (&cc)[4]) {
+            if (!is_regular(p0 - cc[0], p1 - cc[1], p2 - cc[2], cc[3])) {
                 nmask |= 1u << pj;
-                continue;
+                return;
             }
             R f0 = 0, f1 = 0, f2 = 0;
 #pragma unroll
@@ -207,10 +213,21 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
                 f1 += tw * dy;
                 f2 += tw * dz;
             }
-            const double sg = sig[j];
+            const double sg = sig[j0 + pj];
             e0 = fma(sg, (double)f0, e0);
             e1 = fma(sg, (double)f1, e1);
             e2 = fma(sg, (double)f2, e2);
+        };
+        if (pj0 < pj1) pair(pj0, qf, cf);
+        for (int pj = pj0 + 1; pj < pj1; ++pj) {
+            const int64_t j = j0 + pj;
+            R qv[FR_CC];
+            double cc[4];
+#pragma unroll
+            for (int k = 0; k < FR_CC; ++k) qv[k] = panR[FAR_REC * j + k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cc[k] = pan64[FAR_REC * j + FR_CC + k];
+            pair(pj, qv, cc);
         }
     }
     if (SPLIT > 1) {
