@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--extras-only", action="store_true", help="only the gradient and 4096-line runs")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON): reuse one tile choice across runs, e.g. for counter runs")
+    ap.add_argument("--set-tuning", default=None,
+                    help="comma-separated key=value tuning knobs applied after the autotuner (experiments)")
     ap.add_argument("--trace-groups", type=int, default=None,
                     help="line groups of the field-line tracer (1..4; default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -272,6 +274,10 @@ def main():
     ctx.autotune(args.tune_cache)
     if args.trace_groups is not None:
         ctx.set_tuning("trace_groups", args.trace_groups)
+    if args.set_tuning:
+        for kv in args.set_tuning.split(","):
+            key, val = kv.split("=")
+            ctx.set_tuning(key.strip(), int(val))
     tuning = {k: ctx.get_tuning(k) for k in ("far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile",
                                               "trace_splitk", "trace_split", "trace_few", "trace_groups")}
 
