@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _SRC_DUAL = os.path.join(_HERE, "oracle_dual.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-DIRICHLET, FLOATING, INTERFACE = 0, 1, 2
+DIRICHLET, FLOATING, INTERFACE, SHEET = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:

@@ -31,7 +31,9 @@
 
 #define ORC_PI 3.14159265358979323846
 
-enum { ORC_DIRICHLET = 0, ORC_FLOATING = 1, ORC_INTERFACE = 2 };
+/* ORC_SHEET: a thin floating conductive sheet modelled by one (open) surface, Eq. sheets */
+enum { ORC_DIRICHLET = 0, ORC_FLOATING = 1, ORC_INTERFACE = 2, ORC_SHEET = 3 };
+static int is_floating_kind(int32_t kind) { return kind == ORC_FLOATING || kind == ORC_SHEET; }
 
 typedef struct {
     int64_t n_vert;
@@ -231,7 +233,7 @@ static void geom_build(const orc_problem* p, orc_geom* g)
     }
     g->fidx = (int32_t*)malloc(sizeof(int32_t) * (p->n_body > 0 ? p->n_body : 1));
     g->n_float = 0;
-    for (int32_t b = 0; b < p->n_body; ++b) g->fidx[b] = (p->body_kind[b] == ORC_FLOATING) ? g->n_float++ : -1;
+    for (int32_t b = 0; b < p->n_body; ++b) g->fidx[b] = is_floating_kind(p->body_kind[b]) ? g->n_float++ : -1;
 }
 
 static void geom_free(orc_geom* g)
@@ -263,7 +265,7 @@ static void pair_SF(const orc_problem* p, const orc_geom* g, const double x[3], 
 int64_t orc_n_unknowns(const orc_problem* p)
 {
     int64_t n = p->n_tri;
-    for (int32_t b = 0; b < p->n_body; ++b) n += (p->body_kind[b] == ORC_FLOATING);
+    for (int32_t b = 0; b < p->n_body; ++b) n += is_floating_kind(p->body_kind[b]);
     return n;
 }
 
@@ -286,9 +288,14 @@ int orc_classify(const orc_problem* p, int64_t P, const double* pts, int32_t* re
  *                          + (eps+ - eps-) sum_{j != i} K'_ij sigma_j (= 0)
  *   constraint row of f  : sum_{i in f} a_i eps+ (sigma_i / 2 + sum_{j != i} K'_ij sigma_j)
  *                          scaled by 1/(eps+ sum_{i in f} a_i)    (= 0)
+ *   constraint row of a sheet f (Eq. sheets):
+ *                          sum_{i in f} a_i ((eps+ + eps-)/2 sigma_i
+ *                                            + (eps+ - eps-) sum_{j != i} K'_ij sigma_j)
+ *                          scaled by 1/((eps+ + eps-)/2 sum_{i in f} a_i)   (= 0)
  * with S_ij = S(x_i, tau_j) and K'_ij = n_i . F(x_i, tau_j).  The form
- * constraint_form = 1 replaces the constraint row by sum_{i in f} a_i sigma_i
- * (same scaling), its value on a closed body by the Gauss law.
+ * constraint_form = 1 replaces the constraint row of a closed floating body by
+ * sum_{i in f} a_i sigma_i (same scaling), its value on a closed body by the
+ * Gauss law; a sheet is not closed and always keeps Eq. sheets.
  */
 static void assemble_row(const orc_problem* p, const orc_geom* g, int64_t row, double* out)
 {
@@ -299,13 +306,13 @@ static void assemble_row(const orc_problem* p, const orc_geom* g, int64_t row, d
         int32_t b = p->tri_body[i];
         int32_t kind = p->body_kind[b];
         const double* xi = g->cen + 3 * i;
-        if (kind == ORC_DIRICHLET || kind == ORC_FLOATING) {
+        if (kind == ORC_DIRICHLET || is_floating_kind(kind)) {
             for (int64_t j = 0; j < N; ++j) {
                 double S, F[3];
                 pair_SF(p, g, xi, j, j == i, &S, F);
                 out[j] = S;
             }
-            if (kind == ORC_FLOATING) out[N + g->fidx[b]] = -1.0;
+            if (is_floating_kind(kind)) out[N + g->fidx[b]] = -1.0;
         } else {
             double ep = p->eps_plus[b], em = p->eps_minus[b];
             for (int64_t j = 0; j < N; ++j) {
@@ -324,27 +331,33 @@ static void assemble_row(const orc_problem* p, const orc_geom* g, int64_t row, d
     int32_t f = (int32_t)(row - N), fb = -1;
     for (int32_t b = 0; b < p->n_body; ++b)
         if (g->fidx[b] == f) fb = b;
+    const int sheet = p->body_kind[fb] == ORC_SHEET;
     double ep = p->eps_plus[fb];
+    /* coefficients of sigma_i and of (K' sigma)(x_i): eps+/2 and eps+ for a closed body (no
+       field inside the metal), (eps+ + eps-)/2 and eps+ - eps- for a sheet */
+    double c_self = sheet ? 0.5 * (ep + p->eps_minus[fb]) : 0.5 * ep;
+    double c_kp = sheet ? ep - p->eps_minus[fb] : ep;
+    double c_scale = sheet ? c_self : ep;
     double asum = 0.0;
     for (int64_t i = 0; i < N; ++i)
         if (p->tri_body[i] == fb) asum += g->area[i];
-    double scale = 1.0 / (ep * asum);
+    double scale = 1.0 / (c_scale * asum);
     for (int64_t i = 0; i < N; ++i) {
         if (p->tri_body[i] != fb) continue;
         double ai = g->area[i];
-        if (p->constraint_form == 1) {
+        if (p->constraint_form == 1 && !sheet) {
             out[i] += scale * ep * ai;
             continue;
         }
         const double* xi = g->cen + 3 * i;
         for (int64_t j = 0; j < N; ++j) {
             if (j == i) {
-                out[j] += scale * ai * ep * 0.5;
+                out[j] += scale * ai * c_self;
                 continue;
             }
             double S, F[3];
             pair_SF(p, g, xi, j, 0, &S, F);
-            out[j] += scale * ai * ep * dot3(g->nrm + 3 * i, F);
+            out[j] += scale * ai * c_kp * dot3(g->nrm + 3 * i, F);
         }
     }
 }
@@ -673,7 +686,7 @@ static int bem_hit(const void* c, const double x0[3], const double x1[3])
     int64_t j = segment_hit(b->p, b->g, x0, x1, &t);
     if (j < 0) return 0;
     int32_t kind = b->p->body_kind[b->p->tri_body[j]];
-    return kind == ORC_DIRICHLET ? 1 : (kind == ORC_FLOATING ? 2 : 3);
+    return kind == ORC_DIRICHLET ? 1 : (is_floating_kind(kind) ? 2 : 3);
 }
 
 /* Field lines of the BEM field for sigma (first N entries of the solution). */

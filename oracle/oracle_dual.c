@@ -371,6 +371,10 @@ int orc_dual_streamer(const orc_problem* p, const double* dvert, const double* b
                       const orc_trace_params* tp, const int32_t* n_steps, double tol, double* u_out, double* du_out,
                       double* I, double* dI)
 {
+    /* thin floating sheets (body kind 3, Eq. sheets) are not differentiated here */
+    for (int32_t b = 0; b < p->n_body; ++b)
+        if (p->body_kind[b] != ORC_DIRICHLET && p->body_kind[b] != ORC_FLOATING && p->body_kind[b] != ORC_INTERFACE)
+            return -2;
     dgeom g;
     dgeom_build(p, dvert, &g);
     int64_t N = p->n_tri, n = N + g.n_float;

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 from workloads import (coated_sphere_problem, coax_problem, floating_shell_problem, sphere_eval_points,
-                       sphere_problem, icosphere)
+                       sphere_problem, sphere_sheet_problem, icosphere)
 from workloads.meshes import Problem
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
@@ -391,6 +391,34 @@ def test_floating_shell(oracle_mod):
     m = p.tri_body == 1
     assert abs(np.sum(area[m] * x[:N][m])) < 5e-2 * np.sum(np.abs(area[m] * x[:N][m]))
     assert abs(np.sum(area[m] * x1[:N][m])) < 1e-12 * np.sum(np.abs(area[m] * x1[:N][m]))
+
+
+@pytest.mark.parametrize("case", range(2))
+def test_floating_sheet_closed_form(oracle_mod, case):
+    """A thin floating sheet (Eq. sheets) between two dielectrics: its potential and the
+    field outside converge to the closed form, and the physical charge of the sheet,
+    sum_i a_i ((eps+ + eps-)/2 sigma_i + (eps+ - eps-) (K' sigma)_i), is zero."""
+    gold = GOLDEN["sphere_sheet"]["cases"][case]
+    errs, errE = [], []
+    for lev in (2, 3):
+        p = sphere_sheet_problem(lev, a=gold["a"], b=gold["b"], eps_in=gold["eps_in"], eps_out=gold["eps_out"])
+        o, A, b, x = _solve(oracle_mod, p)
+        N = p.n_tri
+        assert x.shape[0] == N + 1
+        errs.append(abs(x[N] - gold["Vf_over_V0"]))
+        pts = sphere_eval_points(200, seed=2, rmin=3.0, rmax=4.0)
+        _, E = o.eval(x, pts)
+        r = np.linalg.norm(pts, axis=1)
+        errE.append(np.max(np.abs(np.linalg.norm(E, axis=1) - gold["C_over_V0"] / r ** 2) / (gold["C_over_V0"] / r ** 2)))
+        # the constraint row is the sheet's net charge (scaled): A[N] . x = 0 to rounding
+        assert abs(A[N] @ x) < 1e-12 * np.abs(A[N]).sum() * np.abs(x[:N]).max()
+        # the net-charge form of closed floating bodies does not apply to an open sheet
+        _, A1, _, x1 = _solve(oracle_mod, p, form=1)
+        assert np.array_equal(A1, A) and abs(x1[N] - x[N]) < 1e-13
+    # converging (the K' term of the sheet row makes the potential's order below one on these
+    # meshes); a dropped eps weighting would give 0.5, a swapped eps+ - eps- sign 0.2
+    assert errs[1] < 1e-2 and errs[0] / errs[1] > 1.4, errs
+    assert errE[1] < 2e-2 and errE[0] / errE[1] > 1.8, errE
 
 
 def test_coax_floating_ring_maximum_principle(oracle_mod):

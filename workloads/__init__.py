@@ -15,6 +15,8 @@ from .meshes import (  # noqa: F401
     floating_shell_problem,
     coax_problem,
     coax_problem_for_size,
+    sphere_sheet_problem,
+    bushing_problem,
 )
 from .seeds import (  # noqa: F401
     sphere_eval_points,

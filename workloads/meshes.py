@@ -9,6 +9,8 @@ insulators (dielectric interfaces):
     DIRICHLET = 0   conductor held at a prescribed potential
     FLOATING  = 1   conductor of unknown potential and zero net charge
     INTERFACE = 2   dielectric interface (no free surface charge)
+    SHEET     = 3   thin floating conductive sheet, one (open) surface, zero net
+                    charge counted over both of its sides (Eq. sheets)
 
 The meshes are the stand-ins for the paper's industrial geometries, which are
 not public: an icosphere (sphere closed forms), a conductor coated with a
@@ -27,6 +29,7 @@ import numpy as np
 DIRICHLET = 0
 FLOATING = 1
 INTERFACE = 2
+SHEET = 3
 
 
 @dataclasses.dataclass
@@ -57,7 +60,7 @@ class Problem:
 
     @property
     def n_float(self) -> int:
-        return int(np.count_nonzero(self.body_kind == FLOATING))
+        return int(np.count_nonzero((self.body_kind == FLOATING) | (self.body_kind == SHEET)))
 
     @property
     def n_unknowns(self) -> int:
@@ -251,6 +254,75 @@ def floating_shell_problem(level=3, a=1.0, b1=1.5, b2=2.0, V0=1.0) -> Problem:
         body_kind=np.array([DIRICHLET, FLOATING], dtype=np.int32),
         eps_plus=np.array([1.0, 1.0]), eps_minus=np.array([1.0, 1.0]),
         body_V=np.array([V0, 0.0]), body_names=["conductor", "floating_shell"],
+        start_mask=body == 0)
+
+
+def sphere_sheet_problem(level=3, a=1.0, b=2.0, eps_in=4.0, eps_out=1.0, V0=1.0) -> Problem:
+    """Conductor sphere (radius a, V0) inside a thin floating spherical sheet at r = b.
+
+    Dielectric eps_in fills a < r < b and eps_out the outside; the sheet is the only
+    surface between them, so it is a SHEET body with eps+ = eps_out (its normal points
+    outward) and eps- = eps_in.
+    """
+    vert, tri, body = _concentric(level, [(a, True), (b, True)])
+    return Problem(
+        name=f"sphere_sheet_L{level}", vert=vert, tri=tri, tri_body=body,
+        body_kind=np.array([DIRICHLET, SHEET], dtype=np.int32),
+        eps_plus=np.array([eps_in, eps_out]), eps_minus=np.array([1.0, eps_in]),
+        body_V=np.array([V0, 0.0]), body_names=["conductor", "sheet"],
+        start_mask=body == 0)
+
+
+def _open_cylinder(b: _Builder, body, r, zlo, zhi, h):
+    """Side surface only (no caps), normals pointing outward (+rho)."""
+    n = _n_around(r, h)
+    zs = _levels(zlo, zhi, h)
+    loops = [_circle(b, r, z, n, phase=0.5 * (k % 2)) for k, z in enumerate(zs)]
+    tris = []
+    for (ia, ta), (ib, tb) in zip(loops[:-1], loops[1:]):
+        tris += _zip_loops(ia, ta, ib, tb)
+    vert = np.concatenate(b.v)
+
+    def want(cen):
+        d = np.zeros_like(cen)
+        d[:, 0] = cen[:, 0]
+        d[:, 1] = cen[:, 1]
+        return d
+
+    b.add_triangles(_orient(vert, tris, want), body)
+
+
+BUSHING = dict(
+    rod_r=0.02, rod_z=0.30,           # driven closed cylinder, z in [-0.30, 0.30]
+    foil_r=(0.035, 0.050, 0.065, 0.080, 0.095),   # five coaxial foils, outermost grounded
+    foil_z=(0.26, 0.22, 0.18, 0.14, 0.10),         # half lengths: shorter outward (field grading)
+    ins_r=0.11, ins_z=0.32, ins_eps=4.0,           # insulator: closed cylinder around rod and foils
+)
+
+
+def bushing_problem(h: float, V0: float = 1.0) -> Problem:
+    """Bushing-like device: a conductor on V0 wrapped by an insulator (eps_r 4) in which five
+    thin coaxial conducting foils grade the field; the outermost foil is grounded and the
+    other four float (SHEET bodies, eps+ = eps- = eps_r).  The insulator surface is a
+    dielectric interface (normals outward into air).  Potential zero at infinity.
+
+    Bodies (index: kind): 0 rod DIRICHLET (V0), 1-4 foils SHEET, 5 outer foil DIRICHLET (0),
+    6 insulator INTERFACE.  Element size h (metres) on every surface.
+    """
+    g = BUSHING
+    b = _Builder()
+    _capped_cylinder(b, 0, g["rod_r"], -g["rod_z"], g["rod_z"], h, h, (), True)
+    for k, (r, z) in enumerate(zip(g["foil_r"], g["foil_z"])):
+        _open_cylinder(b, 1 + k, r, -z, z, h)
+    _capped_cylinder(b, 6, g["ins_r"], -g["ins_z"], g["ins_z"], 1.5 * h, 1.5 * h, (), True)
+    vert, tri, body = b.finish()
+    e = g["ins_eps"]
+    return Problem(
+        name=f"bushing_h{h:g}", vert=vert, tri=tri, tri_body=body,
+        body_kind=np.array([DIRICHLET, SHEET, SHEET, SHEET, SHEET, DIRICHLET, INTERFACE], dtype=np.int32),
+        eps_plus=np.array([e, e, e, e, e, e, 1.0]), eps_minus=np.array([1.0, e, e, e, e, 1.0, e]),
+        body_V=np.array([V0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0]),
+        body_names=["rod", "foil1", "foil2", "foil3", "foil4", "foil5_grounded", "insulator"],
         start_mask=body == 0)
 
 
