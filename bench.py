@@ -209,6 +209,40 @@ def c3_run(bem, torch):
     return out
 
 
+def bushing_run(bem, torch):
+    """Bushing-like device with thin floating sheets (element size 8 mm, ~30k panels): FP64
+    assembly and solve to 1e-10 (after a warm-up solve), the four floating foils' potentials,
+    and 256 field lines from the rod to the first foil."""
+    from workloads import bushing_problem, electrode_line_starts
+    p = bushing_problem(0.008)
+    N = p.n_tri
+    ctx = bem.Context.from_problem(p, eta=6.0)
+    ctx.assemble()
+    ctx.solve(p.body_V, tol=1e-10, max_iter=20000)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.assemble()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol, info = ctx.solve(p.body_V, tol=1e-10, max_iter=20000)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    starts, _, _ = electrode_line_starts(p, 256, seed=3)
+    tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-6)
+    I, ns, st, _ = ctx.streamer_integral(sol, torch.tensor(starts, device="cuda"), tp)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    V = sol[0, N:N + 4].cpu().numpy()
+    out = {"panels": N, "unknowns": int(ctx.n), "assemble_s": t1 - t0, "solve_s": t2 - t1,
+           "iters": info["iters"], "rel_residual": info["rel_residual"],
+           "floating_foil_potentials_over_V0": [float(v) for v in V],
+           "lines": 256, "trace_s": t3 - t2,
+           "stop_code_counts": {str(k): int((st.cpu().numpy() == k).sum()) for k in range(6)}}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(p, x, starts, args):
     """The oracle on a bounded sample: a block of matrix rows and a few short lines."""
     import oracle
@@ -266,7 +300,8 @@ def main():
         ctx.autotune(None)
         print(json.dumps({"gradient_coax_128_lines": gradient_run(bem, torch, p, ctx),
                           "cases_64_x_lines_64": cases_by_lines_run(bem, torch, p, ctx),
-                          "coax_60k_mixed_vs_fp64": c3_run(bem, torch)}))
+                          "coax_60k_mixed_vs_fp64": c3_run(bem, torch),
+                          "bushing_thin_sheets": bushing_run(bem, torch)}))
         ctx.close()
         return
     # tile shapes for this problem, timed before the timed region (tuning re-assembles)
@@ -340,6 +375,7 @@ def main():
         extras["gradient_coax_128_lines"] = gradient_run(bem, torch, p, ctx)
         extras["cases_64_x_lines_64"] = cases_by_lines_run(bem, torch, p, ctx)
         extras["coax_60k_mixed_vs_fp64"] = c3_run(bem, torch)
+        extras["bushing_thin_sheets"] = bushing_run(bem, torch)
 
     tts = None
     if not args.no_tts:

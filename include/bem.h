@@ -49,7 +49,13 @@ typedef enum {
 typedef enum {
     BEM_DIRICHLET = 0, /* rows of Eq. Final1: sum_j S_ij sigma_j = V_body */
     BEM_FLOATING = 1,  /* rows of Eq. Final2 (S sigma - V_f = 0) plus one row of Eq. Final4 per body */
-    BEM_INTERFACE = 2  /* rows of Eq. Final3 / Eq. nonconductors, using K' of Eq. ADL */
+    BEM_INTERFACE = 2, /* rows of Eq. Final3 / Eq. nonconductors, using K' of Eq. ADL */
+    BEM_FLOATING_SHEET = 3 /* thin floating conductive sheet modelled by one (open) surface: rows of
+                              Eq. Final2 plus one row of Eq. sheets per body, the net charge over both
+                              sides, sum_i a_i ((eps+ + eps-)/2 sigma_i + (eps+ - eps-) (K' sigma)_i)
+                              = 0, whatever constraint_form says; eps_plus / eps_minus are the
+                              permittivities on the normal side and the other side.  Not supported
+                              by bem_streamer_grad. */
 } bem_kind;
 
 typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
@@ -59,7 +65,7 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
 typedef struct {
     int32_t kind;      /* bem_kind */
     double eps_plus;   /* permittivity on the normal side */
-    double eps_minus;  /* permittivity on the other side (INTERFACE only) */
+    double eps_minus;  /* permittivity on the other side (INTERFACE and FLOATING_SHEET) */
 } bem_body;
 
 typedef struct {
@@ -209,7 +215,7 @@ bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, 
  *  dJ_dvert     dev [n_vert][3] (written)
  *  dJ_dV        dev [nrhs][n_body] (written; 0 for non-conductor bodies)
  *  dJ_dstart    dev [L][3] or NULL: dJ/d starts[l] at fixed mesh
- * FP64 precision only; alpha_p >= 1.  Errors: STATE (not assembled), INVALID,
+ * FP64 precision only; alpha_p >= 1; no FLOATING_SHEET bodies.  Errors: STATE (not assembled), INVALID,
  * NOCONV (an adjoint solve missed tol), OOM, HIP. */
 bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t L,
                              const int32_t* line_rhs, const double* starts, const int32_t* start_panel,

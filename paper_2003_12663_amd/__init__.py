@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _lib
 
-DIRICHLET, FLOATING, INTERFACE = 0, 1, 2
+DIRICHLET, FLOATING, INTERFACE, FLOATING_SHEET = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 STOP_NAMES = {0: "max_steps", 1: "dirichlet", 2: "floating", 3: "interface", 4: "weak_field", 5: "nonfinite"}
 

@@ -173,7 +173,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         if (!std::isfinite(vert[k])) return fail(BEM_ERR_INVALID, "non-finite vertex coordinate");
     for (int32_t b = 0; b < n_body; ++b) {
         const bem_body& bd = bodies[b];
-        if (bd.kind < BEM_DIRICHLET || bd.kind > BEM_INTERFACE) return fail(BEM_ERR_INVALID, "unknown body kind");
+        if (bd.kind < BEM_DIRICHLET || bd.kind > BEM_FLOATING_SHEET) return fail(BEM_ERR_INVALID, "unknown body kind");
         if (!(bd.eps_plus > 0.0) || !std::isfinite(bd.eps_plus)) return fail(BEM_ERR_INVALID, "eps_plus must be > 0");
         if (bd.kind == BEM_INTERFACE && (!(bd.eps_minus > 0.0) || !std::isfinite(bd.eps_minus)))
             return fail(BEM_ERR_INVALID, "eps_minus must be > 0 on an interface");
@@ -205,7 +205,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         min_R = std::min(min_R, lu * lw * le / (4.0 * area));
     }
     for (int32_t b = 0; b < n_body; ++b)
-        if (bodies[b].kind == BEM_FLOATING && per_body[b] == 0)
+        if ((bodies[b].kind == BEM_FLOATING || bodies[b].kind == BEM_FLOATING_SHEET) && per_body[b] == 0)
             return fail(BEM_ERR_INVALID, "floating body without panels");
 
     API_TRY
@@ -233,7 +233,8 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         c->h_body_kind[b] = bodies[b].kind;
         c->h_epsp[b] = bodies[b].eps_plus;
         c->h_epsm[b] = bodies[b].eps_minus;
-        if (bodies[b].kind == BEM_FLOATING) c->h_body_fidx[b] = c->n_float++;
+        if (bodies[b].kind == BEM_FLOATING || bodies[b].kind == BEM_FLOATING_SHEET) c->h_body_fidx[b] = c->n_float++;
+        if (bodies[b].kind == BEM_FLOATING_SHEET) c->has_sheet = true;
     }
     c->n = c->N + c->n_float;
     c->ld = (c->n + 31) / 32 * 32;
@@ -258,7 +259,12 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     upload(c->vert, vert, (size_t)(3 * n_vert), s);
     upload(c->tri, tri, (size_t)(3 * n_tri), s);
     upload(c->tri_body, tri_body, (size_t)n_tri, s);
-    upload(c->body_kind, c->h_body_kind.data(), (size_t)n_body, s);
+    // on the device a sheet is a floating body (its rows, columns and stop code); only the
+    // constraint row, built on the host's kind list, differs
+    std::vector<int32_t> dkind(c->h_body_kind);
+    for (int32_t& k : dkind)
+        if (k == BEM_FLOATING_SHEET) k = BEM_FLOATING;
+    upload(c->body_kind, dkind.data(), (size_t)n_body, s);
     upload(c->body_epsp, c->h_epsp.data(), (size_t)n_body, s);
     upload(c->body_epsm, c->h_epsm.data(), (size_t)n_body, s);
     upload(c->body_fidx, c->h_body_fidx.data(), (size_t)n_body, s);
@@ -312,7 +318,7 @@ bem_status bem_assemble(bem_ctx* c) {
                   : sizeof(double) * (size_t)n * ld;
     need += sizeof(uint64_t) * (size_t)nblk * N;                 // near masks
     need += (size_t)N * 160 * (mixed ? 16 : 8);                   // near list, ~90-160 pairs per row
-    if (c->opt.constraint_form == 0) need += sizeof(double) * nflt * N;
+    if (c->opt.constraint_form == 0 || c->has_sheet) need += sizeof(double) * nflt * N;
     size_t free_b = 0, total_b = 0;
     BEM_HIP(hipMemGetInfo(&free_b, &total_b));
     const size_t have = free_b + c->A64.bytes + c->A32.bytes + c->Kf.bytes + c->near_col.bytes + c->near_row.bytes +
@@ -328,7 +334,7 @@ bem_status bem_assemble(bem_ctx* c) {
         c->A32.release();
         c->A64.alloc(sizeof(double) * (size_t)n * ld);
     }
-    if (c->opt.constraint_form == 0 && nflt > 0) c->Kf.alloc(sizeof(double) * nflt * N);
+    if ((c->opt.constraint_form == 0 || c->has_sheet) && nflt > 0) c->Kf.alloc(sizeof(double) * nflt * N);
     c->nearmask.alloc(sizeof(uint64_t) * nblk * N);
     c->diag.alloc(sizeof(double) * ld);
     bem::launch_far_assemble(c);
@@ -338,7 +344,7 @@ bem_status bem_assemble(bem_ctx* c) {
     bem::launch_near_assemble(c);
     bem::launch_finalize(c);
     c->nearmask.release();
-    if (c->opt.constraint_form == 0) c->Kf.release();
+    if (c->opt.constraint_form == 0 || c->has_sheet) c->Kf.release();
     BEM_HIP(hipStreamSynchronize(c->stream));
     c->assembled = true;
     return BEM_OK;
@@ -523,6 +529,7 @@ bem_status bem_streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_
     API_TRY
     if (!c->assembled) throw bem::Error(BEM_ERR_STATE, "assemble the system first");
     if (c->opt.precision != BEM_FP64) throw bem::Error(BEM_ERR_INVALID, "the gradient needs precision FP64");
+    if (c->has_sheet) throw bem::Error(BEM_ERR_INVALID, "the gradient does not support thin floating sheets");
     check_trace(c, nrhs, sol, L, line_rhs, starts, tp);
     if (!(tp->alpha_p >= 1.0)) throw bem::Error(BEM_ERR_INVALID, "the gradient needs alpha_p >= 1");
     if (!(tol > 0.0) || !(tol < 1.0)) throw bem::Error(BEM_ERR_INVALID, "tol must be in (0, 1)");

@@ -175,18 +175,22 @@ __global__ __launch_bounds__(256) void k_near(const double* __restrict__ tri64, 
     if (Kf && kind == BEM_FLOATING) Kf[(int64_t)row_slot[i] * N + j] = kp;
 }
 
-// Constraint row of one floating body (Eq. Final4 scaled by 1/(eps+ sum a_i)):
-// row[j] = sum_{i in body} a_i (delta_ij / 2 + K'_ij) / sum_{i in body} a_i
+// Constraint row of one floating body:
+// row[j] = sum_{i in body} a_i (c_self delta_ij + c_kp K'_ij) / sum_{i in body} a_i
+// with (c_self, c_kp) = (1/2, 1) for a closed body (Eq. Final4, eps+ (sigma/2 + K' sigma), scaled
+// by 1/(eps+ sum a_i)) and (1, 2 (eps+ - eps-) / (eps+ + eps-)) for a thin sheet (Eq. sheets,
+// (eps+ + eps-)/2 sigma + (eps+ - eps-) K' sigma, scaled by 2/((eps+ + eps-) sum a_i)).
 __global__ __launch_bounds__(256) void k_constraint(const double* __restrict__ Kf, int64_t N,
                                                     const int32_t* __restrict__ rows_flt, int64_t s0, int64_t s1,
-                                                    const double* __restrict__ tri64, double* __restrict__ out) {
+                                                    const double* __restrict__ tri64, double c_self, double c_kp,
+                                                    double* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= N) return;
     double acc = 0.0, asum = 0.0;
     for (int64_t s = s0; s < s1; ++s) {
         const int64_t i = rows_flt[s];
         const double a = tri64[(int64_t)TRI_REC * i + TR_A];
-        acc += a * (Kf[s * N + j] + (i == j ? 0.5 : 0.0));
+        acc += a * (c_kp * Kf[s * N + j] + (i == j ? c_self : 0.0));
         asum += a;
     }
     out[j] = acc / asum;
@@ -314,7 +318,7 @@ void launch_far_assemble(bem_ctx* c) {
     launch(0, c->rows_pot, npot, nullptr, false, true, A, c->ld, mixed);
     launch(1, c->rows_int, nint, scale_int, false, true, A, c->ld, mixed);
     // K' block of floating rows (FP64 in both modes) for the constraint rows
-    if (nflt > 0 && c->opt.constraint_form == 0)
+    if (nflt > 0 && (c->opt.constraint_form == 0 || c->has_sheet))
         launch(1, c->rows_flt, nflt, scale_one, true, false, c->Kf.p, c->N, false);
 }
 
@@ -344,7 +348,8 @@ void launch_near_assemble(bem_ctx* c) {
     KTimer t(c, "near_assemble");
     const bool mixed = c->opt.precision == BEM_MIXED;
     if (c->near_nnz == 0) return;
-    double* Kf = (c->opt.constraint_form == 0 && !c->h_rows_flt.empty()) ? c->Kf.as<double>() : nullptr;
+    double* Kf = ((c->opt.constraint_form == 0 || c->has_sheet) && !c->h_rows_flt.empty()) ? c->Kf.as<double>()
+                                                                                              : nullptr;
     hipLaunchKernelGGL(k_near, dim3((unsigned)ceil_div(c->near_nnz, 256)), dim3(256), 0, c->stream,
                        c->tri64.as<double>(), c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(),
                        c->body_epsp.as<double>(), c->body_epsm.as<double>(), c->row_slot.as<int32_t>(), c->near_nnz,
@@ -368,10 +373,16 @@ void launch_finalize(bem_ctx* c) {
             if (c->h_body_fidx[b] == f) fb = b;
         int64_t s1 = s0;
         while (s1 < (int64_t)c->h_rows_flt.size() && c->h_tri_body[c->h_rows_flt[s1]] == fb) ++s1;
-        if (c->opt.constraint_form == 0)
+        const bool sheet = c->h_body_kind[fb] == BEM_FLOATING_SHEET;
+        if (sheet) {   // Eq. sheets, whatever the constraint form
+            const double ep = c->h_epsp[fb], em = c->h_epsm[fb];
             hipLaunchKernelGGL(k_constraint, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream,
-                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(),
-                               tail + (int64_t)f * ld);
+                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), 1.0,
+                               2.0 * (ep - em) / (ep + em), tail + (int64_t)f * ld);
+        } else if (c->opt.constraint_form == 0)
+            hipLaunchKernelGGL(k_constraint, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream,
+                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), 0.5,
+                               1.0, tail + (int64_t)f * ld);
         else
             hipLaunchKernelGGL(k_constraint_reduced, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream, N,
                                c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), tail + (int64_t)f * ld);

@@ -196,7 +196,8 @@ int autotune(bem_ctx* c, const char* cache_path) {
     {
         const int64_t nblk = ceil_div(N, 64);
         c->nearmask.alloc(sizeof(uint64_t) * nblk * N);
-        if (c->opt.constraint_form == 0 && !c->h_rows_flt.empty()) c->Kf.alloc(sizeof(double) * c->h_rows_flt.size() * N);
+        if ((c->opt.constraint_form == 0 || c->has_sheet) && !c->h_rows_flt.empty())
+            c->Kf.alloc(sizeof(double) * c->h_rows_flt.size() * N);
         c->tune_far_rows = pick(c, {32, 64, 128}, 64, [&](int v) {
             c->tune_far_rows = v;
             launch_far_assemble(c);

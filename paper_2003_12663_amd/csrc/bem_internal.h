@@ -109,7 +109,8 @@ struct bem_ctx {
     double shift[3] = {0, 0, 0};   // mesh translated by -shift on the device (FP32 accuracy)
     double min_R = 0.0;
 
-    std::vector<int32_t> h_tri, h_tri_body, h_body_kind, h_body_fidx;
+    std::vector<int32_t> h_tri, h_tri_body, h_body_kind, h_body_fidx;   // h_body_kind: as given (sheets kept)
+    bool has_sheet = false;   // some floating body is a thin sheet (its constraint row needs the K' block)
     std::vector<double> h_epsp, h_epsm;
     std::vector<int32_t> h_rows_pot, h_rows_int, h_rows_flt;   // row segments by kind (Sec. 4)
 
