@@ -27,7 +27,9 @@
 
 #define ORC_PI 3.14159265358979323846
 
-enum { ORC_DIRICHLET = 0, ORC_FLOATING = 1, ORC_INTERFACE = 2 };
+/* ORC_SHEET: thin floating sheet, one (open) surface, constraint row of Eq. sheets */
+enum { ORC_DIRICHLET = 0, ORC_FLOATING = 1, ORC_INTERFACE = 2, ORC_SHEET = 3 };
+static int is_floating_kind(int32_t kind) { return kind == ORC_FLOATING || kind == ORC_SHEET; }
 
 typedef struct {
     int64_t n_vert;
@@ -133,7 +135,7 @@ static void dgeom_build(const orc_problem* p, const double* dvert, dgeom* g)
     }
     g->fidx = (int32_t*)malloc(sizeof(int32_t) * (p->n_body > 0 ? p->n_body : 1));
     g->n_float = 0;
-    for (int32_t b = 0; b < p->n_body; ++b) g->fidx[b] = (p->body_kind[b] == ORC_FLOATING) ? g->n_float++ : -1;
+    for (int32_t b = 0; b < p->n_body; ++b) g->fidx[b] = is_floating_kind(p->body_kind[b]) ? g->n_float++ : -1;
 }
 
 static void dgeom_free(dgeom* g)
@@ -253,14 +255,14 @@ static void dassemble_row(const orc_problem* p, const dgeom* g, int64_t row, dou
         int32_t b = p->tri_body[i];
         int32_t kind = p->body_kind[b];
         const dl* xi = g->cen + 3 * i;
-        if (kind == ORC_DIRICHLET || kind == ORC_FLOATING) {
+        if (kind == ORC_DIRICHLET || is_floating_kind(kind)) {
             for (int64_t j = 0; j < N; ++j) {
                 dl S, F[3];
                 dpair(p, g, xi, j, j == i, &S, F);
                 Av[j] = S.v;
                 Ad[j] = S.d;
             }
-            if (kind == ORC_FLOATING) Av[N + g->fidx[b]] = -1.0;
+            if (is_floating_kind(kind)) Av[N + g->fidx[b]] = -1.0;
         } else {
             double ep = p->eps_plus[b], em = p->eps_minus[b];
             for (int64_t j = 0; j < N; ++j) {
@@ -280,6 +282,12 @@ static void dassemble_row(const orc_problem* p, const dgeom* g, int64_t row, dou
     int32_t f = (int32_t)(row - N), fb = -1;
     for (int32_t b = 0; b < p->n_body; ++b)
         if (g->fidx[b] == f) fb = b;
+    /* (coefficient of sigma_i, of (K' sigma)_i) after the row scaling: a closed body's Eq. Final4
+       over eps+ sum a gives (1/2, 1); a sheet's Eq. sheets over (eps+ + eps-)/2 sum a gives
+       (1, 2 (eps+ - eps-) / (eps+ + eps-)), whatever constraint_form says */
+    const int sheet = p->body_kind[fb] == ORC_SHEET;
+    const double c_self = sheet ? 1.0 : 0.5;
+    const double c_kp = sheet ? 2.0 * (p->eps_plus[fb] - p->eps_minus[fb]) / (p->eps_plus[fb] + p->eps_minus[fb]) : 1.0;
     dl asum = cst(0.0);
     for (int64_t i = 0; i < N; ++i)
         if (p->tri_body[i] == fb) asum = add(asum, g->area[i]);
@@ -287,20 +295,20 @@ static void dassemble_row(const orc_problem* p, const dgeom* g, int64_t row, dou
     for (int64_t j = 0; j < N; ++j) acc[j] = cst(0.0);
     for (int64_t i = 0; i < N; ++i) {
         if (p->tri_body[i] != fb) continue;
-        dl wi = dvd(g->area[i], asum);   /* a_i eps+ / (eps+ sum a) */
-        if (p->constraint_form == 1) {
+        dl wi = dvd(g->area[i], asum);   /* a_i / sum a */
+        if (p->constraint_form == 1 && !sheet) {
             acc[i] = add(acc[i], wi);
             continue;
         }
         const dl* xi = g->cen + 3 * i;
         for (int64_t j = 0; j < N; ++j) {
             if (j == i) {
-                acc[j] = add(acc[j], scl(wi, 0.5));
+                acc[j] = add(acc[j], scl(wi, c_self));
                 continue;
             }
             dl S, F[3];
             dpair(p, g, xi, j, 0, &S, F);
-            acc[j] = add(acc[j], mul(wi, vdot(g->nrm + 3 * i, F)));
+            acc[j] = add(acc[j], scl(mul(wi, vdot(g->nrm + 3 * i, F)), c_kp));
         }
     }
     for (int64_t j = 0; j < N; ++j) {
@@ -371,10 +379,6 @@ int orc_dual_streamer(const orc_problem* p, const double* dvert, const double* b
                       const orc_trace_params* tp, const int32_t* n_steps, double tol, double* u_out, double* du_out,
                       double* I, double* dI)
 {
-    /* thin floating sheets (body kind 3, Eq. sheets) are not differentiated here */
-    for (int32_t b = 0; b < p->n_body; ++b)
-        if (p->body_kind[b] != ORC_DIRICHLET && p->body_kind[b] != ORC_FLOATING && p->body_kind[b] != ORC_INTERFACE)
-            return -2;
     dgeom g;
     dgeom_build(p, dvert, &g);
     int64_t N = p->n_tri, n = N + g.n_float;

@@ -7,7 +7,7 @@ It is pinned here by things that do not come from it:
   * its derivative equals central finite differences of the plain oracle
     (mesh, solve, line starts and lines all recomputed at the perturbed
     vertices, h = 1e-6), for conductor, floating-conductor (both constraint
-    forms) and dielectric-interface rows, and for body potentials,
+    forms), thin-sheet and dielectric-interface rows, and for body potentials,
   * rigid motions of the whole mesh (line starts move with their panels) leave
     every integral unchanged, so the derivative along a translation or an
     infinitesimal rotation vanishes.
@@ -21,7 +21,8 @@ import dataclasses
 import numpy as np
 import pytest
 
-from workloads import coated_sphere_problem, coax_problem, electrode_line_starts, floating_shell_problem, sphere_problem
+from workloads import (bushing_problem, coated_sphere_problem, coax_problem, electrode_line_starts, floating_shell_problem,
+                       sphere_problem, sphere_sheet_problem, union_problem)
 
 
 def _setup(oracle_mod, p, L, steps, h, constraint_form=0, seed=6):
@@ -45,6 +46,11 @@ def _plain_I(oracle_mod, p, vert, body_V, panel, bary, tp, constraint_form=0):
     return ns, st, I
 
 
+def _sheet_and_shell():
+    return union_problem(sphere_sheet_problem(1, V0=100.0, eps_in=4.0), floating_shell_problem(1, V0=50.0),
+                         (6.0, 0.0, 0.0))
+
+
 CASES = [
     # (problem, lines, steps, h, constraint form)
     ("sphere", lambda: sphere_problem(1, V0=50.0), 4, 60, 1e-2, 0),
@@ -53,7 +59,21 @@ CASES = [
     ("coated_sphere", lambda: coated_sphere_problem(1, V0=200.0), 4, 30, 5e-3, 0),
     # coplanar panels (disc faces, caps): collocation points in the plane of other panels
     ("coarse_coax", lambda: coax_problem(0.03, V0=30.0), 3, 60, 2e-4, 0),
+    # a thin floating sheet between two dielectrics (Eq. sheets row, K' weighted by eps+ - eps-)
+    ("sphere_sheet", lambda: sphere_sheet_problem(1, V0=100.0, eps_in=4.0), 4, 30, 5e-3, 0),
+    # two floating bodies with different constraint rows: the sheet above and a closed shell,
+    # the shell's row literal (form 0) or the net charge (form 1)
+    ("sheet_and_shell", lambda: _sheet_and_shell(), 6, 30, 5e-3, 0),
+    ("sheet_and_shell_reduced", lambda: _sheet_and_shell(), 6, 30, 5e-3, 1),
+    # four floating sheets in one insulator (eps+ = eps-) and its interface; lines end on the first foil
+    ("bushing", lambda: bushing_problem(0.08, V0=5.0), 6, 40, 2e-3, 0),
 ]
+
+
+# Residual of the dual solves: 1e-15 where GMRES reaches it, else the smallest it reaches.  The
+# default 1e-13 leaves ~cond(A) 1e-13 of solution error (cond ~ 5e2 on the two-device case),
+# more than the 1e-12 value-part bar.
+DUAL_TOL = {"coarse_coax": 1e-13, "bushing": 1e-14}
 
 
 @pytest.mark.parametrize("name,make,L,steps,h,cf", CASES, ids=[c[0] for c in CASES])
@@ -63,7 +83,7 @@ def test_dual_matches_finite_differences(oracle_mod, name, make, L, steps, h, cf
     ns, st, I0 = _plain_I(oracle_mod, p, p.vert, p.body_V, panel, bary, tp, cf)
     assert np.all(I0 > 0.0), "the case must have a non-trivial integral"
     dv = np.random.default_rng(8).standard_normal(p.vert.shape)
-    I, dI, u, du, rc = o.dual_streamer(dv, p.body_V, None, panel, bary, tp, ns)
+    I, dI, u, du, rc = o.dual_streamer(dv, p.body_V, None, panel, bary, tp, ns, tol=DUAL_TOL.get(name, 1e-15))
     assert rc == 0
     # value part = the plain oracle
     assert np.max(np.abs(I - I0)) <= 1e-12 * np.max(np.abs(I0))

@@ -17,6 +17,7 @@ from .meshes import (  # noqa: F401
     coax_problem_for_size,
     sphere_sheet_problem,
     bushing_problem,
+    union_problem,
 )
 from .seeds import (  # noqa: F401
     sphere_eval_points,

@@ -273,6 +273,23 @@ def sphere_sheet_problem(level=3, a=1.0, b=2.0, eps_in=4.0, eps_out=1.0, V0=1.0)
         start_mask=body == 0)
 
 
+def union_problem(p: Problem, q: Problem, offset=(0.0, 0.0, 0.0)) -> Problem:
+    """Both devices in one problem: q translated by offset, its bodies numbered after p's."""
+    sm_p = p.start_mask if p.start_mask is not None else np.zeros(p.n_tri, dtype=bool)
+    sm_q = q.start_mask if q.start_mask is not None else np.zeros(q.n_tri, dtype=bool)
+    return Problem(
+        name=f"{p.name}+{q.name}",
+        vert=np.concatenate([p.vert, q.vert + np.asarray(offset, dtype=np.float64)]),
+        tri=np.concatenate([p.tri, q.tri + p.n_vert]).astype(np.int32),
+        tri_body=np.concatenate([p.tri_body, q.tri_body + p.n_body]).astype(np.int32),
+        body_kind=np.concatenate([p.body_kind, q.body_kind]).astype(np.int32),
+        eps_plus=np.concatenate([p.eps_plus, q.eps_plus]),
+        eps_minus=np.concatenate([p.eps_minus, q.eps_minus]),
+        body_V=np.concatenate([p.body_V, q.body_V]),
+        body_names=list(p.body_names) + list(q.body_names),
+        start_mask=np.concatenate([sm_p, sm_q]))
+
+
 def _open_cylinder(b: _Builder, body, r, zlo, zhi, h):
     """Side surface only (no caps), normals pointing outward (+rho)."""
     n = _n_around(r, h)
