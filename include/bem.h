@@ -215,7 +215,7 @@ bem_status bem_streamer_integral(bem_ctx* ctx, int32_t nrhs, const double* sol, 
  *  dJ_dvert     dev [n_vert][3] (written)
  *  dJ_dV        dev [nrhs][n_body] (written; 0 for non-conductor bodies)
  *  dJ_dstart    dev [L][3] or NULL: dJ/d starts[l] at fixed mesh
- * FP64 precision only; alpha_p >= 1; no FLOATING_SHEET bodies.  Errors: STATE (not assembled), INVALID,
+ * FP64 precision only; alpha_p >= 1.  Errors: STATE (not assembled), INVALID,
  * NOCONV (an adjoint solve missed tol), OOM, HIP. */
 bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t L,
                              const int32_t* line_rhs, const double* starts, const int32_t* start_panel,

@@ -291,22 +291,25 @@ __global__ __launch_bounds__(256) void k_pan_fold(double* __restrict__ acc, int6
 }
 
 // ---- point side of the system rows ------------------------------------------------------
-// Q_i of the constraint rows (floating panels): literal form Q = sigma_i / 2 + n_i . E_i,
-// reduced form Q = sigma_i.
+// Q_i of the constraint rows (floating panels): Q = c_self sigma_i + c_kp n_i . E_i with the
+// body's coefficients coef[2f], coef[2f+1] (closed body literal (1/2, 1) or reduced (1, 0),
+// thin sheet (1, 2 (eps+ - eps-) / (eps+ + eps-)), Eq. Final4 and Eq. sheets).
 __global__ __launch_bounds__(256) void k_row_Q(int64_t N, const int32_t* __restrict__ tri_body,
-                                               const int32_t* __restrict__ body_kind, const double* __restrict__ tri64,
-                                               const double* __restrict__ sigma, const double* __restrict__ EH,
-                                               int constraint_form, double* __restrict__ Q) {
+                                               const int32_t* __restrict__ body_kind,
+                                               const int32_t* __restrict__ fidx, const double* __restrict__ coef,
+                                               const double* __restrict__ tri64, const double* __restrict__ sigma,
+                                               const double* __restrict__ EH, double* __restrict__ Q) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    if (body_kind[tri_body[i]] != BEM_FLOATING) {
+    const int32_t b = tri_body[i];
+    if (body_kind[b] != BEM_FLOATING) {
         Q[i] = 0.0;
         return;
     }
+    const int f = fidx[b];
     const double* T = tri64 + (int64_t)TRI_REC * i;
     const double* e = EH + i * 9;
-    Q[i] = constraint_form == 0 ? 0.5 * sigma[i] + (T[TR_N] * e[0] + T[TR_N + 1] * e[1] + T[TR_N + 2] * e[2])
-                                : sigma[i];
+    Q[i] = coef[2 * f] * sigma[i] + coef[2 * f + 1] * (T[TR_N] * e[0] + T[TR_N + 1] * e[1] + T[TR_N + 2] * e[2]);
 }
 
 // Per floating body f (one block each, panels rows_flt[s0[f] .. s0[f+1])): A_f = sum a_i and
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(256) void k_float_sums(const int32_t* __restrict__ 
 
 // Row weights and the point-side terms of -lambda^T (dA) u for row i:
 //   wS = lambda_i on conductor/floating rows, wK = lambda_i (eps+ - eps-) on interface rows,
-//   plus lambda_f a_i / A_f on floating rows (literal constraint);
+//   plus lambda_f c_kp a_i / A_f on floating rows;
 //   GX_i -= -wS E_i + wK H_i n_i,  GN_i -= wK E_i,  GA_i -= lambda_f (Q_i - c_f) / A_f.
 __global__ __launch_bounds__(256) void k_row_adj(int64_t N, const int32_t* __restrict__ tri_body,
                                                  const int32_t* __restrict__ body_kind, const double* __restrict__ epsp,
@@ -349,7 +352,8 @@ __global__ __launch_bounds__(256) void k_row_adj(int64_t N, const int32_t* __res
                                                  const double* __restrict__ tri64, const double* __restrict__ lam,
                                                  const double* __restrict__ EH, const double* __restrict__ Q,
                                                  const double* __restrict__ Af, const double* __restrict__ cf,
-                                                 int constraint_form, double* __restrict__ aw, double* __restrict__ cw,
+                                                 const double* __restrict__ coef, double* __restrict__ aw,
+                                                 double* __restrict__ cw,
                                                  double* __restrict__ GX, double* __restrict__ GN,
                                                  double* __restrict__ GA) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -365,7 +369,7 @@ __global__ __launch_bounds__(256) void k_row_adj(int64_t N, const int32_t* __res
     if (kind == BEM_FLOATING) {
         const int f = fidx[b];
         const double lf = lam[N + f];
-        if (constraint_form == 0) wK += lf * area / Af[f];
+        wK += lf * coef[2 * f + 1] * area / Af[f];
         GA[i] -= lf * (Q[i] - cf[f]) / Af[f];
     }
     const double* e = EH + i * 9;   // E (3), H xx yy zz xy xz yz
@@ -678,7 +682,8 @@ void streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const
         // 8. matrix terms, point side: E and dE/dx at the centroids for sigma_r
         launch_rows_EH(c, sig_r, N, cen, EH);
         hipLaunchKernelGGL(k_row_Q, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, N, c->tri_body.as<int32_t>(),
-                           c->body_kind.as<int32_t>(), c->tri64.as<double>(), sig_r, EH, c->opt.constraint_form, Qb);
+                           c->body_kind.as<int32_t>(), c->body_fidx.as<int32_t>(), c->flt_coef.as<double>(),
+                           c->tri64.as<double>(), sig_r, EH, Qb);
         BEM_CHECK_LAUNCH();
         if (c->n_float > 0) {
             hipLaunchKernelGGL(k_float_sums, dim3((unsigned)c->n_float), dim3(256), 0, s, c->rows_flt.as<int32_t>(),
@@ -688,7 +693,7 @@ void streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const
         hipLaunchKernelGGL(k_row_adj, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, N,
                            c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), c->body_epsp.as<double>(),
                            c->body_epsm.as<double>(), c->body_fidx.as<int32_t>(), c->tri64.as<double>(), lam, EH, Qb,
-                           Af, cf, c->opt.constraint_form, awb, cwb, GX, GN, GA);
+                           Af, cf, c->flt_coef.as<double>(), awb, cwb, GX, GN, GA);
         BEM_CHECK_LAUNCH();
         // 9. matrix terms, panel side (row weights as point weights; self pairs move with the panel)
         panel_side(c, N, cen, awb, cwb, true, acc);

@@ -238,6 +238,21 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     }
     c->n = c->N + c->n_float;
     c->ld = (c->n + 31) / 32 * 32;
+    c->h_flt_coef.assign(2 * (size_t)std::max(c->n_float, 1), 0.0);
+    for (int32_t b = 0; b < n_body; ++b) {
+        const int32_t f = c->h_body_fidx[b];
+        if (f < 0) continue;
+        double cs = 0.5, ck = 1.0;   // Eq. Final4 over eps+ sum a
+        if (bodies[b].kind == BEM_FLOATING_SHEET) {   // Eq. sheets over (eps+ + eps-) / 2 sum a
+            cs = 1.0;
+            ck = 2.0 * (bodies[b].eps_plus - bodies[b].eps_minus) / (bodies[b].eps_plus + bodies[b].eps_minus);
+        } else if (o.constraint_form == 1) {   // net charge
+            cs = 1.0;
+            ck = 0.0;
+        }
+        c->h_flt_coef[2 * f] = cs;
+        c->h_flt_coef[2 * f + 1] = ck;
+    }
     // row segments by kind (Sec. 4: rows grouped by type); floating rows sorted by
     // (body, panel) so that each body's rows are contiguous
     std::vector<int32_t> slot(n_tri, -1);
@@ -268,6 +283,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     upload(c->body_epsp, c->h_epsp.data(), (size_t)n_body, s);
     upload(c->body_epsm, c->h_epsm.data(), (size_t)n_body, s);
     upload(c->body_fidx, c->h_body_fidx.data(), (size_t)n_body, s);
+    upload(c->flt_coef, c->h_flt_coef.data(), c->h_flt_coef.size(), s);
     upload(c->rows_pot, c->h_rows_pot.data(), c->h_rows_pot.size(), s);
     upload(c->rows_int, c->h_rows_int.data(), c->h_rows_int.size(), s);
     upload(c->rows_flt, c->h_rows_flt.data(), c->h_rows_flt.size(), s);
@@ -529,7 +545,6 @@ bem_status bem_streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_
     API_TRY
     if (!c->assembled) throw bem::Error(BEM_ERR_STATE, "assemble the system first");
     if (c->opt.precision != BEM_FP64) throw bem::Error(BEM_ERR_INVALID, "the gradient needs precision FP64");
-    if (c->has_sheet) throw bem::Error(BEM_ERR_INVALID, "the gradient does not support thin floating sheets");
     check_trace(c, nrhs, sol, L, line_rhs, starts, tp);
     if (!(tp->alpha_p >= 1.0)) throw bem::Error(BEM_ERR_INVALID, "the gradient needs alpha_p >= 1");
     if (!(tol > 0.0) || !(tol < 1.0)) throw bem::Error(BEM_ERR_INVALID, "tol must be in (0, 1)");

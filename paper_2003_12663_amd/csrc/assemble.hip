@@ -373,16 +373,11 @@ void launch_finalize(bem_ctx* c) {
             if (c->h_body_fidx[b] == f) fb = b;
         int64_t s1 = s0;
         while (s1 < (int64_t)c->h_rows_flt.size() && c->h_tri_body[c->h_rows_flt[s1]] == fb) ++s1;
-        const bool sheet = c->h_body_kind[fb] == BEM_FLOATING_SHEET;
-        if (sheet) {   // Eq. sheets, whatever the constraint form
-            const double ep = c->h_epsp[fb], em = c->h_epsm[fb];
+        // Eq. sheets for a sheet whatever the constraint form; Eq. Final4 literal for a closed body
+        if (c->h_body_kind[fb] == BEM_FLOATING_SHEET || c->opt.constraint_form == 0)
             hipLaunchKernelGGL(k_constraint, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream,
-                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), 1.0,
-                               2.0 * (ep - em) / (ep + em), tail + (int64_t)f * ld);
-        } else if (c->opt.constraint_form == 0)
-            hipLaunchKernelGGL(k_constraint, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream,
-                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), 0.5,
-                               1.0, tail + (int64_t)f * ld);
+                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(),
+                               c->h_flt_coef[2 * f], c->h_flt_coef[2 * f + 1], tail + (int64_t)f * ld);
         else
             hipLaunchKernelGGL(k_constraint_reduced, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream, N,
                                c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), tail + (int64_t)f * ld);

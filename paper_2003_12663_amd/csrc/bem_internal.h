@@ -112,9 +112,13 @@ struct bem_ctx {
     std::vector<int32_t> h_tri, h_tri_body, h_body_kind, h_body_fidx;   // h_body_kind: as given (sheets kept)
     bool has_sheet = false;   // some floating body is a thin sheet (its constraint row needs the K' block)
     std::vector<double> h_epsp, h_epsm;
+    // per floating body f (index fidx): the constraint row after its scaling is
+    // sum_i a_i (c_self sigma_i + c_kp (K' sigma)_i) / sum_i a_i, with (c_self, c_kp) at [2f], [2f+1]:
+    // closed body (1/2, 1) literal or (1, 0) reduced, sheet (1, 2 (eps+ - eps-) / (eps+ + eps-))
+    std::vector<double> h_flt_coef;
     std::vector<int32_t> h_rows_pot, h_rows_int, h_rows_flt;   // row segments by kind (Sec. 4)
 
-    bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx;
+    bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx, flt_coef;
     bem::DBuf far64, far32, tri64;
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;

@@ -10,8 +10,8 @@ rigid-motion invariance and the autograd wrapper.
 import numpy as np
 import pytest
 
-from workloads import (coated_sphere_problem, coax_problem_for_size, electrode_line_starts, floating_shell_problem,
-                       sphere_problem)
+from workloads import (bushing_problem, coated_sphere_problem, coax_problem_for_size, electrode_line_starts,
+                       floating_shell_problem, sphere_problem, sphere_sheet_problem, union_problem)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,12 +65,24 @@ def _oracle_dir(oracle_mod, p, c, dvert, dV, cf=0):
     return J, dJ
 
 
+def _sheet_and_shell():
+    return union_problem(sphere_sheet_problem(1, V0=100.0, eps_in=4.0), floating_shell_problem(1, V0=50.0),
+                         (6.0, 0.0, 0.0))
+
+
 CASES = [
     ("sphere", lambda: sphere_problem(1, V0=50.0), 4, 60, 1e-2, 0, 1),
     ("floating_shell_hits", lambda: floating_shell_problem(1, V0=50.0), 6, 200, 5e-3, 0, 1),
     ("floating_shell_reduced", lambda: floating_shell_problem(1, V0=50.0), 4, 30, 5e-3, 1, 1),
     ("coated_sphere", lambda: coated_sphere_problem(1, V0=200.0), 4, 30, 5e-3, 0, 1),
     ("sphere_two_load_cases", lambda: sphere_problem(2, V0=50.0), 6, 40, 1e-2, 0, 2),
+    # thin floating sheets (Eq. sheets): a sheet between two dielectrics, a sheet next to a closed
+    # floating shell (per-body constraint rows, both forms), a coarse bushing (four sheets and an
+    # insulator interface; lines end on the first foil)
+    ("sphere_sheet", lambda: sphere_sheet_problem(1, V0=100.0, eps_in=4.0), 4, 30, 5e-3, 0, 1),
+    ("sheet_and_shell", lambda: _sheet_and_shell(), 6, 30, 5e-3, 0, 1),
+    ("sheet_and_shell_reduced", lambda: _sheet_and_shell(), 6, 30, 5e-3, 1, 1),
+    ("bushing", lambda: bushing_problem(0.08, V0=5.0), 6, 40, 2e-3, 0, 2),
 ]
 
 

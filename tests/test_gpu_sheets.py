@@ -96,14 +96,3 @@ def test_bushing_mixed_precision(bem):
     assert rel(s32.cpu().numpy(), s64.cpu().numpy()) <= 1e-5
     c64.close()
     c32.close()
-
-
-def test_gradient_rejects_sheets(bem):
-    p, c = _bushing(bem)
-    sol, _ = c.solve(p.body_V, tol=1e-10, max_iter=20000)
-    starts, panel, bary = electrode_line_starts(p, 2, seed=3)
-    g = torch.ones(2, dtype=torch.float64, device="cuda")
-    with pytest.raises(bem.BemError):
-        c.streamer_grad(sol, torch.tensor(starts, device="cuda"), g, bem.trace_params(h=1e-3, max_steps=5),
-                        start_panel=panel, start_bary=bary)
-    c.close()
