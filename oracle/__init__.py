@@ -115,6 +115,33 @@ class Oracle:
         self.lib.orc_rhs(ctypes.byref(self.p), _ptr(bv), _ptr(b))
         return b
 
+    # -- nodal linear basis, vertex collocation (Sec. 3, Eq. Matrix) --
+    @property
+    def n_p1(self) -> int:
+        return int(self.lib.orc_p1_n_unknowns(ctypes.byref(self.p)))
+
+    def p1_assemble(self) -> np.ndarray:
+        A = np.empty((self.n_p1, self.n_p1), dtype=np.float64)
+        rc = self.lib.orc_p1_assemble(ctypes.byref(self.p), _ptr(A))
+        if rc != 0:
+            raise ValueError(f"orc_p1_assemble: {rc}")
+        return A
+
+    def p1_rhs(self, body_V) -> np.ndarray:
+        bv = _f64(body_V)
+        b = np.empty(self.n_p1, dtype=np.float64)
+        rc = self.lib.orc_p1_rhs(ctypes.byref(self.p), _ptr(bv), _ptr(b))
+        if rc != 0:
+            raise ValueError(f"orc_p1_rhs: {rc}")
+        return b
+
+    def p1_potential(self, u, pts) -> np.ndarray:
+        u = _f64(u)
+        pts = _f64(pts, (-1, 3))
+        phi = np.empty(len(pts), dtype=np.float64)
+        self.lib.orc_p1_potential(ctypes.byref(self.p), _ptr(u), ctypes.c_int64(len(pts)), _ptr(pts), _ptr(phi))
+        return phi
+
     def classify(self, pts) -> np.ndarray:
         pts = _f64(pts, (-1, 3))
         out = np.empty((len(pts), self.N), dtype=np.int32)
@@ -213,6 +240,15 @@ def tri_analytic(x, v1, v2, v3, on_plane=False):
     lib.orc_tri_analytic(_ptr(x), _ptr(v1), _ptr(v2), _ptr(v3), ctypes.c_int(int(on_plane)), ctypes.byref(S),
                          _ptr(F))
     return S.value, F
+
+
+def tri_linear_analytic(x, v1, v2, v3, on_plane=False):
+    """int lambda_k / (4 pi |x - y|) dS over the flat triangle for its three vertices."""
+    lib = _load()
+    out = np.empty(3, dtype=np.float64)
+    a = [_f64(v) for v in (x, v1, v2, v3)]
+    lib.orc_tri_linear_analytic(*[_ptr(v) for v in a], ctypes.c_int(1 if on_plane else 0), _ptr(out))
+    return out
 
 
 def tri_quad7(x, v1, v2, v3):

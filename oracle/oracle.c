@@ -4,7 +4,9 @@
  * A plain, slow, obviously-correct FP64 CPU implementation of the indirect
  * single-layer collocation BEM of "Dielectric Breakdown Prediction with
  * GPU-Accelerated BEM" (arXiv 2003.12663), discretised with flat triangles,
- * piecewise-constant virtual charge sigma and centroid collocation.  It exists
+ * piecewise-constant virtual charge sigma and centroid collocation, and (for
+ * conductor bodies) the paper's own nodal piecewise-linear basis with vertex
+ * collocation (the orc_p1_* functions).  It exists
  * only to check the GPU library: tests, the smoke check and the benchmark's
  * CPU-baseline leg may call it; the product path never does.  It shares no
  * source, header or table with the GPU library.
@@ -546,6 +548,227 @@ int orc_eval(const orc_problem* p, const double* sigma, int64_t P, const double*
         field_at(p, &g, sigma, pts + 3 * i, on_panel ? on_panel[i] : -1, &ph, e);
         if (phi) phi[i] = ph;
         for (int k = 0; k < 3; ++k) E[3 * i + k] = e[k];
+    }
+    geom_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------ nodal linear basis (Sec. 3)
+ * The paper's own discretisation: sigma_h = sum_k u_k psi_k with psi_k the
+ * continuous piecewise-linear hat of vertex k (1 at x_k, 0 at every other
+ * vertex, linear on each flat triangle), collocated at the vertices x_i.  The
+ * entry of Eq. Matrix, v_ik = int psi_k(y) / (4 pi |x_i - y|) dS, collects over
+ * the triangles tau that hold vertex k the integral of tau's barycentric
+ * coordinate of k.
+ *
+ * Closed form of int_T lambda_k(y) / |x - y| dS on a flat triangle.  With rho
+ * the projection of x on the plane, lambda_k is affine, so
+ *   lambda_k(y) = lambda_k(rho) + g_k . (y - rho),
+ *   g_k = n x (v_{k+2} - v_{k+1}) / (2 A)   (in-plane gradient of lambda_k),
+ * and int lambda_k / R = lambda_k(rho) int 1/R + g_k . int (y - rho)/R.
+ * int 1/R dS is the unit-density closed form above.  The in-plane gradient of
+ * R = |x - y| is (y - rho)/R, so the divergence theorem in the plane gives
+ *   int (y - rho)/R dS = sum_e m_e int_e R dl,
+ *   int_e R dl = (s+ R+ - s- R- + R0^2 f_e) / 2     (edge notation as above).
+ * on_plane (x is a vertex of T) forces w = 0 and rho = x; an edge that ends at
+ * x then has t = R0 = 0, and its t f_e and R0^2 f_e terms vanish in the limit,
+ * so they are dropped (f_e is infinite there).
+ * out[k] = int lambda_k / (4 pi R) dS for the vertices in the order v1, v2, v3.
+ */
+void orc_tri_linear_analytic(const double x[3], const double v1[3], const double v2[3], const double v3[3],
+                             int on_plane, double out[3])
+{
+    const double* v[3] = {v1, v2, v3};
+    double e1[3], e2[3], cr[3], n[3];
+    sub3(v2, v1, e1);
+    sub3(v3, v1, e2);
+    cross3(e1, e2, cr);
+    double len = norm3(cr);   /* 2 A */
+    for (int k = 0; k < 3; ++k) n[k] = cr[k] / len;
+    double xv[3];
+    sub3(x, v1, xv);
+    double w = on_plane ? 0.0 : dot3(xv, n);
+    double rho[3];
+    for (int k = 0; k < 3; ++k) rho[k] = x[k] - w * n[k];
+    double aw = fabs(w);
+    double sum_tf = 0.0, sum_beta = 0.0, I1[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < 3; ++e) {
+        const double* a = v[e];
+        const double* b = v[(e + 1) % 3];
+        double ab[3], l[3], m[3];
+        sub3(b, a, ab);
+        double lab = norm3(ab);
+        for (int k = 0; k < 3; ++k) l[k] = ab[k] / lab;
+        cross3(l, n, m);
+        double ar[3], br[3], xa[3], xb[3];
+        sub3(a, rho, ar);
+        sub3(b, rho, br);
+        double sm = dot3(ar, l), sp = dot3(br, l), t = dot3(ar, m);
+        sub3(x, a, xa);
+        sub3(x, b, xb);
+        double Rm = norm3(xa), Rp = norm3(xb);
+        double edge_R = 0.5 * (sp * Rp - sm * Rm);
+        if (!(on_plane && (Rm == 0.0 || Rp == 0.0))) {
+            double R02 = t * t + w * w;
+            double f;
+            if (sp + sm > 0.0)
+                f = log((Rp + sp) / (Rm + sm));
+            else
+                f = log((Rm - sm) / (Rp - sp));
+            double beta = atan2(t * sp, R02 + aw * Rp) - atan2(t * sm, R02 + aw * Rm);
+            sum_tf += t * f;
+            sum_beta += beta;
+            edge_R += 0.5 * R02 * f;
+        }
+        for (int k = 0; k < 3; ++k) I1[k] += m[k] * edge_R;
+    }
+    double I0 = sum_tf - aw * sum_beta;
+    for (int k = 0; k < 3; ++k) {
+        const double* p1 = v[(k + 1) % 3];
+        const double* p2 = v[(k + 2) % 3];
+        double opp[3], g[3], r1[3], r2[3], c[3];
+        sub3(p2, p1, opp);
+        cross3(n, opp, g);
+        sub3(p1, rho, r1);
+        sub3(p2, rho, r2);
+        cross3(r1, r2, c);
+        double lam = dot3(c, n) / len;   /* barycentric coordinate of rho */
+        out[k] = (lam * I0 + dot3(g, I1) / len) / (4.0 * ORC_PI);
+    }
+}
+
+/* Vertex -> body map of the nodal basis.  Returns 0, or -1 if a vertex is in
+ * no triangle or in triangles of two bodies, -2 if a body is not a conductor
+ * (DIRICHLET) or floating conductor (FLOATING): interface and sheet rows need
+ * the normal at the collocation point, which a vertex of flat panels lacks. */
+static int p1_vertex_body(const orc_problem* p, int32_t* vb)
+{
+    for (int32_t b = 0; b < p->n_body; ++b)
+        if (p->body_kind[b] != ORC_DIRICHLET && p->body_kind[b] != ORC_FLOATING) return -2;
+    for (int64_t i = 0; i < p->n_vert; ++i) vb[i] = -1;
+    for (int64_t j = 0; j < p->n_tri; ++j)
+        for (int c = 0; c < 3; ++c) {
+            int32_t k = p->tri[3 * j + c];
+            if (vb[k] >= 0 && vb[k] != p->tri_body[j]) return -1;
+            vb[k] = p->tri_body[j];
+        }
+    for (int64_t i = 0; i < p->n_vert; ++i)
+        if (vb[i] < 0) return -1;
+    return 0;
+}
+
+/* The three hat integrals of triangle j at x (Sec. 4 classification: the
+ * 7-point rule with the rule's barycentric weights on regular pairs, the
+ * closed form otherwise; a vertex of j is always singular). */
+static void p1_pair(const orc_problem* p, const orc_geom* g, const double x[3], int64_t j, int is_vertex,
+                    double c[3])
+{
+    const double* v = g->v + 9 * j;
+    if (!is_vertex && pair_is_regular(p, g, x, j)) {
+        double bary[7][3], wt[7];
+        orc_quad7_rule(bary, wt);
+        c[0] = c[1] = c[2] = 0.0;
+        for (int q = 0; q < 7; ++q) {
+            double y[3], d[3];
+            for (int k = 0; k < 3; ++k) y[k] = bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
+            sub3(x, y, d);
+            double s = wt[q] * g->area[j] / (4.0 * ORC_PI) / norm3(d);
+            for (int k = 0; k < 3; ++k) c[k] += s * bary[q][k];
+        }
+    } else {
+        orc_tri_linear_analytic(x, v, v + 3, v + 6, is_vertex, c);
+    }
+}
+
+int64_t orc_p1_n_unknowns(const orc_problem* p)
+{
+    int32_t nf = 0;
+    for (int32_t b = 0; b < p->n_body; ++b) nf += p->body_kind[b] == ORC_FLOATING;
+    return p->n_vert + nf;
+}
+
+/* Dense row-major system of the nodal basis, n x n with n = n_vert + N_float,
+ * unknowns [u_1..u_nvert, V_1..V_Nfl]:
+ *   conductor vertex i   : sum_k v_ik u_k                 (= V_body)
+ *   floating vertex i in f: sum_k v_ik u_k - V_f          (= 0)
+ *   row of floating body f: sum_k u_k int_f psi_k / area_f  (= 0, net charge)
+ * with int_f psi_k = sum over the triangles of f holding k of area/3.  The
+ * literal Eq. Final4 row needs n . E at the collocation points, undefined at a
+ * vertex of flat panels; its Gauss-law reduction is the net charge.
+ * Returns 0, or the error of the vertex map. */
+int orc_p1_assemble(const orc_problem* p, double* A)
+{
+    int32_t* vb = (int32_t*)malloc(sizeof(int32_t) * (p->n_vert > 0 ? p->n_vert : 1));
+    int rc = p1_vertex_body(p, vb);
+    if (rc != 0) {
+        free(vb);
+        return rc;
+    }
+    orc_geom g;
+    geom_build(p, &g);
+    const int64_t nv = p->n_vert, n = orc_p1_n_unknowns(p);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nv; ++i) {
+        double* row = A + i * n;
+        for (int64_t k = 0; k < n; ++k) row[k] = 0.0;
+        const double* x = p->vert + 3 * i;
+        for (int64_t j = 0; j < p->n_tri; ++j) {
+            const int32_t* t = p->tri + 3 * j;
+            int is_vertex = (t[0] == i) || (t[1] == i) || (t[2] == i);
+            double c[3];
+            p1_pair(p, &g, x, j, is_vertex, c);
+            for (int k = 0; k < 3; ++k) row[t[k]] += c[k];
+        }
+        if (p->body_kind[vb[i]] == ORC_FLOATING) row[nv + g.fidx[vb[i]]] = -1.0;
+    }
+    for (int32_t b = 0; b < p->n_body; ++b) {
+        if (p->body_kind[b] != ORC_FLOATING) continue;
+        double* row = A + (nv + g.fidx[b]) * n;
+        for (int64_t k = 0; k < n; ++k) row[k] = 0.0;
+        double asum = 0.0;
+        for (int64_t j = 0; j < p->n_tri; ++j)
+            if (p->tri_body[j] == b) asum += g.area[j];
+        for (int64_t j = 0; j < p->n_tri; ++j)
+            if (p->tri_body[j] == b)
+                for (int k = 0; k < 3; ++k) row[p->tri[3 * j + k]] += g.area[j] / 3.0 / asum;
+    }
+    geom_free(&g);
+    free(vb);
+    return 0;
+}
+
+/* Right-hand side of the nodal system: V of the body on conductor vertex rows,
+ * 0 elsewhere.  Returns as orc_p1_assemble. */
+int orc_p1_rhs(const orc_problem* p, const double* body_V, double* b)
+{
+    int32_t* vb = (int32_t*)malloc(sizeof(int32_t) * (p->n_vert > 0 ? p->n_vert : 1));
+    int rc = p1_vertex_body(p, vb);
+    if (rc == 0) {
+        const int64_t n = orc_p1_n_unknowns(p);
+        for (int64_t i = 0; i < n; ++i) b[i] = 0.0;
+        for (int64_t i = 0; i < p->n_vert; ++i)
+            if (p->body_kind[vb[i]] == ORC_DIRICHLET) b[i] = body_V[vb[i]];
+    }
+    free(vb);
+    return rc;
+}
+
+/* phi(x) = sum_k u_k int psi_k / (4 pi |x - y|) dS at points off the mesh
+ * vertices (same classification as the assembly). */
+int orc_p1_potential(const orc_problem* p, const double* u, int64_t P, const double* pts, double* phi)
+{
+    orc_geom g;
+    geom_build(p, &g);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < P; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < p->n_tri; ++j) {
+            const int32_t* t = p->tri + 3 * j;
+            double c[3];
+            p1_pair(p, &g, pts + 3 * i, j, 0, c);
+            s += c[0] * u[t[0]] + c[1] * u[t[1]] + c[2] * u[t[2]];
+        }
+        phi[i] = s;
     }
     geom_free(&g);
     return 0;
