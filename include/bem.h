@@ -60,6 +60,20 @@ typedef enum {
 
 typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
 
+/* Discretisation of the virtual charge (Sec. 3).
+ *  CONSTANT: one value per flat triangle, collocated at the centroids (n = N + N_float).
+ *  LINEAR:   the paper's own nodal basis: continuous piecewise-linear hats of the vertices,
+ *            collocated at the vertices (Eq. Matrix; n = n_vert + N_float, unknowns
+ *            [u_1..u_nvert, V_1..V_Nfl]).  Conductor and floating-conductor bodies only
+ *            (interface and sheet rows need the normal at the collocation point, which a
+ *            vertex of flat panels lacks); a floating body's row is its net charge
+ *            (constraint_form must be 1); FP64 only; every vertex in at least one triangle and
+ *            all triangles at a vertex of one body.  Supported calls: bem_assemble,
+ *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres and the potential of
+ *            bem_eval_field; the field, field lines, the streamer integral, its gradient and
+ *            the autotuner need CONSTANT (INVALID otherwise). */
+typedef enum { BEM_BASIS_CONSTANT = 0, BEM_BASIS_LINEAR = 1 } bem_basis;
+
 /* One body.  Triangle normals (right-hand rule of the vertex order) point
  * into the eps_plus side. */
 typedef struct {
@@ -79,6 +93,7 @@ typedef struct {
                                 Regular pairs use the 7-point rule, the others closed forms. */
     int32_t restart;         /* GMRES restart length m, 1..1000 */
     int32_t constraint_form; /* 0: Eq. Final4 as printed (literal); 1: net charge sum a_i sigma_i = 0 */
+    int32_t basis;           /* bem_basis */
 } bem_options;
 
 typedef struct {
@@ -116,7 +131,7 @@ enum {
  *  tri       host [n_tri][3] vertex indices, CCW about the eps+ normal
  *  tri_body  host [n_tri] body index of each triangle
  *  bodies    host [n_body]
- *  opt       host; NULL = {FP64, eta 6, restart 100, literal constraint}
+ *  opt       host; NULL = {FP64, eta 6, restart 100, literal constraint, CONSTANT basis}
  *  hip_stream  a hipStream_t (NULL = default stream) of the current device
  * Errors: INVALID (indices, non-finite coordinates, kinds, options),
  * DEGENERATE (area <= 1e-14 * longest edge^2), HIP. */
@@ -126,7 +141,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
 void bem_destroy(bem_ctx* ctx);
 const char* bem_last_error(void);
 
-/* Number of unknowns n = N + N_float, and the leading dimension of the dense matrix. */
+/* Number of unknowns n (N + N_float, or n_vert + N_float for the LINEAR basis). */
 int64_t bem_n_unknowns(const bem_ctx* ctx);
 
 /* Assemble the collocation system of Eqs. Final1-Final4 (Sec. 4 quadrature:

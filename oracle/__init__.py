@@ -127,6 +127,14 @@ class Oracle:
             raise ValueError(f"orc_p1_assemble: {rc}")
         return A
 
+    def p1_assemble_rows(self, rows) -> np.ndarray:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.empty((len(rows), self.n_p1), dtype=np.float64)
+        rc = self.lib.orc_p1_assemble_rows(ctypes.byref(self.p), ctypes.c_int64(len(rows)), _ptr(rows), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"orc_p1_assemble_rows: {rc}")
+        return out
+
     def p1_rhs(self, body_V) -> np.ndarray:
         bv = _f64(body_V)
         b = np.empty(self.n_p1, dtype=np.float64)

@@ -696,6 +696,32 @@ int64_t orc_p1_n_unknowns(const orc_problem* p)
  * literal Eq. Final4 row needs n . E at the collocation points, undefined at a
  * vertex of flat panels; its Gauss-law reduction is the net charge.
  * Returns 0, or the error of the vertex map. */
+static void p1_row(const orc_problem* p, const orc_geom* g, const int32_t* vb, int64_t i, double* row)
+{
+    const int64_t nv = p->n_vert, n = orc_p1_n_unknowns(p);
+    for (int64_t k = 0; k < n; ++k) row[k] = 0.0;
+    if (i < nv) {
+        const double* x = p->vert + 3 * i;
+        for (int64_t j = 0; j < p->n_tri; ++j) {
+            const int32_t* t = p->tri + 3 * j;
+            int is_vertex = (t[0] == i) || (t[1] == i) || (t[2] == i);
+            double c[3];
+            p1_pair(p, g, x, j, is_vertex, c);
+            for (int k = 0; k < 3; ++k) row[t[k]] += c[k];
+        }
+        if (p->body_kind[vb[i]] == ORC_FLOATING) row[nv + g->fidx[vb[i]]] = -1.0;
+        return;
+    }
+    int32_t b = 0;
+    while (g->fidx[b] != i - nv) ++b;
+    double asum = 0.0;
+    for (int64_t j = 0; j < p->n_tri; ++j)
+        if (p->tri_body[j] == b) asum += g->area[j];
+    for (int64_t j = 0; j < p->n_tri; ++j)
+        if (p->tri_body[j] == b)
+            for (int k = 0; k < 3; ++k) row[p->tri[3 * j + k]] += g->area[j] / 3.0 / asum;
+}
+
 int orc_p1_assemble(const orc_problem* p, double* A)
 {
     int32_t* vb = (int32_t*)malloc(sizeof(int32_t) * (p->n_vert > 0 ? p->n_vert : 1));
@@ -706,32 +732,28 @@ int orc_p1_assemble(const orc_problem* p, double* A)
     }
     orc_geom g;
     geom_build(p, &g);
-    const int64_t nv = p->n_vert, n = orc_p1_n_unknowns(p);
+    const int64_t n = orc_p1_n_unknowns(p);
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t i = 0; i < nv; ++i) {
-        double* row = A + i * n;
-        for (int64_t k = 0; k < n; ++k) row[k] = 0.0;
-        const double* x = p->vert + 3 * i;
-        for (int64_t j = 0; j < p->n_tri; ++j) {
-            const int32_t* t = p->tri + 3 * j;
-            int is_vertex = (t[0] == i) || (t[1] == i) || (t[2] == i);
-            double c[3];
-            p1_pair(p, &g, x, j, is_vertex, c);
-            for (int k = 0; k < 3; ++k) row[t[k]] += c[k];
-        }
-        if (p->body_kind[vb[i]] == ORC_FLOATING) row[nv + g.fidx[vb[i]]] = -1.0;
+    for (int64_t i = 0; i < n; ++i) p1_row(p, &g, vb, i, A + i * n);
+    geom_free(&g);
+    free(vb);
+    return 0;
+}
+
+/* Selected rows of the nodal system (for checks at sizes where the full matrix is too big). */
+int orc_p1_assemble_rows(const orc_problem* p, int64_t n_rows, const int64_t* rows, double* out)
+{
+    int32_t* vb = (int32_t*)malloc(sizeof(int32_t) * (p->n_vert > 0 ? p->n_vert : 1));
+    int rc = p1_vertex_body(p, vb);
+    if (rc != 0) {
+        free(vb);
+        return rc;
     }
-    for (int32_t b = 0; b < p->n_body; ++b) {
-        if (p->body_kind[b] != ORC_FLOATING) continue;
-        double* row = A + (nv + g.fidx[b]) * n;
-        for (int64_t k = 0; k < n; ++k) row[k] = 0.0;
-        double asum = 0.0;
-        for (int64_t j = 0; j < p->n_tri; ++j)
-            if (p->tri_body[j] == b) asum += g.area[j];
-        for (int64_t j = 0; j < p->n_tri; ++j)
-            if (p->tri_body[j] == b)
-                for (int k = 0; k < 3; ++k) row[p->tri[3 * j + k]] += g.area[j] / 3.0 / asum;
-    }
+    orc_geom g;
+    geom_build(p, &g);
+    const int64_t n = orc_p1_n_unknowns(p);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < n_rows; ++r) p1_row(p, &g, vb, rows[r], out + r * n);
     geom_free(&g);
     free(vb);
     return 0;

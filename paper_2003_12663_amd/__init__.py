@@ -16,6 +16,7 @@ from . import _lib
 
 DIRICHLET, FLOATING, INTERFACE, FLOATING_SHEET = 0, 1, 2, 3
 FP64, MIXED = 0, 1
+BASIS_CONSTANT, BASIS_LINEAR = 0, 1   # per-panel constants at centroids / vertex hats at vertices (Sec. 3)
 STOP_NAMES = {0: "max_steps", 1: "dirichlet", 2: "floating", 3: "interface", 4: "weak_field", 5: "nonfinite"}
 
 
@@ -48,7 +49,7 @@ class Context:
     """One assembled BEM problem on the current GPU (bem_create / bem_destroy)."""
 
     def __init__(self, vert, tri, tri_body, body_kind, eps_plus, eps_minus, precision=FP64, eta=6.0, restart=100,
-                 constraint_form=0, stream=None):
+                 constraint_form=0, stream=None, basis=BASIS_CONSTANT):
         torch = _torch()
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -60,7 +61,7 @@ class Context:
         em = np.asarray(eps_minus, dtype=np.float64)
         self.n_body = len(kinds)
         bodies = (_lib.Body * self.n_body)(*[_lib.Body(int(k), float(a), float(b)) for k, a, b in zip(kinds, ep, em)])
-        opt = _lib.Options(int(precision), float(eta), int(restart), int(constraint_form))
+        opt = _lib.Options(int(precision), float(eta), int(restart), int(constraint_form), int(basis))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._ctx = ctypes.c_void_p()
         rc = self.lib.bem_create(len(self._vert), self._vert.ctypes.data, len(self._tri), self._tri.ctypes.data,
@@ -70,6 +71,7 @@ class Context:
         self.N = len(self._tri)
         self.n = int(self.lib.bem_n_unknowns(self._ctx))
         self.precision = int(precision)
+        self.basis = int(basis)
 
     @classmethod
     def from_problem(cls, p, **kw):
@@ -147,6 +149,22 @@ class Context:
         _check(self.lib.bem_eval_field(self._ctx, nrhs, _dev_ptr(sol2), P, _dev_ptr(pts), _dev_ptr(op),
                                        _dev_ptr(phi), _dev_ptr(E)), self.lib)
         return phi, E
+
+    def potential(self, sol, pts):
+        """phi at points (either basis; E is not computed).  Returns [nrhs, P] on the GPU."""
+        torch = _torch()
+        sol2 = sol.reshape(-1, self.n).contiguous()
+        nrhs = sol2.shape[0]
+        pts = torch.as_tensor(pts, dtype=torch.float64, device=self.device).reshape(-1, 3).contiguous()
+        P = pts.shape[0]
+        phi = torch.empty((nrhs, P), dtype=torch.float64, device=self.device)
+        if self.basis == BASIS_CONSTANT:
+            E = torch.empty((nrhs, P, 3), dtype=torch.float64, device=self.device)
+        else:
+            E = None
+        _check(self.lib.bem_eval_field(self._ctx, nrhs, _dev_ptr(sol2), P, _dev_ptr(pts), None,
+                                       _dev_ptr(phi), _dev_ptr(E)), self.lib)
+        return phi
 
     def _line_args(self, sol, starts, line_rhs):
         torch = _torch()

@@ -25,7 +25,7 @@ class Body(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("eta", ctypes.c_double), ("restart", ctypes.c_int32),
-                ("constraint_form", ctypes.c_int32)]
+                ("constraint_form", ctypes.c_int32), ("basis", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

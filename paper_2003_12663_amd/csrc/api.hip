@@ -82,6 +82,8 @@ void check_points(const bem_ctx* c, int64_t P, const double* pts) {
 
 void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                  const double* starts, const bem_trace_params* tp) {
+    if (c->opt.basis != BEM_BASIS_CONSTANT)
+        throw bem::Error(BEM_ERR_INVALID, "field lines need the CONSTANT basis (the nodal basis has no field yet)");
     if (!tp) throw bem::Error(BEM_ERR_INVALID, "trace parameters are NULL");
     if (nrhs < 1) throw bem::Error(BEM_ERR_INVALID, "nrhs must be >= 1");
     if (!sol) throw bem::Error(BEM_ERR_INVALID, "solution pointer is NULL");
@@ -163,12 +165,22 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     if (n_vert < 3 || n_tri < 1 || n_body < 1)
         return fail(BEM_ERR_INVALID, "mesh needs >= 3 vertices, >= 1 triangle, >= 1 body");
     if (n_tri >= ((int64_t)1 << 31) || n_vert >= ((int64_t)1 << 31)) return fail(BEM_ERR_INVALID, "mesh too large");
-    bem_options o = {BEM_FP64, 6.0, 100, 0};
+    bem_options o = {BEM_FP64, 6.0, 100, 0, BEM_BASIS_CONSTANT};
     if (opt) o = *opt;
     if (o.precision != BEM_FP64 && o.precision != BEM_MIXED) return fail(BEM_ERR_INVALID, "unknown precision");
     if (!(o.eta >= 1.0) || !std::isfinite(o.eta)) return fail(BEM_ERR_INVALID, "eta must be finite and >= 1");
     if (o.restart < 1 || o.restart > 1000) return fail(BEM_ERR_INVALID, "restart out of 1..1000");
     if (o.constraint_form != 0 && o.constraint_form != 1) return fail(BEM_ERR_INVALID, "unknown constraint_form");
+    if (o.basis != BEM_BASIS_CONSTANT && o.basis != BEM_BASIS_LINEAR) return fail(BEM_ERR_INVALID, "unknown basis");
+    if (o.basis == BEM_BASIS_LINEAR) {
+        if (o.precision != BEM_FP64) return fail(BEM_ERR_INVALID, "the LINEAR basis is FP64 only");
+        if (o.constraint_form != 1)
+            return fail(BEM_ERR_INVALID, "the LINEAR basis uses the net-charge row (constraint_form 1)");
+        if (n_tri >= ((int64_t)1 << 29)) return fail(BEM_ERR_INVALID, "mesh too large for the LINEAR basis");
+        for (int32_t b = 0; b < n_body; ++b)
+            if (bodies[b].kind != BEM_DIRICHLET && bodies[b].kind != BEM_FLOATING)
+                return fail(BEM_ERR_INVALID, "the LINEAR basis takes DIRICHLET and FLOATING bodies only");
+    }
     for (int64_t k = 0; k < 3 * n_vert; ++k)
         if (!std::isfinite(vert[k])) return fail(BEM_ERR_INVALID, "non-finite vertex coordinate");
     for (int32_t b = 0; b < n_body; ++b) {
@@ -237,6 +249,28 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         if (bodies[b].kind == BEM_FLOATING_SHEET) c->has_sheet = true;
     }
     c->n = c->N + c->n_float;
+    std::vector<int32_t> fan_ptr, fan;
+    if (o.basis == BEM_BASIS_LINEAR) {
+        // vertex -> body (one body per vertex, every vertex used) and the vertex fans
+        c->h_vert_body.assign(n_vert, -1);
+        fan_ptr.assign(n_vert + 1, 0);
+        for (int64_t j = 0; j < n_tri; ++j)
+            for (int k = 0; k < 3; ++k) {
+                int32_t& vb = c->h_vert_body[tri[3 * j + k]];
+                if (vb >= 0 && vb != tri_body[j])
+                    return fail(BEM_ERR_INVALID, "LINEAR basis: a vertex is shared by triangles of two bodies");
+                vb = tri_body[j];
+                ++fan_ptr[tri[3 * j + k] + 1];
+            }
+        for (int64_t i = 0; i < n_vert; ++i)
+            if (c->h_vert_body[i] < 0) return fail(BEM_ERR_INVALID, "LINEAR basis: a vertex is in no triangle");
+        for (int64_t i = 0; i < n_vert; ++i) fan_ptr[i + 1] += fan_ptr[i];
+        fan.resize(3 * (size_t)n_tri);
+        std::vector<int32_t> fill(fan_ptr.begin(), fan_ptr.end() - 1);
+        for (int64_t j = 0; j < n_tri; ++j)   // triangles ascending within each fan
+            for (int k = 0; k < 3; ++k) fan[fill[tri[3 * j + k]]++] = (int32_t)((j << 2) | k);
+        c->n = n_vert + c->n_float;
+    }
     c->ld = (c->n + 31) / 32 * 32;
     c->h_flt_coef.assign(2 * (size_t)std::max(c->n_float, 1), 0.0);
     for (int32_t b = 0; b < n_body; ++b) {
@@ -284,6 +318,11 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     upload(c->body_epsm, c->h_epsm.data(), (size_t)n_body, s);
     upload(c->body_fidx, c->h_body_fidx.data(), (size_t)n_body, s);
     upload(c->flt_coef, c->h_flt_coef.data(), c->h_flt_coef.size(), s);
+    if (o.basis == BEM_BASIS_LINEAR) {
+        upload(c->vert_body, c->h_vert_body.data(), c->h_vert_body.size(), s);
+        upload(c->fan_ptr, fan_ptr.data(), fan_ptr.size(), s);
+        upload(c->fan, fan.data(), fan.size(), s);
+    }
     upload(c->rows_pot, c->h_rows_pot.data(), c->h_rows_pot.size(), s);
     upload(c->rows_int, c->h_rows_int.data(), c->h_rows_int.size(), s);
     upload(c->rows_flt, c->h_rows_flt.data(), c->h_rows_flt.size(), s);
@@ -324,6 +363,21 @@ bem_status bem_assemble(bem_ctx* c) {
     if (!c) return fail(BEM_ERR_INVALID, "NULL context");
     DeviceGuard g(c->device);
     API_TRY
+    if (c->opt.basis == BEM_BASIS_LINEAR) {
+        const size_t need = sizeof(double) * (size_t)c->n * c->ld;
+        size_t free_b = 0, total_b = 0;
+        BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (need > free_b + c->A64.bytes)
+            throw bem::Error(BEM_ERR_OOM, "assembly needs " + std::to_string(need >> 20) + " MiB, " +
+                                              std::to_string((free_b + c->A64.bytes) >> 20) + " MiB free");
+        c->assembled = false;
+        c->A64.alloc(need);
+        c->diag.alloc(sizeof(double) * c->ld);
+        bem::launch_nodal_assemble(c);
+        BEM_HIP(hipStreamSynchronize(c->stream));
+        c->assembled = true;
+        return BEM_OK;
+    }
     const bool mixed = c->opt.precision == BEM_MIXED;
     const int64_t N = c->N, n = c->n, ld = c->ld;
     const int64_t nblk = bem::ceil_div(N, 64);
@@ -495,6 +549,15 @@ bem_status bem_eval_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P
     if (!c) return fail(BEM_ERR_INVALID, "NULL context");
     DeviceGuard g(c->device);
     API_TRY
+    if (c->opt.basis == BEM_BASIS_LINEAR) {
+        if (nrhs < 1 || !sol || (P > 0 && !phi))
+            throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL sol, phi required");
+        if (E || on_panel)
+            throw bem::Error(BEM_ERR_INVALID, "the LINEAR basis evaluates the potential only (E and on_panel NULL)");
+        check_points(c, P, pts);
+        bem::launch_nodal_potential(c, nrhs, sol, P, pts, phi);
+        return BEM_OK;
+    }
     if (nrhs < 1 || !sol || (P > 0 && !E)) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL sol, E required");
     check_points(c, P, pts);
     if (on_panel) {
@@ -623,6 +686,7 @@ bem_status bem_autotune(bem_ctx* c, const char* cache_path, int32_t* from_cache)
     if (!c) return fail(BEM_ERR_INVALID, "NULL context");
     DeviceGuard g(c->device);
     API_TRY
+    if (c->opt.basis != BEM_BASIS_CONSTANT) throw bem::Error(BEM_ERR_INVALID, "the autotuner needs the CONSTANT basis");
     const int r = bem::autotune(c, cache_path);
     if (from_cache) *from_cache = r;
     return BEM_OK;

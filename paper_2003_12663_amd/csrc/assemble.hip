@@ -260,15 +260,16 @@ __global__ __launch_bounds__(256) void k_scatter_near_rows(const int64_t* __rest
     for (int64_t e = ptr[row0 + r]; e < ptr[row0 + r + 1]; ++e) out[r * n + col[e]] += val[e];
 }
 
-__global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind,
-                                             int64_t N, int64_t n, int32_t n_body, int32_t nrhs,
+// rows [0, nb) carry a body (panels, or vertices of the nodal basis); the others are constraint rows
+__global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ row_body, const int32_t* __restrict__ body_kind,
+                                             int64_t nb, int64_t n, int32_t n_body, int32_t nrhs,
                                              const double* __restrict__ bodyV, double* __restrict__ b) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= (int64_t)nrhs * n) return;
     const int64_t r = t / n, i = t % n;
     double v = 0.0;
-    if (i < N) {
-        const int32_t bd = tri_body[i];
+    if (i < nb) {
+        const int32_t bd = row_body[i];
         if (body_kind[bd] == BEM_DIRICHLET) v = bodyV[r * n_body + bd];
     }
     b[t] = v;
@@ -440,8 +441,10 @@ void launch_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out) {
 }
 
 void launch_rhs(bem_ctx* c, int32_t nrhs, const double* d_bodyV, double* b) {
+    const bool nodal = c->opt.basis == BEM_BASIS_LINEAR;
     hipLaunchKernelGGL(k_rhs, dim3((unsigned)ceil_div((int64_t)nrhs * c->n, 256)), dim3(256), 0, c->stream,
-                       c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), c->N, c->n, c->n_body, nrhs, d_bodyV, b);
+                       nodal ? c->vert_body.as<int32_t>() : c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(),
+                       nodal ? c->n_vert : c->N, c->n, c->n_body, nrhs, d_bodyV, b);
     BEM_CHECK_LAUNCH();
 }
 

@@ -116,9 +116,13 @@ struct bem_ctx {
     // sum_i a_i (c_self sigma_i + c_kp (K' sigma)_i) / sum_i a_i, with (c_self, c_kp) at [2f], [2f+1]:
     // closed body (1/2, 1) literal or (1, 0) reduced, sheet (1, 2 (eps+ - eps-) / (eps+ + eps-))
     std::vector<double> h_flt_coef;
+    // nodal basis (opt.basis == BEM_BASIS_LINEAR): body of each vertex and the fan of each
+    // vertex, fan[fan_ptr[k] .. fan_ptr[k+1]) = (triangle << 2) | local index, triangles ascending
+    std::vector<int32_t> h_vert_body;
     std::vector<int32_t> h_rows_pot, h_rows_int, h_rows_flt;   // row segments by kind (Sec. 4)
 
     bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx, flt_coef;
+    bem::DBuf vert_body, fan_ptr, fan, nodal_mass;   // nodal basis only
     bem::DBuf far64, far32, tri64;
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;
@@ -200,6 +204,9 @@ void launch_near_assemble(bem_ctx* c);                             // assemble.h
 void launch_finalize(bem_ctx* c);                                  // assemble.hip
 void launch_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out);
 void launch_rhs(bem_ctx* c, int32_t nrhs, const double* d_bodyV, double* b);
+void launch_nodal_assemble(bem_ctx* c);                                          // nodal.hip
+void launch_nodal_potential(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts,
+                            double* phi);                                           // nodal.hip
 void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      // gemv.hip
 void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s);    // gemv.hip
 int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,

@@ -1,0 +1,337 @@
+// Nodal piecewise-linear basis with vertex collocation (Sec. 3; the matrix of
+// Eq. Matrix).  sigma_h = sum_k u_k psi_k with psi_k the hat of vertex k;
+// row i collocates at vertex x_i, so
+//   v_ik = sum over the triangles tau holding k of int lambda_k^tau(y) / (4 pi |x_i - y|) dS,
+// lambda_k^tau being tau's barycentric coordinate of k.  Conductor and
+// floating-conductor bodies; a floating body's row is its net charge.
+//
+// Assembly keeps the collision-free ownership of Sec. 5 (each collocation
+// point owns its row) at wave granularity: the 64 lanes of a wave are 64
+// consecutive rows, while the column and the triangle are wave-uniform, so
+// triangle records arrive through the scalar cache and every lane adds into
+// its own row only.  A column is summed over the fan of its vertex (a CSR
+// built at create), so each entry is written once, with no read-modify-write
+// and no atomics; the price is that a (row, triangle) pair is integrated once
+// per vertex of the triangle.  16 columns per wave are staged in LDS and
+// leave as 128-byte row segments.
+#include <cmath>
+
+#include "bem_device.h"
+
+namespace bem {
+namespace {
+
+constexpr int NODAL_COLS = 16;   // columns per wave
+
+// The rule's barycentric coordinate of local vertex c at node q (node order of
+// the panel records: centroid, then the orbits (a, a, 1 - 2a) for a = a1, a2
+// with the odd coordinate last, middle, first).
+struct NodeBary {
+    double b[7];
+    __device__ NodeBary(int c) {
+        const double s15 = sqrt(15.0);
+        const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+        b[0] = 1.0 / 3.0;
+#pragma unroll
+        for (int q = 1; q <= 3; ++q) b[q] = (c == 3 - q) ? 1.0 - 2.0 * a1 : a1;
+#pragma unroll
+        for (int q = 4; q <= 6; ++q) b[q] = (c == 6 - q) ? 1.0 - 2.0 * a2 : a2;
+    }
+};
+
+// Closed form of int lambda_c(y) / (4 pi |x - y|) dS over the flat triangle T
+// (16-double exact-geometry record) for its local vertex c.  With rho the foot
+// point of x on the plane and w the height,
+//   lambda_c(y) = lambda_c(rho) + g_c . (y - rho),  g_c = n x (v_{c+2} - v_{c+1}) / (2A),
+//   int 1/R dS = sum_e t f_e - |w| Omega                 (unit density),
+//   int (y - rho)/R dS = sum_e m_e int_e R dl,  int_e R dl = (s+ R+ - s- R- + R0^2 f_e)/2,
+// the second by the divergence theorem in the plane (the in-plane gradient of
+// R is (y - rho)/R); edge notation and Omega as in flat_tri_SF.  vtx: x is a
+// vertex of T, so w = 0 and rho = x; on the two edges that end at x, t = R0 = 0
+// and their t f_e and R0^2 f_e terms vanish in the limit (f_e itself is
+// infinite there), so they are skipped.
+__device__ __forceinline__ void hat_edges(const double* __restrict__ T, double x0, double x1, double x2, bool vtx,
+                                          double& I0, double& r0, double& r1, double& r2, double& J0, double& J1,
+                                          double& J2) {
+    const double n0 = T[TR_N + 0], n1 = T[TR_N + 1], n2 = T[TR_N + 2];
+    const double w = vtx ? 0.0 : (x0 - T[0]) * n0 + (x1 - T[1]) * n1 + (x2 - T[2]) * n2;
+    r0 = x0 - w * n0;
+    r1 = x1 - w * n1;
+    r2 = x2 - w * n2;
+    const double aw = fabs(w);
+    double V[3][3], Rv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        V[k][0] = T[3 * k] - x0;
+        V[k][1] = T[3 * k + 1] - x1;
+        V[k][2] = T[3 * k + 2] - x2;
+        Rv[k] = sqrt(V[k][0] * V[k][0] + V[k][1] * V[k][1] + V[k][2] * V[k][2]);
+    }
+    double st = 0.0;
+    J0 = J1 = J2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int b = (e + 1) % 3;
+        const double ax = T[3 * e], ay = T[3 * e + 1], az = T[3 * e + 2];
+        double l0 = T[3 * b] - ax, l1 = T[3 * b + 1] - ay, l2 = T[3 * b + 2] - az;
+        const double len = sqrt(l0 * l0 + l1 * l1 + l2 * l2);
+        const double il = 1.0 / len;
+        l0 *= il; l1 *= il; l2 *= il;
+        const double m0 = l1 * n2 - l2 * n1, m1 = l2 * n0 - l0 * n2, m2 = l0 * n1 - l1 * n0;
+        const double q0 = ax - r0, q1 = ay - r1, q2 = az - r2;
+        const double sm = q0 * l0 + q1 * l1 + q2 * l2;
+        const double sp = sm + len;
+        const double t = q0 * m0 + q1 * m1 + q2 * m2;
+        const double Rm = Rv[e], Rp = Rv[b];
+        double er = 0.5 * (sp * Rp - sm * Rm);
+        if (!(vtx && (Rm == 0.0 || Rp == 0.0))) {
+            double f;
+            if (sp + sm > 0.0)
+                f = log((Rp + sp) / (Rm + sm));
+            else
+                f = log((Rm - sm) / (Rp - sp));
+            st += t * f;
+            er += 0.5 * (t * t + w * w) * f;
+        }
+        J0 += m0 * er;
+        J1 += m1 * er;
+        J2 += m2 * er;
+    }
+    double omega = 0.0;
+    if (!vtx) {
+        const double c0 = V[1][1] * V[2][2] - V[1][2] * V[2][1];
+        const double c1 = V[1][2] * V[2][0] - V[1][0] * V[2][2];
+        const double c2 = V[1][0] * V[2][1] - V[1][1] * V[2][0];
+        const double triple = V[0][0] * c0 + V[0][1] * c1 + V[0][2] * c2;
+        const double d01 = V[0][0] * V[1][0] + V[0][1] * V[1][1] + V[0][2] * V[1][2];
+        const double d02 = V[0][0] * V[2][0] + V[0][1] * V[2][1] + V[0][2] * V[2][2];
+        const double d12 = V[1][0] * V[2][0] + V[1][1] * V[2][1] + V[1][2] * V[2][2];
+        const double den = Rv[0] * Rv[1] * Rv[2] + d01 * Rv[2] + d02 * Rv[1] + d12 * Rv[0];
+        omega = 2.0 * atan2(fabs(triple), den);
+    }
+    I0 = st - aw * omega;
+}
+
+// lambda_c(rho) I0 + g_c . J over 4 pi (see hat_edges)
+__device__ __forceinline__ double hat_value(const double* __restrict__ T, int c, double I0, double r0, double r1,
+                                           double r2, double J0, double J1, double J2) {
+    const double n0 = T[TR_N + 0], n1 = T[TR_N + 1], n2 = T[TR_N + 2];
+    const double* p = T + 3 * ((c + 1) % 3);
+    const double* q = T + 3 * ((c + 2) % 3);
+    const double a0 = p[0] - r0, a1 = p[1] - r1, a2 = p[2] - r2;
+    const double b0 = q[0] - r0, b1 = q[1] - r1, b2 = q[2] - r2;
+    const double two_area = 2.0 * T[TR_A];
+    // barycentric coordinate of rho: signed area of (p, q, rho) over A
+    const double lam = (n0 * (a1 * b2 - a2 * b1) + n1 * (a2 * b0 - a0 * b2) + n2 * (a0 * b1 - a1 * b0)) / two_area;
+    // g = n x (q - p)
+    const double e0 = q[0] - p[0], e1 = q[1] - p[1], e2 = q[2] - p[2];
+    const double g0 = n1 * e2 - n2 * e1, g1 = n2 * e0 - n0 * e2, g2 = n0 * e1 - n1 * e0;
+    return (lam * I0 + (g0 * J0 + g1 * J1 + g2 * J2) / two_area) * INV4PI;
+}
+
+// One wave: rows i0 + lane, columns j0 .. j0 + 15.  grid (row tiles of 64, groups of 4 x 16 columns).
+__global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, const double* __restrict__ vert,
+                                                        const int32_t* __restrict__ tri,
+                                                        const int32_t* __restrict__ fan_ptr,
+                                                        const int32_t* __restrict__ fan,
+                                                        const double* __restrict__ pan64,
+                                                        const double* __restrict__ tri64, double* __restrict__ A,
+                                                        double* __restrict__ diag) {
+    __shared__ double tile[4][NODAL_COLS][65];   // padded: the row-segment reads stride 65
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int64_t i = i0 + lane;
+    const int64_t ic = i < nv ? i : nv - 1;
+    const double x0 = vert[3 * ic], x1 = vert[3 * ic + 1], x2 = vert[3 * ic + 2];
+    const int64_t j0 = ((int64_t)blockIdx.y * 4 + wv) * NODAL_COLS;
+    for (int cc = 0; cc < NODAL_COLS; ++cc) {
+        const int64_t j = j0 + cc;
+        double acc = 0.0;
+        if (j < nv) {
+            const int32_t e1 = fan_ptr[j + 1];
+            for (int32_t e = fan_ptr[j]; e < e1; ++e) {
+                const int32_t pk = fan[e];
+                const int64_t t = pk >> 2;
+                const int c = pk & 3;
+                const double* P = pan64 + (int64_t)FAR_REC * t;
+                const int32_t* tv = tri + 3 * t;
+                const bool vtx = (tv[0] == i) || (tv[1] == i) || (tv[2] == i);
+                if (!vtx && is_regular(x0 - P[FR_CC], x1 - P[FR_CC + 1], x2 - P[FR_CC + 2], P[FR_RR])) {
+                    const NodeBary nb(c);
+                    double s = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) {
+                        const double d0 = x0 - P[FR_X + q], d1 = x1 - P[FR_Y + q], d2 = x2 - P[FR_Z + q];
+                        s += P[FR_W + q] * nb.b[q] * rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
+                    }
+                    acc += s;
+                } else {
+                    const double* T = tri64 + (int64_t)TRI_REC * t;
+                    double I0, r0, r1, r2, J0, J1, J2;
+                    hat_edges(T, x0, x1, x2, vtx, I0, r0, r1, r2, J0, J1, J2);
+                    acc += hat_value(T, c, I0, r0, r1, r2, J0, J1, J2);
+                }
+            }
+            if (j == i) diag[i] = acc;
+        }
+        tile[wv][cc][lane] = acc;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int s = 0; s < 16; ++s) {
+        const int r = (lane >> 4) + 4 * s, cc = lane & 15;
+        const int64_t ii = i0 + r, jj = j0 + cc;
+        if (ii < nv && jj < nv) A[ii * ld + jj] = tile[wv][cc][r];
+    }
+}
+
+// columns [nv, ld) of the vertex rows: -1 in the column of the row's floating body, else 0
+__global__ __launch_bounds__(256) void k_nodal_tail(int64_t nv, int64_t ld, const int32_t* __restrict__ vert_body,
+                                                    const int32_t* __restrict__ body_kind,
+                                                    const int32_t* __restrict__ fidx, double* __restrict__ A) {
+    const int64_t ncol = ld - nv;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nv * ncol) return;
+    const int64_t i = t / ncol, k = t % ncol;
+    const int32_t b = vert_body[i];
+    A[i * ld + nv + k] = (body_kind[b] == BEM_FLOATING && fidx[b] == k) ? -1.0 : 0.0;
+}
+
+// m_k = int psi_k dS = sum over the fan of k of area / 3
+__global__ __launch_bounds__(256) void k_nodal_mass(int64_t nv, const int32_t* __restrict__ fan_ptr,
+                                                    const int32_t* __restrict__ fan, const double* __restrict__ tri64,
+                                                    double* __restrict__ mass) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nv) return;
+    double s = 0.0;
+    for (int32_t e = fan_ptr[k]; e < fan_ptr[k + 1]; ++e) s += tri64[(int64_t)TRI_REC * (fan[e] >> 2) + TR_A];
+    mass[k] = s / 3.0;
+}
+
+// area of floating body f (one block each): sum of m_k over its vertices, fixed order
+__global__ __launch_bounds__(256) void k_nodal_body_area(int64_t nv, const int32_t* __restrict__ vert_body,
+                                                         const int32_t* __restrict__ fidx,
+                                                         const double* __restrict__ mass, double* __restrict__ Af) {
+    __shared__ double red[4];
+    const int f = blockIdx.x;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < nv; k += 256)
+        if (fidx[vert_body[k]] == f) s += mass[k];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) Af[f] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// row nv + f: m_k / area_f on the vertices of floating body f, 0 elsewhere (all ld
+// columns); its Jacobi diagonal is 1 (the entry is 0)
+__global__ __launch_bounds__(256) void k_nodal_constraint(int64_t nv, int64_t ld, int32_t n_float,
+                                                          const int32_t* __restrict__ vert_body,
+                                                          const int32_t* __restrict__ fidx,
+                                                          const double* __restrict__ mass,
+                                                          const double* __restrict__ Af, double* __restrict__ A,
+                                                          double* __restrict__ diag) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)n_float * ld) return;
+    const int64_t f = t / ld, k = t % ld;
+    A[(nv + f) * ld + k] = (k < nv && fidx[vert_body[k]] == f) ? mass[k] / Af[f] : 0.0;
+    if (k == 0) diag[nv + f] = 1.0;
+}
+
+// phi at points from vertex densities: 64 points per block, the triangles split
+// over the 4 waves, partial sums folded in LDS.  grid (point tiles, load cases).
+__global__ __launch_bounds__(256) void k_nodal_potential(int64_t P, const double* __restrict__ pts, int64_t N,
+                                                         const int32_t* __restrict__ tri,
+                                                         const double* __restrict__ pan64,
+                                                         const double* __restrict__ tri64,
+                                                         const double* __restrict__ sol, int64_t n,
+                                                         double* __restrict__ phi) {
+    __shared__ double part[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t pc = p < P ? p : P - 1;
+    const double x0 = pts[3 * pc], x1 = pts[3 * pc + 1], x2 = pts[3 * pc + 2];
+    const double* u = sol + (int64_t)blockIdx.y * n;
+    const double s15 = sqrt(15.0);
+    const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+    const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
+    const int64_t per = (N + 3) / 4;
+    const int64_t t0 = wv * per, t1 = t0 + per < N ? t0 + per : N;
+    double acc = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int32_t* tv = tri + 3 * t;
+        const double u0 = u[tv[0]], u1 = u[tv[1]], u2 = u[tv[2]];
+        const double* Pr = pan64 + (int64_t)FAR_REC * t;
+        if (is_regular(x0 - Pr[FR_CC], x1 - Pr[FR_CC + 1], x2 - Pr[FR_CC + 2], Pr[FR_RR])) {
+            // density at the nodes (same barycentrics as NodeBary)
+            const double sq[7] = {(u0 + u1 + u2) / 3.0,
+                                  a1 * u0 + a1 * u1 + b1 * u2, a1 * u0 + b1 * u1 + a1 * u2, b1 * u0 + a1 * u1 + a1 * u2,
+                                  a2 * u0 + a2 * u1 + b2 * u2, a2 * u0 + b2 * u1 + a2 * u2, b2 * u0 + a2 * u1 + a2 * u2};
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const double d0 = x0 - Pr[FR_X + q], d1 = x1 - Pr[FR_Y + q], d2 = x2 - Pr[FR_Z + q];
+                s += Pr[FR_W + q] * sq[q] * rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
+            }
+            acc += s;
+        } else {
+            const double* T = tri64 + (int64_t)TRI_REC * t;
+            double I0, r0, r1, r2, J0, J1, J2;
+            hat_edges(T, x0, x1, x2, false, I0, r0, r1, r2, J0, J1, J2);
+            acc += u0 * hat_value(T, 0, I0, r0, r1, r2, J0, J1, J2) + u1 * hat_value(T, 1, I0, r0, r1, r2, J0, J1, J2) +
+                   u2 * hat_value(T, 2, I0, r0, r1, r2, J0, J1, J2);
+        }
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && p < P) phi[(int64_t)blockIdx.y * P + p] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+}  // namespace
+
+void launch_nodal_assemble(bem_ctx* c) {
+    KTimer kt(c, "nodal_assemble");
+    const int64_t nv = c->n_vert, ld = c->ld;
+    hipStream_t s = c->stream;
+    if (ceil_div(nv, 4 * NODAL_COLS) > 65535) throw Error(BEM_ERR_INVALID, "too many vertices for the LINEAR basis");
+    dim3 grid((unsigned)ceil_div(nv, 64), (unsigned)ceil_div(nv, 4 * NODAL_COLS));
+    hipLaunchKernelGGL(k_nodal_assemble, grid, dim3(256), 0, s, nv, ld, c->vert.as<double>(), c->tri.as<int32_t>(),
+                       c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->pan64.as<double>(), c->tri64.as<double>(),
+                       c->A64.as<double>(), c->diag.as<double>());
+    BEM_CHECK_LAUNCH();
+    if (ld > nv) {
+        hipLaunchKernelGGL(k_nodal_tail, dim3((unsigned)ceil_div(nv * (ld - nv), 256)), dim3(256), 0, s, nv, ld,
+                           c->vert_body.as<int32_t>(), c->body_kind.as<int32_t>(), c->body_fidx.as<int32_t>(),
+                           c->A64.as<double>());
+        BEM_CHECK_LAUNCH();
+    }
+    if (c->n_float > 0) {
+        c->nodal_mass.alloc(sizeof(double) * (size_t)(nv + c->n_float));
+        double* mass = c->nodal_mass.as<double>();
+        double* Af = mass + nv;
+        hipLaunchKernelGGL(k_nodal_mass, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv,
+                           c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->tri64.as<double>(), mass);
+        BEM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_nodal_body_area, dim3((unsigned)c->n_float), dim3(256), 0, s, nv,
+                           c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(), mass, Af);
+        BEM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_nodal_constraint, dim3((unsigned)ceil_div((int64_t)c->n_float * ld, 256)), dim3(256), 0,
+                           s, nv, ld, c->n_float, c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(), mass, Af,
+                           c->A64.as<double>(), c->diag.as<double>());
+        BEM_CHECK_LAUNCH();
+    }
+}
+
+void launch_nodal_potential(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi) {
+    KTimer kt(c, "nodal_potential");
+    if (P == 0) return;
+    for (int32_t r0 = 0; r0 < nrhs; r0 += 65535) {   // load cases on grid.y
+        const int32_t nr = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
+        hipLaunchKernelGGL(k_nodal_potential, dim3((unsigned)ceil_div(P, 64), (unsigned)nr), dim3(256), 0, c->stream,
+                           P, pts, c->N, c->tri.as<int32_t>(), c->pan64.as<double>(), c->tri64.as<double>(),
+                           sol + (int64_t)r0 * c->n, c->n, phi + (int64_t)r0 * P);
+        BEM_CHECK_LAUNCH();
+    }
+}
+
+}  // namespace bem

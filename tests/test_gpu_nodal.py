@@ -1,0 +1,139 @@
+"""Nodal piecewise-linear basis (Sec. 3, Eq. Matrix) on the GPU against the FP64 oracle.
+
+Vertex hats collocated at the vertices, conductor and floating-conductor
+bodies, a floating body's row its net charge.  Bars as for the constant basis:
+matrix entries 1e-12 of the row's largest, right-hand sides exact, solutions
+and potentials 1e-10.  Cases: spheres and a floating shell (vertex counts that
+leave ragged row tiles and column groups), two devices in one problem, and a
+level-5 sphere (10,242 vertices) on sampled oracle rows.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import floating_shell_problem, sphere_problem, union_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bem():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_12663_amd as bem
+    return bem
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _ctx(bem, p):
+    c = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1)
+    c.assemble()
+    return c
+
+
+CASES = [
+    ("sphere_L1", lambda: sphere_problem(1, V0=2.0)),
+    ("sphere_L3", lambda: sphere_problem(3)),
+    ("floating_shell_L2", lambda: floating_shell_problem(2, V0=3.0)),
+    ("sphere_and_shell", lambda: union_problem(sphere_problem(2, V0=1.5), floating_shell_problem(1, V0=-1.0),
+                                               (4.0, 0.5, 0.0))),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_nodal_matrix_rhs_solution(bem, name, make):
+    p = make()
+    o = oracle.Oracle(p)
+    A = o.p1_assemble()
+    b_ref = o.p1_rhs(p.body_V)
+    x_ref = np.linalg.solve(A, b_ref)
+    c = _ctx(bem, p)
+    print(f"[nodal] {name}: n_vert {p.n_vert}, n {c.n}", flush=True)
+    assert c.n == A.shape[0] == p.n_vert + int(np.sum(p.body_kind == 1))
+    G = c.copy_rows(0, c.n).cpu().numpy()
+    assert (np.abs(G - A) / np.abs(A).max(axis=1, keepdims=True)).max() <= 1e-12
+    b = c.rhs(p.body_V)[0].cpu().numpy()
+    assert np.array_equal(b, b_ref)
+    sol, info = c.solve(p.body_V, tol=1e-13, max_iter=5000)
+    assert info["converged"]
+    assert rel(sol[0].cpu().numpy(), x_ref) <= 1e-10
+    # potential at points inside, outside and near the surface
+    rng = np.random.default_rng(4)
+    pts = np.concatenate([rng.uniform(-3, 3, (40, 3)), p.vert[rng.integers(0, p.n_vert, 8)] * 1.02])
+    phi = c.potential(sol, pts)[0].cpu().numpy()
+    phi_ref = o.p1_potential(sol[0].cpu().numpy(), pts)
+    assert rel(phi, phi_ref) <= 1e-10
+    c.close()
+
+
+def test_nodal_matches_closed_form_sphere(bem):
+    """Conductor sphere at V0: u = V0/R at every vertex to the discretisation error
+    (second order: level 4 below 2e-3), potential V0 R/|x| outside."""
+    p = sphere_problem(4, V0=1.0)
+    c = _ctx(bem, p)
+    sol, info = c.solve(p.body_V, tol=1e-12, max_iter=5000)
+    u = sol[0].cpu().numpy()
+    assert np.max(np.abs(u - 1.0)) < 2e-3
+    pts = np.array([[0.0, 0.0, 3.0], [2.0, -1.0, 0.5], [0.1, 0.2, -0.3]])
+    phi = c.potential(sol, pts)[0].cpu().numpy()
+    r = np.linalg.norm(pts, axis=1)
+    assert np.max(np.abs(phi - np.where(r > 1, 1 / r, 1.0))) < 2e-3
+    c.close()
+
+
+def test_nodal_large_sampled_rows(bem):
+    """Level-5 sphere (10,242 vertices, 20,480 triangles): sampled rows of the
+    GPU matrix against the oracle's rows, and the GPU solution's residual on
+    those rows."""
+    p = sphere_problem(5)
+    c = _ctx(bem, p)
+    rows = np.unique(np.concatenate([[0, 1, 63, 64, p.n_vert - 1], np.random.default_rng(2).integers(0, p.n_vert, 11)]))
+    R = oracle.Oracle(p).p1_assemble_rows(rows)
+    for k, r in enumerate(rows):
+        g = c.copy_rows(int(r), 1)[0].cpu().numpy()
+        assert np.abs(g - R[k]).max() <= 1e-12 * np.abs(R[k]).max(), r
+    sol, info = c.solve(p.body_V, tol=1e-12, max_iter=5000)
+    x = sol[0].cpu().numpy()
+    b = oracle.Oracle(p).p1_rhs(p.body_V)[rows]
+    assert np.abs(R @ x - b).max() <= 1e-10
+    c.close()
+
+
+def test_nodal_batched_load_cases(bem):
+    """Several load cases in one call agree with one-by-one solves."""
+    p = union_problem(sphere_problem(2, V0=1.0), sphere_problem(2, V0=0.0), (3.0, 0.0, 0.0))
+    c = _ctx(bem, p)
+    bv = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, -1.0]])
+    sol, info = c.solve(bv, tol=1e-12, max_iter=5000)
+    for r in range(3):
+        s1, _ = c.solve(bv[r], tol=1e-12, max_iter=5000)
+        assert rel(sol[r].cpu().numpy(), s1[0].cpu().numpy()) <= 1e-9
+    # linearity: case 2 = case 0 - case 1
+    s = sol.cpu().numpy()
+    assert rel(s[2], s[0] - s[1]) <= 1e-9
+    c.close()
+
+
+def test_nodal_refusals(bem):
+    p = sphere_problem(1)
+    with pytest.raises(bem.BemError):   # the net-charge row is required
+        bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=0)
+    with pytest.raises(bem.BemError):   # FP64 only
+        bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
+    from workloads import coated_sphere_problem
+    with pytest.raises(bem.BemError):   # interface bodies need a normal at the vertex
+        bem.Context.from_problem(coated_sphere_problem(1), basis=bem.BASIS_LINEAR, constraint_form=1)
+    c = _ctx(bem, p)
+    sol, _ = c.solve(p.body_V, tol=1e-10)
+    with pytest.raises(bem.BemError):   # no field for the nodal basis
+        c.eval_field(sol, np.zeros((1, 3)) + 2.0)
+    with pytest.raises(bem.BemError):   # no field lines either
+        c.streamer_integral(sol, torch.tensor([[0.0, 0.0, 1.2]], device="cuda"), bem.trace_params(h=1e-3))
+    c.close()
