@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the gradient and the 64-load-case x 64-line runs")
     ap.add_argument("--extras-only", action="store_true", help="only the gradient and 4096-line runs")
+    ap.add_argument("--nodal-only", action="store_true", help="only the nodal-basis sphere run")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON): reuse one tile choice across runs, e.g. for counter runs")
     ap.add_argument("--set-tuning", default=None,
@@ -243,6 +244,44 @@ def bushing_run(bem, torch):
     return out
 
 
+def nodal_run(bem, torch):
+    """The paper's nodal piecewise-linear basis (vertex collocation, Eq. Matrix) beside the
+    constant basis on the conductor sphere, whose density is V0/R exactly: FP64 assembly
+    (timed after a warm-up) and solve to 1e-10, and the largest density error.  Nodal on
+    icospheres of level 5 (10,242 vertices, 20,480 panels) and 6 (40,962 / 81,920);
+    constant on level 5 (20,480 unknowns)."""
+    from workloads import sphere_problem
+    out = {}
+
+    def one(level, basis):
+        p = sphere_problem(level)
+        kw = dict(basis=bem.BASIS_LINEAR, constraint_form=1) if basis else {}
+        ctx = bem.Context.from_problem(p, **kw)
+        ctx.assemble()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.assemble()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sol, info = ctx.solve(p.body_V, tol=1e-10, max_iter=5000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        nu = p.n_vert if basis else p.n_tri
+        dens = sol[0, :nu].cpu().numpy()
+        rows = p.n_vert if basis else p.n_tri
+        r = {"unknowns": int(ctx.n), "panels": p.n_tri, "assemble_s": t1 - t0,
+             "row_panel_pairs_per_s": rows * p.n_tri / (t1 - t0), "solve_s": t2 - t1, "iters": info["iters"],
+             "max_density_error": float(np.max(np.abs(dens - 1.0)))}
+        ctx.close()
+        torch.cuda.empty_cache()
+        return r
+
+    out["linear_L5"] = one(5, True)
+    out["linear_L6"] = one(6, True)
+    out["constant_L5"] = one(5, False)
+    return out
+
+
 def cpu_baseline(p, x, starts, args):
     """The oracle on a bounded sample: a block of matrix rows and a few short lines."""
     import oracle
@@ -290,6 +329,10 @@ def main():
     tp = bem.trace_params(h=1e-4, max_steps=args.max_steps, e_min=1e-3)
     ctx = bem.Context.from_problem(p, precision=bem.FP64, eta=6.0, restart=100)
     print(f"[bench] coax N={N} lines={args.lines}", file=sys.stderr, flush=True)
+    if args.nodal_only:
+        ctx.close()
+        print(json.dumps({"nodal_basis_sphere": nodal_run(bem, torch)}))
+        return
     if args.tts_only:
         ctx.assemble()
         print(json.dumps({"time_to_solve_64_load_cases": time_to_solve(bem, torch, p, ctx)}))
@@ -301,7 +344,8 @@ def main():
         print(json.dumps({"gradient_coax_128_lines": gradient_run(bem, torch, p, ctx),
                           "cases_64_x_lines_64": cases_by_lines_run(bem, torch, p, ctx),
                           "coax_60k_mixed_vs_fp64": c3_run(bem, torch),
-                          "bushing_thin_sheets": bushing_run(bem, torch)}))
+                          "bushing_thin_sheets": bushing_run(bem, torch),
+                          "nodal_basis_sphere": nodal_run(bem, torch)}))
         ctx.close()
         return
     # tile shapes for this problem, timed before the timed region (tuning re-assembles)
@@ -376,6 +420,7 @@ def main():
         extras["cases_64_x_lines_64"] = cases_by_lines_run(bem, torch, p, ctx)
         extras["coax_60k_mixed_vs_fp64"] = c3_run(bem, torch)
         extras["bushing_thin_sheets"] = bushing_run(bem, torch)
+        extras["nodal_basis_sphere"] = nodal_run(bem, torch)
 
     tts = None
     if not args.no_tts:

@@ -249,7 +249,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         if (bodies[b].kind == BEM_FLOATING_SHEET) c->has_sheet = true;
     }
     c->n = c->N + c->n_float;
-    std::vector<int32_t> fan_ptr, fan;
+    std::vector<int32_t> fan_ptr, fan, row_order;
     if (o.basis == BEM_BASIS_LINEAR) {
         // vertex -> body (one body per vertex, every vertex used) and the vertex fans
         c->h_vert_body.assign(n_vert, -1);
@@ -270,6 +270,37 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         for (int64_t j = 0; j < n_tri; ++j)   // triangles ascending within each fan
             for (int k = 0; k < 3; ++k) fan[fill[tri[3 * j + k]]++] = (int32_t)((j << 2) | k);
         c->n = n_vert + c->n_float;
+        // vertices in Morton (Z-curve) order of their positions in the bounding box, 21 bits
+        // per axis: the near-pair pass takes its rows in this order so that a wave's rows are
+        // neighbours
+        double lo[3] = {vert[0], vert[1], vert[2]}, hi[3] = {vert[0], vert[1], vert[2]};
+        for (int64_t i = 0; i < n_vert; ++i)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], vert[3 * i + k]);
+                hi[k] = std::max(hi[k], vert[3 * i + k]);
+            }
+        auto spread = [](uint64_t v) {   // 21 bits -> every third bit of 63
+            v &= 0x1fffff;
+            v = (v | v << 32) & 0x1f00000000ffffULL;
+            v = (v | v << 16) & 0x1f0000ff0000ffULL;
+            v = (v | v << 8) & 0x100f00f00f00f00fULL;
+            v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+            v = (v | v << 2) & 0x1249249249249249ULL;
+            return v;
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key(n_vert);
+        for (int64_t i = 0; i < n_vert; ++i) {
+            uint64_t m = 0;
+            for (int k = 0; k < 3; ++k) {
+                const double ext = hi[k] - lo[k];
+                const double f = ext > 0.0 ? (vert[3 * i + k] - lo[k]) / ext : 0.0;
+                m |= spread((uint64_t)std::min(f * 2097151.0, 2097151.0)) << k;
+            }
+            key[i] = {m, (int32_t)i};
+        }
+        std::sort(key.begin(), key.end());
+        row_order.resize(n_vert);
+        for (int64_t i = 0; i < n_vert; ++i) row_order[i] = key[i].second;
     }
     c->ld = (c->n + 31) / 32 * 32;
     c->h_flt_coef.assign(2 * (size_t)std::max(c->n_float, 1), 0.0);
@@ -322,6 +353,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         upload(c->vert_body, c->h_vert_body.data(), c->h_vert_body.size(), s);
         upload(c->fan_ptr, fan_ptr.data(), fan_ptr.size(), s);
         upload(c->fan, fan.data(), fan.size(), s);
+        upload(c->row_order, row_order.data(), row_order.size(), s);
     }
     upload(c->rows_pot, c->h_rows_pot.data(), c->h_rows_pot.size(), s);
     upload(c->rows_int, c->h_rows_int.data(), c->h_rows_int.size(), s);

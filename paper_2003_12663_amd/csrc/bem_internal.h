@@ -122,7 +122,7 @@ struct bem_ctx {
     std::vector<int32_t> h_rows_pot, h_rows_int, h_rows_flt;   // row segments by kind (Sec. 4)
 
     bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx, flt_coef;
-    bem::DBuf vert_body, fan_ptr, fan, nodal_mass;   // nodal basis only
+    bem::DBuf vert_body, fan_ptr, fan, nodal_mass, nodal_bounds, row_order;   // nodal basis only
     bem::DBuf far64, far32, tri64;
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;

@@ -11,9 +11,13 @@
 // triangle records arrive through the scalar cache and every lane adds into
 // its own row only.  A column is summed over the fan of its vertex (a CSR
 // built at create), so each entry is written once, with no read-modify-write
-// and no atomics; the price is that a (row, triangle) pair is integrated once
-// per vertex of the triangle.  16 columns per wave are staged in LDS and
-// leave as 128-byte row segments.
+// and no atomics; the price is that a regular (row, triangle) pair is
+// integrated once per vertex of the triangle.  16 columns per wave are staged
+// in LDS and leave as 128-byte row segments.  This pass takes the regular
+// pairs only; the near-singular and singular ones (a small fraction, each a
+// long closed form) follow in a second pass with one lane per row, which adds
+// all three hats of a near triangle into its own row, so the first pass keeps
+// few registers and many waves in flight.
 #include <cmath>
 
 #include "bem_device.h"
@@ -134,9 +138,7 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, 
                                                         const int32_t* __restrict__ tri,
                                                         const int32_t* __restrict__ fan_ptr,
                                                         const int32_t* __restrict__ fan,
-                                                        const double* __restrict__ pan64,
-                                                        const double* __restrict__ tri64, double* __restrict__ A,
-                                                        double* __restrict__ diag) {
+                                                        const double* __restrict__ pan64, double* __restrict__ A) {
     __shared__ double tile[4][NODAL_COLS][65];   // padded: the row-segment reads stride 65
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -156,6 +158,7 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, 
                 const double* P = pan64 + (int64_t)FAR_REC * t;
                 const int32_t* tv = tri + 3 * t;
                 const bool vtx = (tv[0] == i) || (tv[1] == i) || (tv[2] == i);
+                // near and singular pairs are left to k_nodal_near (same predicate)
                 if (!vtx && is_regular(x0 - P[FR_CC], x1 - P[FR_CC + 1], x2 - P[FR_CC + 2], P[FR_RR])) {
                     const NodeBary nb(c);
                     double s = 0.0;
@@ -165,14 +168,8 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, 
                         s += P[FR_W + q] * nb.b[q] * rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
                     }
                     acc += s;
-                } else {
-                    const double* T = tri64 + (int64_t)TRI_REC * t;
-                    double I0, r0, r1, r2, J0, J1, J2;
-                    hat_edges(T, x0, x1, x2, vtx, I0, r0, r1, r2, J0, J1, J2);
-                    acc += hat_value(T, c, I0, r0, r1, r2, J0, J1, J2);
                 }
             }
-            if (j == i) diag[i] = acc;
         }
         tile[wv][cc][lane] = acc;
     }
@@ -183,6 +180,108 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, 
         const int64_t ii = i0 + r, jj = j0 + cc;
         if (ii < nv && jj < nv) A[ii * ld + jj] = tile[wv][cc][r];
     }
+}
+
+// Bound of each chunk of 64 consecutive triangles: a centre and a radius such
+// that every point within eta R of a circumcentre of the chunk lies in the ball
+// (radius = max |cc - centre| + eta R), so a ball of rows apart from it by more
+// than the two radii makes only regular pairs with the chunk.
+__global__ __launch_bounds__(256) void k_nodal_chunk_bounds(int64_t N, int64_t Np, const double* __restrict__ far64,
+                                                            double* __restrict__ cb) {
+    const int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t t0 = ch * 64;
+    if (t0 >= N) return;
+    const int64_t t1 = t0 + 64 < N ? t0 + 64 : N;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        m0 += far64[(int64_t)(FR_CC + 0) * Np + t];
+        m1 += far64[(int64_t)(FR_CC + 1) * Np + t];
+        m2 += far64[(int64_t)(FR_CC + 2) * Np + t];
+    }
+    const double inv = 1.0 / (double)(t1 - t0);
+    m0 *= inv; m1 *= inv; m2 *= inv;
+    double r = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const double d0 = far64[(int64_t)(FR_CC + 0) * Np + t] - m0, d1 = far64[(int64_t)(FR_CC + 1) * Np + t] - m1;
+        const double d2 = far64[(int64_t)(FR_CC + 2) * Np + t] - m2;
+        const double e = sqrt(d0 * d0 + d1 * d1 + d2 * d2) + sqrt(far64[(int64_t)FR_RR * Np + t]);
+        r = e > r ? e : r;
+    }
+    cb[4 * ch] = m0;
+    cb[4 * ch + 1] = m1;
+    cb[4 * ch + 2] = m2;
+    cb[4 * ch + 3] = r;
+}
+
+__device__ __forceinline__ double lane_bcast(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k), hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Near-singular and singular pairs of the vertex rows (one lane per row, 64 rows
+// per block, the rows taken in a spatial (Morton) order of the vertices so that
+// a block's rows are neighbours).  Chunks of 64 triangles whose bound is beyond
+// reach of the rows' ball are skipped; in the others every triangle is classified with the
+// predicate of the first pass, its circumcentre, (eta R)^2 and vertex indices
+// loaded by the lanes together (component-major records) and broadcast from a
+// lane register.  A near triangle adds its three hats into the lane's own row.
+__global__ __launch_bounds__(64) void k_nodal_near(int64_t nv, int64_t ld, int64_t N, int64_t Np,
+                                                   const int32_t* __restrict__ row_order,
+                                                   const double* __restrict__ vert, const int32_t* __restrict__ tri,
+                                                   const double* __restrict__ far64, const double* __restrict__ cb,
+                                                   const double* __restrict__ tri64, double* __restrict__ A) {
+    const int lane = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = s < nv;
+    const int64_t ic = row_order[live ? s : nv - 1];
+    const int64_t i = live ? ic : -1;   // -1 matches no vertex
+    const double x0 = vert[3 * ic], x1 = vert[3 * ic + 1], x2 = vert[3 * ic + 2];
+    double* row = A + ic * ld;
+    // ball of the 64 rows
+    const double g0 = wave_sum(x0) / 64.0, g1 = wave_sum(x1) / 64.0, g2 = wave_sum(x2) / 64.0;
+    double rg = sqrt((x0 - g0) * (x0 - g0) + (x1 - g1) * (x1 - g1) + (x2 - g2) * (x2 - g2));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double other = __shfl_xor(rg, o, 64);
+        rg = other > rg ? other : rg;
+    }
+    for (int64_t t0 = 0; t0 < N; t0 += 64) {
+        const double* B = cb + 4 * (t0 >> 6);
+        const double e0 = B[0] - g0, e1 = B[1] - g1, e2 = B[2] - g2;
+        const double reach = (rg + B[3]) * (1.0 + 1e-9) + 1e-300;
+        if (e0 * e0 + e1 * e1 + e2 * e2 > reach * reach) continue;   // every pair regular
+        const int64_t tl = t0 + lane < N ? t0 + lane : N - 1;
+        const double c0 = far64[(int64_t)(FR_CC + 0) * Np + tl], c1 = far64[(int64_t)(FR_CC + 1) * Np + tl];
+        const double c2 = far64[(int64_t)(FR_CC + 2) * Np + tl], rr = far64[(int64_t)FR_RR * Np + tl];
+        const int32_t v0 = tri[3 * tl], v1 = tri[3 * tl + 1], v2 = tri[3 * tl + 2];
+        const int kend = N - t0 < 64 ? (int)(N - t0) : 64;
+        for (int k = 0; k < kend; ++k) {
+            const double cc0 = lane_bcast(c0, k), cc1 = lane_bcast(c1, k), cc2 = lane_bcast(c2, k);
+            const double crr = lane_bcast(rr, k);
+            const int32_t a = __builtin_amdgcn_readlane(v0, k), b = __builtin_amdgcn_readlane(v1, k);
+            const int32_t c = __builtin_amdgcn_readlane(v2, k);
+            const bool vtx = (a == i) || (b == i) || (c == i);
+            const bool near = vtx || !is_regular(x0 - cc0, x1 - cc1, x2 - cc2, crr);
+            if (near && live) {
+                // the three entries are read first so that their latency overlaps the closed form
+                const double ya = row[a], yb = row[b], yc = row[c];
+                const double* T = tri64 + (int64_t)TRI_REC * (t0 + k);
+                double I0, r0, r1, r2, J0, J1, J2;
+                hat_edges(T, x0, x1, x2, vtx, I0, r0, r1, r2, J0, J1, J2);
+                row[a] = ya + hat_value(T, 0, I0, r0, r1, r2, J0, J1, J2);
+                row[b] = yb + hat_value(T, 1, I0, r0, r1, r2, J0, J1, J2);
+                row[c] = yc + hat_value(T, 2, I0, r0, r1, r2, J0, J1, J2);
+            }
+        }
+    }
+}
+
+// Jacobi diagonal of the vertex rows
+__global__ __launch_bounds__(256) void k_nodal_diag(int64_t nv, int64_t ld, const double* __restrict__ A,
+                                                    double* __restrict__ diag) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < nv) diag[i] = A[i * ld + i];
 }
 
 // columns [nv, ld) of the vertex rows: -1 in the column of the row's floating body, else 0
@@ -296,8 +395,20 @@ void launch_nodal_assemble(bem_ctx* c) {
     if (ceil_div(nv, 4 * NODAL_COLS) > 65535) throw Error(BEM_ERR_INVALID, "too many vertices for the LINEAR basis");
     dim3 grid((unsigned)ceil_div(nv, 64), (unsigned)ceil_div(nv, 4 * NODAL_COLS));
     hipLaunchKernelGGL(k_nodal_assemble, grid, dim3(256), 0, s, nv, ld, c->vert.as<double>(), c->tri.as<int32_t>(),
-                       c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->pan64.as<double>(), c->tri64.as<double>(),
-                       c->A64.as<double>(), c->diag.as<double>());
+                       c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->pan64.as<double>(), c->A64.as<double>());
+    BEM_CHECK_LAUNCH();
+    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
+    const int64_t nch = ceil_div(c->N, 64);
+    c->nodal_bounds.alloc(sizeof(double) * 4 * (size_t)nch);
+    hipLaunchKernelGGL(k_nodal_chunk_bounds, dim3((unsigned)ceil_div(nch, 256)), dim3(256), 0, s, c->N, Np,
+                       c->far64.as<double>(), c->nodal_bounds.as<double>());
+    BEM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_nodal_near, dim3((unsigned)ceil_div(nv, 64)), dim3(64), 0, s, nv, ld, c->N, Np,
+                       c->row_order.as<int32_t>(), c->vert.as<double>(), c->tri.as<int32_t>(), c->far64.as<double>(), c->nodal_bounds.as<double>(),
+                       c->tri64.as<double>(), c->A64.as<double>());
+    BEM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_nodal_diag, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv, ld, c->A64.as<double>(),
+                       c->diag.as<double>());
     BEM_CHECK_LAUNCH();
     if (ld > nv) {
         hipLaunchKernelGGL(k_nodal_tail, dim3((unsigned)ceil_div(nv * (ld - nv), 256)), dim3(256), 0, s, nv, ld,
