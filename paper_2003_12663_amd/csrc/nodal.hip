@@ -133,19 +133,27 @@ __device__ __forceinline__ double hat_value(const double* __restrict__ T, int c,
     return (lam * I0 + (g0 * J0 + g1 * J1 + g2 * J2) / two_area) * INV4PI;
 }
 
-// One wave: rows i0 + lane, columns j0 .. j0 + 15.  grid (row tiles of 64, groups of 4 x 16 columns).
-__global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, const double* __restrict__ vert,
+// One wave: rows i0 + lane, columns j0 .. j0 + 15; the four waves of a block take
+// the same columns on four row tiles, so three of four record loads hit the
+// scalar cache.  1-D grid of n_rt x n_cg blocks (row tiles of 256 rows, column
+// groups of 16, n_cg a multiple of 8): blocks are dealt to the 8 XCDs in turn,
+// so block b runs on XCD b % 8, and each XCD sweeps all row tiles of one column
+// group before the next, keeping that group's records in its own L2.
+__global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, int64_t n_rt,
+                                                        const double* __restrict__ vert,
                                                         const int32_t* __restrict__ tri,
                                                         const int32_t* __restrict__ fan_ptr,
                                                         const int32_t* __restrict__ fan,
                                                         const double* __restrict__ pan64, double* __restrict__ A) {
     __shared__ double tile[4][NODAL_COLS][65];   // padded: the row-segment reads stride 65
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int64_t b = blockIdx.x, xcd = b & 7, slot = b >> 3;
+    const int64_t cg = (slot / n_rt) * 8 + xcd, rt = slot % n_rt;
+    const int64_t i0 = (rt * 4 + wv) * 64;
     const int64_t i = i0 + lane;
     const int64_t ic = i < nv ? i : nv - 1;
     const double x0 = vert[3 * ic], x1 = vert[3 * ic + 1], x2 = vert[3 * ic + 2];
-    const int64_t j0 = ((int64_t)blockIdx.y * 4 + wv) * NODAL_COLS;
+    const int64_t j0 = cg * NODAL_COLS;
     for (int cc = 0; cc < NODAL_COLS; ++cc) {
         const int64_t j = j0 + cc;
         double acc = 0.0;
@@ -392,10 +400,11 @@ void launch_nodal_assemble(bem_ctx* c) {
     KTimer kt(c, "nodal_assemble");
     const int64_t nv = c->n_vert, ld = c->ld;
     hipStream_t s = c->stream;
-    if (ceil_div(nv, 4 * NODAL_COLS) > 65535) throw Error(BEM_ERR_INVALID, "too many vertices for the LINEAR basis");
-    dim3 grid((unsigned)ceil_div(nv, 64), (unsigned)ceil_div(nv, 4 * NODAL_COLS));
-    hipLaunchKernelGGL(k_nodal_assemble, grid, dim3(256), 0, s, nv, ld, c->vert.as<double>(), c->tri.as<int32_t>(),
-                       c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->pan64.as<double>(), c->A64.as<double>());
+    const int64_t n_rt = ceil_div(nv, 256), n_cg = ceil_div(ceil_div(nv, NODAL_COLS), 8) * 8;
+    if (n_rt * n_cg > ((int64_t)1 << 31) - 1) throw Error(BEM_ERR_INVALID, "too many vertices for the LINEAR basis");
+    hipLaunchKernelGGL(k_nodal_assemble, dim3((unsigned)(n_rt * n_cg)), dim3(256), 0, s, nv, ld, n_rt,
+                       c->vert.as<double>(), c->tri.as<int32_t>(), c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(),
+                       c->pan64.as<double>(), c->A64.as<double>());
     BEM_CHECK_LAUNCH();
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t nch = ceil_div(c->N, 64);
