@@ -249,7 +249,9 @@ def nodal_run(bem, torch):
     constant basis on the conductor sphere, whose density is V0/R exactly: FP64 assembly
     (timed after a warm-up) and solve to 1e-10, and the largest density error.  Nodal on
     icospheres of level 5 (10,242 vertices, 20,480 panels) and 6 (40,962 / 81,920);
-    constant on level 5 (20,480 unknowns)."""
+    constant on level 5 (20,480 unknowns).  Then the nodal system of the coaxial conductors
+    (rod, grounded shell, floating ring) at 67,729 vertices, the node count of the paper's
+    Table 3 device."""
     from workloads import sphere_problem
     out = {}
 
@@ -279,6 +281,25 @@ def nodal_run(bem, torch):
     out["linear_L5"] = one(5, True)
     out["linear_L6"] = one(6, True)
     out["constant_L5"] = one(5, False)
+    # the coaxial conductors at the node count of the paper's Table 3 device (68,218)
+    from workloads import coax_conductors_for_vertices
+    p = coax_conductors_for_vertices(68218)
+    ctx = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1)
+    ctx.assemble()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.assemble()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol, info = ctx.solve(p.body_V, tol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["linear_coax_conductors"] = {
+        "unknowns": int(ctx.n), "vertices": p.n_vert, "panels": p.n_tri, "assemble_s": t1 - t0,
+        "row_panel_pairs_per_s": p.n_vert * p.n_tri / (t1 - t0), "matrix_entries_per_s": ctx.n ** 2 / (t1 - t0),
+        "solve_s": t2 - t1, "iters": info["iters"], "ring_potential_over_V0": float(sol[0, p.n_vert].cpu())}
+    ctx.close()
+    torch.cuda.empty_cache()
     return out
 
 

@@ -4,15 +4,18 @@ Vertex hats collocated at the vertices, conductor and floating-conductor
 bodies, a floating body's row its net charge.  Bars as for the constant basis:
 matrix entries 1e-12 of the row's largest, right-hand sides exact, solutions
 and potentials 1e-10.  Cases: spheres and a floating shell (vertex counts that
-leave ragged row tiles and column groups), two devices in one problem, and a
-level-5 sphere (10,242 vertices) on sampled oracle rows.
+leave ragged row tiles and column groups), two devices in one problem, the
+coaxial conductors with a floating ring (flat caps: coplanar near pairs), and
+on sampled oracle rows a level-5 sphere (10,242 vertices) and the coaxial
+conductors at 67,729 vertices.
 """
 
 import numpy as np
 import pytest
 
 import oracle
-from workloads import floating_shell_problem, sphere_problem, union_problem
+from workloads import (coax_conductors_for_vertices, coax_conductors_problem, floating_shell_problem, sphere_problem,
+                       union_problem)
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +47,8 @@ CASES = [
     ("floating_shell_L2", lambda: floating_shell_problem(2, V0=3.0)),
     ("sphere_and_shell", lambda: union_problem(sphere_problem(2, V0=1.5), floating_shell_problem(1, V0=-1.0),
                                                (4.0, 0.5, 0.0))),
+    # rod, grounded shell and floating ring; flat caps give coplanar near pairs
+    ("coax_conductors", lambda: coax_conductors_problem(0.012)),
 ]
 
 
@@ -104,6 +109,29 @@ def test_nodal_large_sampled_rows(bem):
     b = oracle.Oracle(p).p1_rhs(p.body_V)[rows]
     assert np.abs(R @ x - b).max() <= 1e-10
     c.close()
+
+
+def test_nodal_paper_size_sampled_rows(bem):
+    """The coaxial conductors at 67,729 vertices (135,450 panels; the paper's Table 3
+    device has 68,218 nodes): sampled rows against the oracle, the GPU solution's
+    residual on them, and the floating ring between its neighbours' potentials."""
+    p = coax_conductors_for_vertices(68218)
+    print(f"[nodal] coax conductors: {p.n_vert} vertices, {p.n_tri} panels", flush=True)
+    c = _ctx(bem, p)
+    nv = p.n_vert
+    rows = np.unique(np.concatenate([[0, 255, 256, nv - 1, nv], np.random.default_rng(5).integers(0, nv, 7)]))
+    o = oracle.Oracle(p)
+    R = o.p1_assemble_rows(rows)
+    for k, r in enumerate(rows):
+        g = c.copy_rows(int(r), 1)[0].cpu().numpy()
+        assert np.abs(g - R[k]).max() <= 1e-12 * np.abs(R[k]).max(), r
+    sol, info = c.solve(p.body_V, tol=1e-10, max_iter=5000)
+    assert info["converged"]
+    x = sol[0].cpu().numpy()
+    assert np.abs(R @ x - o.p1_rhs(p.body_V)[rows]).max() <= 1e-8
+    assert 0.0 < x[nv] < 1.0
+    c.close()
+    torch.cuda.empty_cache()
 
 
 def test_nodal_batched_load_cases(bem):

@@ -15,6 +15,8 @@ from .meshes import (  # noqa: F401
     floating_shell_problem,
     coax_problem,
     coax_problem_for_size,
+    coax_conductors_problem,
+    coax_conductors_for_vertices,
     sphere_sheet_problem,
     bushing_problem,
     union_problem,

@@ -481,6 +481,44 @@ def coax_problem(h: float, V0: float = 1.0) -> Problem:
         body_names=["shell", "rod", "ring", "disc"], start_mask=start_mask)
 
 
+def coax_conductors_problem(h: float, V0: float = 1.0) -> Problem:
+    """The coaxial device without its spacer disc: grounded shell (body 0), rod at V0
+    (body 1) and floating torus (body 2), all in air, with the element sizes of
+    coax_problem.  Conductors only, so it also suits the nodal basis (every vertex on
+    one body)."""
+    g = COAX
+    b = _Builder()
+    h_shell = 2.6 * h
+    _capped_cylinder(b, 0, g["shell_r"], -g["shell_z"], g["shell_z"], h_shell, h_shell, (), outward=False)
+    _capped_cylinder(b, 1, g["rod_r"], -g["rod_z"], g["rod_z"], h, h, (), outward=True)
+    _torus(b, 2, g["ring_R"], g["ring_r"], g["ring_z"], 0.85 * h)
+    vert, tri, body = b.finish()
+    return Problem(
+        name=f"coax_conductors_h{h:.5f}", vert=vert, tri=tri, tri_body=body,
+        body_kind=np.array([DIRICHLET, DIRICHLET, FLOATING], dtype=np.int32),
+        eps_plus=np.ones(3), eps_minus=np.ones(3), body_V=np.array([0.0, V0, 0.0]),
+        body_names=["shell", "rod", "ring"], start_mask=body == 1)
+
+
+def coax_conductors_for_vertices(n_target: int, V0: float = 1.0, tol: float = 0.02) -> Problem:
+    """coax_conductors_problem whose vertex count lies within n_target*(1 +- tol)
+    (bisection on log h; deterministic)."""
+    lo, hi = 1e-4, 2e-2
+    best = None
+    for _ in range(60):
+        h = math.sqrt(lo * hi)
+        p = coax_conductors_problem(h, V0)
+        if best is None or abs(p.n_vert - n_target) < abs(best.n_vert - n_target):
+            best = p
+        if abs(p.n_vert - n_target) <= tol * n_target:
+            return p
+        if p.n_vert > n_target:
+            lo = h
+        else:
+            hi = h
+    return best
+
+
 def coax_problem_for_size(n_target: int, V0: float = 1.0, tol: float = 0.05) -> Problem:
     """Coax mesh whose panel count lies within n_target*(1 +- tol).
 
