@@ -150,6 +150,15 @@ class Oracle:
         self.lib.orc_p1_potential(ctypes.byref(self.p), _ptr(u), ctypes.c_int64(len(pts)), _ptr(pts), _ptr(phi))
         return phi
 
+    def p1_field(self, u, pts):
+        """(phi [P], E [P, 3]) of the nodal density u at volume points."""
+        u = _f64(u)
+        pts = _f64(pts, (-1, 3))
+        phi = np.empty(len(pts), dtype=np.float64)
+        E = np.empty((len(pts), 3), dtype=np.float64)
+        self.lib.orc_p1_field(ctypes.byref(self.p), _ptr(u), ctypes.c_int64(len(pts)), _ptr(pts), _ptr(phi), _ptr(E))
+        return phi, E
+
     def classify(self, pts) -> np.ndarray:
         pts = _f64(pts, (-1, 3))
         out = np.empty((len(pts), self.N), dtype=np.int32)
@@ -256,6 +265,15 @@ def tri_linear_analytic(x, v1, v2, v3, on_plane=False):
     out = np.empty(3, dtype=np.float64)
     a = [_f64(v) for v in (x, v1, v2, v3)]
     lib.orc_tri_linear_analytic(*[_ptr(v) for v in a], ctypes.c_int(1 if on_plane else 0), _ptr(out))
+    return out
+
+
+def tri_linear_field(x, v1, v2, v3):
+    """int lambda_k (x - y) / (4 pi |x - y|^3) dS over the flat triangle, [3 vertices][3]."""
+    lib = _load()
+    out = np.empty((3, 3), dtype=np.float64)
+    a = [_f64(v) for v in (x, v1, v2, v3)]
+    lib.orc_tri_linear_field(*[_ptr(v) for v in a], _ptr(out))
     return out
 
 

@@ -637,6 +637,90 @@ void orc_tri_linear_analytic(const double x[3], const double v1[3], const double
     }
 }
 
+/* Field of the hats: out[k] = int lambda_k(y) (x - y) / (4 pi |x - y|^3) dS for
+ * x off the triangle's plane or outside it (volume points).  With u = y - rho
+ * (in-plane) and x - y = w n - u,
+ *   int lambda_k (x - y)/R^3 = lambda_k(rho) F0 + w n (g_k . int u/R^3) - int (g_k . u) u/R^3,
+ * F0 = int (x - y)/R^3 = sum_e m_e f_e + sign(w) n Omega (unit density, above), and
+ * in-plane divergence identities with grad_u (1/R) = -u/R^3 and
+ * grad_u ((g . u)/R) = g/R - (g . u) u/R^3:
+ *   int u/R^3 dS = -sum_e m_e f_e,
+ *   int (g . u) u/R^3 dS = g int 1/R dS - sum_e m_e int_e (g . u)/R dl,
+ * where on edge e, u = t m_e + s l_e (s from s- to s+), so
+ *   int_e (g . u)/R dl = t (g . m_e) f_e + (g . l_e)(R+ - R-).
+ * (g_k is divided by 2A as in orc_tri_linear_analytic.) */
+void orc_tri_linear_field(const double x[3], const double v1[3], const double v2[3], const double v3[3],
+                          double out[3][3])
+{
+    const double* v[3] = {v1, v2, v3};
+    double e1[3], e2[3], cr[3], n[3];
+    sub3(v2, v1, e1);
+    sub3(v3, v1, e2);
+    cross3(e1, e2, cr);
+    double len = norm3(cr);   /* 2 A */
+    for (int k = 0; k < 3; ++k) n[k] = cr[k] / len;
+    double xv[3];
+    sub3(x, v1, xv);
+    double w = dot3(xv, n);
+    double rho[3];
+    for (int k = 0; k < 3; ++k) rho[k] = x[k] - w * n[k];
+    double aw = fabs(w);
+    double sum_tf = 0.0, sum_beta = 0.0, mf[3] = {0.0, 0.0, 0.0};
+    double f_e[3], t_e[3], dR_e[3], m_e[3][3], l_e[3][3];
+    for (int e = 0; e < 3; ++e) {
+        const double* a = v[e];
+        const double* b = v[(e + 1) % 3];
+        double ab[3], ar[3], br[3], xa[3], xb[3];
+        sub3(b, a, ab);
+        double lab = norm3(ab);
+        for (int k = 0; k < 3; ++k) l_e[e][k] = ab[k] / lab;
+        cross3(l_e[e], n, m_e[e]);
+        sub3(a, rho, ar);
+        sub3(b, rho, br);
+        double sm = dot3(ar, l_e[e]), sp = dot3(br, l_e[e]), t = dot3(ar, m_e[e]);
+        sub3(x, a, xa);
+        sub3(x, b, xb);
+        double Rm = norm3(xa), Rp = norm3(xb);
+        double R02 = t * t + w * w;
+        double f;
+        if (sp + sm > 0.0)
+            f = log((Rp + sp) / (Rm + sm));
+        else
+            f = log((Rm - sm) / (Rp - sp));
+        double beta = atan2(t * sp, R02 + aw * Rp) - atan2(t * sm, R02 + aw * Rm);
+        sum_tf += t * f;
+        sum_beta += beta;
+        for (int k = 0; k < 3; ++k) mf[k] += m_e[e][k] * f;
+        f_e[e] = f;
+        t_e[e] = t;
+        dR_e[e] = Rp - Rm;
+    }
+    double sgn = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
+    double I0 = sum_tf - aw * sum_beta;
+    double F0[3];
+    for (int k = 0; k < 3; ++k) F0[k] = mf[k] + sgn * n[k] * sum_beta;
+    for (int k = 0; k < 3; ++k) {
+        const double* p1 = v[(k + 1) % 3];
+        const double* p2 = v[(k + 2) % 3];
+        double opp[3], g[3], r1[3], r2[3], c[3];
+        sub3(p2, p1, opp);
+        cross3(n, opp, g);
+        for (int d = 0; d < 3; ++d) g[d] /= len;
+        sub3(p1, rho, r1);
+        sub3(p2, rho, r2);
+        cross3(r1, r2, c);
+        double lam = dot3(c, n) / len;
+        double gu3 = -dot3(g, mf);                 /* g . int u/R^3 */
+        double edge[3] = {0.0, 0.0, 0.0};          /* sum_e m_e int_e (g . u)/R dl */
+        for (int e = 0; e < 3; ++e) {
+            double ge = t_e[e] * dot3(g, m_e[e]) * f_e[e] + dot3(g, l_e[e]) * dR_e[e];
+            for (int d = 0; d < 3; ++d) edge[d] += m_e[e][d] * ge;
+        }
+        for (int d = 0; d < 3; ++d)
+            out[k][d] = (lam * F0[d] + w * n[d] * gu3 - (g[d] * I0 - edge[d])) / (4.0 * ORC_PI);
+    }
+}
+
 /* Vertex -> body map of the nodal basis.  Returns 0, or -1 if a vertex is in
  * no triangle or in triangles of two bodies, -2 if a body is not a conductor
  * (DIRICHLET) or floating conductor (FLOATING): interface and sheet rows need
@@ -773,6 +857,53 @@ int orc_p1_rhs(const orc_problem* p, const double* body_V, double* b)
     }
     free(vb);
     return rc;
+}
+
+/* phi(x) = sum_k u_k int psi_k / (4 pi |x - y|) dS and E(x) = sum_k u_k
+ * int psi_k (x - y) / (4 pi |x - y|^3) dS (the field formula closing Sec. 2) at
+ * volume points (off the mesh), with the classification of the assembly:
+ * regular pairs by the 7-point rule with the density at the nodes, the others
+ * by the closed forms.  phi or E may be NULL. */
+int orc_p1_field(const orc_problem* p, const double* u, int64_t P, const double* pts, double* phi, double* E)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    double bary[7][3], wt[7];
+    orc_quad7_rule(bary, wt);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < P; ++i) {
+        const double* x = pts + 3 * i;
+        double s = 0.0, e[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < p->n_tri; ++j) {
+            const int32_t* t = p->tri + 3 * j;
+            const double* v = g.v + 9 * j;
+            if (pair_is_regular(p, &g, x, j)) {
+                for (int q = 0; q < 7; ++q) {
+                    double y[3], d[3];
+                    for (int k = 0; k < 3; ++k) y[k] = bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
+                    sub3(x, y, d);
+                    double r = norm3(d);
+                    double sig = bary[q][0] * u[t[0]] + bary[q][1] * u[t[1]] + bary[q][2] * u[t[2]];
+                    double c = wt[q] * g.area[j] / (4.0 * ORC_PI) * sig;
+                    s += c / r;
+                    for (int k = 0; k < 3; ++k) e[k] += c * d[k] / (r * r * r);
+                }
+            } else {
+                double c[3], F[3][3];
+                orc_tri_linear_analytic(x, v, v + 3, v + 6, 0, c);
+                orc_tri_linear_field(x, v, v + 3, v + 6, F);
+                for (int k = 0; k < 3; ++k) {
+                    s += c[k] * u[t[k]];
+                    for (int d = 0; d < 3; ++d) e[d] += F[k][d] * u[t[k]];
+                }
+            }
+        }
+        if (phi) phi[i] = s;
+        if (E)
+            for (int k = 0; k < 3; ++k) E[3 * i + k] = e[k];
+    }
+    geom_free(&g);
+    return 0;
 }
 
 /* phi(x) = sum_k u_k int psi_k / (4 pi |x - y|) dS at points off the mesh

@@ -14,6 +14,10 @@ The oracle's pieces are pinned by things that do not come from it:
   * a floating shell (its potential V_f = 0.6 V0, net charge zero);
   * the matrix of Eq. Matrix against a 7-point-free brute-force row (every
     triangle integrated by the brute force) on a coarse sphere;
+  * the field of the hats against a brute force (1e-10), against central
+    differences of the hat potentials and, summed, against the unit-density
+    field; the sphere's field V0 R x/|x|^3 outside and 0 inside with
+    second-order convergence;
   * refusal of interface bodies and of vertices shared by two bodies.
 """
 
@@ -147,6 +151,102 @@ def test_hat_integrals_at_a_vertex(oracle_mod, seed):
         assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)), (k, got, ref)
         # the vertex's own hat carries more than the others at its vertex
         assert got[k] > max(got[(k + 1) % 3], got[(k + 2) % 3])
+
+
+def brute_hat_fields(x, v1, v2, v3, nv=200, nu=32):
+    """Brute-force int lambda_k (x - y) / (4 pi |x - y|^3) dS, [k][3], by the
+    splitting and graded Duffy rule of brute_hats."""
+    x, v1, v2, v3 = (np.asarray(a, dtype=np.float64) for a in (x, v1, v2, v3))
+    cr0 = np.cross(v2 - v1, v3 - v1)
+    twoA = np.linalg.norm(cr0)
+    n = cr0 / twoA
+    w = float(np.dot(x - v1, n))
+    rho = x - w * n
+    size = max(np.linalg.norm(v2 - v1), np.linalg.norm(v3 - v2), np.linalg.norm(v1 - v3))
+    base = max(abs(w) / (4 * size), 1e-7)
+    bps = [0.0]
+    b = base / 64
+    while b < 1.0:
+        bps.append(b)
+        b *= 2.0
+    bps.append(1.0)
+    ug, uw = _gl(nu)
+    vg, vw = _gl(nv)
+    out = np.zeros((3, 3))
+    V = (v1, v2, v3)
+    for a, bb in ((v1, v2), (v2, v3), (v3, v1)):
+        pa, pb = a - rho, bb - rho
+        cr = np.cross(pa, pb)
+        sgn = np.sign(np.dot(cr, n))
+        J = np.linalg.norm(cr)
+        if J < 1e-300:
+            continue
+        for lo, hi in zip(bps[:-1], bps[1:]):
+            u = lo + (hi - lo) * ug
+            wu = (hi - lo) * uw
+            U, Vv = np.meshgrid(u, vg, indexing="ij")
+            W = np.outer(wu, vw)
+            d = (1 - Vv)[..., None] * pa + Vv[..., None] * pb
+            y = rho + U[..., None] * d
+            r = x - y
+            R = np.linalg.norm(r, axis=-1)
+            jac = U * J * W * sgn / R ** 3
+            for k in range(3):
+                p1, p2 = V[(k + 1) % 3], V[(k + 2) % 3]
+                lam = np.einsum("ijk,k->ij", np.cross(p1 - y, p2 - y), n) / twoA
+                out[k] += np.einsum("ij,ijk->k", jac * lam, r)
+    return out / (4 * math.pi)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_hat_fields(oracle_mod, seed):
+    """Field of the hats: against the brute force (1e-10; the 1/R^3 kernel is
+    harder for it), against central differences of the hat potentials (whose
+    closed form the brute force pins to 1e-12), and their sum against the
+    unit-density field of the plain closed form."""
+    v = _tri(seed)
+    rng = np.random.default_rng(200 + seed)
+    for name, x in _points(v, rng):
+        if name == "coplanar_outside":
+            x = x + 1e-3 * np.cross(v[1] - v[0], v[2] - v[0])   # a volume point just off the plane
+        got = oracle_mod.tri_linear_field(x, *v)
+        ref = brute_hat_fields(x, *v)
+        tol = 1e-9 if name == "far" else 1e-10
+        assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)), (name, got, ref)
+        # E = -grad phi, hat by hat (not on the far point: the closed-form potential's
+        # cancellation there, ~1e-15, over the step would swamp the bar)
+        if name == "far":
+            continue
+        h = 1e-5 * max(np.linalg.norm(v[1] - v[0]), 1.0)
+        fd = np.zeros((3, 3))
+        for d in range(3):
+            e = np.zeros(3)
+            e[d] = h
+            fd[:, d] = -(oracle_mod.tri_linear_analytic(x + e, *v) - oracle_mod.tri_linear_analytic(x - e, *v)) / (2 * h)
+        assert np.max(np.abs(got - fd)) <= 1e-7 * np.max(np.abs(got)), name
+    for name, x in _points(v, rng):
+        if name == "coplanar_outside":
+            x = x + 1e-3 * np.cross(v[1] - v[0], v[2] - v[0])
+        got = oracle_mod.tri_linear_field(x, *v)
+        _, F = oracle_mod.tri_analytic(x, *v)
+        assert np.max(np.abs(got.sum(axis=0) - F)) <= 1e-11 * np.max(np.abs(F)), name
+
+
+def test_sphere_nodal_field(oracle_mod):
+    """E of the nodal solution on the conductor sphere: V0 R x/|x|^3 outside and
+    0 inside, second order in h."""
+    pts = np.array([[0.0, 0.0, 1.5], [1.2, -0.9, 0.4], [0.2, 0.1, -0.3], [-0.4, 0.3, 0.2]])
+    r = np.linalg.norm(pts, axis=1)
+    exact = np.where((r > 1.0)[:, None], pts / r[:, None] ** 3, 0.0)
+    errs = []
+    for level in (2, 3, 4):
+        p = sphere_problem(level)
+        o = oracle_mod.Oracle(p)
+        u = np.linalg.solve(o.p1_assemble(), o.p1_rhs(p.body_V))
+        phi, E = o.p1_field(u, pts)
+        assert np.allclose(phi, o.p1_potential(u, pts), rtol=0, atol=1e-13)
+        errs.append(np.max(np.abs(E - exact)))
+    assert errs[-1] < 2e-3 and errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
 
 
 def test_matrix_against_brute_force_rows(oracle_mod):
