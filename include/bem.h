@@ -69,9 +69,9 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
  *            vertex of flat panels lacks); a floating body's row is its net charge
  *            (constraint_form must be 1); FP64 only; every vertex in at least one triangle and
  *            all triangles at a vertex of one body.  Supported calls: bem_assemble,
- *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres and the potential of
- *            bem_eval_field; the field, field lines, the streamer integral, its gradient and
- *            the autotuner need CONSTANT (INVALID otherwise). */
+ *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres and bem_eval_field at
+ *            volume points (on_panel NULL; phi or E may be NULL); field lines, the streamer
+ *            integral, its gradient and the autotuner need CONSTANT (INVALID otherwise). */
 typedef enum { BEM_BASIS_CONSTANT = 0, BEM_BASIS_LINEAR = 1 } bem_basis;
 
 /* One body.  Triangle normals (right-hand rule of the vertex order) point
@@ -185,7 +185,7 @@ bem_status bem_solve_gmres(bem_ctx* ctx, int32_t nrhs, const double* body_V, dou
  *  on_panel dev [P] or NULL: >= 0 marks the point as that panel's centroid and
  *           returns the limit from the eps+ side (principal value + sigma n / 2);
  *           -1 = volume point (must not lie on a panel edge).
- *  phi      dev [nrhs][P] or NULL;  E dev [nrhs][P][3]. */
+ *  phi      dev [nrhs][P] or NULL;  E dev [nrhs][P][3] (may be NULL for the LINEAR basis). */
 bem_status bem_eval_field(bem_ctx* ctx, int32_t nrhs, const double* sol, int64_t P, const double* pts,
                           const int32_t* on_panel, double* phi, double* E);
 

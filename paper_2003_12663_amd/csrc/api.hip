@@ -582,12 +582,11 @@ bem_status bem_eval_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P
     DeviceGuard g(c->device);
     API_TRY
     if (c->opt.basis == BEM_BASIS_LINEAR) {
-        if (nrhs < 1 || !sol || (P > 0 && !phi))
-            throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL sol, phi required");
-        if (E || on_panel)
-            throw bem::Error(BEM_ERR_INVALID, "the LINEAR basis evaluates the potential only (E and on_panel NULL)");
+        if (nrhs < 1 || !sol || (P > 0 && !phi && !E))
+            throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1, non-NULL sol and phi or E required");
+        if (on_panel) throw bem::Error(BEM_ERR_INVALID, "the LINEAR basis evaluates at volume points (on_panel NULL)");
         check_points(c, P, pts);
-        bem::launch_nodal_potential(c, nrhs, sol, P, pts, phi);
+        bem::launch_nodal_field(c, nrhs, sol, P, pts, phi, E);
         return BEM_OK;
     }
     if (nrhs < 1 || !sol || (P > 0 && !E)) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL sol, E required");

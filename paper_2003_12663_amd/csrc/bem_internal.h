@@ -205,8 +205,8 @@ void launch_finalize(bem_ctx* c);                                  // assemble.h
 void launch_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out);
 void launch_rhs(bem_ctx* c, int32_t nrhs, const double* d_bodyV, double* b);
 void launch_nodal_assemble(bem_ctx* c);                                          // nodal.hip
-void launch_nodal_potential(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts,
-                            double* phi);                                           // nodal.hip
+void launch_nodal_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi,
+                        double* E);                                                  // nodal.hip
 void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      // gemv.hip
 void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s);    // gemv.hip
 int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,

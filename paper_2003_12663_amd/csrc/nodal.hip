@@ -133,6 +133,96 @@ __device__ __forceinline__ double hat_value(const double* __restrict__ T, int c,
     return (lam * I0 + (g0 * J0 + g1 * J1 + g2 * J2) / two_area) * INV4PI;
 }
 
+// Potential and field at a volume point x of the linear density on the flat
+// triangle T with vertex values u0, u1, u2, added to phi and E.  With
+// sigma(y) = sigma(rho) + G . (y - rho) (G the in-plane gradient of the
+// density, sum_k u_k g_k) and x - y = w n - (y - rho):
+//   4 pi phi = sigma(rho) int 1/R + G . int (y - rho)/R,
+//   4 pi E   = sigma(rho) F0 - w n (G . sum_e m_e f_e)
+//              - G int 1/R + sum_e m_e (t (G . m_e) f_e + (G . l_e)(R+ - R-)),
+// F0 = sum_e m_e f_e + sign(w) n Omega the unit-density field; the last two
+// terms are int (G . u) u / R^3 by the in-plane divergence identity
+// grad_u ((G . u)/R) = G/R - (G . u) u/R^3, whose edge integrals are
+// t (G . m) f_e + (G . l)(R+ - R-) for u = t m + s l.  Edge notation as in
+// hat_edges; x must not lie on the triangle.
+__device__ __forceinline__ void nodal_tri_phiE(const double* __restrict__ T, double x0, double x1, double x2,
+                                               double u0, double u1, double u2, double& phi, double& E0, double& E1,
+                                               double& E2) {
+    const double n0 = T[TR_N + 0], n1 = T[TR_N + 1], n2 = T[TR_N + 2];
+    const double two_area = 2.0 * T[TR_A];
+    const double w = (x0 - T[0]) * n0 + (x1 - T[1]) * n1 + (x2 - T[2]) * n2;
+    const double r0 = x0 - w * n0, r1 = x1 - w * n1, r2 = x2 - w * n2;
+    const double aw = fabs(w);
+    const double uk[3] = {u0, u1, u2};
+    // sigma(rho) and G
+    double srho = 0.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double* p = T + 3 * ((c + 1) % 3);
+        const double* q = T + 3 * ((c + 2) % 3);
+        const double a0 = p[0] - r0, a1 = p[1] - r1, a2 = p[2] - r2;
+        const double b0 = q[0] - r0, b1 = q[1] - r1, b2 = q[2] - r2;
+        srho += uk[c] * (n0 * (a1 * b2 - a2 * b1) + n1 * (a2 * b0 - a0 * b2) + n2 * (a0 * b1 - a1 * b0));
+        const double e0 = q[0] - p[0], e1 = q[1] - p[1], e2 = q[2] - p[2];
+        G0 += uk[c] * (n1 * e2 - n2 * e1);
+        G1 += uk[c] * (n2 * e0 - n0 * e2);
+        G2 += uk[c] * (n0 * e1 - n1 * e0);
+    }
+    srho /= two_area;
+    G0 /= two_area; G1 /= two_area; G2 /= two_area;
+    double V[3][3], Rv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        V[k][0] = T[3 * k] - x0;
+        V[k][1] = T[3 * k + 1] - x1;
+        V[k][2] = T[3 * k + 2] - x2;
+        Rv[k] = sqrt(V[k][0] * V[k][0] + V[k][1] * V[k][1] + V[k][2] * V[k][2]);
+    }
+    double st = 0.0, mf0 = 0.0, mf1 = 0.0, mf2 = 0.0, J0 = 0.0, J1 = 0.0, J2 = 0.0, K0 = 0.0, K1 = 0.0, K2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int b = (e + 1) % 3;
+        const double ax = T[3 * e], ay = T[3 * e + 1], az = T[3 * e + 2];
+        double l0 = T[3 * b] - ax, l1 = T[3 * b + 1] - ay, l2 = T[3 * b + 2] - az;
+        const double len = sqrt(l0 * l0 + l1 * l1 + l2 * l2);
+        const double il = 1.0 / len;
+        l0 *= il; l1 *= il; l2 *= il;
+        const double m0 = l1 * n2 - l2 * n1, m1 = l2 * n0 - l0 * n2, m2 = l0 * n1 - l1 * n0;
+        const double q0 = ax - r0, q1 = ay - r1, q2 = az - r2;
+        const double sm = q0 * l0 + q1 * l1 + q2 * l2;
+        const double sp = sm + len;
+        const double t = q0 * m0 + q1 * m1 + q2 * m2;
+        const double Rm = Rv[e], Rp = Rv[b];
+        double f;
+        if (sp + sm > 0.0)
+            f = log((Rp + sp) / (Rm + sm));
+        else
+            f = log((Rm - sm) / (Rp - sp));
+        st += t * f;
+        mf0 += m0 * f; mf1 += m1 * f; mf2 += m2 * f;
+        const double er = 0.5 * (sp * Rp - sm * Rm + (t * t + w * w) * f);
+        J0 += m0 * er; J1 += m1 * er; J2 += m2 * er;
+        const double ge = t * (G0 * m0 + G1 * m1 + G2 * m2) * f + (G0 * l0 + G1 * l1 + G2 * l2) * (Rp - Rm);
+        K0 += m0 * ge; K1 += m1 * ge; K2 += m2 * ge;
+    }
+    const double c0 = V[1][1] * V[2][2] - V[1][2] * V[2][1];
+    const double c1 = V[1][2] * V[2][0] - V[1][0] * V[2][2];
+    const double c2 = V[1][0] * V[2][1] - V[1][1] * V[2][0];
+    const double triple = V[0][0] * c0 + V[0][1] * c1 + V[0][2] * c2;
+    const double d01 = V[0][0] * V[1][0] + V[0][1] * V[1][1] + V[0][2] * V[1][2];
+    const double d02 = V[0][0] * V[2][0] + V[0][1] * V[2][1] + V[0][2] * V[2][2];
+    const double d12 = V[1][0] * V[2][0] + V[1][1] * V[2][1] + V[1][2] * V[2][2];
+    const double den = Rv[0] * Rv[1] * Rv[2] + d01 * Rv[2] + d02 * Rv[1] + d12 * Rv[0];
+    const double omega = 2.0 * atan2(fabs(triple), den);
+    const double I0 = st - aw * omega;
+    const double sg = (w > 0.0) ? omega : ((w < 0.0) ? -omega : 0.0);
+    const double Gmf = G0 * mf0 + G1 * mf1 + G2 * mf2;
+    phi += (srho * I0 + G0 * J0 + G1 * J1 + G2 * J2) * INV4PI;
+    E0 += (srho * (mf0 + sg * n0) - w * n0 * Gmf - G0 * I0 + K0) * INV4PI;
+    E1 += (srho * (mf1 + sg * n1) - w * n1 * Gmf - G1 * I0 + K1) * INV4PI;
+    E2 += (srho * (mf2 + sg * n2) - w * n2 * Gmf - G2 * I0 + K2) * INV4PI;
+}
+
 // One wave: rows i0 + lane, columns j0 .. j0 + 15; the four waves of a block take
 // the same columns on four row tiles, so three of four record loads hit the
 // scalar cache.  1-D grid of n_rt x n_cg blocks (row tiles of 256 rows, column
@@ -345,15 +435,18 @@ __global__ __launch_bounds__(256) void k_nodal_constraint(int64_t nv, int64_t ld
     if (k == 0) diag[nv + f] = 1.0;
 }
 
-// phi at points from vertex densities: 64 points per block, the triangles split
-// over the 4 waves, partial sums folded in LDS.  grid (point tiles, load cases).
-__global__ __launch_bounds__(256) void k_nodal_potential(int64_t P, const double* __restrict__ pts, int64_t N,
-                                                         const int32_t* __restrict__ tri,
-                                                         const double* __restrict__ pan64,
-                                                         const double* __restrict__ tri64,
-                                                         const double* __restrict__ sol, int64_t n,
-                                                         double* __restrict__ phi) {
-    __shared__ double part[4][64];
+// phi and E at volume points from vertex densities (the field formula closing
+// Sec. 2): 64 points per block, the triangles split over the 4 waves, partial
+// sums folded in LDS.  Regular pairs by the 7-point rule with the density at the
+// nodes, the others by nodal_tri_phiE.  grid (point tiles, load cases); phi or E
+// may be null.
+__global__ __launch_bounds__(256) void k_nodal_field(int64_t P, const double* __restrict__ pts, int64_t N,
+                                                     const int32_t* __restrict__ tri,
+                                                     const double* __restrict__ pan64,
+                                                     const double* __restrict__ tri64,
+                                                     const double* __restrict__ sol, int64_t n,
+                                                     double* __restrict__ phi, double* __restrict__ E) {
+    __shared__ double part[4][4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * 64 + lane;
     const int64_t pc = p < P ? p : P - 1;
@@ -364,7 +457,7 @@ __global__ __launch_bounds__(256) void k_nodal_potential(int64_t P, const double
     const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
     const int64_t per = (N + 3) / 4;
     const int64_t t0 = wv * per, t1 = t0 + per < N ? t0 + per : N;
-    double acc = 0.0;
+    double ph = 0.0, e0 = 0.0, e1 = 0.0, e2 = 0.0;
     for (int64_t t = t0; t < t1; ++t) {
         const int32_t* tv = tri + 3 * t;
         const double u0 = u[tv[0]], u1 = u[tv[1]], u2 = u[tv[2]];
@@ -374,24 +467,38 @@ __global__ __launch_bounds__(256) void k_nodal_potential(int64_t P, const double
             const double sq[7] = {(u0 + u1 + u2) / 3.0,
                                   a1 * u0 + a1 * u1 + b1 * u2, a1 * u0 + b1 * u1 + a1 * u2, b1 * u0 + a1 * u1 + a1 * u2,
                                   a2 * u0 + a2 * u1 + b2 * u2, a2 * u0 + b2 * u1 + a2 * u2, b2 * u0 + a2 * u1 + a2 * u2};
-            double s = 0.0;
 #pragma unroll
             for (int q = 0; q < 7; ++q) {
                 const double d0 = x0 - Pr[FR_X + q], d1 = x1 - Pr[FR_Y + q], d2 = x2 - Pr[FR_Z + q];
-                s += Pr[FR_W + q] * sq[q] * rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
+                const double ir = rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
+                const double c = Pr[FR_W + q] * sq[q] * ir;
+                const double c3 = c * ir * ir;
+                ph += c;
+                e0 += c3 * d0;
+                e1 += c3 * d1;
+                e2 += c3 * d2;
             }
-            acc += s;
         } else {
-            const double* T = tri64 + (int64_t)TRI_REC * t;
-            double I0, r0, r1, r2, J0, J1, J2;
-            hat_edges(T, x0, x1, x2, false, I0, r0, r1, r2, J0, J1, J2);
-            acc += u0 * hat_value(T, 0, I0, r0, r1, r2, J0, J1, J2) + u1 * hat_value(T, 1, I0, r0, r1, r2, J0, J1, J2) +
-                   u2 * hat_value(T, 2, I0, r0, r1, r2, J0, J1, J2);
+            nodal_tri_phiE(tri64 + (int64_t)TRI_REC * t, x0, x1, x2, u0, u1, u2, ph, e0, e1, e2);
         }
     }
-    part[wv][lane] = acc;
+    part[0][wv][lane] = ph;
+    part[1][wv][lane] = e0;
+    part[2][wv][lane] = e1;
+    part[3][wv][lane] = e2;
     __syncthreads();
-    if (wv == 0 && p < P) phi[(int64_t)blockIdx.y * P + p] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (wv == 0 && p < P) {
+        const int64_t o = (int64_t)blockIdx.y * P + p;
+        double r[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) r[c] = (part[c][0][lane] + part[c][1][lane]) + (part[c][2][lane] + part[c][3][lane]);
+        if (phi) phi[o] = r[0];
+        if (E) {
+            E[3 * o] = r[1];
+            E[3 * o + 1] = r[2];
+            E[3 * o + 2] = r[3];
+        }
+    }
 }
 
 }  // namespace
@@ -442,14 +549,16 @@ void launch_nodal_assemble(bem_ctx* c) {
     }
 }
 
-void launch_nodal_potential(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi) {
-    KTimer kt(c, "nodal_potential");
+void launch_nodal_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi,
+                        double* E) {
+    KTimer kt(c, "nodal_field");
     if (P == 0) return;
     for (int32_t r0 = 0; r0 < nrhs; r0 += 65535) {   // load cases on grid.y
         const int32_t nr = nrhs - r0 < 65535 ? nrhs - r0 : 65535;
-        hipLaunchKernelGGL(k_nodal_potential, dim3((unsigned)ceil_div(P, 64), (unsigned)nr), dim3(256), 0, c->stream,
-                           P, pts, c->N, c->tri.as<int32_t>(), c->pan64.as<double>(), c->tri64.as<double>(),
-                           sol + (int64_t)r0 * c->n, c->n, phi + (int64_t)r0 * P);
+        hipLaunchKernelGGL(k_nodal_field, dim3((unsigned)ceil_div(P, 64), (unsigned)nr), dim3(256), 0, c->stream, P,
+                           pts, c->N, c->tri.as<int32_t>(), c->pan64.as<double>(), c->tri64.as<double>(),
+                           sol + (int64_t)r0 * c->n, c->n, phi ? phi + (int64_t)r0 * P : nullptr,
+                           E ? E + (int64_t)r0 * P * 3 : nullptr);
         BEM_CHECK_LAUNCH();
     }
 }

@@ -2,8 +2,8 @@
 
 Vertex hats collocated at the vertices, conductor and floating-conductor
 bodies, a floating body's row its net charge.  Bars as for the constant basis:
-matrix entries 1e-12 of the row's largest, right-hand sides exact, solutions
-and potentials 1e-10.  Cases: spheres and a floating shell (vertex counts that
+matrix entries 1e-12 of the row's largest, right-hand sides exact, solutions,
+potentials and fields 1e-10.  Cases: spheres and a floating shell (vertex counts that
 leave ragged row tiles and column groups), two devices in one problem, the
 coaxial conductors with a floating ring (flat caps: coplanar near pairs), and
 on sampled oracle rows a level-5 sphere (10,242 vertices) and the coaxial
@@ -73,23 +73,29 @@ def test_nodal_matrix_rhs_solution(bem, name, make):
     rng = np.random.default_rng(4)
     pts = np.concatenate([rng.uniform(-3, 3, (40, 3)), p.vert[rng.integers(0, p.n_vert, 8)] * 1.02])
     phi = c.potential(sol, pts)[0].cpu().numpy()
-    phi_ref = o.p1_potential(sol[0].cpu().numpy(), pts)
+    phi_ref, E_ref = o.p1_field(sol[0].cpu().numpy(), pts)
     assert rel(phi, phi_ref) <= 1e-10
+    phi2, E = c.eval_field(sol, pts)
+    assert np.array_equal(phi2[0].cpu().numpy(), phi)
+    assert rel(E[0].cpu().numpy(), E_ref) <= 1e-10
     c.close()
 
 
 def test_nodal_matches_closed_form_sphere(bem):
     """Conductor sphere at V0: u = V0/R at every vertex to the discretisation error
-    (second order: level 4 below 2e-3), potential V0 R/|x| outside."""
+    (second order: level 4 below 2e-3), potential V0 R/|x| and field V0 R x/|x|^3
+    outside, V0 and 0 inside."""
     p = sphere_problem(4, V0=1.0)
     c = _ctx(bem, p)
     sol, info = c.solve(p.body_V, tol=1e-12, max_iter=5000)
     u = sol[0].cpu().numpy()
     assert np.max(np.abs(u - 1.0)) < 2e-3
-    pts = np.array([[0.0, 0.0, 3.0], [2.0, -1.0, 0.5], [0.1, 0.2, -0.3]])
-    phi = c.potential(sol, pts)[0].cpu().numpy()
+    pts = np.array([[0.0, 0.0, 3.0], [2.0, -1.0, 0.5], [0.1, 0.2, -0.3], [0.0, 1.3, 0.2]])
+    phi, E = c.eval_field(sol, pts)
+    phi, E = phi[0].cpu().numpy(), E[0].cpu().numpy()
     r = np.linalg.norm(pts, axis=1)
     assert np.max(np.abs(phi - np.where(r > 1, 1 / r, 1.0))) < 2e-3
+    assert np.max(np.abs(E - np.where((r > 1)[:, None], pts / r[:, None] ** 3, 0.0))) < 2e-3
     c.close()
 
 
@@ -160,8 +166,8 @@ def test_nodal_refusals(bem):
         bem.Context.from_problem(coated_sphere_problem(1), basis=bem.BASIS_LINEAR, constraint_form=1)
     c = _ctx(bem, p)
     sol, _ = c.solve(p.body_V, tol=1e-10)
-    with pytest.raises(bem.BemError):   # no field for the nodal basis
-        c.eval_field(sol, np.zeros((1, 3)) + 2.0)
+    with pytest.raises(bem.BemError):   # volume points only
+        c.eval_field(sol, p.vert[p.tri[:1]].mean(axis=1), on_panel=np.zeros(1, dtype=np.int32))
     with pytest.raises(bem.BemError):   # no field lines either
         c.streamer_integral(sol, torch.tensor([[0.0, 0.0, 1.2]], device="cuda"), bem.trace_params(h=1e-3))
     c.close()
