@@ -195,6 +195,19 @@ class Oracle:
                            _ptr(ns), _ptr(st), _ptr(I), _ptr(path))
         return (ns, st, I, path) if want_path else (ns, st, I)
 
+    def p1_trace(self, u, starts, params: TraceParams, want_path=False):
+        """Field lines and streamer integrals of the nodal density u (orc_p1_trace)."""
+        u = _f64(u)
+        starts = _f64(starts, (-1, 3))
+        L = len(starts)
+        ns = np.empty(L, dtype=np.int32)
+        st = np.empty(L, dtype=np.int32)
+        I = np.empty(L, dtype=np.float64)
+        path = np.full((L, params.max_steps + 1, 3), np.nan) if want_path else None
+        self.lib.orc_p1_trace(ctypes.byref(self.p), _ptr(u), ctypes.c_int64(L), _ptr(starts), ctypes.byref(params),
+                              _ptr(ns), _ptr(st), _ptr(I), _ptr(path))
+        return (ns, st, I, path) if want_path else (ns, st, I)
+
     def dual_streamer(self, dvert, body_V, dbody_V, start_panel, start_bary, params: TraceParams, n_steps,
                       tol=1e-13):
         """Forward-mode derivative of the streamer integrals along (dvert, dbody_V), with the

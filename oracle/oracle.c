@@ -864,40 +864,48 @@ int orc_p1_rhs(const orc_problem* p, const double* body_V, double* b)
  * volume points (off the mesh), with the classification of the assembly:
  * regular pairs by the 7-point rule with the density at the nodes, the others
  * by the closed forms.  phi or E may be NULL. */
+static void p1_field_at(const orc_problem* p, const orc_geom* g, const double* u, const double x[3], double* phi,
+                        double E[3])
+{
+    double bary[7][3], wt[7];
+    orc_quad7_rule(bary, wt);
+    double s = 0.0, e[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = 0; j < p->n_tri; ++j) {
+        const int32_t* t = p->tri + 3 * j;
+        const double* v = g->v + 9 * j;
+        if (pair_is_regular(p, g, x, j)) {
+            for (int q = 0; q < 7; ++q) {
+                double y[3], d[3];
+                for (int k = 0; k < 3; ++k) y[k] = bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
+                sub3(x, y, d);
+                double r = norm3(d);
+                double sig = bary[q][0] * u[t[0]] + bary[q][1] * u[t[1]] + bary[q][2] * u[t[2]];
+                double c = wt[q] * g->area[j] / (4.0 * ORC_PI) * sig;
+                s += c / r;
+                for (int k = 0; k < 3; ++k) e[k] += c * d[k] / (r * r * r);
+            }
+        } else {
+            double c[3], F[3][3];
+            orc_tri_linear_analytic(x, v, v + 3, v + 6, 0, c);
+            orc_tri_linear_field(x, v, v + 3, v + 6, F);
+            for (int k = 0; k < 3; ++k) {
+                s += c[k] * u[t[k]];
+                for (int d = 0; d < 3; ++d) e[d] += F[k][d] * u[t[k]];
+            }
+        }
+    }
+    *phi = s;
+    for (int k = 0; k < 3; ++k) E[k] = e[k];
+}
+
 int orc_p1_field(const orc_problem* p, const double* u, int64_t P, const double* pts, double* phi, double* E)
 {
     orc_geom g;
     geom_build(p, &g);
-    double bary[7][3], wt[7];
-    orc_quad7_rule(bary, wt);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < P; ++i) {
-        const double* x = pts + 3 * i;
-        double s = 0.0, e[3] = {0.0, 0.0, 0.0};
-        for (int64_t j = 0; j < p->n_tri; ++j) {
-            const int32_t* t = p->tri + 3 * j;
-            const double* v = g.v + 9 * j;
-            if (pair_is_regular(p, &g, x, j)) {
-                for (int q = 0; q < 7; ++q) {
-                    double y[3], d[3];
-                    for (int k = 0; k < 3; ++k) y[k] = bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
-                    sub3(x, y, d);
-                    double r = norm3(d);
-                    double sig = bary[q][0] * u[t[0]] + bary[q][1] * u[t[1]] + bary[q][2] * u[t[2]];
-                    double c = wt[q] * g.area[j] / (4.0 * ORC_PI) * sig;
-                    s += c / r;
-                    for (int k = 0; k < 3; ++k) e[k] += c * d[k] / (r * r * r);
-                }
-            } else {
-                double c[3], F[3][3];
-                orc_tri_linear_analytic(x, v, v + 3, v + 6, 0, c);
-                orc_tri_linear_field(x, v, v + 3, v + 6, F);
-                for (int k = 0; k < 3; ++k) {
-                    s += c[k] * u[t[k]];
-                    for (int d = 0; d < 3; ++d) e[d] += F[k][d] * u[t[k]];
-                }
-            }
-        }
+        double s, e[3];
+        p1_field_at(p, &g, u, pts + 3 * i, &s, e);
         if (phi) phi[i] = s;
         if (E)
             for (int k = 0; k < 3; ++k) E[3 * i + k] = e[k];
@@ -1076,6 +1084,31 @@ int orc_trace(const orc_problem* p, const double* sigma, int64_t L, const double
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t l = 0; l < L; ++l)
         trace_one(&c, bem_field, bem_hit, tp, starts + 3 * l, n_steps + l, stop + l, integral + l,
+                  path ? path + l * stride : NULL);
+    geom_free(&g);
+    return 0;
+}
+
+/* Field lines of the nodal density u (Sec. 3 basis; the first n_vert entries of
+ * the nodal solution): the same stepping, stops and integral as orc_trace, with
+ * the field of orc_p1_field. */
+static void p1_field_cb(const void* c, const double x[3], double E[3])
+{
+    const bem_field_ctx* b = (const bem_field_ctx*)c;
+    double phi;
+    p1_field_at(b->p, b->g, b->sigma, x, &phi, E);
+}
+
+int orc_p1_trace(const orc_problem* p, const double* u, int64_t L, const double* starts,
+                 const orc_trace_params* tp, int32_t* n_steps, int32_t* stop, double* integral, double* path)
+{
+    orc_geom g;
+    geom_build(p, &g);
+    bem_field_ctx c = {p, &g, u};
+    int64_t stride = 3 * ((int64_t)tp->max_steps + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t l = 0; l < L; ++l)
+        trace_one(&c, p1_field_cb, bem_hit, tp, starts + 3 * l, n_steps + l, stop + l, integral + l,
                   path ? path + l * stride : NULL);
     geom_free(&g);
     return 0;

@@ -18,6 +18,8 @@ The oracle's pieces are pinned by things that do not come from it:
     differences of the hat potentials and, summed, against the unit-density
     field; the sphere's field V0 R x/|x|^3 outside and 0 inside with
     second-order convergence;
+  * field lines of the nodal density on the sphere against the closed-form
+    streamer integral of a radial line, second order;
   * refusal of interface bodies and of vertices shared by two bodies.
 """
 
@@ -246,6 +248,34 @@ def test_sphere_nodal_field(oracle_mod):
         phi, E = o.p1_field(u, pts)
         assert np.allclose(phi, o.p1_potential(u, pts), rtol=0, atol=1e-13)
         errs.append(np.max(np.abs(E - exact)))
+    assert errs[-1] < 2e-3 and errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+def test_sphere_nodal_streamer_integral(oracle_mod):
+    """Field lines of the nodal solution on the conductor sphere at V0 run
+    radially; the streamer integral from r0 to r1 is then
+    a [-V0^2/(3 r^3) + 2 V0 e0 / r + e0^2 r] between them (alpha = a (E - e0)^2,
+    E = V0/r^2 > e0).  The nodal lines converge to it at second order, and the
+    path stays radial."""
+    V0, a, e0 = 100.0, 1e-3, 25.0
+    dirs = np.array([[0.3, -0.5, 0.81], [-0.7, 0.2, 0.1], [0.05, 0.9, -0.4]])
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    r0, h, steps = 1.1, 5e-3, 100   # away from the flat panels, where the error is asymptotic
+    r1 = r0 + h * steps
+    F = lambda r: a * (-V0 ** 2 / (3 * r ** 3) + 2 * V0 * e0 / r + e0 ** 2 * r)
+    exact = F(r1) - F(r0)
+    tp = oracle_mod.trace_params(h=h, max_steps=steps, e_min=1e-3, alpha_a=a, alpha_e0=e0, alpha_p=2.0)
+    errs = []
+    for level in (2, 3, 4):
+        p = sphere_problem(level, V0=V0)
+        o = oracle_mod.Oracle(p)
+        u = np.linalg.solve(o.p1_assemble(), o.p1_rhs(p.body_V))
+        ns, st, I, path = o.p1_trace(u, r0 * dirs, tp, want_path=True)
+        assert np.all(ns == steps) and np.all(st == 0)
+        end = path[:, steps]
+        assert np.max(np.abs(np.linalg.norm(end, axis=1) - r1)) < 1e-2
+        assert np.max(np.linalg.norm(np.cross(end, dirs), axis=1)) < 1e-2
+        errs.append(np.max(np.abs(I - exact)) / exact)
     assert errs[-1] < 2e-3 and errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
 
 
