@@ -82,8 +82,9 @@ void check_points(const bem_ctx* c, int64_t P, const double* pts) {
 
 void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                  const double* starts, const bem_trace_params* tp) {
-    if (c->opt.basis != BEM_BASIS_CONSTANT)
-        throw bem::Error(BEM_ERR_INVALID, "field lines need the CONSTANT basis (the nodal basis has no field yet)");
+    if (c->opt.basis == BEM_BASIS_LINEAR && (nrhs != 1 || c->trace_mode == 2))
+        throw bem::Error(BEM_ERR_INVALID,
+                         "field lines of the LINEAR basis take one load case and the batched layout (trace_mode 0/1)");
     if (!tp) throw bem::Error(BEM_ERR_INVALID, "trace parameters are NULL");
     if (nrhs < 1) throw bem::Error(BEM_ERR_INVALID, "nrhs must be >= 1");
     if (!sol) throw bem::Error(BEM_ERR_INVALID, "solution pointer is NULL");
@@ -639,6 +640,7 @@ bem_status bem_streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_
     API_TRY
     if (!c->assembled) throw bem::Error(BEM_ERR_STATE, "assemble the system first");
     if (c->opt.precision != BEM_FP64) throw bem::Error(BEM_ERR_INVALID, "the gradient needs precision FP64");
+    if (c->opt.basis != BEM_BASIS_CONSTANT) throw bem::Error(BEM_ERR_INVALID, "the gradient needs the CONSTANT basis");
     check_trace(c, nrhs, sol, L, line_rhs, starts, tp);
     if (!(tp->alpha_p >= 1.0)) throw bem::Error(BEM_ERR_INVALID, "the gradient needs alpha_p >= 1");
     if (!(tol > 0.0) || !(tol < 1.0)) throw bem::Error(BEM_ERR_INVALID, "tol must be in (0, 1)");

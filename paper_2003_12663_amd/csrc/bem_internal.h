@@ -123,6 +123,7 @@ struct bem_ctx {
 
     bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx, flt_coef;
     bem::DBuf vert_body, fan_ptr, fan, nodal_mass, nodal_bounds, row_order;   // nodal basis only
+    bem::DBuf nod_pan64, nod_far64, nod_ones;   // nodal density folded into the panel records (field lines)
     bem::DBuf far64, far32, tri64;
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;
@@ -205,6 +206,7 @@ void launch_finalize(bem_ctx* c);                                  // assemble.h
 void launch_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out);
 void launch_rhs(bem_ctx* c, int32_t nrhs, const double* d_bodyV, double* b);
 void launch_nodal_assemble(bem_ctx* c);                                          // nodal.hip
+void launch_nodal_records(bem_ctx* c, const double* u);                          // nodal.hip
 void launch_nodal_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi,
                         double* E);                                                  // nodal.hip
 void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      // gemv.hip

@@ -21,6 +21,7 @@
 #include <cmath>
 
 #include "bem_device.h"
+#include "nodal_device.h"
 
 namespace bem {
 namespace {
@@ -131,96 +132,6 @@ __device__ __forceinline__ double hat_value(const double* __restrict__ T, int c,
     const double e0 = q[0] - p[0], e1 = q[1] - p[1], e2 = q[2] - p[2];
     const double g0 = n1 * e2 - n2 * e1, g1 = n2 * e0 - n0 * e2, g2 = n0 * e1 - n1 * e0;
     return (lam * I0 + (g0 * J0 + g1 * J1 + g2 * J2) / two_area) * INV4PI;
-}
-
-// Potential and field at a volume point x of the linear density on the flat
-// triangle T with vertex values u0, u1, u2, added to phi and E.  With
-// sigma(y) = sigma(rho) + G . (y - rho) (G the in-plane gradient of the
-// density, sum_k u_k g_k) and x - y = w n - (y - rho):
-//   4 pi phi = sigma(rho) int 1/R + G . int (y - rho)/R,
-//   4 pi E   = sigma(rho) F0 - w n (G . sum_e m_e f_e)
-//              - G int 1/R + sum_e m_e (t (G . m_e) f_e + (G . l_e)(R+ - R-)),
-// F0 = sum_e m_e f_e + sign(w) n Omega the unit-density field; the last two
-// terms are int (G . u) u / R^3 by the in-plane divergence identity
-// grad_u ((G . u)/R) = G/R - (G . u) u/R^3, whose edge integrals are
-// t (G . m) f_e + (G . l)(R+ - R-) for u = t m + s l.  Edge notation as in
-// hat_edges; x must not lie on the triangle.
-__device__ __forceinline__ void nodal_tri_phiE(const double* __restrict__ T, double x0, double x1, double x2,
-                                               double u0, double u1, double u2, double& phi, double& E0, double& E1,
-                                               double& E2) {
-    const double n0 = T[TR_N + 0], n1 = T[TR_N + 1], n2 = T[TR_N + 2];
-    const double two_area = 2.0 * T[TR_A];
-    const double w = (x0 - T[0]) * n0 + (x1 - T[1]) * n1 + (x2 - T[2]) * n2;
-    const double r0 = x0 - w * n0, r1 = x1 - w * n1, r2 = x2 - w * n2;
-    const double aw = fabs(w);
-    const double uk[3] = {u0, u1, u2};
-    // sigma(rho) and G
-    double srho = 0.0, G0 = 0.0, G1 = 0.0, G2 = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double* p = T + 3 * ((c + 1) % 3);
-        const double* q = T + 3 * ((c + 2) % 3);
-        const double a0 = p[0] - r0, a1 = p[1] - r1, a2 = p[2] - r2;
-        const double b0 = q[0] - r0, b1 = q[1] - r1, b2 = q[2] - r2;
-        srho += uk[c] * (n0 * (a1 * b2 - a2 * b1) + n1 * (a2 * b0 - a0 * b2) + n2 * (a0 * b1 - a1 * b0));
-        const double e0 = q[0] - p[0], e1 = q[1] - p[1], e2 = q[2] - p[2];
-        G0 += uk[c] * (n1 * e2 - n2 * e1);
-        G1 += uk[c] * (n2 * e0 - n0 * e2);
-        G2 += uk[c] * (n0 * e1 - n1 * e0);
-    }
-    srho /= two_area;
-    G0 /= two_area; G1 /= two_area; G2 /= two_area;
-    double V[3][3], Rv[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        V[k][0] = T[3 * k] - x0;
-        V[k][1] = T[3 * k + 1] - x1;
-        V[k][2] = T[3 * k + 2] - x2;
-        Rv[k] = sqrt(V[k][0] * V[k][0] + V[k][1] * V[k][1] + V[k][2] * V[k][2]);
-    }
-    double st = 0.0, mf0 = 0.0, mf1 = 0.0, mf2 = 0.0, J0 = 0.0, J1 = 0.0, J2 = 0.0, K0 = 0.0, K1 = 0.0, K2 = 0.0;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        const int b = (e + 1) % 3;
-        const double ax = T[3 * e], ay = T[3 * e + 1], az = T[3 * e + 2];
-        double l0 = T[3 * b] - ax, l1 = T[3 * b + 1] - ay, l2 = T[3 * b + 2] - az;
-        const double len = sqrt(l0 * l0 + l1 * l1 + l2 * l2);
-        const double il = 1.0 / len;
-        l0 *= il; l1 *= il; l2 *= il;
-        const double m0 = l1 * n2 - l2 * n1, m1 = l2 * n0 - l0 * n2, m2 = l0 * n1 - l1 * n0;
-        const double q0 = ax - r0, q1 = ay - r1, q2 = az - r2;
-        const double sm = q0 * l0 + q1 * l1 + q2 * l2;
-        const double sp = sm + len;
-        const double t = q0 * m0 + q1 * m1 + q2 * m2;
-        const double Rm = Rv[e], Rp = Rv[b];
-        double f;
-        if (sp + sm > 0.0)
-            f = log((Rp + sp) / (Rm + sm));
-        else
-            f = log((Rm - sm) / (Rp - sp));
-        st += t * f;
-        mf0 += m0 * f; mf1 += m1 * f; mf2 += m2 * f;
-        const double er = 0.5 * (sp * Rp - sm * Rm + (t * t + w * w) * f);
-        J0 += m0 * er; J1 += m1 * er; J2 += m2 * er;
-        const double ge = t * (G0 * m0 + G1 * m1 + G2 * m2) * f + (G0 * l0 + G1 * l1 + G2 * l2) * (Rp - Rm);
-        K0 += m0 * ge; K1 += m1 * ge; K2 += m2 * ge;
-    }
-    const double c0 = V[1][1] * V[2][2] - V[1][2] * V[2][1];
-    const double c1 = V[1][2] * V[2][0] - V[1][0] * V[2][2];
-    const double c2 = V[1][0] * V[2][1] - V[1][1] * V[2][0];
-    const double triple = V[0][0] * c0 + V[0][1] * c1 + V[0][2] * c2;
-    const double d01 = V[0][0] * V[1][0] + V[0][1] * V[1][1] + V[0][2] * V[1][2];
-    const double d02 = V[0][0] * V[2][0] + V[0][1] * V[2][1] + V[0][2] * V[2][2];
-    const double d12 = V[1][0] * V[2][0] + V[1][1] * V[2][1] + V[1][2] * V[2][2];
-    const double den = Rv[0] * Rv[1] * Rv[2] + d01 * Rv[2] + d02 * Rv[1] + d12 * Rv[0];
-    const double omega = 2.0 * atan2(fabs(triple), den);
-    const double I0 = st - aw * omega;
-    const double sg = (w > 0.0) ? omega : ((w < 0.0) ? -omega : 0.0);
-    const double Gmf = G0 * mf0 + G1 * mf1 + G2 * mf2;
-    phi += (srho * I0 + G0 * J0 + G1 * J1 + G2 * J2) * INV4PI;
-    E0 += (srho * (mf0 + sg * n0) - w * n0 * Gmf - G0 * I0 + K0) * INV4PI;
-    E1 += (srho * (mf1 + sg * n1) - w * n1 * Gmf - G1 * I0 + K1) * INV4PI;
-    E2 += (srho * (mf2 + sg * n2) - w * n2 * Gmf - G2 * I0 + K2) * INV4PI;
 }
 
 // One wave: rows i0 + lane, columns j0 .. j0 + 15; the four waves of a block take
@@ -501,7 +412,53 @@ __global__ __launch_bounds__(256) void k_nodal_field(int64_t P, const double* __
     }
 }
 
+// Panel records of a nodal density for the field-line passes: the copy of each
+// record (both layouts) with node weight q scaled by the density at node q,
+// sum_c b_qc u_c, so that the constant-basis far kernels, run with a density of
+// one per panel, sum the nodal density's far field.  Padding panels keep their
+// zero weights.
+__global__ __launch_bounds__(256) void k_nodal_records(int64_t N, int64_t Np, const int32_t* __restrict__ tri,
+                                                       const double* __restrict__ pan64, const double* __restrict__ u,
+                                                       double* __restrict__ npan, double* __restrict__ nfar,
+                                                       double* __restrict__ ones) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= Np) return;
+    double sq[7] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+    if (j < N) {
+        const double u0 = u[tri[3 * j]], u1 = u[tri[3 * j + 1]], u2 = u[tri[3 * j + 2]];
+        const double s15 = sqrt(15.0);
+        const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+        const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
+        sq[0] = (u0 + u1 + u2) / 3.0;
+        sq[1] = a1 * u0 + a1 * u1 + b1 * u2;
+        sq[2] = a1 * u0 + b1 * u1 + a1 * u2;
+        sq[3] = b1 * u0 + a1 * u1 + a1 * u2;
+        sq[4] = a2 * u0 + a2 * u1 + b2 * u2;
+        sq[5] = a2 * u0 + b2 * u1 + a2 * u2;
+        sq[6] = b2 * u0 + a2 * u1 + a2 * u2;
+    }
+#pragma unroll
+    for (int k = 0; k < FAR_REC; ++k) {
+        double v = pan64[(int64_t)FAR_REC * j + k];
+        if (k >= FR_W && k < FR_W + 7) v *= sq[k - FR_W];
+        npan[(int64_t)FAR_REC * j + k] = v;
+        nfar[(int64_t)k * Np + j] = v;
+    }
+    ones[j] = 1.0;
+}
+
 }  // namespace
+
+void launch_nodal_records(bem_ctx* c, const double* u) {
+    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
+    c->nod_pan64.alloc(sizeof(double) * FAR_REC * (size_t)Np);
+    c->nod_far64.alloc(sizeof(double) * FAR_REC * (size_t)Np);
+    c->nod_ones.alloc(sizeof(double) * (size_t)Np);
+    hipLaunchKernelGGL(k_nodal_records, dim3((unsigned)ceil_div(Np, 256)), dim3(256), 0, c->stream, c->N, Np,
+                       c->tri.as<int32_t>(), c->pan64.as<double>(), u, c->nod_pan64.as<double>(),
+                       c->nod_far64.as<double>(), c->nod_ones.as<double>());
+    BEM_CHECK_LAUNCH();
+}
 
 void launch_nodal_assemble(bem_ctx* c) {
     KTimer kt(c, "nodal_assemble");

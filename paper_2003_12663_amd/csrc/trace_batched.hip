@@ -28,6 +28,7 @@
 #include <climits>
 
 #include "bem_device.h"
+#include "nodal_device.h"
 
 namespace bem {
 namespace {
@@ -353,6 +354,9 @@ constexpr int LB_MREG = 8;    // near masks per thread held in registers by k_lb
 // first (the live count, the slot's state, its partial row and masks) is indexed by the slot
 // alone, so those loads go out together; a line that goes on is written whole to the slot it
 // draws in the next buffer.
+// NODAL: the density is the nodal one (vertex values nu, vertex indices ntri): near
+// pairs take the linear-density closed form; otherwise sigma per panel.
+template <bool NODAL>
 __global__ __launch_bounds__(256) void k_lb_step(
     int64_t N, int64_t KS, int64_t KSP, const int32_t* __restrict__ count, int32_t* __restrict__ count_next,
     const double* __restrict__ part, const uint32_t* __restrict__ pmask, int phase, LBState cur, LBState nxt,
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
     const int32_t* __restrict__ line_rhs, const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind,
     int32_t* __restrict__ n_steps, int32_t* __restrict__ stop_code, double* __restrict__ integral,
     uint8_t* __restrict__ exceeds, double* __restrict__ path, int64_t pstride,
-    unsigned long long* __restrict__ near_count) {
+    unsigned long long* __restrict__ near_count, const int32_t* __restrict__ ntri, const double* __restrict__ nu) {
     __shared__ int32_t list[LB_Q];
     __shared__ int32_t scan[4];
     __shared__ double red[4][4];
@@ -459,12 +463,18 @@ __global__ __launch_bounds__(256) void k_lb_step(
         for (int q = tid; q < nq; q += 256) {
             const int j = list[q];
             const double* Tj = tri64 + (int64_t)TRI_REC * j;
-            double S, F0, F1, F2;
-            flat_tri_SF<false, true>(Tj, p0, p1, p2, false, S, F0, F1, F2);
-            const double sg = sigma[j];
-            n0 = fma(sg, F0, n0);
-            n1 = fma(sg, F1, n1);
-            n2 = fma(sg, F2, n2);
+            if constexpr (NODAL) {
+                double ph = 0.0;
+                nodal_tri_phiE(Tj, p0, p1, p2, nu[ntri[3 * (int64_t)j]], nu[ntri[3 * (int64_t)j + 1]],
+                               nu[ntri[3 * (int64_t)j + 2]], ph, n0, n1, n2);
+            } else {
+                double S, F0, F1, F2;
+                flat_tri_SF<false, true>(Tj, p0, p1, p2, false, S, F0, F1, F2);
+                const double sg = sigma[j];
+                n0 = fma(sg, F0, n0);
+                n1 = fma(sg, F1, n1);
+                n2 = fma(sg, F2, n2);
+            }
             if (hit_pass) {
                 const double th = lb_segment_tri(Tj, q0, q1, q2, p0 - q0, p1 - q1, p2 - q2);
                 if (th >= 0.0 && (th < bt || (th == bt && j < bj))) {
@@ -793,6 +803,14 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     } join{c, G > 1};
     unsigned long long* near_count = reinterpret_cast<unsigned long long*>(c->counters.p);
     const bool fp64 = c->opt.precision == BEM_FP64;
+    // nodal basis (one load case): the far passes read records whose node weights carry the
+    // density, with a density of one per panel; the step kernel's near pairs read the vertex values
+    const bool nodal = c->opt.basis == BEM_BASIS_LINEAR;
+    if (nodal) launch_nodal_records(c, sol);
+    const double* P64 = nodal ? c->nod_pan64.as<double>() : c->pan64.as<double>();
+    const double* F64 = nodal ? c->nod_far64.as<double>() : c->far64.as<double>();
+    const double* fsol = nodal ? c->nod_ones.as<double>() : sol;
+    const int64_t fn = nodal ? 0 : c->n;
     const int64_t max_pass = 4 * (int64_t)tp->max_steps + 1;
     int cur = 0;
     int32_t* host = c->host_stage.as<int32_t>();
@@ -825,9 +843,8 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             const int32_t ntile = (int32_t)ceil_div(q.known, tile);
             dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                            \
-    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, c->pan64.as<double>(), \
-                       FR, N, sol, c->n, line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart,   \
-                       gmask, ntile, KS)
+    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, P64, FR, N, fsol, fn, \
+                       line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask, ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -844,15 +861,15 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             if (few) {
                 KSP = Np / 256;
                 if (fp64)
-                    hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)KSP), dim3(256), 0, q.st,
-                                       c->far64.as<double>(), c->far64.as<double>(), Np, N, sol, c->n, line_rhs,
-                                       sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask, KS);
+                    hipLaunchKernelGGL((k_lb_far_few<double>), dim3((unsigned)KSP), dim3(256), 0, q.st, F64, F64, Np,
+                                       N, fsol, fn, line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y,
+                                       gpart, gmask, KS);
                 else
                     hipLaunchKernelGGL((k_lb_far_few<float>), dim3((unsigned)KSP), dim3(256), 0, q.st,
                                        c->far64.as<double>(), c->far32.as<float>(), Np, N, sol, c->n, line_rhs,
                                        sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask, KS);
             } else if (fp64) {
-                BEM_LB_FAR_ALL(double, c->pan64.as<double>());
+                BEM_LB_FAR_ALL(double, P64);
             } else {
                 BEM_LB_FAR_ALL(float, c->pan32.as<float>());
             }
@@ -863,10 +880,17 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             }
             {
             KTimer ts(c, "trace_step", timed, q.st);
-            hipLaunchKernelGGL(k_lb_step, dim3((unsigned)q.known), dim3(256), 0, q.st, N, KS, KSP, q.cnt[cur],
-                               q.cnt[cur ^ 1], gpart, gmask, phase, sc, sn, a, c->tri64.as<double>(), sol, c->n,
-                               line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps, stop_code,
-                               integral, exceeds, path, pstride, near_count);
+            if (nodal)
+                hipLaunchKernelGGL(k_lb_step<true>, dim3((unsigned)q.known), dim3(256), 0, q.st, N, KS, KSP,
+                                   q.cnt[cur], q.cnt[cur ^ 1], gpart, gmask, phase, sc, sn, a, c->tri64.as<double>(),
+                                   sol, c->n, line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps,
+                                   stop_code, integral, exceeds, path, pstride, near_count, c->tri.as<int32_t>(), sol);
+            else
+                hipLaunchKernelGGL(k_lb_step<false>, dim3((unsigned)q.known), dim3(256), 0, q.st, N, KS, KSP,
+                                   q.cnt[cur], q.cnt[cur ^ 1], gpart, gmask, phase, sc, sn, a, c->tri64.as<double>(),
+                                   sol, c->n, line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps,
+                                   stop_code, integral, exceeds, path, pstride, near_count, (const int32_t*)nullptr,
+                                   (const double*)nullptr);
             BEM_CHECK_LAUNCH();
             }
         }

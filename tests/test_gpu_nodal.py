@@ -7,7 +7,8 @@ potentials and fields 1e-10.  Cases: spheres and a floating shell (vertex counts
 leave ragged row tiles and column groups), two devices in one problem, the
 coaxial conductors with a floating ring (flat caps: coplanar near pairs), and
 on sampled oracle rows a level-5 sphere (10,242 vertices) and the coaxial
-conductors at 67,729 vertices.
+conductors at 67,729 vertices.  Field lines and streamer integrals of the nodal
+density against the oracle's: step counts and stop codes exact, integrals 1e-10.
 """
 
 import numpy as np
@@ -140,6 +141,47 @@ def test_nodal_paper_size_sampled_rows(bem):
     torch.cuda.empty_cache()
 
 
+def _lines_vs_oracle(bem, p, starts, tp_kw):
+    o = oracle.Oracle(p)
+    u_ref = np.linalg.solve(o.p1_assemble(), o.p1_rhs(p.body_V))
+    c = _ctx(bem, p)
+    sol, info = c.solve(p.body_V, tol=1e-13, max_iter=5000)
+    assert rel(sol[0].cpu().numpy(), u_ref) <= 1e-10
+    ns_o, st_o, I_o = o.p1_trace(sol[0].cpu().numpy(), starts, oracle.trace_params(**tp_kw))
+    I, ns, st, _ = c.streamer_integral(sol, torch.tensor(starts, device="cuda"), bem.trace_params(**tp_kw))
+    ns, st, I = ns.cpu().numpy(), st.cpu().numpy(), I.cpu().numpy()
+    assert np.array_equal(ns, ns_o) and np.array_equal(st, st_o)
+    assert np.max(np.abs(I - I_o)) <= 1e-10 * max(np.max(np.abs(I_o)), 1e-300)
+    c.close()
+    return ns, st, I
+
+
+def test_nodal_field_lines_sphere(bem):
+    """Radial lines of the nodal solution on the conductor sphere at V0 = 100:
+    step counts and stop codes exact, integrals 1e-10 against the oracle, and
+    the integral within the discretisation error of the closed form."""
+    p = sphere_problem(3, V0=100.0)
+    dirs = np.random.default_rng(9).standard_normal((12, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    kw = dict(h=5e-3, max_steps=100, e_min=1e-3, alpha_a=1e-3, alpha_e0=25.0, alpha_p=2.0)
+    ns, st, I = _lines_vs_oracle(bem, p, 1.1 * dirs, kw)
+    F = lambda r: 1e-3 * (-1e4 / (3 * r ** 3) + 2 * 100.0 * 25.0 / r + 625.0 * r)
+    assert np.all(ns == 100) and np.max(np.abs(I / (F(1.6) - F(1.1)) - 1.0)) < 1e-2
+
+
+def test_nodal_field_lines_coax(bem):
+    """40 lines from the rod of the coaxial conductors (nodal basis): lines end
+    on the shell (code 1) or the floating ring (code 2) or run out of steps; the
+    far passes go from the split to the few-line kernel as lines stop."""
+    from workloads import electrode_line_starts
+    p = coax_conductors_problem(0.012, V0=40.0)
+    starts, _, _ = electrode_line_starts(p, 40, seed=4)
+    kw = dict(h=2e-3, max_steps=300, e_min=1e-3, alpha_a=1e-3, alpha_e0=25.0, alpha_p=2.0)
+    ns, st, I = _lines_vs_oracle(bem, p, starts, kw)
+    print(f"[nodal] coax lines: stop codes {np.bincount(st, minlength=6)}", flush=True)
+    assert np.any(st == 1) and np.any(ns > 20) and np.any(I > 0)
+
+
 def test_nodal_batched_load_cases(bem):
     """Several load cases in one call agree with one-by-one solves."""
     p = union_problem(sphere_problem(2, V0=1.0), sphere_problem(2, V0=0.0), (3.0, 0.0, 0.0))
@@ -168,6 +210,10 @@ def test_nodal_refusals(bem):
     sol, _ = c.solve(p.body_V, tol=1e-10)
     with pytest.raises(bem.BemError):   # volume points only
         c.eval_field(sol, p.vert[p.tri[:1]].mean(axis=1), on_panel=np.zeros(1, dtype=np.int32))
-    with pytest.raises(bem.BemError):   # no field lines either
-        c.streamer_integral(sol, torch.tensor([[0.0, 0.0, 1.2]], device="cuda"), bem.trace_params(h=1e-3))
+    with pytest.raises(bem.BemError):   # field lines of one load case only
+        c.streamer_integral(torch.cat([sol, sol]), torch.tensor([[0.0, 0.0, 1.2]], device="cuda"),
+                            bem.trace_params(h=1e-3), line_rhs=np.array([1], dtype=np.int32))
+    with pytest.raises(bem.BemError):   # no gradient
+        c.streamer_grad(sol, torch.tensor([[0.0, 0.0, 1.2]], device="cuda"),
+                        torch.ones(1, dtype=torch.float64, device="cuda"), bem.trace_params(h=1e-3, max_steps=5))
     c.close()
