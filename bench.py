@@ -251,7 +251,8 @@ def nodal_run(bem, torch):
     icospheres of level 5 (10,242 vertices, 20,480 panels) and 6 (40,962 / 81,920);
     constant on level 5 (20,480 unknowns).  Then the nodal system of the coaxial conductors
     (rod, grounded shell, floating ring) at 67,729 vertices, the node count of the paper's
-    Table 3 device."""
+    Table 3 device, with 256 field lines from the rod (RK4, h = 1e-4, <= 2000 steps) and
+    their streamer integrals."""
     from workloads import sphere_problem
     out = {}
 
@@ -294,10 +295,22 @@ def nodal_run(bem, torch):
     sol, info = ctx.solve(p.body_V, tol=1e-10, max_iter=5000)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    from workloads import electrode_line_starts
+    starts, _, _ = electrode_line_starts(p, 256, seed=2)
+    tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-3)
+    st_d = torch.tensor(starts, device="cuda")
+    ctx.streamer_integral(sol, st_d, tp)   # warm-up
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    I, ns, st, _ = ctx.streamer_integral(sol, st_d, tp)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
     out["linear_coax_conductors"] = {
         "unknowns": int(ctx.n), "vertices": p.n_vert, "panels": p.n_tri, "assemble_s": t1 - t0,
         "row_panel_pairs_per_s": p.n_vert * p.n_tri / (t1 - t0), "matrix_entries_per_s": ctx.n ** 2 / (t1 - t0),
-        "solve_s": t2 - t1, "iters": info["iters"], "ring_potential_over_V0": float(sol[0, p.n_vert].cpu())}
+        "solve_s": t2 - t1, "iters": info["iters"], "ring_potential_over_V0": float(sol[0, p.n_vert].cpu()),
+        "lines": 256, "trace_s": t4 - t3, "steps_total": int(ns.sum().cpu()),
+        "stop_code_counts": {str(k): int((st.cpu().numpy() == k).sum()) for k in range(6)}}
     ctx.close()
     torch.cuda.empty_cache()
     return out
