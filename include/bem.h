@@ -67,7 +67,10 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
  *            [u_1..u_nvert, V_1..V_Nfl]).  Conductor and floating-conductor bodies only
  *            (interface and sheet rows need the normal at the collocation point, which a
  *            vertex of flat panels lacks); a floating body's row is its net charge
- *            (constraint_form must be 1); FP64 only; every vertex in at least one triangle and
+ *            (constraint_form must be 1); FP64, or MIXED with the vertex rows stored in FP32
+ *            (each entry formed in FP64 and rounded once, as the paper stores its matrix in
+ *            single precision) and the constraint rows in FP64, solved inside FP64 iterative
+ *            refinement; every vertex in at least one triangle and
  *            all triangles at a vertex of one body.  Supported calls: bem_assemble,
  *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres and bem_eval_field at
  *            volume points (on_panel NULL; phi or E may be NULL); field lines, the streamer
@@ -155,7 +158,8 @@ bem_status bem_assemble(bem_ctx* ctx);
  * FP32 far entries widened, plus the FP64 near entries. */
 bem_status bem_copy_rows(bem_ctx* ctx, int64_t row0, int64_t n_rows, double* out);
 
-/* Number of near-singular and singular (row, panel) pairs of the assembly. */
+/* Number of near-singular and singular (row, panel) pairs of the assembly (CONSTANT
+ * basis; 0 for LINEAR, whose near pass keeps no list). */
 int64_t bem_near_pairs(const bem_ctx* ctx);
 
 /* Right-hand sides for body potentials: b (dev [nrhs][n]); body_V host [nrhs][n_body]

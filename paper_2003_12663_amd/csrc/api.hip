@@ -174,7 +174,6 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     if (o.constraint_form != 0 && o.constraint_form != 1) return fail(BEM_ERR_INVALID, "unknown constraint_form");
     if (o.basis != BEM_BASIS_CONSTANT && o.basis != BEM_BASIS_LINEAR) return fail(BEM_ERR_INVALID, "unknown basis");
     if (o.basis == BEM_BASIS_LINEAR) {
-        if (o.precision != BEM_FP64) return fail(BEM_ERR_INVALID, "the LINEAR basis is FP64 only");
         if (o.constraint_form != 1)
             return fail(BEM_ERR_INVALID, "the LINEAR basis uses the net-charge row (constraint_form 1)");
         if (n_tri >= ((int64_t)1 << 29)) return fail(BEM_ERR_INVALID, "mesh too large for the LINEAR basis");
@@ -250,6 +249,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         if (bodies[b].kind == BEM_FLOATING_SHEET) c->has_sheet = true;
     }
     c->n = c->N + c->n_float;
+    c->nb = c->N;
     std::vector<int32_t> fan_ptr, fan, row_order;
     if (o.basis == BEM_BASIS_LINEAR) {
         // vertex -> body (one body per vertex, every vertex used) and the vertex fans
@@ -271,6 +271,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         for (int64_t j = 0; j < n_tri; ++j)   // triangles ascending within each fan
             for (int k = 0; k < 3; ++k) fan[fill[tri[3 * j + k]]++] = (int32_t)((j << 2) | k);
         c->n = n_vert + c->n_float;
+        c->nb = n_vert;
         // vertices in Morton (Z-curve) order of their positions in the bounding box, 21 bits
         // per axis: the near-pair pass takes its rows in this order so that a wave's rows are
         // neighbours
@@ -397,14 +398,32 @@ bem_status bem_assemble(bem_ctx* c) {
     DeviceGuard g(c->device);
     API_TRY
     if (c->opt.basis == BEM_BASIS_LINEAR) {
-        const size_t need = sizeof(double) * (size_t)c->n * c->ld;
+        // FP64: one n x ld matrix.  MIXED: the vertex rows in FP32 (nb x ld) and the constraint
+        // rows in FP64 (n_float x ld), with an empty list of FP64 near remainders
+        const bool mixed = c->opt.precision == BEM_MIXED;
+        const size_t nfl = (size_t)(c->n_float > 0 ? c->n_float : 1);
+        const size_t need = mixed ? sizeof(float) * (size_t)c->nb * c->ld + sizeof(double) * nfl * c->ld
+                                  : sizeof(double) * (size_t)c->n * c->ld;
         size_t free_b = 0, total_b = 0;
         BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-        if (need > free_b + c->A64.bytes)
+        const size_t have = free_b + c->A64.bytes + c->A32.bytes;
+        if (need > have)
             throw bem::Error(BEM_ERR_OOM, "assembly needs " + std::to_string(need >> 20) + " MiB, " +
-                                              std::to_string((free_b + c->A64.bytes) >> 20) + " MiB free");
+                                              std::to_string(have >> 20) + " MiB free");
         c->assembled = false;
-        c->A64.alloc(need);
+        if (mixed) {
+            c->A64.release();
+            c->A32.alloc(sizeof(float) * (size_t)c->nb * c->ld);
+            c->A64.alloc(sizeof(double) * nfl * c->ld);
+            c->near_ptr.alloc(sizeof(int64_t) * (size_t)(c->nb + 1));
+            BEM_HIP(hipMemsetAsync(c->near_ptr.p, 0, sizeof(int64_t) * (size_t)(c->nb + 1), c->stream));
+            c->near_col.alloc(sizeof(int32_t));
+            c->near_val.alloc(sizeof(double));
+            c->near_nnz = 0;
+        } else {
+            c->A32.release();
+            c->A64.alloc(need);
+        }
         c->diag.alloc(sizeof(double) * c->ld);
         bem::launch_nodal_assemble(c);
         BEM_HIP(hipStreamSynchronize(c->stream));

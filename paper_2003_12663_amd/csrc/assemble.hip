@@ -414,7 +414,7 @@ void launch_finalize(bem_ctx* c) {
 
 void launch_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out) {
     const bool mixed = c->opt.precision == BEM_MIXED;
-    const int64_t N = c->N, n = c->n, ld = c->ld;
+    const int64_t N = c->nb, n = c->n, ld = c->ld;
     if (!mixed) {
         hipLaunchKernelGGL(k_copy_rows64, dim3((unsigned)ceil_div(n_rows * n, 256)), dim3(256), 0, c->stream,
                            c->A64.as<double>(), ld, row0, n_rows, n, out);

@@ -105,6 +105,9 @@ struct bem_ctx {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     bem_options opt{};
     int64_t N = 0, n = 0, ld = 0, n_vert = 0;
+    // rows that carry a body's density: N panels, or n_vert vertices for the LINEAR basis; in
+    // MIXED mode they are the FP32 block and the constraint rows after them stay FP64
+    int64_t nb = 0;
     int32_t n_body = 0, n_float = 0;
     double shift[3] = {0, 0, 0};   // mesh translated by -shift on the device (FP32 accuracy)
     double min_R = 0.0;

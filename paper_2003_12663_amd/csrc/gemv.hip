@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_sum_slabs(const double* __restrict__ pa
 
 template <int RB>
 void matvec_rb(bem_ctx* c, const double* x, double* y, hipStream_t s) {
-    const int64_t n = c->n, N = c->N, ld = c->ld;
+    const int64_t n = c->n, N = c->nb, ld = c->ld;
     if (c->opt.precision == BEM_FP64) {
         hipLaunchKernelGGL((k_gemv64<RB>), dim3((unsigned)ceil_div(n, RB)), dim3(256), 0, s, c->A64.as<double>(), ld,
                            n, n, x, y);

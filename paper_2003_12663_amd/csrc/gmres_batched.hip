@@ -324,7 +324,7 @@ void batched_apply_exact(bem_ctx* c, int nr, const double* X, double* Y) {
     w.c = c;
     w.nr = nr;
     w.n = c->n;
-    w.N = c->N;
+    w.N = c->nb;
     w.ld = c->ld;
     w.s = c->stream;
     const size_t ld = (size_t)w.ld;
@@ -349,7 +349,7 @@ int gmres_solve_batched(bem_ctx* c, int nr, const double* B, double* X, double t
     w.m = c->opt.restart;
     w.m1 = w.m + 1;
     w.n = c->n;
-    w.N = c->N;
+    w.N = c->nb;
     w.ld = c->ld;
     w.s = c->stream;
     w.G = (int)std::min<int64_t>(ceil_div(w.n, 256), 128);

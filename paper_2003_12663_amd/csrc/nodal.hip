@@ -140,12 +140,13 @@ __device__ __forceinline__ double hat_value(const double* __restrict__ T, int c,
 // groups of 16, n_cg a multiple of 8): blocks are dealt to the 8 XCDs in turn,
 // so block b runs on XCD b % 8, and each XCD sweeps all row tiles of one column
 // group before the next, keeping that group's records in its own L2.
+template <class T>   // stored type: double (FP64) or float (MIXED)
 __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, int64_t n_rt,
                                                         const double* __restrict__ vert,
                                                         const int32_t* __restrict__ tri,
                                                         const int32_t* __restrict__ fan_ptr,
                                                         const int32_t* __restrict__ fan,
-                                                        const double* __restrict__ pan64, double* __restrict__ A) {
+                                                        const double* __restrict__ pan64, T* __restrict__ A) {
     __shared__ double tile[4][NODAL_COLS][65];   // padded: the row-segment reads stride 65
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = blockIdx.x, xcd = b & 7, slot = b >> 3;
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, 
     for (int s = 0; s < 16; ++s) {
         const int r = (lane >> 4) + 4 * s, cc = lane & 15;
         const int64_t ii = i0 + r, jj = j0 + cc;
-        if (ii < nv && jj < nv) A[ii * ld + jj] = tile[wv][cc][r];
+        if (ii < nv && jj < nv) A[ii * ld + jj] = (T)tile[wv][cc][r];
     }
 }
 
@@ -235,18 +236,19 @@ __device__ __forceinline__ double lane_bcast(double v, int k) {
 // predicate of the first pass, its circumcentre, (eta R)^2 and vertex indices
 // loaded by the lanes together (component-major records) and broadcast from a
 // lane register.  A near triangle adds its three hats into the lane's own row.
+template <class T>
 __global__ __launch_bounds__(64) void k_nodal_near(int64_t nv, int64_t ld, int64_t N, int64_t Np,
                                                    const int32_t* __restrict__ row_order,
                                                    const double* __restrict__ vert, const int32_t* __restrict__ tri,
                                                    const double* __restrict__ far64, const double* __restrict__ cb,
-                                                   const double* __restrict__ tri64, double* __restrict__ A) {
+                                                   const double* __restrict__ tri64, T* __restrict__ A) {
     const int lane = threadIdx.x;
     const int64_t s = (int64_t)blockIdx.x * 64 + lane;
     const bool live = s < nv;
     const int64_t ic = row_order[live ? s : nv - 1];
     const int64_t i = live ? ic : -1;   // -1 matches no vertex
     const double x0 = vert[3 * ic], x1 = vert[3 * ic + 1], x2 = vert[3 * ic + 2];
-    double* row = A + ic * ld;
+    T* row = A + ic * ld;
     // ball of the 64 rows
     const double g0 = wave_sum(x0) / 64.0, g1 = wave_sum(x1) / 64.0, g2 = wave_sum(x2) / 64.0;
     double rg = sqrt((x0 - g0) * (x0 - g0) + (x1 - g1) * (x1 - g1) + (x2 - g2) * (x2 - g2));
@@ -273,36 +275,39 @@ __global__ __launch_bounds__(64) void k_nodal_near(int64_t nv, int64_t ld, int64
             const bool vtx = (a == i) || (b == i) || (c == i);
             const bool near = vtx || !is_regular(x0 - cc0, x1 - cc1, x2 - cc2, crr);
             if (near && live) {
-                // the three entries are read first so that their latency overlaps the closed form
-                const double ya = row[a], yb = row[b], yc = row[c];
-                const double* T = tri64 + (int64_t)TRI_REC * (t0 + k);
+                // the three entries are read first so that their latency overlaps the closed form;
+                // the sum is formed in FP64 and rounded once to the stored type
+                const double ya = (double)row[a], yb = (double)row[b], yc = (double)row[c];
+                const double* Tr = tri64 + (int64_t)TRI_REC * (t0 + k);
                 double I0, r0, r1, r2, J0, J1, J2;
-                hat_edges(T, x0, x1, x2, vtx, I0, r0, r1, r2, J0, J1, J2);
-                row[a] = ya + hat_value(T, 0, I0, r0, r1, r2, J0, J1, J2);
-                row[b] = yb + hat_value(T, 1, I0, r0, r1, r2, J0, J1, J2);
-                row[c] = yc + hat_value(T, 2, I0, r0, r1, r2, J0, J1, J2);
+                hat_edges(Tr, x0, x1, x2, vtx, I0, r0, r1, r2, J0, J1, J2);
+                row[a] = (T)(ya + hat_value(Tr, 0, I0, r0, r1, r2, J0, J1, J2));
+                row[b] = (T)(yb + hat_value(Tr, 1, I0, r0, r1, r2, J0, J1, J2));
+                row[c] = (T)(yc + hat_value(Tr, 2, I0, r0, r1, r2, J0, J1, J2));
             }
         }
     }
 }
 
 // Jacobi diagonal of the vertex rows
-__global__ __launch_bounds__(256) void k_nodal_diag(int64_t nv, int64_t ld, const double* __restrict__ A,
+template <class T>
+__global__ __launch_bounds__(256) void k_nodal_diag(int64_t nv, int64_t ld, const T* __restrict__ A,
                                                     double* __restrict__ diag) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < nv) diag[i] = A[i * ld + i];
+    if (i < nv) diag[i] = (double)A[i * ld + i];
 }
 
 // columns [nv, ld) of the vertex rows: -1 in the column of the row's floating body, else 0
+template <class T>
 __global__ __launch_bounds__(256) void k_nodal_tail(int64_t nv, int64_t ld, const int32_t* __restrict__ vert_body,
                                                     const int32_t* __restrict__ body_kind,
-                                                    const int32_t* __restrict__ fidx, double* __restrict__ A) {
+                                                    const int32_t* __restrict__ fidx, T* __restrict__ A) {
     const int64_t ncol = ld - nv;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= nv * ncol) return;
     const int64_t i = t / ncol, k = t % ncol;
     const int32_t b = vert_body[i];
-    A[i * ld + nv + k] = (body_kind[b] == BEM_FLOATING && fidx[b] == k) ? -1.0 : 0.0;
+    A[i * ld + nv + k] = (T)((body_kind[b] == BEM_FLOATING && fidx[b] == k) ? -1.0 : 0.0);
 }
 
 // m_k = int psi_k dS = sum over the fan of k of area / 3
@@ -331,9 +336,9 @@ __global__ __launch_bounds__(256) void k_nodal_body_area(int64_t nv, const int32
     if (threadIdx.x == 0) Af[f] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// row nv + f: m_k / area_f on the vertices of floating body f, 0 elsewhere (all ld
-// columns); its Jacobi diagonal is 1 (the entry is 0)
-__global__ __launch_bounds__(256) void k_nodal_constraint(int64_t nv, int64_t ld, int32_t n_float,
+// row nv + f (stored at row0 + f): m_k / area_f on the vertices of floating body f, 0
+// elsewhere (all ld columns); its Jacobi diagonal is 1 (the entry is 0)
+__global__ __launch_bounds__(256) void k_nodal_constraint(int64_t nv, int64_t row0, int64_t ld, int32_t n_float,
                                                           const int32_t* __restrict__ vert_body,
                                                           const int32_t* __restrict__ fidx,
                                                           const double* __restrict__ mass,
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(256) void k_nodal_constraint(int64_t nv, int64_t ld
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= (int64_t)n_float * ld) return;
     const int64_t f = t / ld, k = t % ld;
-    A[(nv + f) * ld + k] = (k < nv && fidx[vert_body[k]] == f) ? mass[k] / Af[f] : 0.0;
+    A[(row0 + f) * ld + k] = (k < nv && fidx[vert_body[k]] == f) ? mass[k] / Af[f] : 0.0;
     if (k == 0) diag[nv + f] = 1.0;
 }
 
@@ -460,15 +465,15 @@ void launch_nodal_records(bem_ctx* c, const double* u) {
     BEM_CHECK_LAUNCH();
 }
 
-void launch_nodal_assemble(bem_ctx* c) {
-    KTimer kt(c, "nodal_assemble");
+template <class T>
+static void nodal_assemble_t(bem_ctx* c, T* A, double* Atail, int64_t tail_row0) {
     const int64_t nv = c->n_vert, ld = c->ld;
     hipStream_t s = c->stream;
     const int64_t n_rt = ceil_div(nv, 256), n_cg = ceil_div(ceil_div(nv, NODAL_COLS), 8) * 8;
     if (n_rt * n_cg > ((int64_t)1 << 31) - 1) throw Error(BEM_ERR_INVALID, "too many vertices for the LINEAR basis");
-    hipLaunchKernelGGL(k_nodal_assemble, dim3((unsigned)(n_rt * n_cg)), dim3(256), 0, s, nv, ld, n_rt,
+    hipLaunchKernelGGL(k_nodal_assemble<T>, dim3((unsigned)(n_rt * n_cg)), dim3(256), 0, s, nv, ld, n_rt,
                        c->vert.as<double>(), c->tri.as<int32_t>(), c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(),
-                       c->pan64.as<double>(), c->A64.as<double>());
+                       c->pan64.as<double>(), A);
     BEM_CHECK_LAUNCH();
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t nch = ceil_div(c->N, 64);
@@ -476,17 +481,16 @@ void launch_nodal_assemble(bem_ctx* c) {
     hipLaunchKernelGGL(k_nodal_chunk_bounds, dim3((unsigned)ceil_div(nch, 256)), dim3(256), 0, s, c->N, Np,
                        c->far64.as<double>(), c->nodal_bounds.as<double>());
     BEM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_nodal_near, dim3((unsigned)ceil_div(nv, 64)), dim3(64), 0, s, nv, ld, c->N, Np,
-                       c->row_order.as<int32_t>(), c->vert.as<double>(), c->tri.as<int32_t>(), c->far64.as<double>(), c->nodal_bounds.as<double>(),
-                       c->tri64.as<double>(), c->A64.as<double>());
+    hipLaunchKernelGGL(k_nodal_near<T>, dim3((unsigned)ceil_div(nv, 64)), dim3(64), 0, s, nv, ld, c->N, Np,
+                       c->row_order.as<int32_t>(), c->vert.as<double>(), c->tri.as<int32_t>(), c->far64.as<double>(),
+                       c->nodal_bounds.as<double>(), c->tri64.as<double>(), A);
     BEM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_nodal_diag, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv, ld, c->A64.as<double>(),
+    hipLaunchKernelGGL(k_nodal_diag<T>, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv, ld, A,
                        c->diag.as<double>());
     BEM_CHECK_LAUNCH();
     if (ld > nv) {
-        hipLaunchKernelGGL(k_nodal_tail, dim3((unsigned)ceil_div(nv * (ld - nv), 256)), dim3(256), 0, s, nv, ld,
-                           c->vert_body.as<int32_t>(), c->body_kind.as<int32_t>(), c->body_fidx.as<int32_t>(),
-                           c->A64.as<double>());
+        hipLaunchKernelGGL(k_nodal_tail<T>, dim3((unsigned)ceil_div(nv * (ld - nv), 256)), dim3(256), 0, s, nv, ld,
+                           c->vert_body.as<int32_t>(), c->body_kind.as<int32_t>(), c->body_fidx.as<int32_t>(), A);
         BEM_CHECK_LAUNCH();
     }
     if (c->n_float > 0) {
@@ -500,10 +504,18 @@ void launch_nodal_assemble(bem_ctx* c) {
                            c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(), mass, Af);
         BEM_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_nodal_constraint, dim3((unsigned)ceil_div((int64_t)c->n_float * ld, 256)), dim3(256), 0,
-                           s, nv, ld, c->n_float, c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(), mass, Af,
-                           c->A64.as<double>(), c->diag.as<double>());
+                           s, nv, tail_row0, ld, c->n_float, c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(),
+                           mass, Af, Atail, c->diag.as<double>());
         BEM_CHECK_LAUNCH();
     }
+}
+
+void launch_nodal_assemble(bem_ctx* c) {
+    KTimer kt(c, "nodal_assemble");
+    if (c->opt.precision == BEM_MIXED)   // vertex rows FP32 in A32, constraint rows FP64 from row 0 of A64
+        nodal_assemble_t<float>(c, c->A32.as<float>(), c->A64.as<double>(), 0);
+    else
+        nodal_assemble_t<double>(c, c->A64.as<double>(), c->A64.as<double>(), c->n_vert);
 }
 
 void launch_nodal_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi,

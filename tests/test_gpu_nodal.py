@@ -182,6 +182,49 @@ def test_nodal_field_lines_coax(bem):
     assert np.any(st == 1) and np.any(ns > 20) and np.any(I > 0)
 
 
+@pytest.mark.parametrize("name,make", [CASES[2], CASES[4]], ids=[CASES[2][0], CASES[4][0]])
+def test_nodal_mixed_precision(bem, name, make):
+    """MIXED storage of the nodal system: vertex rows in FP32 (each entry formed in
+    FP64, then rounded; a near contribution adds a second rounding, and all
+    entries are positive, so within 2.4e-7 of the FP64 entry), constraint rows in
+    FP64 and equal to the FP64 matrix's; the solution with iterative refinement and
+    its field within 1e-5 of FP64."""
+    p = make()
+    c64 = _ctx(bem, p)
+    c32 = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
+    c32.assemble()
+    nv = p.n_vert
+    G64 = c64.copy_rows(0, c64.n).cpu().numpy()
+    G32 = c32.copy_rows(0, c32.n).cpu().numpy()
+    assert np.all(np.abs(G32[:nv] - G64[:nv]) <= 2.4e-7 * np.abs(G64[:nv]))
+    assert np.array_equal(G32[nv:], G64[nv:])
+    s64, _ = c64.solve(p.body_V, tol=1e-12, max_iter=5000)
+    s32, info = c32.solve(p.body_V, tol=1e-8, max_iter=5000)
+    assert info["converged"] and info["refinements"] >= 1
+    assert rel(s32[0].cpu().numpy(), s64[0].cpu().numpy()) <= 1e-5
+    pts = np.random.default_rng(7).uniform(-0.3, 0.3, (32, 3)) + np.array([0.0, 0.0, 1.8 if name != "coax_conductors" else 0.2])
+    _, E64 = c64.eval_field(s64, pts)
+    _, E32 = c32.eval_field(s32, pts)
+    assert rel(E32[0].cpu().numpy(), E64[0].cpu().numpy()) <= 1e-5
+    print(f"[nodal] mixed {name}: sigma {rel(s32[0].cpu().numpy(), s64[0].cpu().numpy()):.2e} "
+          f"iters {info['iters']} refinements {info['refinements']}", flush=True)
+    c64.close()
+    c32.close()
+
+
+def test_nodal_empty_inputs(bem):
+    """No points and no lines are no-ops."""
+    p = sphere_problem(1)
+    c = _ctx(bem, p)
+    sol, _ = c.solve(p.body_V, tol=1e-12)
+    phi, E = c.eval_field(sol, np.zeros((0, 3)))
+    assert phi.shape == (1, 0) and E.shape == (1, 0, 3)
+    I, ns, st, _ = c.streamer_integral(sol, torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                                       bem.trace_params(h=1e-3))
+    assert I.numel() == 0 and ns.numel() == 0
+    c.close()
+
+
 def test_nodal_batched_load_cases(bem):
     """Several load cases in one call agree with one-by-one solves."""
     p = union_problem(sphere_problem(2, V0=1.0), sphere_problem(2, V0=0.0), (3.0, 0.0, 0.0))
@@ -201,8 +244,6 @@ def test_nodal_refusals(bem):
     p = sphere_problem(1)
     with pytest.raises(bem.BemError):   # the net-charge row is required
         bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=0)
-    with pytest.raises(bem.BemError):   # FP64 only
-        bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
     from workloads import coated_sphere_problem
     with pytest.raises(bem.BemError):   # interface bodies need a normal at the vertex
         bem.Context.from_problem(coated_sphere_problem(1), basis=bem.BASIS_LINEAR, constraint_form=1)
