@@ -252,7 +252,9 @@ def nodal_run(bem, torch):
     constant on level 5 (20,480 unknowns).  Then the nodal system of the coaxial conductors
     (rod, grounded shell, floating ring) at 67,729 vertices, the node count of the paper's
     Table 3 device, with 256 field lines from the rod (RK4, h = 1e-4, <= 2000 steps) and
-    their streamer integrals."""
+    their streamer integrals; the same system with FP32 vertex rows (MIXED, as the paper
+    stores its matrix); and the conductors at the paper's 232,029-node count in MIXED
+    (about 215 GB of FP32 matrix on one GPU)."""
     from workloads import sphere_problem
     out = {}
 
@@ -311,8 +313,51 @@ def nodal_run(bem, torch):
         "solve_s": t2 - t1, "iters": info["iters"], "ring_potential_over_V0": float(sol[0, p.n_vert].cpu()),
         "lines": 256, "trace_s": t4 - t3, "steps_total": int(ns.sum().cpu()),
         "stop_code_counts": {str(k): int((st.cpu().numpy() == k).sum()) for k in range(6)}}
+    x64 = sol[0].cpu().numpy()
     ctx.close()
     torch.cuda.empty_cache()
+    # the same system stored as the paper stores its matrix: FP32 vertex rows (MIXED),
+    # solved inside FP64 iterative refinement to 1e-8
+    ctx = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
+    ctx.assemble()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.assemble()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol, info = ctx.solve(p.body_V, tol=1e-8, max_iter=5000)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    x32 = sol[0].cpu().numpy()
+    out["linear_coax_conductors_mixed"] = {
+        "unknowns": int(ctx.n), "assemble_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"],
+        "refinements": info["refinements"],
+        "density_error_vs_fp64": float(np.abs(x32 - x64).max() / np.abs(x64).max())}
+    ctx.close()
+    torch.cuda.empty_cache()
+    # the node count of the paper's 232,029-node case, FP32 vertex rows (about 215 GB), one GPU
+    p = coax_conductors_for_vertices(232029)
+    ctx = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.assemble()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sol, info = ctx.solve(p.body_V, tol=1e-8, max_iter=5000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out["linear_coax_conductors_232k_mixed"] = {
+            "unknowns": int(ctx.n), "vertices": p.n_vert, "panels": p.n_tri,
+            "matrix_gb": 4.0 * p.n_vert * ctx.n / 1e9, "assemble_s": t1 - t0,
+            "row_panel_pairs_per_s": p.n_vert * p.n_tri / (t1 - t0), "solve_s": t2 - t1, "iters": info["iters"],
+            "refinements": info["refinements"], "rel_residual": info["rel_residual"],
+            "ring_potential_over_V0": float(sol[0, p.n_vert].cpu())}
+    except bem.BemError as e:   # e.g. a GPU with less memory than the 218 GB this needs
+        out["linear_coax_conductors_232k_mixed"] = {"error": str(e)}
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
     return out
 
 

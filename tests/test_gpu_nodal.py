@@ -212,6 +212,36 @@ def test_nodal_mixed_precision(bem, name, make):
     c32.close()
 
 
+def test_nodal_mixed_232k_sampled_rows(bem):
+    """The coaxial conductors at 233,519 vertices (the paper's 232,029-node case) in
+    MIXED storage, 218 GB of FP32 rows on one GPU.  Checked: sampled rows within 2.4e-7
+    of the oracle's FP64 rows, the constraint row exactly, the solution's residual
+    against those FP64 rows, and the ring's potential against the 67,729-vertex FP64
+    solution's (0.41826 V0)."""
+    p = coax_conductors_for_vertices(232029)
+    print(f"[nodal] coax conductors: {p.n_vert} vertices, {p.n_tri} panels, MIXED", flush=True)
+    c = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
+    c.assemble()
+    nv = p.n_vert
+    rows = np.unique(np.concatenate([[0, nv - 1, nv], np.random.default_rng(6).integers(0, nv, 5)]))
+    o = oracle.Oracle(p)
+    R = o.p1_assemble_rows(rows)
+    for k, r in enumerate(rows):
+        g = c.copy_rows(int(r), 1)[0].cpu().numpy()
+        if r < nv:
+            assert np.all(np.abs(g - R[k]) <= 2.4e-7 * np.abs(R[k]) + 1e-300), r
+        else:
+            assert np.array_equal(g, R[k]) or np.abs(g - R[k]).max() <= 1e-15 * np.abs(R[k]).max(), r
+    sol, info = c.solve(p.body_V, tol=1e-8, max_iter=5000)
+    assert info["converged"]
+    x = sol[0].cpu().numpy()
+    b = o.p1_rhs(p.body_V)[rows]
+    assert np.abs(R @ x - b).max() <= 1e-5 * np.abs(b).max() + 1e-5
+    assert abs(x[nv] - 0.41826) < 1e-3
+    c.close()
+    torch.cuda.empty_cache()
+
+
 def test_nodal_empty_inputs(bem):
     """No points and no lines are no-ops."""
     p = sphere_problem(1)
