@@ -215,7 +215,7 @@ def test_nodal_mixed_precision(bem, name, make):
 def test_nodal_mixed_232k_sampled_rows(bem):
     """The coaxial conductors at 233,519 vertices (the paper's 232,029-node case) in
     MIXED storage, 218 GB of FP32 rows on one GPU.  Checked: sampled rows within 2.4e-7
-    of the oracle's FP64 rows, the constraint row exactly, the solution's residual
+    of the oracle's FP64 rows, the FP64 constraint row to its summation order, the solution's residual
     against those FP64 rows, and the ring's potential against the 67,729-vertex FP64
     solution's (0.41826 V0)."""
     p = coax_conductors_for_vertices(232029)
@@ -230,8 +230,9 @@ def test_nodal_mixed_232k_sampled_rows(bem):
         g = c.copy_rows(int(r), 1)[0].cpu().numpy()
         if r < nv:
             assert np.all(np.abs(g - R[k]) <= 2.4e-7 * np.abs(R[k]) + 1e-300), r
-        else:
-            assert np.array_equal(g, R[k]) or np.abs(g - R[k]).max() <= 1e-15 * np.abs(R[k]).max(), r
+        else:   # FP64 constraint row: the body's area is a sum over 233,519 vertices on the GPU and
+            # over triangles in the oracle, so the two differ in summation order (bound ~ n eps)
+            assert np.abs(g - R[k]).max() <= 1e-11 * np.abs(R[k]).max(), r
     sol, info = c.solve(p.body_V, tol=1e-8, max_iter=5000)
     assert info["converged"]
     x = sol[0].cpu().numpy()
