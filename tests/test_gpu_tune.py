@@ -69,8 +69,12 @@ def test_tuning_knob_validation(bem):
                      ("trace_tile", 96), ("trace_groups", 0), ("trace_groups", 3), ("grad_batch", 8), ("nope", 1)):
         with pytest.raises(bem.BemError):
             ctx.set_tuning(key, bad)
+    assert ctx.get_tuning("gemv_rows") == 4      # FP64 default
     ctx.set_tuning("gemv_rows", 8)
     assert ctx.get_tuning("gemv_rows") == 8
     with pytest.raises(bem.BemError):
         ctx.autotune(None)          # not assembled yet
+    ctx.close()
+    ctx = bem.Context.from_problem(p, precision=bem.MIXED)
+    assert ctx.get_tuning("gemv_rows") == 8      # MIXED default (FP32 rows, FP64 x)
     ctx.close()
