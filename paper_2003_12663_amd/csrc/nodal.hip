@@ -13,7 +13,8 @@
 // built at create), so each entry is written once, with no read-modify-write
 // and no atomics; the price is that a regular (row, triangle) pair is
 // integrated once per vertex of the triangle.  16 columns per wave are staged
-// in LDS and leave as 128-byte row segments.  This pass takes the regular
+// in LDS and leave as 128-byte row segments (64 bytes when the rows are stored
+// in FP32, MIXED precision).  This pass takes the regular
 // pairs only; the near-singular and singular ones (a small fraction, each a
 // long closed form) follow in a second pass with one lane per row, which adds
 // all three hats of a near triangle into its own row, so the first pass keeps
