@@ -74,9 +74,9 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
  *            all triangles at a vertex of one body.  Supported calls: bem_assemble,
  *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres, bem_eval_field at volume
  *            points (on_panel NULL; phi or E may be NULL), and bem_trace_lines /
- *            bem_streamer_integral for one load case (nrhs 1) in the batched layout
- *            (trace_mode 0 or 1); the gradient and the autotuner need CONSTANT (INVALID
- *            otherwise). */
+ *            bem_streamer_integral in the batched layout (trace_mode 0 or 1; lines of several
+ *            load cases run case by case); the gradient and the autotuner need CONSTANT
+ *            (INVALID otherwise). */
 typedef enum { BEM_BASIS_CONSTANT = 0, BEM_BASIS_LINEAR = 1 } bem_basis;
 
 /* One body.  Triangle normals (right-hand rule of the vertex order) point

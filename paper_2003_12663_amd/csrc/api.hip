@@ -82,9 +82,8 @@ void check_points(const bem_ctx* c, int64_t P, const double* pts) {
 
 void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                  const double* starts, const bem_trace_params* tp) {
-    if (c->opt.basis == BEM_BASIS_LINEAR && (nrhs != 1 || c->trace_mode == 2))
-        throw bem::Error(BEM_ERR_INVALID,
-                         "field lines of the LINEAR basis take one load case and the batched layout (trace_mode 0/1)");
+    if (c->opt.basis == BEM_BASIS_LINEAR && c->trace_mode == 2)
+        throw bem::Error(BEM_ERR_INVALID, "field lines of the LINEAR basis need the batched layout (trace_mode 0/1)");
     if (!tp) throw bem::Error(BEM_ERR_INVALID, "trace parameters are NULL");
     if (nrhs < 1) throw bem::Error(BEM_ERR_INVALID, "nrhs must be >= 1");
     if (!sol) throw bem::Error(BEM_ERR_INVALID, "solution pointer is NULL");

@@ -127,6 +127,7 @@ struct bem_ctx {
     bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx, flt_coef;
     bem::DBuf vert_body, fan_ptr, fan, nodal_mass, nodal_bounds, row_order;   // nodal basis only
     bem::DBuf nod_pan64, nod_far64, nod_ones;   // nodal density folded into the panel records (field lines)
+    bem::DBuf tr_cases;                          // staging of the nodal basis's per-load-case line runs
     bem::DBuf far64, far32, tri64;
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;
@@ -227,6 +228,9 @@ void launch_point_mask(bem_ctx* c, int64_t P, const double* pts, const int32_t* 
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                   const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                   double* path, double* integral, uint8_t* exceeds);   // trace.hip
+void launch_trace_nodal_cases(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                              const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                              double* path, double* integral, uint8_t* exceeds);   // trace_batched.hip
 void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                           const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                           double* path, double* integral, uint8_t* exceeds);   // trace_batched.hip

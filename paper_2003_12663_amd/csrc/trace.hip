@@ -360,7 +360,11 @@ void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const 
     // 4 to 4096 lines; the per-line layout is bound by per-CU load bandwidth)
     const int mode = c->trace_mode != 0 ? c->trace_mode : 1;
     if (mode == 1) {
-        launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds);
+        if (c->opt.basis == BEM_BASIS_LINEAR && nrhs > 1 && line_rhs)
+            launch_trace_nodal_cases(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral,
+                                     exceeds);
+        else
+            launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds);
         return;
     }
     KTimer t(c, "trace");

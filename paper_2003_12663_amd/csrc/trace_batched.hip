@@ -921,4 +921,76 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     }
 }
 
+namespace {
+__global__ __launch_bounds__(256) void k_gather_starts(int64_t m, const int32_t* __restrict__ idx,
+                                                       const double* __restrict__ starts, double* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= m) return;
+    const int64_t l = idx[t];
+    out[3 * t] = starts[3 * l];
+    out[3 * t + 1] = starts[3 * l + 1];
+    out[3 * t + 2] = starts[3 * l + 2];
+}
+
+// one lane per gathered line: its results back to the caller's slot l = idx[t]; a path copies
+// only x_0 .. x_{n_steps}, so the caller's later slots stay untouched
+__global__ __launch_bounds__(256) void k_scatter_lines(int64_t m, const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ ns, const int32_t* __restrict__ st,
+                                                       const double* __restrict__ I, const uint8_t* __restrict__ ex,
+                                                       const double* __restrict__ tpath, int64_t pstride,
+                                                       int32_t* __restrict__ n_steps, int32_t* __restrict__ stop_code,
+                                                       double* __restrict__ integral, uint8_t* __restrict__ exceeds,
+                                                       double* __restrict__ path) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= m) return;
+    const int64_t l = idx[t];
+    n_steps[l] = ns[t];
+    stop_code[l] = st[t];
+    if (integral) integral[l] = I[t];
+    if (exceeds) exceeds[l] = ex[t];
+    if (path)
+        for (int64_t k = 0; k < 3 * ((int64_t)ns[t] + 1); ++k) path[l * pstride + k] = tpath[t * pstride + k];
+}
+}  // namespace
+
+// Nodal basis with several load cases: the far passes read panel records built for one
+// density, so the lines run case by case (gathered, traced as one load case, scattered back).
+void launch_trace_nodal_cases(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                              const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                              double* path, double* integral, uint8_t* exceeds) {
+    std::vector<int32_t> h((size_t)L);
+    BEM_HIP(hipMemcpyAsync(h.data(), line_rhs, sizeof(int32_t) * (size_t)L, hipMemcpyDeviceToHost, c->stream));
+    BEM_HIP(hipStreamSynchronize(c->stream));
+    const int64_t pstride = 3 * ((int64_t)tp->max_steps + 1);
+    for (int32_t r = 0; r < nrhs; ++r) {
+        std::vector<int32_t> idx;
+        for (int64_t l = 0; l < L; ++l)
+            if (h[l] == r) idx.push_back((int32_t)l);
+        const int64_t m = (int64_t)idx.size();
+        if (m == 0) continue;
+        // staging: indices, starts, and the per-line outputs of this case
+        const size_t bytes = sizeof(int32_t) * m + sizeof(double) * 3 * m + sizeof(int32_t) * 2 * m +
+                             sizeof(double) * m + m + (path ? sizeof(double) * (size_t)(pstride * m) : 0) + 64;
+        c->tr_cases.alloc(bytes);
+        char* base = static_cast<char*>(c->tr_cases.p);
+        double* tst = reinterpret_cast<double*>(base);
+        double* tI = tst + 3 * m;
+        double* tpath = tI + m;
+        int32_t* didx = reinterpret_cast<int32_t*>(tpath + (path ? pstride * m : 0));
+        int32_t* tns = didx + m;
+        int32_t* tsc = tns + m;
+        uint8_t* tex = reinterpret_cast<uint8_t*>(tsc + m);
+        BEM_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_gather_starts, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, c->stream, m, didx, starts,
+                           tst);
+        BEM_CHECK_LAUNCH();
+        launch_trace_batched(c, 1, sol + (int64_t)r * c->n, m, nullptr, tst, tp, tns, tsc, path ? tpath : nullptr,
+                             integral ? tI : nullptr, exceeds ? tex : nullptr);
+        hipLaunchKernelGGL(k_scatter_lines, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, c->stream, m, didx, tns,
+                           tsc, tI, tex, tpath, pstride, n_steps, stop_code, integral, exceeds, path);
+        BEM_CHECK_LAUNCH();
+        BEM_HIP(hipStreamSynchronize(c->stream));   // idx (host) and the staging buffer are reused
+    }
+}
+
 }  // namespace bem

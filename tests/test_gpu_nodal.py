@@ -182,6 +182,39 @@ def test_nodal_field_lines_coax(bem):
     assert np.any(st == 1) and np.any(ns > 20) and np.any(I > 0)
 
 
+def test_nodal_field_lines_two_load_cases(bem):
+    """Lines of two load cases in one call (nodal basis: traced case by case inside)
+    equal the single-case calls bit for bit and the oracle's lines per case to
+    1e-10; paths keep the slots after each line's last point untouched."""
+    p = union_problem(sphere_problem(2, V0=100.0), sphere_problem(2, V0=0.0), (3.0, 0.0, 0.0))
+    c = _ctx(bem, p)
+    bv = np.array([[100.0, 0.0], [0.0, 80.0]])
+    sol, _ = c.solve(bv, tol=1e-13, max_iter=5000)
+    dirs = np.random.default_rng(12).standard_normal((10, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    starts = 1.15 * dirs + np.where((np.arange(10) % 2 == 1)[:, None], np.array([3.0, 0.0, 0.0]), 0.0)
+    lr = (np.arange(10) % 2).astype(np.int32)
+    kw = dict(h=5e-3, max_steps=60, e_min=1e-3, alpha_a=1e-3, alpha_e0=25.0, alpha_p=2.0)
+    tp = bem.trace_params(**kw)
+    I, ns, st, _ = c.streamer_integral(sol, torch.tensor(starts, device="cuda"), tp, line_rhs=lr)
+    ns_p, st_p, path = c.trace_lines(sol, torch.tensor(starts, device="cuda"), tp, line_rhs=lr, want_path=True)
+    I, ns, st = I.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
+    assert np.array_equal(ns, ns_p.cpu().numpy()) and np.array_equal(st, st_p.cpu().numpy())
+    o = oracle.Oracle(p)
+    for r in range(2):
+        sel = np.nonzero(lr == r)[0]
+        I1, ns1, st1, _ = c.streamer_integral(sol[r:r + 1], torch.tensor(starts[sel], device="cuda"), tp)
+        assert np.array_equal(I[sel], I1.cpu().numpy()) and np.array_equal(ns[sel], ns1.cpu().numpy())
+        ns_o, st_o, I_o = o.p1_trace(sol[r].cpu().numpy(), starts[sel], oracle.trace_params(**kw))
+        assert np.array_equal(ns[sel], ns_o) and np.array_equal(st[sel], st_o)
+        assert np.max(np.abs(I[sel] - I_o)) <= 1e-10 * np.max(np.abs(I_o))
+    P = path.cpu().numpy()   # NaN-filled before the call
+    for l in range(10):
+        assert np.all(np.isfinite(P[l, :ns[l] + 1])) and np.all(np.isnan(P[l, ns[l] + 1:]))
+        assert np.allclose(P[l, 0], starts[l], rtol=0, atol=0)
+    c.close()
+
+
 @pytest.mark.parametrize("name,make", [CASES[2], CASES[4]], ids=[CASES[2][0], CASES[4][0]])
 def test_nodal_mixed_precision(bem, name, make):
     """MIXED storage of the nodal system: vertex rows in FP32 (each entry formed in
@@ -282,9 +315,10 @@ def test_nodal_refusals(bem):
     sol, _ = c.solve(p.body_V, tol=1e-10)
     with pytest.raises(bem.BemError):   # volume points only
         c.eval_field(sol, p.vert[p.tri[:1]].mean(axis=1), on_panel=np.zeros(1, dtype=np.int32))
-    with pytest.raises(bem.BemError):   # field lines of one load case only
-        c.streamer_integral(torch.cat([sol, sol]), torch.tensor([[0.0, 0.0, 1.2]], device="cuda"),
-                            bem.trace_params(h=1e-3), line_rhs=np.array([1], dtype=np.int32))
+    c.set_tuning("trace_mode", 2)
+    with pytest.raises(bem.BemError):   # field lines in the batched layout only
+        c.streamer_integral(sol, torch.tensor([[0.0, 0.0, 1.2]], device="cuda"), bem.trace_params(h=1e-3))
+    c.set_tuning("trace_mode", 0)
     with pytest.raises(bem.BemError):   # no gradient
         c.streamer_grad(sol, torch.tensor([[0.0, 0.0, 1.2]], device="cuda"),
                         torch.ones(1, dtype=torch.float64, device="cuda"), bem.trace_params(h=1e-3, max_steps=5))
