@@ -20,6 +20,8 @@ The oracle's pieces are pinned by things that do not come from it:
     second-order convergence;
   * field lines of the nodal density on the sphere against the closed-form
     streamer integral of a radial line, second order;
+  * rigid motions of the mesh leave the matrix and solution unchanged and
+    rotate the field;
   * refusal of interface bodies and of vertices shared by two bodies.
 """
 
@@ -331,6 +333,31 @@ def test_floating_shell_nodal(oracle_mod):
         # the net charge of the floating body is zero (its constraint row)
         assert abs(A[nv] @ u) < 1e-12
     assert errs[-1] < 2e-4 and errs[0] / errs[1] > 4.0, errs
+
+
+def test_nodal_rigid_motion_invariance(oracle_mod):
+    """A rotation plus translation of the whole mesh changes no entry of the nodal
+    matrix beyond rounding, and rotates the field of the solution with it."""
+    import dataclasses
+    p = floating_shell_problem(1, V0=2.0)
+    o = oracle_mod.Oracle(p)
+    A = o.p1_assemble()
+    u = np.linalg.solve(A, o.p1_rhs(p.body_V))
+    th = 0.7
+    Rz = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, np.cos(0.3), -np.sin(0.3)], [0.0, np.sin(0.3), np.cos(0.3)]])
+    Q = Rx @ Rz
+    shift = np.array([0.4, -1.1, 2.3])
+    q = dataclasses.replace(p, vert=p.vert @ Q.T + shift)
+    oq = oracle_mod.Oracle(q)
+    Aq = oq.p1_assemble()
+    assert np.max(np.abs(Aq - A)) <= 1e-12 * np.max(np.abs(A))
+    uq = np.linalg.solve(Aq, oq.p1_rhs(q.body_V))
+    assert np.max(np.abs(uq - u)) <= 1e-10 * np.max(np.abs(u))
+    pts = np.array([[0.0, 0.0, 2.5], [1.2, 1.9, -0.4], [0.3, -0.2, 0.1]])
+    _, E = o.p1_field(u, pts)
+    _, Eq = oq.p1_field(uq, pts @ Q.T + shift)
+    assert np.max(np.abs(Eq - E @ Q.T)) <= 1e-10 * np.max(np.abs(E))
 
 
 def test_refuses_interfaces_and_shared_vertices(oracle_mod):
