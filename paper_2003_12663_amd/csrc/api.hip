@@ -218,6 +218,20 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     for (int32_t b = 0; b < n_body; ++b)
         if ((bodies[b].kind == BEM_FLOATING || bodies[b].kind == BEM_FLOATING_SHEET) && per_body[b] == 0)
             return fail(BEM_ERR_INVALID, "floating body without panels");
+    // LINEAR basis: every vertex in a triangle, and all triangles at a vertex of one body
+    std::vector<int32_t> vert_body;
+    if (o.basis == BEM_BASIS_LINEAR) {
+        vert_body.assign(n_vert, -1);
+        for (int64_t j = 0; j < n_tri; ++j)
+            for (int k = 0; k < 3; ++k) {
+                int32_t& vb = vert_body[tri[3 * j + k]];
+                if (vb >= 0 && vb != tri_body[j])
+                    return fail(BEM_ERR_INVALID, "LINEAR basis: a vertex is shared by triangles of two bodies");
+                vb = tri_body[j];
+            }
+        for (int64_t i = 0; i < n_vert; ++i)
+            if (vert_body[i] < 0) return fail(BEM_ERR_INVALID, "LINEAR basis: a vertex is in no triangle");
+    }
 
     API_TRY
     int dev = 0;
@@ -254,19 +268,11 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     if (o.precision == BEM_MIXED) c->tune_gemv_rows = 8;
     std::vector<int32_t> fan_ptr, fan, row_order;
     if (o.basis == BEM_BASIS_LINEAR) {
-        // vertex -> body (one body per vertex, every vertex used) and the vertex fans
-        c->h_vert_body.assign(n_vert, -1);
+        // vertex -> body (checked above) and the vertex fans
+        c->h_vert_body = vert_body;
         fan_ptr.assign(n_vert + 1, 0);
         for (int64_t j = 0; j < n_tri; ++j)
-            for (int k = 0; k < 3; ++k) {
-                int32_t& vb = c->h_vert_body[tri[3 * j + k]];
-                if (vb >= 0 && vb != tri_body[j])
-                    return fail(BEM_ERR_INVALID, "LINEAR basis: a vertex is shared by triangles of two bodies");
-                vb = tri_body[j];
-                ++fan_ptr[tri[3 * j + k] + 1];
-            }
-        for (int64_t i = 0; i < n_vert; ++i)
-            if (c->h_vert_body[i] < 0) return fail(BEM_ERR_INVALID, "LINEAR basis: a vertex is in no triangle");
+            for (int k = 0; k < 3; ++k) ++fan_ptr[tri[3 * j + k] + 1];
         for (int64_t i = 0; i < n_vert; ++i) fan_ptr[i + 1] += fan_ptr[i];
         fan.resize(3 * (size_t)n_tri);
         std::vector<int32_t> fill(fan_ptr.begin(), fan_ptr.end() - 1);

@@ -82,6 +82,56 @@ def test_validation_before_any_hip_call(lib):
     assert ctx.value is None
 
 
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes structs of the binding have the sizes and field offsets of the C
+    structs in include/bem.h (a probe compiled here with gcc)."""
+    import subprocess
+    from paper_2003_12663_amd import _lib
+    structs = {"bem_body": _lib.Body, "bem_options": _lib.Options, "bem_solve_info": _lib.SolveInfo,
+               "bem_trace_params": _lib.TraceParams}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bem.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_nodal_basis_validation_before_any_hip_call(lib):
+    """The LINEAR basis: the net-charge row is required, interface bodies and
+    vertices shared by two bodies are refused, all in host-side validation."""
+    from paper_2003_12663_amd import _lib
+    ctx = ctypes.c_void_p()
+    vert = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    tri = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], dtype=np.int32)
+
+    def create(tb, bodies, opt):
+        arr = (_lib.Body * len(bodies))(*[_lib.Body(*b) for b in bodies])
+        tb = np.asarray(tb, dtype=np.int32)
+        return lib.bem_create(len(vert), vert.ctypes.data, len(tri), tri.ctypes.data, tb.ctypes.data, len(bodies),
+                              ctypes.addressof(arr), ctypes.byref(opt), None, ctypes.byref(ctx))
+
+    one = [(0, 1.0, 1.0)]
+    assert create([0, 0, 0, 0], one, _lib.Options(0, 6.0, 100, 0, 1)) == _lib.BEM_ERR_INVALID   # literal row
+    assert b"constraint_form" in lib.bem_last_error()
+    assert create([0, 0, 0, 0], [(2, 1.0, 4.0)], _lib.Options(0, 6.0, 100, 1, 1)) == _lib.BEM_ERR_INVALID
+    assert create([0, 0, 0, 0], one, _lib.Options(0, 6.0, 100, 1, 2)) == _lib.BEM_ERR_INVALID   # no such basis
+    two = [(0, 1.0, 1.0), (0, 1.0, 1.0)]
+    assert create([0, 0, 1, 1], two, _lib.Options(0, 6.0, 100, 1, 1)) == _lib.BEM_ERR_INVALID   # shared vertices
+    assert b"shared" in lib.bem_last_error()
+    assert ctx.value is None
+
+
 def test_product_path_never_touches_the_oracle():
     for dirpath, _, files in os.walk(PKG):
         for f in files:
