@@ -254,7 +254,7 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
  *                refinement); 0 = one right-hand side after another.
  *  Tile shapes (set by bem_autotune, or by hand):
  *  "far_rows":    collocation rows per block of the far-field assembly (32, 64, 128; default 64)
- *  "gemv_rows":   matrix rows per block of the GMRES matvec (2, 4, 8; default 4 for FP64, 8 for MIXED)
+ *  "gemv_rows":   matrix rows per block of the GMRES matvec (2, 4, 8, 16; default 4 for FP64, 8 for MIXED)
  *  "gemm_blocks": minimum blocks of the FP32 multi-vector product, by K ranges (64..65536; 1024)
  *  "eval_blocks": target blocks of the field evaluation, by panel ranges (64..65536; 2048)
  *  "trace_tile":  lines per block of an unsplit field-line pass (64, 128, 256; default 256)

@@ -704,7 +704,7 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         bool pow2_choice;
     };
     static const Knob knobs[] = {
-        {"far_rows", &bem_ctx::tune_far_rows, 32, 128, true},     {"gemv_rows", &bem_ctx::tune_gemv_rows, 2, 8, true},
+        {"far_rows", &bem_ctx::tune_far_rows, 32, 128, true},     {"gemv_rows", &bem_ctx::tune_gemv_rows, 2, 16, true},
         {"gemm_blocks", &bem_ctx::tune_gemm_blocks, 64, 65536, false},
         {"eval_blocks", &bem_ctx::tune_eval_blocks, 64, 65536, false},
         {"trace_split", &bem_ctx::tune_trace_split, 0, 4096, false},

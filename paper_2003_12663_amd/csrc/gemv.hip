@@ -194,6 +194,7 @@ void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s) {
     switch (c->tune_gemv_rows) {
         case 2: matvec_rb<2>(c, x, y, s); break;
         case 8: matvec_rb<8>(c, x, y, s); break;
+        case 16: matvec_rb<16>(c, x, y, s); break;
         default: matvec_rb<4>(c, x, y, s); break;
     }
 }
