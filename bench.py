@@ -14,6 +14,16 @@ field-line tracer (k_lb_far, one launch per RK4 stage of all live lines):
 algorithmic FP64 flops per launch (regular pairs x 141 flop) / its average
 duration, measured with HIP events on the stream it runs on.  cpu_baseline
 times the plain FP64 CPU oracle on a bounded sample of the same workload.
+
+After the timed steps, "extras" reports runs outside the step:
+- the gradient of 128 lines;
+- 64 load cases x 64 lines;
+- the 57,230-panel coax in FP64 and mixed precision;
+- the bushing with thin sheets;
+- the paper's nodal basis: spheres against the constant basis, and the coaxial
+  conductors at 67,729 vertices (FP64 and MIXED, with 256 field lines) and at
+  233,519 vertices (MIXED).
+--extras-only and --nodal-only run those without the timed steps.
 """
 
 from __future__ import annotations
