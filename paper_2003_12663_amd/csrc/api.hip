@@ -266,7 +266,8 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     // the FP32 matvec reads an FP64 x per FP32 entry: 8 rows per block halve that L2 traffic
     // (measured 9-10 % faster than 4 at 67k and 233k unknowns); FP64 keeps 4
     if (o.precision == BEM_MIXED) c->tune_gemv_rows = 8;
-    std::vector<int32_t> fan_ptr, fan, row_order;
+    std::vector<int32_t> fan_ptr, fan, row_order, grp_ptr, grp_tri;
+    std::vector<uint32_t> grp_loc;
     if (o.basis == BEM_BASIS_LINEAR) {
         // vertex -> body (checked above) and the vertex fans
         c->h_vert_body = vert_body;
@@ -278,6 +279,41 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         std::vector<int32_t> fill(fan_ptr.begin(), fan_ptr.end() - 1);
         for (int64_t j = 0; j < n_tri; ++j)   // triangles ascending within each fan
             for (int k = 0; k < 3; ++k) fan[fill[tri[3 * j + k]]++] = (int32_t)((j << 2) | k);
+        // column groups of 16 vertices: each triangle once per group that holds one of its
+        // corners, triangles ascending, with the local column of every corner
+        const int64_t ng = (n_vert + 15) / 16;
+        grp_ptr.assign(ng + 1, 0);
+        for (int64_t j = 0; j < n_tri; ++j) {
+            const int64_t g0 = tri[3 * j] / 16, g1 = tri[3 * j + 1] / 16, g2 = tri[3 * j + 2] / 16;
+            ++grp_ptr[g0 + 1];
+            if (g1 != g0) ++grp_ptr[g1 + 1];
+            if (g2 != g0 && g2 != g1) ++grp_ptr[g2 + 1];
+        }
+        for (int64_t g = 0; g < ng; ++g) grp_ptr[g + 1] += grp_ptr[g];
+        grp_tri.resize((size_t)grp_ptr[ng]);
+        grp_loc.resize((size_t)grp_ptr[ng]);
+        std::vector<int32_t> gfill(grp_ptr.begin(), grp_ptr.end() - 1);
+        for (int64_t j = 0; j < n_tri; ++j) {
+            int64_t gs[3];
+            int ngs = 0;
+            for (int k = 0; k < 3; ++k) {
+                const int64_t g = tri[3 * j + k] / 16;
+                bool seen = false;
+                for (int m = 0; m < ngs; ++m) seen = seen || gs[m] == g;
+                if (!seen) gs[ngs++] = g;
+            }
+            for (int m = 0; m < ngs; ++m) {
+                uint32_t loc = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t v = tri[3 * j + k];
+                    const uint32_t l = (v / 16 == gs[m]) ? (uint32_t)(v % 16) : 0xffu;
+                    loc |= l << (8 * k);
+                }
+                const int32_t pos = gfill[gs[m]]++;
+                grp_tri[pos] = (int32_t)j;
+                grp_loc[pos] = loc;
+            }
+        }
         c->n = n_vert + c->n_float;
         c->nb = n_vert;
         // vertices in Morton (Z-curve) order of their positions in the bounding box, 21 bits
@@ -364,6 +400,9 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         upload(c->fan_ptr, fan_ptr.data(), fan_ptr.size(), s);
         upload(c->fan, fan.data(), fan.size(), s);
         upload(c->row_order, row_order.data(), row_order.size(), s);
+        upload(c->grp_ptr, grp_ptr.data(), grp_ptr.size(), s);
+        upload(c->grp_tri, grp_tri.data(), grp_tri.size(), s);
+        upload(c->grp_loc, grp_loc.data(), grp_loc.size(), s);
     }
     upload(c->rows_pot, c->h_rows_pot.data(), c->h_rows_pot.size(), s);
     upload(c->rows_int, c->h_rows_int.data(), c->h_rows_int.size(), s);

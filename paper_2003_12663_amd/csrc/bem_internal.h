@@ -126,6 +126,9 @@ struct bem_ctx {
 
     bem::DBuf vert, tri, tri_body, body_kind, body_epsp, body_epsm, body_fidx, flt_coef;
     bem::DBuf vert_body, fan_ptr, fan, nodal_mass, nodal_bounds, row_order;   // nodal basis only
+    // per group of 16 consecutive vertex columns: the triangles holding one of its vertices
+    // (ascending) and the local column of each corner (8 bits each, 0xff outside the group)
+    bem::DBuf grp_ptr, grp_tri, grp_loc;
     bem::DBuf nod_pan64, nod_far64, nod_ones;   // nodal density folded into the panel records (field lines)
     bem::DBuf tr_cases;                          // staging of the nodal basis's per-load-case line runs
     bem::DBuf far64, far32, tri64;

@@ -135,18 +135,22 @@ __device__ __forceinline__ double hat_value(const double* __restrict__ T, int c,
     return (lam * I0 + (g0 * J0 + g1 * J1 + g2 * J2) / two_area) * INV4PI;
 }
 
-// One wave: rows i0 + lane, columns j0 .. j0 + 15; the four waves of a block take
-// the same columns on four row tiles, so three of four record loads hit the
-// scalar cache.  1-D grid of n_rt x n_cg blocks (row tiles of 256 rows, column
-// groups of 16, n_cg a multiple of 8): blocks are dealt to the 8 XCDs in turn,
-// so block b runs on XCD b % 8, and each XCD sweeps all row tiles of one column
-// group before the next, keeping that group's records in its own L2.
+// One wave: rows i0 + lane, columns j0 .. j0 + 15 (column group cg).  The wave walks the
+// distinct triangles that hold a vertex of the group (ascending), evaluates the 7-point
+// rule once per triangle and adds each hat whose vertex is in the group into that column's
+// LDS slot, so a pair costs about two visits instead of one per vertex of the triangle.
+// The four waves of a block take the same columns on four row tiles, so three of four
+// record loads hit the scalar cache.  1-D grid of n_rt x n_cg blocks (row tiles of 256
+// rows, n_cg a multiple of 8): blocks are dealt to the 8 XCDs in turn, so block b runs on
+// XCD b % 8, and each XCD sweeps all row tiles of one column group before the next,
+// keeping that group's records in its own L2.
 template <class T>   // stored type: double (FP64) or float (MIXED)
 __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, int64_t n_rt,
                                                         const double* __restrict__ vert,
                                                         const int32_t* __restrict__ tri,
-                                                        const int32_t* __restrict__ fan_ptr,
-                                                        const int32_t* __restrict__ fan,
+                                                        const int32_t* __restrict__ grp_ptr,
+                                                        const int32_t* __restrict__ grp_tri,
+                                                        const uint32_t* __restrict__ grp_loc,
                                                         const double* __restrict__ pan64, T* __restrict__ A) {
     __shared__ double tile[4][NODAL_COLS][65];   // padded: the row-segment reads stride 65
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -157,32 +161,46 @@ __global__ __launch_bounds__(256) void k_nodal_assemble(int64_t nv, int64_t ld, 
     const int64_t ic = i < nv ? i : nv - 1;
     const double x0 = vert[3 * ic], x1 = vert[3 * ic + 1], x2 = vert[3 * ic + 2];
     const int64_t j0 = cg * NODAL_COLS;
-    for (int cc = 0; cc < NODAL_COLS; ++cc) {
-        const int64_t j = j0 + cc;
-        double acc = 0.0;
-        if (j < nv) {
-            const int32_t e1 = fan_ptr[j + 1];
-            for (int32_t e = fan_ptr[j]; e < e1; ++e) {
-                const int32_t pk = fan[e];
-                const int64_t t = pk >> 2;
-                const int c = pk & 3;
-                const double* P = pan64 + (int64_t)FAR_REC * t;
-                const int32_t* tv = tri + 3 * t;
-                const bool vtx = (tv[0] == i) || (tv[1] == i) || (tv[2] == i);
-                // near and singular pairs are left to k_nodal_near (same predicate)
-                if (!vtx && is_regular(x0 - P[FR_CC], x1 - P[FR_CC + 1], x2 - P[FR_CC + 2], P[FR_RR])) {
-                    const NodeBary nb(c);
+#pragma unroll
+    for (int cc = 0; cc < NODAL_COLS; ++cc) tile[wv][cc][lane] = 0.0;
+    if (j0 < nv) {
+        const NodeBary nb0(0), nb1(1), nb2(2);
+        const int32_t e1 = grp_ptr[cg + 1];
+        for (int32_t e = grp_ptr[cg]; e < e1; ++e) {
+            const int64_t t = grp_tri[e];
+            const uint32_t loc = grp_loc[e];   // local column of corners 0, 1, 2 (0xff: not in the group)
+            const double* P = pan64 + (int64_t)FAR_REC * t;
+            const int32_t* tv = tri + 3 * t;
+            const bool vtx = (tv[0] == i) || (tv[1] == i) || (tv[2] == i);
+            // near and singular pairs are left to k_nodal_near (same predicate)
+            if (!vtx && is_regular(x0 - P[FR_CC], x1 - P[FR_CC + 1], x2 - P[FR_CC + 2], P[FR_RR])) {
+                double wr[7];
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const double d0 = x0 - P[FR_X + q], d1 = x1 - P[FR_Y + q], d2 = x2 - P[FR_Z + q];
+                    wr[q] = rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
+                }
+                const uint32_t l0 = loc & 0xffu, l1 = (loc >> 8) & 0xffu, l2 = (loc >> 16) & 0xffu;
+                if (l0 != 0xffu) {
                     double s = 0.0;
 #pragma unroll
-                    for (int q = 0; q < 7; ++q) {
-                        const double d0 = x0 - P[FR_X + q], d1 = x1 - P[FR_Y + q], d2 = x2 - P[FR_Z + q];
-                        s += P[FR_W + q] * nb.b[q] * rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
-                    }
-                    acc += s;
+                    for (int q = 0; q < 7; ++q) s += P[FR_W + q] * nb0.b[q] * wr[q];
+                    tile[wv][l0][lane] += s;
+                }
+                if (l1 != 0xffu) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) s += P[FR_W + q] * nb1.b[q] * wr[q];
+                    tile[wv][l1][lane] += s;
+                }
+                if (l2 != 0xffu) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) s += P[FR_W + q] * nb2.b[q] * wr[q];
+                    tile[wv][l2][lane] += s;
                 }
             }
         }
-        tile[wv][cc][lane] = acc;
     }
     __syncthreads();
 #pragma unroll 4
@@ -473,8 +491,8 @@ static void nodal_assemble_t(bem_ctx* c, T* A, double* Atail, int64_t tail_row0)
     const int64_t n_rt = ceil_div(nv, 256), n_cg = ceil_div(ceil_div(nv, NODAL_COLS), 8) * 8;
     if (n_rt * n_cg > ((int64_t)1 << 31) - 1) throw Error(BEM_ERR_INVALID, "too many vertices for the LINEAR basis");
     hipLaunchKernelGGL(k_nodal_assemble<T>, dim3((unsigned)(n_rt * n_cg)), dim3(256), 0, s, nv, ld, n_rt,
-                       c->vert.as<double>(), c->tri.as<int32_t>(), c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(),
-                       c->pan64.as<double>(), A);
+                       c->vert.as<double>(), c->tri.as<int32_t>(), c->grp_ptr.as<int32_t>(), c->grp_tri.as<int32_t>(),
+                       c->grp_loc.as<uint32_t>(), c->pan64.as<double>(), A);
     BEM_CHECK_LAUNCH();
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t nch = ceil_div(c->N, 64);
