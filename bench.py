@@ -420,7 +420,7 @@ def main():
     print(f"[bench] coax N={N} lines={args.lines}", file=sys.stderr, flush=True)
     if args.nodal_only:
         ctx.close()
-        print(json.dumps({"nodal_basis_sphere": nodal_run(bem, torch)}))
+        print(json.dumps({"nodal_basis": nodal_run(bem, torch)}))
         return
     if args.tts_only:
         ctx.assemble()
@@ -434,7 +434,7 @@ def main():
                           "cases_64_x_lines_64": cases_by_lines_run(bem, torch, p, ctx),
                           "coax_60k_mixed_vs_fp64": c3_run(bem, torch),
                           "bushing_thin_sheets": bushing_run(bem, torch),
-                          "nodal_basis_sphere": nodal_run(bem, torch)}))
+                          "nodal_basis": nodal_run(bem, torch)}))
         ctx.close()
         return
     # tile shapes for this problem, timed before the timed region (tuning re-assembles)
@@ -509,7 +509,7 @@ def main():
         extras["cases_64_x_lines_64"] = cases_by_lines_run(bem, torch, p, ctx)
         extras["coax_60k_mixed_vs_fp64"] = c3_run(bem, torch)
         extras["bushing_thin_sheets"] = bushing_run(bem, torch)
-        extras["nodal_basis_sphere"] = nodal_run(bem, torch)
+        extras["nodal_basis"] = nodal_run(bem, torch)
 
     tts = None
     if not args.no_tts:
