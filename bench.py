@@ -12,8 +12,14 @@ whole step (matrix entries + surface-field pairs + field-line pairs).
 The roofline entry is for the dominant kernel, the far-field pass of the
 field-line tracer (k_lb_far, one launch per RK4 stage of all live lines):
 algorithmic FP64 flops per launch (regular pairs x 141 flop) / its average
-duration, measured with HIP events on the stream it runs on.  cpu_baseline
-times the plain FP64 CPU oracle on a bounded sample of the same workload.
+duration over every launch of the timed steps, measured by HIP events carried
+in the kernel's own dispatches (profiling mode 2: nothing else is timed, no
+event packet is added to the stream).  The per-phase breakdown comes from one
+more step after the timed ones, with every kernel timed.  cpu_baseline times
+the plain FP64 CPU oracle, compiled on the host with -march=native, on a
+bounded sample of the same workload.  The 64-load-case time-to-solve stops
+each path at the loosest tolerance that brings sigma within 1e-5 of the
+reference.
 
 After the timed steps, "extras" reports runs outside the step:
 - the gradient of 128 lines;
@@ -99,36 +105,60 @@ def calibrate_copy():
                       "bytes_written_per_launch": a.numel() * 8, "launches": 5}))
 
 
-def time_to_solve(bem, torch, p, ctx64, nrhs=64, tol=1e-8):
-    """64 load cases (driven electrode U[0.5, 2], shell at 0) from the assembled state:
+TTS_TOLS = (1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8)
+
+
+def time_to_solve(bem, torch, p, ctx64, nrhs=64, target=1e-5):
+    """64 load cases (driven electrode U[0.5, 2], shell at 0) from the assembled state, each path
+    stopped at the loosest GMRES tolerance (from TTS_TOLS) whose solution has sigma within
+    `target` of the reference in every load case (max_j |s_j - s_ref_j| / max_j |s_ref_j|; the
+    reference is the batched FP64 solve to 1e-12, which the parity tests tie to the oracle):
     FP64 one by one, FP64 batched (FP64 matrix cores) and mixed batched (FP32 matrix cores
-    inside FP64 refinement).  Errors are max_j |s_j - s_ref_j| / max_j |s_ref_j| of sigma against
-    a batched FP64 solve to 1e-12."""
+    inside FP64 refinement).  The tolerance search is untimed; the reported time is the best
+    of two runs at the chosen tolerance."""
     from workloads import rod_load_cases
     bv = rod_load_cases(p, nrhs, seed=4)
     N = p.n_tri
     ref, _ = ctx64.solve(bv, tol=1e-12, max_iter=20000)
-    out = {"load_cases": nrhs, "tol": tol}
+    refs = ref[:, :N]
+    out = {"load_cases": nrhs, "target_sigma_rel_err": target,
+           "reference": "batched FP64 solve to 1e-12"}
 
-    def timed(ctx, key):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sol, info = ctx.solve(bv, tol=tol, max_iter=20000)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        err = float(((sol[:, :N] - ref[:, :N]).abs().max() / ref[:, :N].abs().max()).item())
-        out[key] = {"s": dt, "iters": info["iters"], "refinements": info["refinements"], "sigma_rel_err": err}
+    def err_of(sol):
+        return float(((sol[:, :N] - refs).abs().max(dim=1).values / refs.abs().max(dim=1).values).max().item())
+
+    def run(ctx, key):
+        chosen = None
+        for tol in TTS_TOLS:
+            sol, info = ctx.solve(bv, tol=tol, max_iter=20000, raise_on_noconv=False)
+            if info["converged"] and err_of(sol) <= target:
+                chosen = tol
+                break
+        if chosen is None:
+            out[key] = {"error": "no tolerance in the list reached the target"}
+            return
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol, info = ctx.solve(bv, tol=chosen, max_iter=20000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out[key] = {"s": best, "tol": chosen, "iters": info["iters"], "refinements": info["refinements"],
+                    "sigma_rel_err": err_of(sol)}
 
     ctx64.set_tuning("batched_solve", 0)
-    timed(ctx64, "fp64_one_by_one")
+    run(ctx64, "fp64_one_by_one")
     ctx64.set_tuning("batched_solve", 1)
-    timed(ctx64, "fp64_batched")
+    run(ctx64, "fp64_batched")
     ctxm = bem.Context.from_problem(p, precision=bem.MIXED, eta=6.0, restart=100)
     ctxm.assemble()
-    timed(ctxm, "mixed_batched")
+    run(ctxm, "mixed_batched")
     ctxm.close()
-    out["speedup_mixed_vs_fp64_one_by_one"] = out["fp64_one_by_one"]["s"] / out["mixed_batched"]["s"]
-    out["speedup_mixed_vs_fp64_batched"] = out["fp64_batched"]["s"] / out["mixed_batched"]["s"]
+    if all("s" in out[k] for k in ("fp64_one_by_one", "fp64_batched", "mixed_batched")):
+        out["speedup_mixed_vs_fp64_one_by_one"] = out["fp64_one_by_one"]["s"] / out["mixed_batched"]["s"]
+        out["speedup_mixed_vs_fp64_batched"] = out["fp64_batched"]["s"] / out["mixed_batched"]["s"]
     return out
 
 
@@ -371,9 +401,34 @@ def nodal_run(bem, torch):
     return out
 
 
+def host_info():
+    """CPU model, logical CPUs this process may use, and RAM of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram_gb = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpus_available": len(os.sched_getaffinity(0)), "ram_gib": ram_gb}
+
+
 def cpu_baseline(p, x, starts, args):
-    """The oracle on a bounded sample: a block of matrix rows and a few short lines."""
+    """The oracle, compiled here with -O3 -march=native, on a bounded sample: a block of matrix
+    rows and a few short lines.  cores = the OpenMP threads its parallel loops ran with."""
+    import tempfile
+
     import oracle
+    oracle.build_native(os.path.join(tempfile.gettempdir(), "bem_oracle_native"))
     o = oracle.Oracle(p)
     rng = np.random.default_rng(12)
     rows = np.sort(rng.choice(p.n_tri, size=min(args.cpu_sample_rows, p.n_tri), replace=False))
@@ -386,10 +441,12 @@ def cpu_baseline(p, x, starts, args):
     t_lines = time.perf_counter() - t0
     passes = int(np.sum(1 + 4 * ns + 4 * (st != 0)))
     pairs = len(rows) * p.n_tri + passes * p.n_tri
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs / (t_rows + t_lines), "unit": "pairs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(rows)} matrix rows x {p.n_tri} panels + {args.cpu_sample_lines} field lines x "
-                      f"{args.cpu_sample_steps} RK4 steps on the same mesh ({t_rows + t_lines:.1f} s)"}
+    out = {"value": pairs / (t_rows + t_lines), "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{len(rows)} matrix rows x {p.n_tri} panels + {args.cpu_sample_lines} field lines x "
+                     f"{args.cpu_sample_steps} RK4 steps on the same mesh ({t_rows + t_lines:.1f} s)",
+           "build": "gcc -O3 -march=native -ffp-contract=off -fopenmp"}
+    out.update(host_info())
+    return out
 
 
 def main():
@@ -460,7 +517,9 @@ def main():
         step()
         torch.cuda.synchronize()
         print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
-    ctx.set_profiling(True)
+    # timed region: only the dominant kernel is timed, by events carried in its own dispatches
+    # (profiling mode 2), so the steps run as they do unprofiled
+    ctx.set_profiling(2)
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -470,6 +529,16 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.1f} ms/step", file=sys.stderr, flush=True)
+    tf_n, tf_ms = ctx.kernel_stats("trace_far")
+    far_launches = ctx.counter("trace_far_launches") / args.steps
+    far_pairs = ctx.counter("trace_far_pairs") / args.steps   # regular pairs of the far passes
+    near_line_pairs = ctx.counter("trace_near_pairs") / args.steps
+    # one more step, untimed, with every kernel timed: the per-phase breakdown
+    ctx.set_profiling(1)
+    ctx.reset_stats()
+    step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(0)
 
     ns_h = ns.cpu().numpy()
     st_h = st.cpu().numpy()
@@ -484,14 +553,10 @@ def main():
                                                 "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
                                                 "eval_near_csr", "eval_far", "eval_near", "trace", "trace_far",
                                                 "trace_step")}
-    near_line_pairs = ctx.counter("trace_near_pairs") / args.steps
     tr_n, tr_ms = stats["trace"]
     trace_ms = tr_ms / max(tr_n, 1)
-    # dominant kernel: the far-field pass of the field-line tracer (k_lb_far), one launch per RK4 stage;
-    # the library times every 16th launch (a uniform sample of the passes)
-    tf_n, tf_ms = stats["trace_far"]
-    far_launches = ctx.counter("trace_far_launches") / args.steps
-    far_pairs = ctx.counter("trace_far_pairs") / args.steps   # regular pairs of the far passes
+    # dominant kernel: the far-field pass of the field-line tracer (k_lb_far), one launch per RK4 stage,
+    # every launch of the timed steps timed by its dispatch's own events
     far_flop_per_launch = far_pairs * FLOP_FIELD_PAIR / far_launches
     far_avg_ms = tf_ms / max(tf_n, 1)
     achieved = far_flop_per_launch / (far_avg_ms * 1e-3) / 1e12
@@ -499,11 +564,10 @@ def main():
     gemv_ms = gv_ms / max(gv_n, 1)
     gemv_gbs = (8.0 * n_unk * n_unk) / (gemv_ms * 1e-3) / 1e9
     fa_n, fa_ms = stats["far_assemble"]
-    phases = {k: (v[1] / args.steps) for k, v in stats.items()}
+    phases = {k: v[1] for k, v in stats.items()}   # one profiled step after the timed ones
 
     extras = {}
     if not args.no_extras:
-        ctx.set_profiling(False)
         print("[bench] gradient and 64 x 64 lines", file=sys.stderr, flush=True)
         extras["gradient_coax_128_lines"] = gradient_run(bem, torch, p, ctx)
         extras["cases_64_x_lines_64"] = cases_by_lines_run(bem, torch, p, ctx)
@@ -513,7 +577,6 @@ def main():
 
     tts = None
     if not args.no_tts:
-        ctx.set_profiling(False)
         print("[bench] time-to-solve, 64 load cases", file=sys.stderr, flush=True)
         tts = time_to_solve(bem, torch, p, ctx)
 
@@ -557,7 +620,8 @@ def main():
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": K_LB_FAR_TRAFFIC_BYTES,
                      "traffic_unit": "bytes per launch (HBM, counters)",
                      "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": far_pairs / far_launches,
-                     "launches_per_step": far_launches, "avg_launch_ms": far_avg_ms},
+                     "launches_per_step": far_launches, "avg_launch_ms": far_avg_ms,
+                     "timed_launches": tf_n},
         "trace_ms_per_step": trace_ms,
         "trace_near_pairs": near_line_pairs,
         "cpu_baseline": cpu,

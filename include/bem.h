@@ -54,8 +54,8 @@ typedef enum {
                               Eq. Final2 plus one row of Eq. sheets per body, the net charge over both
                               sides, sum_i a_i ((eps+ + eps-)/2 sigma_i + (eps+ - eps-) (K' sigma)_i)
                               = 0, whatever constraint_form says; eps_plus / eps_minus are the
-                              permittivities on the normal side and the other side.  Not supported
-                              by bem_streamer_grad. */
+                              permittivities on the normal side and the other side.  bem_streamer_grad
+                              covers sheets (the row of Eq. sheets is differentiated like Final4). */
 } bem_kind;
 
 typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
@@ -75,8 +75,9 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
  *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres, bem_eval_field at volume
  *            points (on_panel NULL; phi or E may be NULL), and bem_trace_lines /
  *            bem_streamer_integral in the batched layout (trace_mode 0 or 1; lines of several
- *            load cases run case by case); the gradient and the autotuner need CONSTANT
- *            (INVALID otherwise). */
+ *            load cases run case by case; the line passes read FP64 panel records carrying
+ *            the nodal density, in MIXED contexts too); the gradient and the autotuner need
+ *            CONSTANT (INVALID otherwise). */
 typedef enum { BEM_BASIS_CONSTANT = 0, BEM_BASIS_LINEAR = 1 } bem_basis;
 
 /* One body.  Triangle normals (right-hand rule of the vertex order) point
@@ -243,6 +244,16 @@ bem_status bem_streamer_grad(bem_ctx* ctx, int32_t nrhs, const double* sol, int6
                              const double* start_bary, const bem_trace_params* tp, const double* dJ_dI,
                              double tol, double* dJ_dvert, double* dJ_dV, double* dJ_dstart);
 
+/* Points on panels, as field-line starts that sit on an electrode (Sec. 1: breakdown paths
+ * start at the electrode surface):
+ *   out[l] = sum_k bary[l][k] v_k + offset * n   for panel j = panel[l],
+ * v_k the panel's vertices in their stored order, n its unit normal (into eps+).  This is
+ * the placement bem_streamer_grad assumes when its starts move with their panels.
+ *  panel dev [L] int32 in [0, N); bary dev [L][3]; out dev [L][3] (written).
+ * Errors: INVALID (index range, non-finite input). */
+bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const double* bary, double offset,
+                            double* out);
+
 /* Tuning knobs (no effect on results beyond summation order).
  *  "trace_mode": 0 (default) or 1 = all lines advance together (one batched
  *                evaluation per RK4 stage, spread over the GPU), 2 = one
@@ -292,15 +303,21 @@ bem_status bem_get_tuning(const bem_ctx* ctx, const char* key, int64_t* value);
  * invalid cache entry, unwritable file), HIP, OOM. */
 bem_status bem_autotune(bem_ctx* ctx, const char* cache_path, int32_t* from_cache);
 
-/* Per-kernel timing with HIP events recorded around each launch while
- * enabled, on the stream of the launch (the context stream, or the tracer's
- * second stream for its line groups).  Names: "geometry", "far_assemble", "near_mask_csr",
- * "near_assemble", "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
- * "eval_near_csr", "eval_far", "eval_near", "trace" (a whole field-line call),
- * "trace_far" and "trace_step" (the two kernels of a batched pass; every 16th
- * pass is timed, so their launch counts are a sample and total_ms covers that
- * sample), "gemm_f32", "gemm_f64", "bgmres_iter", "grad", "grad_reverse", "grad_rows_EH",
- * "grad_panel_far", "grad_panel_near", "gemvT". */
+/* Per-kernel timing with HIP events, on the stream of the launch (the context stream, or the
+ * tracer's second stream for its line groups).
+ *  enable 0: off.
+ *  enable 1: every kernel, by an event pair recorded around each launch.  Names: "geometry",
+ *            "far_assemble", "near_mask_csr", "near_assemble", "finalize", "gemv", "gmres_ortho",
+ *            "gmres_iter", "eval_mask", "eval_near_csr", "eval_far", "eval_near", "trace" (a
+ *            whole field-line call), "trace_step" (the step kernel of a batched pass; every
+ *            16th pass is timed, so its launch count is a sample and total_ms covers that
+ *            sample), "gemm_f32", "gemm_f64", "gemm_rows", "bgmres_iter", "grad",
+ *            "grad_reverse", "grad_rows_EH", "grad_panel_far", "grad_panel_near", "gemvT".
+ *  enable 1 or 2: "trace_far", every chunked far pass of the batched field-line layout, timed
+ *            by events carried in its own dispatch (hipExtLaunchKernelGGL): the kernel's
+ *            execution interval, with nothing added to the stream.
+ *  enable 2: only "trace_far", so that all other work runs as it does unprofiled.
+ * Errors: INVALID for another value. */
 bem_status bem_set_profiling(bem_ctx* ctx, int32_t enable);
 bem_status bem_kernel_stats(bem_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
 bem_status bem_reset_stats(bem_ctx* ctx);   /* also zeroes the counters below */

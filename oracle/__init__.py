@@ -21,17 +21,41 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 DIRICHLET, FLOATING, INTERFACE, SHEET = 0, 1, 2, 3
 
 
+_FLAGS = ["-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c and oracle_dual.c into liboracle.so (gcc, -O2, no FMA contraction)."""
+    """Compile oracle.c and oracle_dual.c into liboracle.so (gcc -O3, no FMA contraction, no
+    fast-math).  This in-tree build targets x86-64-v3 (AVX2), which every host it is shipped
+    to runs; build_native() makes a copy tuned for the host it runs on."""
     stale = (not os.path.exists(_LIB)
              or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_DUAL)))
     if force or stale:
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-march=x86-64-v2", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_DUAL, "-lm"]
+        cmd = ["gcc", *_FLAGS, "-march=x86-64-v3", "-o", tmp, _SRC, _SRC_DUAL, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_native(out_dir: str) -> str:
+    """Compile the oracle with -O3 -march=native for the CPU it runs on (the timed CPU
+    baseline), into out_dir, and load that copy for this process.  Must be called before
+    any other use of the oracle in the process."""
+    global _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "liboracle_native.so")
+    cmd = ["gcc", *_FLAGS, "-march=native", "-o", path, _SRC, _SRC_DUAL, "-lm"]
+    subprocess.run(cmd, check=True)
+    _lib = ctypes.CDLL(path)
+    return path
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use (omp_get_max_threads)."""
+    return int(_load().orc_num_threads())
 
 
 class _Problem(ctypes.Structure):
@@ -288,6 +312,24 @@ def tri_linear_field(x, v1, v2, v3):
     a = [_f64(v) for v in (x, v1, v2, v3)]
     lib.orc_tri_linear_field(*[_ptr(v) for v in a], _ptr(out))
     return out
+
+
+def tri_duffy(x, v1, v2, v3):
+    """The paper's near-singular rule (closest point, subdivision, Duffy, Gauss-Legendre) for a
+    unit-density flat triangle: (S, F); F is NaN when x lies on the triangle."""
+    lib = _load()
+    S = ctypes.c_double(0.0)
+    F = np.empty(3)
+    lib.orc_tri_duffy(*(_ptr(_f64(a)) for a in (x, v1, v2, v3)), ctypes.byref(S), _ptr(F))
+    return S.value, F
+
+
+def closest_point(x, v1, v2, v3):
+    """Closest point of the closed triangle to x (step 1 of the near-singular rule)."""
+    lib = _load()
+    c = np.empty(3)
+    lib.orc_closest_point(*(_ptr(_f64(a)) for a in (x, v1, v2, v3)), _ptr(c))
+    return c
 
 
 def tri_quad7(x, v1, v2, v3):

@@ -27,11 +27,15 @@
  * only splits independent rows, points or lines across threads.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+
+/* threads of the parallel loops below (reported beside the timed CPU baseline) */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* ORC_SHEET: a thin floating conductive sheet modelled by one (open) surface, Eq. sheets */
 enum { ORC_DIRICHLET = 0, ORC_FLOATING = 1, ORC_INTERFACE = 2, ORC_SHEET = 3 };
@@ -202,6 +206,205 @@ void orc_tri_analytic(const double x[3], const double v1[3], const double v2[3],
     double sgn = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
     *S = (sum_tf - aw * sum_beta) / (4.0 * ORC_PI);
     for (int k = 0; k < 3; ++k) F[k] = (mf[k] + sgn * n[k] * sum_beta) / (4.0 * ORC_PI);
+}
+
+/* ------------------------------------- near-singular rule of the paper (Sec. 4)
+ * The paper integrates a near-singular (point, triangle) pair by finding the
+ * point of the triangle closest to x, subdividing the triangle so that this
+ * point is a corner of every piece, and applying the Duffy transformation on
+ * each piece, which cancels the 1/r behaviour at the corner.  Written out:
+ *   1. c = argmin over the closed triangle of |x - y|: the foot point of x in
+ *      the plane when it lies inside, else the nearest point of the three
+ *      edge segments.
+ *   2. pieces (c, a, b) for the edges a -> b of the triangle; pieces of zero
+ *      area (c on that edge) are dropped.  All pieces keep the triangle's
+ *      orientation, so their areas add up to its area.
+ *   3. Duffy map of a piece: y(u, v) = c + u ((1 - v)(a - c) + v (b - c)),
+ *      u, v in [0, 1], dS = u |(a - c) x (b - c)| du dv.
+ *   4. Gauss-Legendre in u and v.  The paper's rule is adaptive; the reading
+ *      here: u is cut geometrically (doubling widths) towards the corner from a
+ *      quarter of d / L (d = |x - c|, L the longest piece edge), and v towards
+ *      the foot of the corner on the opposite edge from a quarter of that
+ *      distance over the edge length (a piece whose corner lies close to its
+ *      opposite edge is narrow, and its Duffy integrand peaks in v there);
+ *      ORC_DUFFY_NU x ORC_DUFFY_NV nodes per cell.
+ * Unit density; S = (1/4pi) int 1/|x - y| dS, F = (1/4pi) int (x - y)/|x - y|^3 dS.
+ * For x on the triangle (d = 0, the singular pair) the Duffy integrand of S is
+ * smooth and S is returned; F is then a principal value that the
+ * transformation does not produce and is returned as NaN.
+ */
+#define ORC_DUFFY_NU 16
+#define ORC_DUFFY_NV 16
+
+/* n-point Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on
+ * the Legendre recurrence (Golub-Welsch would serve equally; n <= 64). */
+static void orc_gauss_legendre01(int n, double* t, double* w)
+{
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = cos(ORC_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+        t[i] = 0.5 * (1.0 - z);
+        t[n - 1 - i] = 0.5 * (1.0 + z);
+        w[i] = 0.5 * wi;
+        w[n - 1 - i] = 0.5 * wi;
+    }
+}
+
+/* closest point of the closed segment [a, b] to x */
+static void orc_closest_on_segment(const double x[3], const double a[3], const double b[3], double c[3])
+{
+    double ab[3], ax[3];
+    sub3(b, a, ab);
+    sub3(x, a, ax);
+    double t = dot3(ax, ab) / dot3(ab, ab);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    for (int k = 0; k < 3; ++k) c[k] = a[k] + t * ab[k];
+}
+
+void orc_closest_point(const double x[3], const double v1[3], const double v2[3], const double v3[3], double c[3])
+{
+    double e1[3], e2[3], n[3], xv[3];
+    sub3(v2, v1, e1);
+    sub3(v3, v1, e2);
+    cross3(e1, e2, n);
+    double nn = dot3(n, n);
+    sub3(x, v1, xv);
+    double w = dot3(xv, n) / nn;
+    double rho[3];
+    for (int k = 0; k < 3; ++k) rho[k] = x[k] - w * n[k];
+    /* barycentric coordinates of rho from signed sub-areas */
+    const double* v[3] = {v1, v2, v3};
+    int inside = 1;
+    for (int e = 0; e < 3; ++e) {
+        double pa[3], pb[3], cr[3];
+        sub3(v[(e + 1) % 3], rho, pa);
+        sub3(v[(e + 2) % 3], rho, pb);
+        cross3(pa, pb, cr);
+        if (dot3(cr, n) < 0.0) inside = 0;
+    }
+    if (inside) {
+        for (int k = 0; k < 3; ++k) c[k] = rho[k];
+        return;
+    }
+    double best = INFINITY;
+    for (int e = 0; e < 3; ++e) {
+        double ce[3], d[3];
+        orc_closest_on_segment(x, v[e], v[(e + 1) % 3], ce);
+        sub3(x, ce, d);
+        double dd = dot3(d, d);
+        if (dd < best) {
+            best = dd;
+            for (int k = 0; k < 3; ++k) c[k] = ce[k];
+        }
+    }
+}
+
+/* breakpoints of [0, 1] graded geometrically towards t0 in [0, 1] on the scale s (> 0): t0 and
+ * t0 -+ (s/4) 2^k for k = 0, 1, ... up to the ends; returns their count (<= 256) */
+static int orc_graded_breaks(double t0, double s, double* bp)
+{
+    double lo[128], hi[128];
+    int nl = 0, nh = 0;
+    for (double w = 0.25 * s; t0 - w > 0.0 && nl < 120; w *= 2.0) lo[nl++] = t0 - w;
+    for (double w = 0.25 * s; t0 + w < 1.0 && nh < 120; w *= 2.0) hi[nh++] = t0 + w;
+    int n = 0;
+    bp[n++] = 0.0;
+    for (int i = nl - 1; i >= 0; --i) bp[n++] = lo[i];
+    if (t0 > 0.0 && t0 < 1.0) bp[n++] = t0;
+    for (int i = 0; i < nh; ++i) bp[n++] = hi[i];
+    bp[n++] = 1.0;
+    return n;
+}
+
+void orc_tri_duffy(const double x[3], const double v1[3], const double v2[3], const double v3[3], double* S,
+                   double F[3])
+{
+    double tu[ORC_DUFFY_NU], wu[ORC_DUFFY_NU], tv[ORC_DUFFY_NV], wv[ORC_DUFFY_NV];
+    orc_gauss_legendre01(ORC_DUFFY_NU, tu, wu);
+    orc_gauss_legendre01(ORC_DUFFY_NV, tv, wv);
+    double c[3], xc[3];
+    orc_closest_point(x, v1, v2, v3, c);
+    sub3(x, c, xc);
+    double d = norm3(xc);
+    const double* v[3] = {v1, v2, v3};
+    double e1[3], e2[3], tn[3];
+    sub3(v2, v1, e1);
+    sub3(v3, v1, e2);
+    cross3(e1, e2, tn);
+    double tarea2 = norm3(tn);
+    /* x within rounding of the triangle (1e-14 of its size) is on it: the singular pair */
+    if (d <= 1e-14 * sqrt(tarea2)) {
+        d = 0.0;
+        for (int k = 0; k < 3; ++k) c[k] = x[k];
+    }
+    double s = 0.0, f[3] = {0.0, 0.0, 0.0};
+    double bu[260], bv[260];
+    for (int e = 0; e < 3; ++e) {
+        const double* a = v[e];
+        const double* b = v[(e + 1) % 3];
+        double pa[3], pb[3], cr[3], ab[3];
+        sub3(a, c, pa);
+        sub3(b, c, pb);
+        sub3(b, a, ab);
+        cross3(pa, pb, cr);
+        double J = norm3(cr);
+        if (J <= 1e-14 * tarea2) continue;   /* c on this edge: no piece */
+        double L = norm3(pa), lab = norm3(ab);
+        if (norm3(pb) > L) L = norm3(pb);
+        if (lab > L) L = lab;
+        /* u: towards the corner on the scale d / L (one interval when x is on the triangle) */
+        int nu = 2;
+        bu[0] = 0.0;
+        bu[1] = 1.0;
+        if (d > 0.0) nu = orc_graded_breaks(0.0, d / L, bu);
+        /* v: towards the foot v* of the corner on the opposite edge, on the scale of the
+         * corner's distance to it over the edge length (the factor 1/|dir(v)| of a narrow piece) */
+        double vs = -dot3(pa, ab) / (lab * lab);
+        if (vs < 0.0) vs = 0.0;
+        if (vs > 1.0) vs = 1.0;
+        double nv = orc_graded_breaks(vs, (J / lab) / lab, bv);
+        for (int iu = 0; iu + 1 < nu; ++iu)
+            for (int i = 0; i < ORC_DUFFY_NU; ++i) {
+                double u = bu[iu] + (bu[iu + 1] - bu[iu]) * tu[i];
+                double wuu = (bu[iu + 1] - bu[iu]) * wu[i];
+                for (int iv = 0; iv + 1 < nv; ++iv)
+                    for (int j = 0; j < ORC_DUFFY_NV; ++j) {
+                        double vv = bv[iv] + (bv[iv + 1] - bv[iv]) * tv[j];
+                        double wvv = (bv[iv + 1] - bv[iv]) * wv[j];
+                        double y[3], r[3];
+                        for (int k = 0; k < 3; ++k) y[k] = c[k] + u * ((1.0 - vv) * pa[k] + vv * pb[k]);
+                        sub3(x, y, r);
+                        double R = norm3(r);
+                        double jw = u * J * wuu * wvv;
+                        s += jw / R;
+                        if (d > 0.0)
+                            for (int k = 0; k < 3; ++k) f[k] += jw * r[k] / (R * R * R);
+                    }
+            }
+    }
+    *S = s / (4.0 * ORC_PI);
+    for (int k = 0; k < 3; ++k) F[k] = (d > 0.0) ? f[k] / (4.0 * ORC_PI) : NAN;
 }
 
 /* ------------------------------------------------------------- problem geometry */

@@ -223,6 +223,18 @@ class Context:
                                           float(tol), _dev_ptr(dvert), _dev_ptr(dV), _dev_ptr(dstart)), self.lib)
         return dvert, dV, dstart
 
+    def panel_points(self, panel, bary, offset=0.0):
+        """Points sum_k bary_k v_k + offset * n on the given panels (bem_panel_points).
+        Returns [L, 3] float64 on the GPU."""
+        torch = _torch()
+        pn = torch.as_tensor(np.asarray(panel), dtype=torch.int32, device=self.device).reshape(-1).contiguous()
+        L = pn.shape[0]
+        bc = torch.as_tensor(np.asarray(bary), dtype=torch.float64, device=self.device).reshape(L, 3).contiguous()
+        out = torch.empty((L, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.bem_panel_points(self._ctx, L, _dev_ptr(pn), _dev_ptr(bc), float(offset), _dev_ptr(out)),
+               self.lib)
+        return out
+
     def set_tuning(self, key: str, value: int):
         _check(self.lib.bem_set_tuning(self._ctx, key.encode(), int(value)), self.lib)
 
@@ -239,8 +251,9 @@ class Context:
         return bool(fc.value)
 
     # -------------------------------------------------------------- profiling
-    def set_profiling(self, on=True):
-        _check(self.lib.bem_set_profiling(self._ctx, int(bool(on))), self.lib)
+    def set_profiling(self, mode=1):
+        """0 off, 1 every kernel, 2 only the field-line far pass (see bem_set_profiling)."""
+        _check(self.lib.bem_set_profiling(self._ctx, int(mode)), self.lib)
 
     def kernel_stats(self, name: str):
         n = ctypes.c_int64(0)
@@ -255,18 +268,6 @@ class Context:
         v = ctypes.c_int64(0)
         _check(self.lib.bem_get_counter(self._ctx, name.encode(), ctypes.byref(v)), self.lib)
         return int(v.value)
-
-
-def line_starts(vert, tri, start_panel, start_bary, offset):
-    """Line starts that sit on panels: sum_k bary_k v_k + offset * n of panel start_panel[l]
-    (torch, differentiable; the same placement bem_streamer_grad assumes)."""
-    torch = _torch()
-    t = torch.as_tensor(np.asarray(tri)[np.asarray(start_panel)], dtype=torch.long, device=vert.device)
-    a, b, c = vert[t[:, 0]], vert[t[:, 1]], vert[t[:, 2]]
-    bary = torch.as_tensor(start_bary, dtype=vert.dtype, device=vert.device)
-    nrm = torch.linalg.cross(b - a, c - a)
-    nrm = nrm / torch.linalg.norm(nrm, dim=1, keepdim=True)
-    return bary[:, :1] * a + bary[:, 1:2] * b + bary[:, 2:3] * c + offset * nrm
 
 
 def _streamer_function():
@@ -286,8 +287,7 @@ def _streamer_function():
                            precision=FP64, eta=eta, constraint_form=constraint_form)
             bctx.assemble()
             sol, _ = bctx.solve(bv, tol=solve_tol, max_iter=100000)
-            starts = line_starts(vert.detach().to(bctx.device), problem.tri, start_panel, start_bary,
-                                 params.start_offset)
+            starts = bctx.panel_points(start_panel, start_bary, params.start_offset)
             I, ns, st, _ = bctx.streamer_integral(sol, starts, params)
             ctx.bctx, ctx.sol, ctx.starts, ctx.params = bctx, sol, starts, params
             ctx.start_panel, ctx.start_bary = start_panel, start_bary

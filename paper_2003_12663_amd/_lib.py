@@ -15,7 +15,7 @@ EXPORTS = [
     "bem_create", "bem_destroy", "bem_last_error", "bem_n_unknowns", "bem_assemble", "bem_copy_rows",
     "bem_near_pairs", "bem_rhs", "bem_matvec", "bem_solve_gmres", "bem_eval_field", "bem_trace_lines",
     "bem_streamer_integral", "bem_set_tuning", "bem_set_profiling", "bem_kernel_stats", "bem_reset_stats",
-    "bem_get_counter", "bem_streamer_grad", "bem_get_tuning", "bem_autotune",
+    "bem_get_counter", "bem_streamer_grad", "bem_get_tuning", "bem_autotune", "bem_panel_points",
 ]
 
 
@@ -73,6 +73,7 @@ def load() -> ctypes.CDLL:
         "bem_streamer_grad": (i32, [P, i32, P, i64, P, P, P, P, P, P, f64, P, P, P]),
         "bem_get_tuning": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i64)]),
         "bem_autotune": (i32, [P, ctypes.c_char_p, ctypes.POINTER(i32)]),
+        "bem_panel_points": (i32, [P, i64, P, P, f64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -110,44 +110,68 @@ void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, c
 
 namespace bem {
 
+void timing_events(bem_ctx* c, hipEvent_t* a, hipEvent_t* b) {
+    hipEvent_t* out[2] = {a, b};
+    for (hipEvent_t* e : out) {
+        if (!c->event_pool.empty()) {
+            *e = c->event_pool.back();
+            c->event_pool.pop_back();
+        } else {
+            BEM_HIP(hipEventCreate(e));
+        }
+    }
+}
+
+void push_timing(bem_ctx* c, const char* name, hipEvent_t a, hipEvent_t b) {
+    c->pending.push_back({name, {a, b}});
+    if (c->pending.size() > 4096) resolve_ready(c);
+}
+
 KTimer::KTimer(bem_ctx* ctx, const char* nm, bool enabled, hipStream_t st)
     : c(ctx), name(nm), s(st ? st : ctx->stream) {
-    if (!c->profiling || !enabled) return;
-    auto get = [&]() {
-        if (!c->event_pool.empty()) {
-            hipEvent_t e = c->event_pool.back();
-            c->event_pool.pop_back();
-            return e;
-        }
-        hipEvent_t e;
-        BEM_HIP(hipEventCreate(&e));
-        return e;
-    };
-    a = get();
-    b = get();
+    if (c->profiling != 1 || !enabled) return;
+    timing_events(c, &a, &b);
     BEM_HIP(hipEventRecord(a, s));
 }
 
 KTimer::~KTimer() {
     if (!a) return;
     if (hipEventRecord(b, s) != hipSuccess) return;
-    c->pending.push_back({name, {a, b}});
-    if (c->pending.size() > 4096) resolve_stats(c);
+    push_timing(c, name, a, b);
 }
+
+namespace {
+// add the pair's time to its statistic and return the events to the pool
+void take(bem_ctx* c, const std::string& name, hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+        auto& s = c->stats[name];
+        s.launches += 1;
+        s.ms += ms;
+    }
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+}
+}  // namespace
 
 void resolve_stats(bem_ctx* c) {
     for (auto& p : c->pending) {
-        float ms = 0.f;
-        if (hipEventSynchronize(p.second.second) == hipSuccess &&
-            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
-            auto& s = c->stats[p.first];
-            s.launches += 1;
-            s.ms += ms;
-        }
-        c->event_pool.push_back(p.second.first);
-        c->event_pool.push_back(p.second.second);
+        (void)hipEventSynchronize(p.second.second);
+        take(c, p.first, p.second.first, p.second.second);
     }
     c->pending.clear();
+}
+
+// Resolves the pending pairs whose end event has completed, in order, without waiting, so that
+// a long profiled run never blocks the host on the GPU to make room.
+void resolve_ready(bem_ctx* c) {
+    size_t k = 0;
+    for (; k < c->pending.size(); ++k) {
+        auto& p = c->pending[k];
+        if (hipEventQuery(p.second.second) != hipSuccess) break;
+        take(c, p.first, p.second.first, p.second.second);
+    }
+    c->pending.erase(c->pending.begin(), c->pending.begin() + (ptrdiff_t)k);
 }
 
 }  // namespace bem
@@ -724,6 +748,25 @@ bem_status bem_streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_
     API_CATCH
 }
 
+bem_status bem_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const double* bary, double offset,
+                            double* out) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (L < 0 || L >= ((int64_t)1 << 31)) throw bem::Error(BEM_ERR_INVALID, "point count out of range");
+    if (L > 0 && (!panel || !bary || !out)) throw bem::Error(BEM_ERR_INVALID, "panel, bary and out are required");
+    if (!std::isfinite(offset)) throw bem::Error(BEM_ERR_INVALID, "offset must be finite");
+    auto hp = fetch_i32(c, panel, (size_t)L);
+    for (int32_t v : hp)
+        if (v < 0 || v >= c->N) throw bem::Error(BEM_ERR_INVALID, "panel entry out of range");
+    auto hb = fetch_f64(c, bary, (size_t)L * 3);
+    for (double v : hb)
+        if (!std::isfinite(v)) throw bem::Error(BEM_ERR_INVALID, "non-finite barycentric coordinate");
+    bem::launch_panel_points(c, L, panel, bary, offset, out);
+    return BEM_OK;
+    API_CATCH
+}
+
 bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return fail(BEM_ERR_INVALID, "NULL argument");
     if (std::strcmp(key, "trace_mode") == 0) {
@@ -794,7 +837,8 @@ bem_status bem_autotune(bem_ctx* c, const char* cache_path, int32_t* from_cache)
 
 bem_status bem_set_profiling(bem_ctx* c, int32_t enable) {
     if (!c) return fail(BEM_ERR_INVALID, "NULL context");
-    c->profiling = enable != 0;
+    if (enable < 0 || enable > 2) return fail(BEM_ERR_INVALID, "profiling mode must be 0, 1 or 2");
+    c->profiling = enable;
     return BEM_OK;
 }
 

@@ -145,7 +145,7 @@ struct bem_ctx {
     bem::HBuf host_stage;
     bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part;
 
-    bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part;   // batched GMRES
+    bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part, rows_part;   // batched GMRES
 
     // gradient of the streamer integrals
     bem::DBuf ad_state, ad_part, ad_mask, ad_cnt, ad_self, ad_ppart, ad_list, ad_path, ad_stage, ad_geo, ad_seg,
@@ -170,8 +170,10 @@ struct bem_ctx {
     int32_t tune_trace_groups = 1;    // line groups of a field-line run, each on its own stream (1 or 2)
     int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
-    // profiling
-    bool profiling = false;
+    // profiling: 0 off; 1 every kernel (event pairs around each launch, the field-line far pass
+    // by events carried in its dispatch); 2 only the field-line far pass, by events carried in its
+    // dispatch, so that the rest of the work runs as it does unprofiled
+    int32_t profiling = 0;
     std::map<std::string, bem::KStat> stats;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> event_pool;
@@ -201,10 +203,17 @@ struct KTimer {
     KTimer(bem_ctx* ctx, const char* nm, bool enabled = true, hipStream_t st = nullptr);
     ~KTimer();
 };
+// resolve_stats waits for every pending event; resolve_ready takes only the completed prefix
 void resolve_stats(bem_ctx* c);
+void resolve_ready(bem_ctx* c);
+// a pair of timing events from the context's pool, and their hand-over to the named statistic
+void timing_events(bem_ctx* c, hipEvent_t* a, hipEvent_t* b);
+void push_timing(bem_ctx* c, const char* name, hipEvent_t a, hipEvent_t b);
 
 // ---- launchers (one translation unit each) --------------------------------
 void launch_geometry(bem_ctx* c);                                  // geometry.hip
+void launch_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const double* bary, double offset,
+                         double* out);                                // geometry.hip
 void launch_far_assemble(bem_ctx* c);                              // assemble.hip
 void launch_near_csr(bem_ctx* c, const uint64_t* mask, int64_t n_targets, DBuf& ptr, DBuf& row, DBuf& col,
                      int64_t* nnz, const char* tname);             // assemble.hip
@@ -228,6 +237,10 @@ void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, 
 // Sec. 4 classification of (point, panel) pairs as ballot masks mask[(j >> 6) * P + p] (bit j & 63 set:
 // not regular, or j == on_panel[p]); ceil(N / 64) * P words.
 void launch_point_mask(bem_ctx* c, int64_t P, const double* pts, const int32_t* on_panel, uint64_t* mask);
+// panel-range split of the field evaluation's far pass for P points (K ranges; span panels each)
+int64_t eval_split(const bem_ctx* c, int64_t P, int64_t* span);   // eval.hip
+void launch_eval_far(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel,
+                     double* part, int64_t KS, int64_t span);    // eval.hip: part[KS][P][4]
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                   const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                   double* path, double* integral, uint8_t* exceeds);   // trace.hip

@@ -154,46 +154,56 @@ void launch_point_mask(bem_ctx* c, int64_t P, const double* pts, const int32_t* 
     BEM_CHECK_LAUNCH();
 }
 
+// K ranges of the panel split of the far pass for P points: about the tuned number of blocks
+// (default 2048); span (panels per range) is a multiple of the LDS tile.
+int64_t eval_split(const bem_ctx* c, int64_t P, int64_t* span) {
+    const int64_t N = c->N;
+    const int64_t pb = ceil_div(P, 256);
+    int64_t KS = c->tune_eval_blocks / pb;
+    if (KS < 1) KS = 1;
+    if (KS > ceil_div(N, EV_TILE)) KS = ceil_div(N, EV_TILE);
+    *span = ceil_div(ceil_div(N, KS), EV_TILE) * EV_TILE;
+    return ceil_div(N, *span);
+}
+
+// far pass of the field evaluation into part[KS][P][4] (phi, E partial sums per panel range)
+void launch_eval_far(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel,
+                     double* part, int64_t KS, int64_t span) {
+    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
+    dim3 grid((unsigned)ceil_div(P, 256), (unsigned)KS);
+    if (c->opt.precision == BEM_FP64)
+        hipLaunchKernelGGL((k_eval_far<double>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
+                           c->far64.as<double>(), Np, c->N, span, sigma, P, pts, on_panel, part);
+    else
+        hipLaunchKernelGGL((k_eval_far<float>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
+                           c->far32.as<float>(), Np, c->N, span, sigma, P, pts, on_panel, part);
+    BEM_CHECK_LAUNCH();
+}
+
 void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, const int32_t* on_panel, double* phi,
                  double* E) {
     if (P == 0) return;
-    const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
     const int64_t N = c->N;
     const int64_t nblk = ceil_div(N, 64);
     c->ev_mask.alloc(sizeof(uint64_t) * nblk * P);
     {
         KTimer t(c, "eval_mask");
-        dim3 grid((unsigned)(Np / 256), (unsigned)ceil_div(P, EV_MASK_PTS));
-        hipLaunchKernelGGL(k_eval_mask, grid, dim3(256), 0, c->stream, c->far64.as<double>(), Np, N, P, pts, on_panel,
-                           c->ev_mask.as<uint64_t>());
-        BEM_CHECK_LAUNCH();
+        launch_point_mask(c, P, pts, on_panel, c->ev_mask.as<uint64_t>());
     }
     int64_t nnz = 0;
     launch_near_csr(c, c->ev_mask.as<uint64_t>(), P, c->ev_ptr, c->ev_row, c->ev_col, &nnz, "eval_near_csr");
-    // split the panel range so that the grid has about the tuned number of blocks (default 2048)
-    const int64_t pb = ceil_div(P, 256);
-    int64_t KS = c->tune_eval_blocks / pb;
-    if (KS < 1) KS = 1;
-    if (KS > ceil_div(N, EV_TILE)) KS = ceil_div(N, EV_TILE);
-    const int64_t span = ceil_div(ceil_div(N, KS), EV_TILE) * EV_TILE;
-    KS = ceil_div(N, span);
+    int64_t span = 0;
+    const int64_t KS = eval_split(c, P, &span);
     c->ev_part.alloc(sizeof(double) * 4 * KS * P);
     {
         KTimer t(c, "eval_far");
-        dim3 grid((unsigned)pb, (unsigned)KS);
-        if (c->opt.precision == BEM_FP64)
-            hipLaunchKernelGGL((k_eval_far<double>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
-                               c->far64.as<double>(), Np, N, span, sigma, P, pts, on_panel, c->ev_part.as<double>());
-        else
-            hipLaunchKernelGGL((k_eval_far<float>), grid, dim3(256), 0, c->stream, c->far64.as<double>(),
-                               c->far32.as<float>(), Np, N, span, sigma, P, pts, on_panel, c->ev_part.as<double>());
-        BEM_CHECK_LAUNCH();
+        launch_eval_far(c, sigma, P, pts, on_panel, c->ev_part.as<double>(), KS, span);
     }
     {
         KTimer t(c, "eval_near");
-        hipLaunchKernelGGL(k_eval_finish, dim3((unsigned)pb), dim3(256), 0, c->stream, c->ev_part.as<double>(), (int)KS,
-                           P, c->ev_ptr.as<int64_t>(), c->ev_col.as<int32_t>(), c->tri64.as<double>(), sigma, pts,
-                           on_panel, phi, E);
+        hipLaunchKernelGGL(k_eval_finish, dim3((unsigned)ceil_div(P, 256)), dim3(256), 0, c->stream,
+                           c->ev_part.as<double>(), (int)KS, P, c->ev_ptr.as<int64_t>(), c->ev_col.as<int32_t>(),
+                           c->tri64.as<double>(), sigma, pts, on_panel, phi, E);
         BEM_CHECK_LAUNCH();
     }
 }

@@ -11,7 +11,10 @@
 //  k_gemm_f64: v_mfma_f64_16x16x4f64, FP64 accumulation, A either FP64 or
 //     FP32 widened exactly (FP32 values are FP64 numbers), so for the FP32
 //     far matrix it is the exact FP64-accumulated product of the mixed
-//     operator.  A wave owns 16 rows x 64 columns over a quarter of K.
+//     operator.  A block owns 64 rows x 64 columns over one of 8 K ranges,
+//     the K range fixed per XCD (see the kernel).
+//  k_rows_part: a few FP64 rows (constraint rows of floating bodies) times
+//     the vectors, K split over hundreds of blocks.
 // Operand k-order: lane (r, h) of a 32-lane half feeds A[row r][k0 + 16h + s]
 // and Z[col][k0 + 16h + s] at step s; any order of k that is the same for both
 // operands gives the same sum.
@@ -26,8 +29,6 @@ namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef double d4v __attribute__((ext_vector_type(4)));
-
-constexpr int GM_WAVES = 4;   // K split over the waves of a block
 
 // FP32 product, LDS-staged: a block owns 128 rows (32 per wave) x 64 columns over
 // one K range (blockIdx.y); per step it stages a 128 x 32 tile of A and a
@@ -127,60 +128,127 @@ __global__ __launch_bounds__(256) void k_gemm_f32_sum(const float* __restrict__ 
     *y = accumulate ? *y + s : s;
 }
 
+// FP64-accumulated product on v_mfma_f64_16x16x4f64.  A block owns 64 rows (16 per wave) x 64
+// columns over one of GD_KS ranges of K.  Workgroups are dealt to the 8 XCDs round-robin, so with
+// the K range taken as blockIdx % GD_KS every block of one XCD works one K range: that range's
+// slice of Z (64 x K/8 doubles, 1.3 MB at 20k unknowns) stays in the XCD's L2 for all row blocks,
+// while each A entry is read from HBM once.  Per 16-wide k step a lane holds 4 consecutive k of
+// its A row and of 4 Z columns, and the wave runs 16 MFMAs; the next step's operands are loaded
+// before this step's MFMAs are issued.  The 64 x 64 partial tile is transposed through LDS and
+// leaves as column segments of 64 rows; k_gemm_f64_sum adds the K ranges in order.
+constexpr int GD_ROWS = 64, GD_KS = 8;
+
 template <typename TA>
-__global__ __launch_bounds__(64 * GM_WAVES) void k_gemm_f64(const TA* __restrict__ A, int64_t lda, int64_t M,
-                                                            int64_t K, const double* __restrict__ Zt, int64_t ldz,
-                                                            int ncols, double* __restrict__ Y, int64_t ldy,
-                                                            int accumulate, double alpha) {
-    __shared__ double part[GM_WAVES][64][17];
+__device__ __forceinline__ void gd_load(const TA* __restrict__ Ap, const double* __restrict__ Zt, int64_t ldz, int r,
+                                        int64_t k, double a[4], double b[4][4]) {
+    if (sizeof(TA) == 4) {
+        const f4v av = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k));
+        a[0] = av[0]; a[1] = av[1]; a[2] = av[2]; a[3] = av[3];
+    } else {
+        const d2v a0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k));
+        const d2v a1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k) + 1);
+        a[0] = a0[0]; a[1] = a0[1]; a[2] = a1[0]; a[3] = a1[1];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double* zp = Zt + (int64_t)(16 * c + r) * ldz + k;
+        const d2v z0 = reinterpret_cast<const d2v*>(zp)[0];
+        const d2v z1 = reinterpret_cast<const d2v*>(zp)[1];
+        b[c][0] = z0[0]; b[c][1] = z0[1]; b[c][2] = z1[0]; b[c][3] = z1[1];
+    }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gemm_f64(const TA* __restrict__ A, int64_t lda, int64_t M, int64_t K,
+                                                  const double* __restrict__ Zt, int64_t ldz, int64_t kb_per, int KS,
+                                                  double* __restrict__ Ypart) {
+    __shared__ double tile[64][GD_ROWS + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int r = lane & 15, q4 = lane >> 4;   // row (A) / column (B) within 16, k group 0..3
-    const int64_t row0 = (int64_t)blockIdx.x * 16;
-    const int64_t arow = row0 + r < M ? row0 + r : M - 1;
+    const int r = lane & 15, q4 = lane >> 4;   // row (A) / column (Z) within 16, k group 0..3
+    const int64_t ks = blockIdx.x % KS, rb = blockIdx.x / KS;
+    const int64_t row0 = rb * GD_ROWS;
+    const int64_t arow = row0 + 16 * wv + r < M ? row0 + 16 * wv + r : M - 1;   // rows past M: read, not stored
     const TA* __restrict__ Ap = A + arow * lda;
     const int64_t kblocks = K / 16;
-    const int64_t kb0 = kblocks * wv / GM_WAVES, kb1 = kblocks * (wv + 1) / GM_WAVES;
+    const int64_t kb0 = ks * kb_per, kb1 = kb0 + kb_per < kblocks ? kb0 + kb_per : kblocks;
     d4v acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = (d4v){0.0, 0.0, 0.0, 0.0};
+    double a[4], b[4][4], an[4], bn[4][4];
+    if (kb0 < kb1) gd_load(Ap, Zt, ldz, r, kb0 * 16 + 4 * q4, a, b);
     for (int64_t kb = kb0; kb < kb1; ++kb) {
-        const int64_t k = kb * 16 + 4 * q4;   // this lane's 4 consecutive k
-        double a[4];
-        if (sizeof(TA) == 4) {
-            const f4v av = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k));
-            a[0] = av[0]; a[1] = av[1]; a[2] = av[2]; a[3] = av[3];
-        } else {
-            const d2v a0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k));
-            const d2v a1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k) + 1);
-            a[0] = a0[0]; a[1] = a0[1]; a[2] = a1[0]; a[3] = a1[1];
-        }
-        double b[4][4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double* zp = Zt + (int64_t)(16 * c + r) * ldz + k;
-            const d2v z0 = reinterpret_cast<const d2v*>(zp)[0];
-            const d2v z1 = reinterpret_cast<const d2v*>(zp)[1];
-            b[c][0] = z0[0]; b[c][1] = z0[1]; b[c][2] = z1[0]; b[c][3] = z1[1];
-        }
+        if (kb + 1 < kb1) gd_load(Ap, Zt, ldz, r, (kb + 1) * 16 + 4 * q4, an, bn);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[c][s], acc[c], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            a[s] = an[s];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c][s] = bn[c][s];
+        }
     }
-    // accumulator element v of lane (r, q4): row 4 v + q4, column r (+16 c)
+    // accumulator element v of lane (r, q4): row 4 v + q4 (+16 wv), column r (+16 c)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) part[wv][16 * c + r][4 * v + q4] = acc[c][v];
+        for (int v = 0; v < 4; ++v) tile[16 * c + r][16 * wv + 4 * v + q4] = acc[c][v];
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 16; e += 64 * GM_WAVES) {
-        const int col = e >> 4, row = e & 15;
+    double* out = Ypart + ks * 64 * M;
+    for (int e = threadIdx.x; e < 64 * GD_ROWS; e += 256) {
+        const int col = e / GD_ROWS, row = e % GD_ROWS;
         const int64_t i = row0 + row;
-        if (i >= M || col >= ncols) continue;
-        const double s = alpha * (((part[0][col][row] + part[1][col][row]) + part[2][col][row]) + part[3][col][row]);
-        double* y = Y + (int64_t)col * ldy + i;
-        *y = accumulate ? *y + s : s;
+        if (i < M) out[(int64_t)col * M + i] = tile[col][row];
     }
+}
+
+// Y[col][i] (+)= alpha * sum over the K ranges of Ypart[ks][col][i], in K-range order
+__global__ __launch_bounds__(256) void k_gemm_f64_sum(const double* __restrict__ Ypart, int KS, int64_t M, int ncols,
+                                                      double* __restrict__ Y, int64_t ldy, int accumulate,
+                                                      double alpha) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int col = blockIdx.y;
+    if (i >= M || col >= ncols) return;
+    double s = 0.0;
+    for (int k = 0; k < KS; ++k) s += Ypart[((int64_t)k * 64 + col) * M + i];
+    s *= alpha;
+    double* y = Y + (int64_t)col * ldy + i;
+    *y = accumulate ? *y + s : s;
+}
+
+// A few FP64 rows (the floating bodies' constraint rows) times up to 64 vectors, K split over
+// many blocks: block b sums its K slice for every (row, column), Zn[k][col] vector-interleaved so
+// a wave reads 64 consecutive doubles per k; the 4 waves take every 4th k and are added in a fixed
+// order.  part[b][m][col].
+__global__ __launch_bounds__(256) void k_rows_part(const double* __restrict__ A, int64_t lda, int M, int64_t K,
+                                                   const double* __restrict__ Zn, int64_t kper,
+                                                   double* __restrict__ part) {
+    __shared__ double red[4][64];
+    const int col = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t k0 = (int64_t)blockIdx.x * kper;
+    const int64_t k1 = k0 + kper < K ? k0 + kper : K;
+    for (int m = 0; m < M; ++m) {
+        const double* a = A + (int64_t)m * lda;
+        double s = 0.0;
+        for (int64_t k = k0 + q; k < k1; k += 4) s = fma(a[k], Zn[k * 64 + col], s);
+        red[q][col] = s;
+        __syncthreads();
+        if (q == 0) part[((int64_t)blockIdx.x * M + m) * 64 + col] = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
+        __syncthreads();
+    }
+}
+
+// Y[col][m] (+)= alpha * sum_b part[b][m][col], blocks in order
+__global__ __launch_bounds__(64) void k_rows_sum(const double* __restrict__ part, int G, int M, int ncols,
+                                                 double* __restrict__ Y, int64_t ldy, int accumulate, double alpha) {
+    const int col = threadIdx.x, m = blockIdx.x;
+    if (col >= ncols) return;
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) s += part[((int64_t)b * M + m) * 64 + col];
+    s *= alpha;
+    double* y = Y + (int64_t)col * ldy + m;
+    *y = accumulate ? *y + s : s;
 }
 
 }  // namespace
@@ -211,12 +279,44 @@ void launch_gemm_f64(bem_ctx* c, const void* A, bool a_is_f32, int64_t lda, int6
     if (M <= 0) return;
     if (K % 16 != 0 || ldz % 2 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f64 shape not padded");
     KTimer t(c, "gemm_f64");
+    const int64_t rb = ceil_div(M, GD_ROWS);
+    const int64_t kblocks = K / 16;
+    int64_t KS = std::min<int64_t>(GD_KS, kblocks);
+    const int64_t kb_per = ceil_div(kblocks, KS);
+    KS = ceil_div(kblocks, kb_per);
+    if (rb * KS > ((int64_t)1 << 31) - 1) throw Error(BEM_ERR_INVALID, "gemm_f64 grid too large");
+    c->gemm_part.alloc(sizeof(double) * (size_t)KS * 64 * M);
+    double* part = c->gemm_part.as<double>();
+    const dim3 grid((unsigned)(rb * KS));
     if (a_is_f32)
-        hipLaunchKernelGGL((k_gemm_f64<float>), dim3((unsigned)ceil_div(M, 16)), dim3(64 * GM_WAVES), 0, c->stream,
-                           (const float*)A, lda, M, K, Zt, ldz, ncols, Y, ldy, (int)accumulate, alpha);
+        hipLaunchKernelGGL((k_gemm_f64<float>), grid, dim3(256), 0, c->stream, (const float*)A, lda, M, K, Zt, ldz,
+                           kb_per, (int)KS, part);
     else
-        hipLaunchKernelGGL((k_gemm_f64<double>), dim3((unsigned)ceil_div(M, 16)), dim3(64 * GM_WAVES), 0, c->stream,
-                           (const double*)A, lda, M, K, Zt, ldz, ncols, Y, ldy, (int)accumulate, alpha);
+        hipLaunchKernelGGL((k_gemm_f64<double>), grid, dim3(256), 0, c->stream, (const double*)A, lda, M, K, Zt, ldz,
+                           kb_per, (int)KS, part);
+    BEM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_gemm_f64_sum, dim3((unsigned)ceil_div(M, 256), (unsigned)ncols), dim3(256), 0, c->stream,
+                       part, (int)KS, M, ncols, Y, ldy, (int)accumulate, alpha);
+    BEM_CHECK_LAUNCH();
+}
+
+// Y[c][0..M) (+)= alpha A[0..M)[0..K) Zn[.][c] for a few FP64 rows, Zn[k][64] vector-interleaved (each
+// row re-reads Zn, so this suits the handful of constraint rows, not a matrix).
+void launch_gemm_rows(bem_ctx* c, const double* A, int64_t lda, int64_t M, int64_t K, const double* Zn, int ncols,
+                      double* Y, int64_t ldy, bool accumulate, double alpha) {
+    if (M <= 0) return;
+    if (M > 65535) throw Error(BEM_ERR_INVALID, "gemm_rows: too many rows");
+    KTimer t(c, "gemm_rows");
+    // about 64 k per block and at most 512 blocks
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(K, 64)));
+    const int64_t kper = ceil_div(K, G);
+    const int64_t Gn = ceil_div(K, kper);
+    c->rows_part.alloc(sizeof(double) * (size_t)Gn * M * 64);
+    hipLaunchKernelGGL(k_rows_part, dim3((unsigned)Gn), dim3(256), 0, c->stream, A, lda, (int)M, K, Zn, kper,
+                       c->rows_part.as<double>());
+    BEM_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)M), dim3(64), 0, c->stream, c->rows_part.as<double>(), (int)Gn,
+                       (int)M, ncols, Y, ldy, (int)accumulate, alpha);
     BEM_CHECK_LAUNCH();
 }
 

@@ -108,7 +108,29 @@ __global__ __launch_bounds__(256) void k_geometry(const double* __restrict__ ver
     T[TR_A] = area;
 }
 
+// One lane per point: the point of panel j = panel[l] with barycentric coordinates bary[l] (over
+// the panel's vertices in their stored order), lifted by `offset` along the panel's unit normal.
+__global__ __launch_bounds__(256) void k_panel_points(int64_t L, const int32_t* __restrict__ panel,
+                                                      const double* __restrict__ bary, double offset,
+                                                      const double* __restrict__ tri64, double* __restrict__ out) {
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l >= L) return;
+    const double* T = tri64 + (int64_t)TRI_REC * panel[l];
+    const double b0 = bary[3 * l], b1 = bary[3 * l + 1], b2 = bary[3 * l + 2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        out[3 * l + k] = b0 * T[TR_V + k] + b1 * T[TR_V + 3 + k] + b2 * T[TR_V + 6 + k] + offset * T[TR_N + k];
+}
+
 }  // namespace
+
+void launch_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const double* bary, double offset,
+                         double* out) {
+    if (L == 0) return;
+    hipLaunchKernelGGL(k_panel_points, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, panel, bary,
+                       offset, c->tri64.as<double>(), out);
+    BEM_CHECK_LAUNCH();
+}
 
 void launch_geometry(bem_ctx* c) {
     KTimer t(c, "geometry");

@@ -6,7 +6,7 @@
 // FP64 mode: the product uses the FP64 matrix on the FP64 matrix cores.
 // Mixed mode: the inner product is the FP32 matrix (far entries and the FP32
 // heads of the near entries) on the FP32 matrix cores, FP32 operands and
-// accumulation, plus the FP64 constraint rows; an outer FP64 iterative
+// accumulation, plus the FP64 constraint rows (a K-split row product); an outer FP64 iterative
 // refinement recomputes the residual with the exact FP64-accumulated product
 // of the mixed operator (FP32 matrix widened + FP64 near remainders), so the
 // FP32 rounding of the inner products does not limit the final residual.
@@ -27,6 +27,8 @@ void launch_gemm_f32(bem_ctx* c, const float* A, int64_t lda, int64_t M, int64_t
                      int ncols, double* Y, int64_t ldy, bool accumulate);
 void launch_gemm_f64(bem_ctx* c, const void* A, bool a_is_f32, int64_t lda, int64_t M, int64_t K, const double* Zt,
                      int64_t ldz, int ncols, double* Y, int64_t ldy, bool accumulate, double alpha);
+void launch_gemm_rows(bem_ctx* c, const double* A, int64_t lda, int64_t M, int64_t K, const double* Zn, int ncols,
+                      double* Y, int64_t ldy, bool accumulate, double alpha);
 
 namespace {
 
@@ -177,13 +179,13 @@ void apply(BW& w, const double* src, int64_t sstride, const double* d, bool exac
         BEM_CHECK_LAUNCH();
     }
     if (w.n > w.N) {
-        // constraint rows (FP64) need the FP64 vectors
+        // constraint rows (FP64, a few) need the FP64 vectors, vector-interleaved for the K-split row product
         if (f32) {
             hipLaunchKernelGGL(k_b_prep, dim3((unsigned)ceil_div(w.ld, 256), BR), dim3(256), 0, w.s, src, sstride,
-                               w.nr, w.n, w.ld, d, (float*)nullptr, w.zt64, (double*)nullptr);
+                               w.nr, w.n, w.ld, d, (float*)nullptr, (double*)nullptr, w.zn64);
             BEM_CHECK_LAUNCH();
         }
-        launch_gemm_f64(c, c->A64.p, false, w.ld, w.n - w.N, w.ld, w.zt64, w.ld, w.nr, w.W + w.N, w.ld, false, 1.0);
+        launch_gemm_rows(c, c->A64.as<double>(), w.ld, w.n - w.N, w.ld, w.zn64, w.nr, w.W + w.N, w.ld, false, 1.0);
     }
 }
 

@@ -30,6 +30,8 @@
 #include "bem_device.h"
 #include "nodal_device.h"
 
+#include <hip/hip_ext.h>
+
 namespace bem {
 namespace {
 
@@ -802,10 +804,12 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         }
     } join{c, G > 1};
     unsigned long long* near_count = reinterpret_cast<unsigned long long*>(c->counters.p);
-    const bool fp64 = c->opt.precision == BEM_FP64;
     // nodal basis (one load case): the far passes read records whose node weights carry the
-    // density, with a density of one per panel; the step kernel's near pairs read the vertex values
+    // density, with a density of one per panel; the step kernel's near pairs read the vertex values.
+    // Those records exist in FP64 only, so nodal lines take the FP64 far passes in either
+    // precision (the FP32 records and the few-line FP32 pass are laid out for the constant basis)
     const bool nodal = c->opt.basis == BEM_BASIS_LINEAR;
+    const bool fp64 = c->opt.precision == BEM_FP64 || nodal;
     if (nodal) launch_nodal_records(c, sol);
     const double* P64 = nodal ? c->nod_pan64.as<double>() : c->pan64.as<double>();
     const double* F64 = nodal ? c->nod_far64.as<double>() : c->far64.as<double>();
@@ -816,11 +820,14 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     int32_t* host = c->host_stage.as<int32_t>();
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
-        // every 16th pass is timed (the event records would otherwise cost more than the short
-        // launches); with two live groups that pass runs its launches one after another, so the
-        // timed far launches measure the kernel alone rather than its overlap with the other group
+        // Profiling: the far pass is timed at every launch by events carried in its dispatch
+        // (hipExtLaunchKernelGGL), which add no work to the stream; the step kernel (profiling
+        // mode 1) by event pairs around every 16th pass, which would otherwise cost more than the
+        // short launches.  With two live groups a pass timed in mode 1 runs its launches one
+        // after another, so the timed launches measure each kernel alone rather than its overlap
+        // with the other group.
         const bool timed = (pass & 15) == 0;
-        const bool serial = timed && G > 1 && grp[0].known > 0 && grp[1].known > 0;
+        const bool serial = c->profiling == 1 && timed && G > 1 && grp[0].known > 0 && grp[1].known > 0;
         for (int32_t g = 0; g < G; ++g) {
             Group& q = grp[g];
             if (q.known == 0) continue;
@@ -835,16 +842,19 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             const bool split = q.known <= c->tune_trace_split;
             int64_t KSP = KS;   // partial rows the step kernel sums
             {
-            KTimer tf(c, "trace_far", !few && timed, q.st);
+            hipEvent_t fa = nullptr, fb = nullptr;   // dispatch timestamps of a chunked far pass
+            const bool tfar = c->profiling != 0 && !few;
+            if (tfar) timing_events(c, &fa, &fb);
             // blocks of tiles past the live count would only launch and exit: size the grids by
             // the last known live count (an upper bound, the count only falls)
             const int tile = split ? 64 : c->tune_trace_tile;
             const int splitk = c->tune_trace_splitk;
             const int32_t ntile = (int32_t)ceil_div(q.known, tile);
             dim3 g1((unsigned)(ntile * ceil_div(KS, 8) * 8));
-#define BEM_LB_FAR(R, SP, TL, FR)                                                                            \
-    hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, P64, FR, N, fsol, fn, \
-                       line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask, ntile, KS)
+#define BEM_LB_FAR(R, SP, TL, FR)                                                                              \
+    hipExtLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, fa, fb, 0, P64, FR, N, \
+                          fsol, fn, line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask,     \
+                          ntile, KS)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -876,6 +886,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
 #undef BEM_LB_FAR_ALL
 #undef BEM_LB_FAR
             BEM_CHECK_LAUNCH();
+            if (tfar) push_timing(c, "trace_far", fa, fb);
             if (!few) ++c->trace_far_launches;
             }
             {

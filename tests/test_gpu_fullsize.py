@@ -1,8 +1,15 @@
 """Parity at the benchmark's full size (coax, ~20k panels, 256 field lines),
-in the launch configuration the benchmark times, on outputs the oracle can
+in the launch configurations the benchmark times, on outputs the oracle can
 compute one by one: sampled matrix rows, the residual of the GPU solution
 against sampled oracle rows, the field at sampled points, and sampled lines
-of the 256-line launch."""
+of the 256-line launch.
+
+The benchmark picks its tile shapes with the autotuner (timing, so the pick
+can differ between runs and boxes).  The field lines are therefore checked
+under the autotuner's pick on this machine, under the pick of the recorded
+benchmark run (4 waves per chunk up to 256 live lines, 128-line tiles above),
+and under the library defaults.  Also sampled: lines of the 4096-line run of
+64 load cases (64 lines per case) in one call."""
 
 import sys
 
@@ -10,10 +17,13 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import coax_problem_for_size, electrode_line_starts, gap_eval_points
+from workloads import coax_problem_for_size, electrode_line_starts, gap_eval_points, rod_load_cases
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+
+TUNE_KEYS = ("far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile", "trace_splitk", "trace_split",
+             "trace_few", "trace_groups")
 
 
 def _say(msg):
@@ -69,6 +79,7 @@ def test_sampled_field(setup):
     Eg = E[0].cpu().numpy()[idx]
     assert np.abs(np.linalg.norm(Eg, axis=1) - np.linalg.norm(E_o, axis=1)).max() <= \
         1e-10 * np.linalg.norm(E_o, axis=1).max()
+    assert np.abs(Eg - E_o).max() <= 1e-10 * np.abs(E_o).max()
     # surface field at sampled centroids (exterior limit), as the benchmark computes it for all
     N = p.n_tri
     cen = p.vert[p.tri].mean(axis=1)
@@ -79,17 +90,62 @@ def test_sampled_field(setup):
     assert np.abs(Es[0].cpu().numpy()[sel] - Es_o).max() <= 1e-10 * np.abs(Es_o).max()
 
 
+def _pick(ns, st, extra):
+    """The shortest line of each stop kind plus fixed ones (oracle cost grows with length)."""
+    pick = {int(np.argmin(np.where(st == k, ns, 10 ** 9))) for k in np.unique(st)} | set(extra)
+    return np.array(sorted(pick))
+
+
 def test_sampled_lines_of_full_launch(setup):
     bem, p, c, o, sol, info = setup
     x = sol[0].cpu().numpy()
     starts, _, _ = electrode_line_starts(p, 256, seed=2)
     tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-3)
-    I, ns, st, _ = c.streamer_integral(sol, starts, tp)
+    defaults = {k: c.get_tuning(k) for k in TUNE_KEYS}
+    c.autotune(None)                                   # the benchmark's procedure
+    tuned = {k: c.get_tuning(k) for k in TUNE_KEYS}
+    _say(f"autotuner pick {tuned}")
+    configs = [("autotuned", tuned),
+               ("recorded_bench", {**defaults, "trace_splitk": 4, "trace_split": 256, "trace_tile": 128}),
+               ("defaults", defaults)]
+    ref = None
+    for name, cfg in configs:
+        for k, v in cfg.items():
+            c.set_tuning(k, v)
+        I, ns, st, _ = c.streamer_integral(sol, starts, tp)
+        I, ns, st = I.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
+        if ref is None:
+            pick = _pick(ns, st, (0, 17))
+            _say(f"oracle lines {pick.tolist()} steps {ns[pick].tolist()}")
+            ref = o.trace(x, starts[pick], oracle.trace_params(h=1e-4, max_steps=2000, e_min=1e-3))
+        nso, sto, Io = ref
+        assert np.array_equal(ns[pick], nso) and np.array_equal(st[pick], sto), name
+        assert np.abs(I[pick] - Io).max() <= 1e-10 * max(np.abs(Io).max(), 1e-300), name
+        _say(f"{name}: {len(pick)} oracle lines equal, integral sum {I.sum():.12e}")
+    for k, v in defaults.items():
+        c.set_tuning(k, v)
+
+
+def test_sampled_lines_of_4096_line_run(setup):
+    """64 load cases (rod U[0.5, 2], seed 4) solved together, 64 lines per case (seed 5) in one
+    call with line_rhs, as the benchmark runs them; lines sampled from several cases against
+    the oracle driven by that case's GPU solution."""
+    bem, p, c, o, sol, info = setup
+    bv = rod_load_cases(p, 64, seed=4)
+    S, sinfo = c.solve(bv, tol=1e-10, max_iter=20000)
+    assert sinfo["converged"]
+    starts, _, _ = electrode_line_starts(p, 4096, seed=5)
+    lr = np.repeat(np.arange(64, dtype=np.int32), 64)
+    tp = bem.trace_params(h=1e-4, max_steps=2000, e_min=1e-3)
+    I, ns, st, _ = c.streamer_integral(S, starts, tp, line_rhs=lr)
     I, ns, st = I.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
-    # the shortest line of each stop kind plus two fixed ones (oracle cost grows with length)
-    pick = {int(np.argmin(np.where(st == k, ns, 10 ** 9))) for k in np.unique(st)} | {0, 17}
-    pick = np.array(sorted(pick))
-    _say(f"oracle lines {pick.tolist()} steps {ns[pick].tolist()}")
-    nso, sto, Io = o.trace(x, starts[pick], oracle.trace_params(h=1e-4, max_steps=2000, e_min=1e-3))
-    assert np.array_equal(ns[pick], nso) and np.array_equal(st[pick], sto)
-    assert np.abs(I[pick] - Io).max() <= 1e-10 * max(np.abs(Io).max(), 1e-300)
+    # plus the shortest line of three spread load cases
+    extra = [64 * r + int(np.argmin(ns[64 * r:64 * r + 64])) for r in (0, 37, 63)]
+    pick = _pick(ns, st, extra)
+    _say(f"4096 lines: stop codes {np.bincount(st, minlength=6).tolist()}; oracle lines {pick.tolist()} "
+         f"(cases {lr[pick].tolist()}) steps {ns[pick].tolist()}")
+    Sh = S.cpu().numpy()
+    for l in pick:
+        nso, sto, Io = o.trace(Sh[lr[l]], starts[l:l + 1], oracle.trace_params(h=1e-4, max_steps=2000, e_min=1e-3))
+        assert ns[l] == nso[0] and st[l] == sto[0], l
+        assert abs(I[l] - Io[0]) <= 1e-10 * max(abs(Io[0]), 1e-300), l

@@ -245,6 +245,46 @@ def test_nodal_mixed_precision(bem, name, make):
     c32.close()
 
 
+def test_nodal_mixed_field_lines(bem):
+    """Field lines of the nodal density in a MIXED context.  The nodal far-field records
+    exist in FP64 only, so the line passes are the FP64 ones in either precision: driven
+    by the same vertex values, a MIXED context's lines equal an FP64 context's bit for
+    bit, one load case and the few-line tail included.  Driven by the MIXED solution
+    (within 1e-5 of FP64), stop codes and step counts match the FP64 run's and the
+    integrals agree to 1e-4 (the density error, amplified by alpha's slope)."""
+    from workloads import electrode_line_starts
+    p = coax_conductors_problem(0.012, V0=40.0)
+    c64 = _ctx(bem, p)
+    c32 = bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=1, precision=bem.MIXED)
+    c32.assemble()
+    starts, _, _ = electrode_line_starts(p, 24, seed=4)
+    kw = dict(h=2e-3, max_steps=300, e_min=1e-3, alpha_a=1e-3, alpha_e0=25.0, alpha_p=2.0)
+    tp = bem.trace_params(**kw)
+    s64, _ = c64.solve(p.body_V, tol=1e-12, max_iter=5000)
+    s32, _ = c32.solve(p.body_V, tol=1e-8, max_iter=5000)
+    I64, ns64, st64, _ = c64.streamer_integral(s64, starts, tp)
+    I32, ns32, st32, _ = c32.streamer_integral(s64, starts, tp)
+    assert np.array_equal(I32.cpu().numpy(), I64.cpu().numpy())
+    assert np.array_equal(ns32.cpu().numpy(), ns64.cpu().numpy())
+    assert np.array_equal(st32.cpu().numpy(), st64.cpu().numpy())
+    Im, nsm, stm, _ = c32.streamer_integral(s32, starts, tp)
+    assert np.array_equal(stm.cpu().numpy(), st64.cpu().numpy())
+    nsm, ns64h = nsm.cpu().numpy(), ns64.cpu().numpy()
+    assert np.abs(nsm - ns64h).max() <= 1
+    same = nsm == ns64h           # a hit can move by one step; compare integrals where it did not
+    assert same.sum() >= len(same) - 2
+    e = rel(Im.cpu().numpy()[same], I64.cpu().numpy()[same])
+    print(f"[nodal] mixed lines: integral error vs FP64 {e:.2e}", flush=True)
+    assert e <= 1e-4
+    # the same lines against the oracle's nodal trace of the FP64 vertex values
+    o = oracle.Oracle(p)
+    ns_o, st_o, I_o = o.p1_trace(s64[0].cpu().numpy(), starts, oracle.trace_params(**kw))
+    assert np.array_equal(ns32.cpu().numpy(), ns_o) and np.array_equal(st32.cpu().numpy(), st_o)
+    assert np.abs(I32.cpu().numpy() - I_o).max() <= 1e-10 * np.abs(I_o).max()
+    c64.close()
+    c32.close()
+
+
 def test_nodal_mixed_232k_sampled_rows(bem):
     """The coaxial conductors at 233,519 vertices (the paper's 232,029-node case) in
     MIXED storage, 218 GB of FP32 rows on one GPU.  Checked: sampled rows within 2.4e-7

@@ -171,6 +171,7 @@ def test_coax_field_parity(bem):
     phi_o, E_o = o.eval(x, pts)
     phi, E = c.eval_field(torch.tensor(x, device="cuda"), pts)
     assert rel(np.linalg.norm(E[0].cpu().numpy(), axis=1), np.linalg.norm(E_o, axis=1)) <= 1e-10
+    assert rel(E[0].cpu().numpy(), E_o) <= 1e-10          # the vector, component by component
     assert rel(phi[0].cpu().numpy(), phi_o) <= 1e-10
     c.close()
 
@@ -218,6 +219,49 @@ def test_coax_trace_stop_codes(bem, mode):
     I, ns, st = _trace_compare(bem, c, o, x, starts, dict(h=1e-3, max_steps=200))
     assert set(st.tolist()) - {0, 1, 2, 3} == set()
     assert (st != 0).any()
+    c.close()
+
+
+_LAYOUT_REF = {}
+
+
+@pytest.mark.parametrize("layout", [
+    dict(trace_splitk=2, trace_split=4096, trace_few=0),    # every pass split over 2, 4 or 8 waves
+    dict(trace_splitk=4, trace_split=4096, trace_few=0),
+    dict(trace_splitk=8, trace_split=4096, trace_few=0),
+    dict(trace_tile=64, trace_split=0, trace_few=0),        # every pass unsplit, 64/128/256-line tiles
+    dict(trace_tile=128, trace_split=0, trace_few=0),
+    dict(trace_tile=256, trace_split=0, trace_few=0),
+    dict(trace_splitk=4, trace_split=256, trace_tile=128, trace_few=8),   # split, then few-line tail
+], ids=["split2", "split4", "split8", "tile64", "tile128", "tile256", "split4_few8"])
+def test_trace_layouts(bem, layout):
+    """Every tile shape of the batched far pass (the split kernels at 2, 4 and 8 waves per
+    chunk, the unsplit ones at 64, 128 and 256 lines per block, the few-line tail) against
+    the oracle on 16 coax lines (seed 21) that end on the shell or the ring or run out of
+    steps: step counts and stop codes exact, integrals and paths 1e-10 / 1e-9."""
+    p = coax_problem(0.012)
+    _say(f"trace layout {layout}")
+    c, o, x, x_ref = _sigma_case(bem, p)
+    for k, v in layout.items():
+        c.set_tuning(k, v)
+    starts, _, _ = electrode_line_starts(p, 16, seed=21)
+    kw = dict(h=1e-3, max_steps=200)
+    sol = torch.tensor(x, device="cuda")
+    I, ns, st, _ = c.streamer_integral(sol, starts, bem.trace_params(**kw))
+    ns2, st2, path = c.trace_lines(sol, starts, bem.trace_params(**kw), want_path=True)
+    I, ns, st, path = I.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy(), path.cpu().numpy()
+    assert np.array_equal(ns, ns2.cpu().numpy()) and np.array_equal(st, st2.cpu().numpy())
+    key = x.tobytes()
+    if key not in _LAYOUT_REF:
+        _LAYOUT_REF.clear()
+        _LAYOUT_REF[key] = o.trace(x, starts, oracle.trace_params(**kw), want_path=True)
+    nso, sto, Io, patho = _LAYOUT_REF[key]
+    assert np.array_equal(ns, nso) and np.array_equal(st, sto)
+    assert len(set(sto.tolist()) - {0}) >= 2
+    assert np.abs(I - Io).max() <= 1e-10 * np.abs(Io).max()
+    for l in range(len(starts)):
+        m = ns[l] + 1
+        assert np.abs(path[l, :m] - patho[l, :m]).max() <= 1e-9 * np.abs(patho[l, :m]).max()
     c.close()
 
 

@@ -26,4 +26,5 @@ from .seeds import (  # noqa: F401
     gap_eval_points,
     electrode_line_starts,
     rod_load_cases,
+    vertex_perturbations,
 )

@@ -76,3 +76,16 @@ def rod_load_cases(p: Problem, n: int = 64, seed: int = 4, lo: float = 0.5, hi: 
     out = np.tile(p.body_V, (n, 1)).astype(np.float64)
     out[:, driven_body] = v
     return np.ascontiguousarray(out)
+
+
+def vertex_perturbations(p: Problem, n: int = 20, seed: int = 8):
+    """n single-vertex perturbation directions of the mesh: draw k = 0, 1, ...: a vertex index
+    ~ U{0..n_vert-1}, then a direction N(0, I_3) normalised, one after the other.  Yields
+    (vertex, unit direction) pairs without end; a consumer that must skip a draw (its
+    classification or step counts change under the perturbation) takes the next one, so the
+    sequence stays deterministic.  Returned as a generator."""
+    rng = np.random.default_rng(seed)
+    while True:
+        v = int(rng.integers(0, p.n_vert))
+        d = rng.standard_normal(3)
+        yield v, d / np.linalg.norm(d)
