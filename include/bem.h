@@ -175,6 +175,18 @@ bem_status bem_rhs(bem_ctx* ctx, int32_t nrhs, const double* body_V, double* b);
  * matrix cores with FP64 accumulation (MIXED: the FP32 far entries widened). */
 bem_status bem_matvec(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, int32_t transpose);
 
+/* The product of bem_matvec without any device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results: each vector goes through the one-vector kernels of bem_matvec (the
+ * batched matrix-core product is not used, so with nrhs >= 2 and "batched_solve" on the sums
+ * differ from bem_matvec's by rounding only).  Its work memory is a fixed device array of
+ * 66 x 65536 doubles (33 MiB) that the library holds on every GPU it runs on until the process
+ * ends: n (bem_n_unknowns) must be <= 65536, else INVALID.  Every call on one GPU uses that GPU's
+ * array, so calls that overlap on one GPU (on different streams or host threads) race.  Enqueued
+ * on the context stream; x and y must not overlap.  Errors: INVALID (sizes, NULL vectors,
+ * transpose in MIXED precision), STATE (not assembled), HIP. */
+bem_status bem_matvec_noalloc(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, int32_t transpose);
+
 /* Solve A sol = b(body_V) for nrhs load cases by restarted GMRES with the
  * diagonal (Jacobi) preconditioner applied on the right (Sec. 5.2), CGS2
  * orthogonalisation, zero initial guess, stopping at ||b - A x|| <= tol ||b||

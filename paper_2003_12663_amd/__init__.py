@@ -122,6 +122,12 @@ class Context:
         _check(self.lib.bem_matvec(self._ctx, x2.shape[0], _dev_ptr(x2), _dev_ptr(y), int(bool(transpose))), self.lib)
         return y.reshape(x.shape)
 
+    def matvec_noalloc(self, x, y, transpose=False):
+        """bem_matvec_noalloc: y = A x (or A^T x) into the caller's y, with no device allocation."""
+        _check(self.lib.bem_matvec_noalloc(self._ctx, x.reshape(-1, self.n).shape[0], _dev_ptr(x), _dev_ptr(y),
+                                           int(bool(transpose))), self.lib)
+        return y
+
     def solve(self, body_V, tol=1e-10, max_iter=10000, raise_on_noconv=True):
         """Returns (sol [nrhs, n] float64 on the GPU, info dict)."""
         torch = _torch()

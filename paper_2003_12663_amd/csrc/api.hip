@@ -264,6 +264,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     BEM_HIP(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         throw bem::Error(BEM_ERR_HIP, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+    bem::noalloc_scratch_init(dev);   // bem_matvec_noalloc's work array on this device
     std::unique_ptr<bem_ctx> c(new bem_ctx());
     c->device = dev;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -595,6 +596,17 @@ bem_status bem_matvec(bem_ctx* c, int32_t nrhs, const double* x, double* y, int3
             bem::launch_matvec(c, xa, ya, c->stream);
         BEM_HIP(hipMemcpyAsync(y + (int64_t)r * c->n, ya, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
     }
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_matvec_noalloc(bem_ctx* c, int32_t nrhs, const double* x, double* y, int32_t transpose) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (nrhs < 1 || !x || !y) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL vectors required");
+    if (transpose != 0 && transpose != 1) throw bem::Error(BEM_ERR_INVALID, "transpose must be 0 or 1");
+    bem::matvec_noalloc(c, nrhs, x, y, transpose);
     return BEM_OK;
     API_CATCH
 }

@@ -227,6 +227,10 @@ void launch_nodal_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, 
                         double* E);                                                  // nodal.hip
 void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      // gemv.hip
 void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s);    // gemv.hip
+// the product without allocation: its work array's device address for the current device (looked
+// up once per device), and the product through that array (gemv.hip)
+void noalloc_scratch_init(int device);
+void matvec_noalloc(bem_ctx* c, int32_t nrhs, const double* x, double* y, int transpose);
 int gmres_solve(bem_ctx* c, const double* b, double* x, double tol, int max_iter, int* iters, double* relres,
                 int* refinements);
 int gmres_solve_batched(bem_ctx* c, int nr, const double* B, double* X, double tol, int max_iter, int* iters,

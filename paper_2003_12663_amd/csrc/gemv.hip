@@ -12,6 +12,9 @@
 // are summed by a second kernel in a fixed order (deterministic).
 #include "bem_device.h"
 
+#include <mutex>
+#include <string>
+
 namespace bem {
 namespace {
 
@@ -199,20 +202,88 @@ void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s) {
     }
 }
 
-// y = A^T x (FP64 mode: the stored matrix; mixed mode: FP64 copy is not kept,
-// so the transpose is formed from the mixed operator row by row)
-void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s) {
-    KTimer t(c, "gemvT");
+// y = A^T x with the slab partials in part (GT_SLABS x n doubles, every entry written before it is
+// read).  FP64 mode only: the mixed mode keeps no FP64 copy of the far entries.
+void matvec_t_into(bem_ctx* c, const double* x, double* y, double* part, hipStream_t s) {
     const int64_t n = c->n;
     if (c->opt.precision != BEM_FP64) throw Error(BEM_ERR_INVALID, "transpose matvec needs precision FP64");
-    c->ev_tmp.alloc(sizeof(double) * GT_SLABS * n);
     dim3 grid((unsigned)ceil_div(ceil_div(n, 2), 256), GT_SLABS);
-    hipLaunchKernelGGL(k_gemvT64_part, grid, dim3(256), 0, s, c->A64.as<double>(), c->ld, n, n, x,
-                       c->ev_tmp.as<double>());
+    hipLaunchKernelGGL(k_gemvT64_part, grid, dim3(256), 0, s, c->A64.as<double>(), c->ld, n, n, x, part);
     BEM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_sum_slabs, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, c->ev_tmp.as<double>(), n,
-                       GT_SLABS, y);
+    hipLaunchKernelGGL(k_sum_slabs, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, n, GT_SLABS, y);
     BEM_CHECK_LAUNCH();
+}
+
+void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s) {
+    KTimer t(c, "gemvT");
+    if (c->opt.precision != BEM_FP64) throw Error(BEM_ERR_INVALID, "transpose matvec needs precision FP64");
+    c->ev_tmp.alloc(sizeof(double) * GT_SLABS * c->n);
+    matvec_t_into(c, x, y, c->ev_tmp.as<double>(), s);
+}
+
+// ---- the product without allocation ---------------------------------------------------------
+// For callers that cannot allocate device memory (code under stream capture, serving loops): the
+// staging of one vector pair and the transposed product's slab partials live in one file-scope
+// device array, 66 x 65536 doubles (33 MiB), which every GPU the library runs on holds until the
+// process ends.  Host code never passes the array's name (a host-side stand-in) to a kernel or a
+// copy: it uses the device address that hipGetSymbolAddress returns for the current device, looked
+// up once per device when a context is created.  Every call on one GPU shares that GPU's array,
+// so calls that overlap on one GPU race.
+constexpr int64_t NOALLOC_MAX_N = 65536;
+constexpr int64_t NOALLOC_DOUBLES = (2 + GT_SLABS) * NOALLOC_MAX_N;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+}  // namespace
+
+// Looks up (once per device; the device must be current) the device address of this device's
+// copy of the array.
+void noalloc_scratch_init(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEV) throw Error(BEM_ERR_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        throw Error(BEM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+}
+
+// y[r] = A x[r] (transpose 0) or A^T x[r] (transpose 1) for r < nrhs, vector by vector through the
+// staging in the device array; no allocation.  Same kernels as the allocating product of one vector.
+void matvec_noalloc(bem_ctx* c, int32_t nrhs, const double* x, double* y, int transpose) {
+    const int64_t n = c->n, ld = c->ld;
+    if (n > NOALLOC_MAX_N || ld > NOALLOC_MAX_N)
+        throw Error(BEM_ERR_INVALID, "bem_matvec_noalloc: at most 65536 unknowns (the fixed work array)");
+    if (transpose && c->opt.precision != BEM_FP64)
+        throw Error(BEM_ERR_INVALID, "transpose matvec needs precision FP64");
+    if (!c->assembled) throw Error(BEM_ERR_STATE, "bem_assemble has not run");
+    double* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (c->device >= 0 && c->device < NOALLOC_MAX_DEV) base = g_scratch_ptr[c->device];
+    }
+    if (!base) throw Error(BEM_ERR_STATE, "bem_matvec_noalloc: work array of this device not set up");
+    double* xa = base;
+    double* ya = base + NOALLOC_MAX_N;
+    double* part = base + 2 * NOALLOC_MAX_N;
+    for (int32_t r = 0; r < nrhs; ++r) {
+        BEM_HIP(hipMemcpyAsync(xa, x + (int64_t)r * n, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        if (transpose) {
+            matvec_t_into(c, xa, ya, part, c->stream);
+        } else {
+            switch (c->tune_gemv_rows) {
+                case 2: matvec_rb<2>(c, xa, ya, c->stream); break;
+                case 8: matvec_rb<8>(c, xa, ya, c->stream); break;
+                case 16: matvec_rb<16>(c, xa, ya, c->stream); break;
+                default: matvec_rb<4>(c, xa, ya, c->stream); break;
+            }
+        }
+        BEM_HIP(hipMemcpyAsync(y + (int64_t)r * n, ya, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    }
 }
 
 }  // namespace bem
