@@ -64,10 +64,16 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
  *  CONSTANT: one value per flat triangle, collocated at the centroids (n = N + N_float).
  *  LINEAR:   the paper's own nodal basis: continuous piecewise-linear hats of the vertices,
  *            collocated at the vertices (Eq. Matrix; n = n_vert + N_float, unknowns
- *            [u_1..u_nvert, V_1..V_Nfl]).  Conductor and floating-conductor bodies only
- *            (interface and sheet rows need the normal at the collocation point, which a
- *            vertex of flat panels lacks); a floating body's row is its net charge
- *            (constraint_form must be 1); FP64, or MIXED with the vertex rows stored in FP32
+ *            [u_1..u_nvert, V_1..V_Nfl]).  Every body kind: conductor and floating vertex
+ *            rows are potentials at the vertex; rows that need the normal field n . E (an
+ *            interface vertex, Eq. nonconductors; a floating body's literal row, Eq. Final4,
+ *            constraint_form 0; a sheet, Eq. sheets), which a vertex of flat panels lacks,
+ *            are the hat-weighted mean of the condition over the centroids of the triangles
+ *            around the vertex (or of the body), each with its triangle's normal;
+ *            constraint_form 1 makes a closed floating body's row its net charge.  Bodies
+ *            that touch carry coincident vertices of their own (a vertex in triangles of
+ *            two bodies is refused); a vertex row meets the other body's triangles through
+ *            the coincident vertex as their vertex.  FP64, or MIXED with the vertex rows stored in FP32
  *            (each entry formed in FP64 and rounded once, as the paper stores its matrix in
  *            single precision) and the constraint rows in FP64, solved inside FP64 iterative
  *            refinement; every vertex in at least one triangle and
@@ -187,6 +193,21 @@ bem_status bem_matvec(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, in
  * transpose in MIXED precision), STATE (not assembled), HIP. */
 bem_status bem_matvec_noalloc(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, int32_t transpose);
 
+/* Single-layer potential S = (1/4pi) int 1/|x - y| dS and field F = -grad S =
+ * (1/4pi) int (x - y)/|x - y|^3 dS of unit density on panel[p] at pts[p], p < P (Sec. 4 and
+ * the field formula closing Sec. 2).  rule 0: the closed forms of the flat triangle
+ * (Wilton et al. / Graglia); a point on the panel (within 1e-14 of its size) gets the
+ * principal value (its normal component 0).  rule 1: the paper's near-singular rule of
+ * Sec. 4: the point of the panel closest to x, the panel cut into pieces with that point as
+ * a corner, the Duffy transformation of each piece and tensor Gauss-Legendre (16 x 16 nodes
+ * per cell) on cells graded geometrically towards the corner and towards its foot on the
+ * opposite edge; a point on the panel gets S, and F = NaN (the principal value is not formed
+ * by this rule).  pts dev [P][3], panel dev int32 [P] (0 <= panel < N), S dev [P], F dev
+ * [P][3] or NULL.  With tuning key "near_rule" = 1 the assembly uses rule 1 for its near and
+ * self pairs (CONSTANT basis).  Errors: INVALID (P, rule, indices, non-finite points), HIP. */
+bem_status bem_pair_integrals(bem_ctx* ctx, int64_t P, const double* pts, const int32_t* panel, int32_t rule,
+                              double* S, double* F);
+
 /* Solve A sol = b(body_V) for nrhs load cases by restarted GMRES with the
  * diagonal (Jacobi) preconditioner applied on the right (Sec. 5.2), CGS2
  * orthogonalisation, zero initial guess, stopping at ||b - A x|| <= tol ||b||
@@ -275,6 +296,10 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
  *                side matrix product per iteration on the matrix cores (FP64:
  *                FP64 cores; MIXED: FP32 cores inside FP64 iterative
  *                refinement); 0 = one right-hand side after another.
+ *  "near_rule":  0 (default) = near and self pairs of the assembly by the closed forms of
+ *                the flat triangle; 1 = by the paper's near-singular rule (closest point,
+ *                subdivision, Duffy; see bem_pair_integrals), CONSTANT basis only.  Takes
+ *                effect at the next bem_assemble; one wave per pair, so far slower than 0.
  *  Tile shapes (set by bem_autotune, or by hand):
  *  "far_rows":    collocation rows per block of the far-field assembly (32, 64, 128; default 64)
  *  "gemv_rows":   matrix rows per block of the GMRES matvec (2, 4, 8, 16; default 4 for FP64, 8 for MIXED)
@@ -286,7 +311,8 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
  *                 lane per panel, all live lines per lane; 0..16; default 8)
  *  "trace_split": live-line count at or below which a field-line pass splits each panel chunk
  *                 over eight waves (0..4096; default 64)
- *  "trace_groups": line groups of a batched field-line run (1 or 2; default 1): lines are cut
+ *  "trace_groups": line groups of a batched field-line run (1 or 2; 0, the default: 2 from 128
+ *                 lines, else 1): lines are cut
  *                 into two contiguous halves that advance on two streams (the context stream
  *                 and a second one the library owns), so that one group's step kernel overlaps
  *                 the other group's far-field pass; the groups are folded into one once the live
@@ -294,6 +320,8 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
  *                 ("trace_few", "trace_split") by its own live count, which can change the
  *                 summation order of a line's far field; with the layout fixed (trace_few 0,
  *                 trace_split 0 or above the line count) results do not depend on the grouping
+ *  "trace_fold":  1 (default) = with two line groups, fold the second into the first once all
+ *                 live lines fit one 64-line tile; 0 = keep both groups to the end
  *  "grad_batch":  points per batch of the pair passes of bem_streamer_grad (64..2^24; default
  *                 131072; bounds scratch memory)
  * Errors: INVALID for an unknown key or value. */

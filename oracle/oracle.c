@@ -153,7 +153,10 @@ void orc_tri_quad7(const double x[3], const double v1[3], const double v2[3], co
  * s- = (a - rho).l, s+ = (b - rho).l, t = (a - rho).m, R- = |x - a|,
  * R+ = |x - b|, R0^2 = t^2 + w^2:
  *   f_e    = ln((R+ + s+)/(R- + s-))     (or the equal ln((R- - s-)/(R+ - s+))
- *                                          when s+ + s- <= 0, to avoid cancellation)
+ *                                          when s+ + s- <= 0, and the equal
+ *                                          ln((R+ + s+)(R- - s-)/R0^2) when
+ *                                          s- < 0 < s+: (R + s)(R - s) = R0^2,
+ *                                          so no form loses digits to R - |s|)
  *   beta_e = atan2(t s+, R0^2 + |w| R+) - atan2(t s-, R0^2 + |w| R-)
  *   int 1/R dS        = sum_e t f_e - |w| sum_e beta_e
  *   grad_x int 1/R dS = -sum_e m f_e - sign(w) n sum_e beta_e
@@ -194,7 +197,9 @@ void orc_tri_analytic(const double x[3], const double v1[3], const double v2[3],
         double Rm = norm3(xa), Rp = norm3(xb);
         double R02 = t * t + w * w;
         double f;
-        if (sp + sm > 0.0)
+        if (sm < 0.0 && sp > 0.0)   /* foot within the edge's span: R- + s- = R0^2 / (R- - s-) */
+            f = log((Rp + sp) * (Rm - sm) / R02);
+        else if (sp + sm > 0.0)
             f = log((Rp + sp) / (Rm + sm));
         else
             f = log((Rm - sm) / (Rp - sp));
@@ -814,7 +819,9 @@ void orc_tri_linear_analytic(const double x[3], const double v1[3], const double
         if (!(on_plane && (Rm == 0.0 || Rp == 0.0))) {
             double R02 = t * t + w * w;
             double f;
-            if (sp + sm > 0.0)
+            if (sm < 0.0 && sp > 0.0)   /* foot within the edge's span: R- + s- = R0^2 / (R- - s-) */
+                f = log((Rp + sp) * (Rm - sm) / R02);
+            else if (sp + sm > 0.0)
                 f = log((Rp + sp) / (Rm + sm));
             else
                 f = log((Rm - sm) / (Rp - sp));
@@ -886,7 +893,9 @@ void orc_tri_linear_field(const double x[3], const double v1[3], const double v2
         double Rm = norm3(xa), Rp = norm3(xb);
         double R02 = t * t + w * w;
         double f;
-        if (sp + sm > 0.0)
+        if (sm < 0.0 && sp > 0.0)   /* foot within the edge's span: R- + s- = R0^2 / (R- - s-) */
+            f = log((Rp + sp) * (Rm - sm) / R02);
+        else if (sp + sm > 0.0)
             f = log((Rp + sp) / (Rm + sm));
         else
             f = log((Rm - sm) / (Rp - sp));
@@ -925,13 +934,10 @@ void orc_tri_linear_field(const double x[3], const double v1[3], const double v2
 }
 
 /* Vertex -> body map of the nodal basis.  Returns 0, or -1 if a vertex is in
- * no triangle or in triangles of two bodies, -2 if a body is not a conductor
- * (DIRICHLET) or floating conductor (FLOATING): interface and sheet rows need
- * the normal at the collocation point, which a vertex of flat panels lacks. */
+ * no triangle or in triangles of two bodies (the density of each body has its
+ * own nodes; bodies that touch carry coincident vertices of their own). */
 static int p1_vertex_body(const orc_problem* p, int32_t* vb)
 {
-    for (int32_t b = 0; b < p->n_body; ++b)
-        if (p->body_kind[b] != ORC_DIRICHLET && p->body_kind[b] != ORC_FLOATING) return -2;
     for (int64_t i = 0; i < p->n_vert; ++i) vb[i] = -1;
     for (int64_t j = 0; j < p->n_tri; ++j)
         for (int c = 0; c < 3; ++c) {
@@ -967,36 +973,120 @@ static void p1_pair(const orc_problem* p, const orc_geom* g, const double x[3], 
     }
 }
 
+/* The normal part at the centroid x_T of triangle T (normal n_T) of the field of
+ * every hat, n_T . int lambda_k^j(y) (x_T - y) / (4 pi |x_T - y|^3) dS summed over the
+ * triangles j != T, added with weight coef into row (the K' part, Eq. ADL, of a row
+ * collocated at x_T).  T itself adds nothing: in its own plane the field of its
+ * density has no normal component (principal value).  Regular pairs by the 7-point
+ * rule with the hats at the nodes, the others by the closed form of the hat fields. */
+static void p1_kp_centroid(const orc_problem* p, const orc_geom* g, int64_t T, double coef, double* row)
+{
+    const double* x = g->cen + 3 * T;
+    const double* nT = g->nrm + 3 * T;
+    double bary[7][3], wt[7];
+    orc_quad7_rule(bary, wt);
+    for (int64_t j = 0; j < p->n_tri; ++j) {
+        if (j == T) continue;
+        const int32_t* t = p->tri + 3 * j;
+        const double* v = g->v + 9 * j;
+        double Ek[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        if (pair_is_regular(p, g, x, j)) {
+            for (int q = 0; q < 7; ++q) {
+                double y[3], d[3];
+                for (int k = 0; k < 3; ++k) y[k] = bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
+                sub3(x, y, d);
+                double r = norm3(d);
+                double s = wt[q] * g->area[j] / (4.0 * ORC_PI) / (r * r * r);
+                for (int c = 0; c < 3; ++c)
+                    for (int k = 0; k < 3; ++k) Ek[c][k] += s * bary[q][c] * d[k];
+            }
+        } else {
+            orc_tri_linear_field(x, v, v + 3, v + 6, Ek);
+        }
+        for (int c = 0; c < 3; ++c) row[t[c]] += coef * dot3(nT, Ek[c]);
+    }
+}
+
+/* Local corner of triangle j at vertex i: by index, or, for a vertex of another
+ * body, by position (within 1e-13 of the triangle's longest edge); -1 if none. */
+static int p1_corner(const orc_problem* p, const orc_geom* g, int64_t i, int64_t j)
+{
+    const int32_t* t = p->tri + 3 * j;
+    for (int c = 0; c < 3; ++c)
+        if (t[c] == i) return c;
+    const double* v = g->v + 9 * j;
+    const double* x = p->vert + 3 * i;
+    double L = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        double d[3];
+        sub3(v + 3 * ((e + 1) % 3), v + 3 * e, d);
+        if (norm3(d) > L) L = norm3(d);
+    }
+    for (int c = 0; c < 3; ++c) {
+        double d[3];
+        sub3(x, v + 3 * c, d);
+        if (norm3(d) <= 1e-13 * L) return c;
+    }
+    return -1;
+}
+
 int64_t orc_p1_n_unknowns(const orc_problem* p)
 {
     int32_t nf = 0;
-    for (int32_t b = 0; b < p->n_body; ++b) nf += p->body_kind[b] == ORC_FLOATING;
+    for (int32_t b = 0; b < p->n_body; ++b) nf += is_floating_kind(p->body_kind[b]);
     return p->n_vert + nf;
 }
 
 /* Dense row-major system of the nodal basis, n x n with n = n_vert + N_float,
  * unknowns [u_1..u_nvert, V_1..V_Nfl]:
- *   conductor vertex i   : sum_k v_ik u_k                 (= V_body)
- *   floating vertex i in f: sum_k v_ik u_k - V_f          (= 0)
- *   row of floating body f: sum_k u_k int_f psi_k / area_f  (= 0, net charge)
- * with int_f psi_k = sum over the triangles of f holding k of area/3.  The
- * literal Eq. Final4 row needs n . E at the collocation points, undefined at a
- * vertex of flat panels; its Gauss-law reduction is the net charge.
- * Returns 0, or the error of the vertex map. */
+ *   conductor vertex i     : sum_k v_ik u_k                 (= V_body)
+ *   floating vertex i in f : sum_k v_ik u_k - V_f           (= 0)   (floating body or sheet)
+ *   interface vertex i     : the hat-weighted mean over i's triangles T of the
+ *       interface condition (Eq. nonconductors) at T's centroid x_T with T's normal,
+ *       sum_T (a_T/3) [ (eps+ + eps-)/2 sigma_h(x_T) + (eps+ - eps-) (K' sigma_h)(x_T) ]
+ *       / sum_T (a_T/3)                                     (= 0)
+ *   row of floating body f : Eq. Final4 with the centroid rule over f's triangles,
+ *       sum_T a_T [ c_self sigma_h(x_T) + c_kp (K' sigma_h)(x_T) ] / sum_T a_T (= 0),
+ *       (c_self, c_kp) = (1/2, 1) (constraint_form 0, literal) or, for a sheet (Eq.
+ *       sheets), (1, 2 (eps+ - eps-)/(eps+ + eps-)); constraint_form 1 for a closed
+ *       floating body: its net charge sum_k u_k int_f psi_k / area_f.
+ * sigma_h(x_T) = (u_a + u_b + u_c)/3.  A vertex has no normal on flat panels, so the
+ * rows that need n . E (interface, Final4, sheets) take it at the centroids of the
+ * triangles around the vertex or of the body; the potential rows stay at the vertex.
+ * A vertex row meets the triangles of another body through a coincident vertex as
+ * their vertex (the singular closed form, at that vertex's exact position). */
 static void p1_row(const orc_problem* p, const orc_geom* g, const int32_t* vb, int64_t i, double* row)
 {
     const int64_t nv = p->n_vert, n = orc_p1_n_unknowns(p);
     for (int64_t k = 0; k < n; ++k) row[k] = 0.0;
     if (i < nv) {
-        const double* x = p->vert + 3 * i;
+        const int32_t b = vb[i];
+        const int32_t kind = p->body_kind[b];
+        if (kind == ORC_INTERFACE) {
+            const double ep = p->eps_plus[b], em = p->eps_minus[b];
+            double W = 0.0;
+            for (int64_t j = 0; j < p->n_tri; ++j) {
+                const int32_t* t = p->tri + 3 * j;
+                if (t[0] == i || t[1] == i || t[2] == i) W += g->area[j] / 3.0;
+            }
+            for (int64_t j = 0; j < p->n_tri; ++j) {
+                const int32_t* t = p->tri + 3 * j;
+                if (!(t[0] == i || t[1] == i || t[2] == i)) continue;
+                const double wT = g->area[j] / 3.0 / W;
+                for (int c = 0; c < 3; ++c) row[t[c]] += wT * 0.5 * (ep + em) / 3.0;
+                p1_kp_centroid(p, g, j, wT * (ep - em), row);
+            }
+            return;
+        }
         for (int64_t j = 0; j < p->n_tri; ++j) {
             const int32_t* t = p->tri + 3 * j;
-            int is_vertex = (t[0] == i) || (t[1] == i) || (t[2] == i);
+            const int c0 = p1_corner(p, g, i, j);
             double c[3];
-            p1_pair(p, g, x, j, is_vertex, c);
+            /* at a coincident vertex of another body the closed form is taken at that vertex */
+            p1_pair(p, g, c0 >= 0 ? g->v + 9 * j + 3 * c0 : p->vert + 3 * i, j, c0 >= 0, c);
             for (int k = 0; k < 3; ++k) row[t[k]] += c[k];
         }
-        if (p->body_kind[vb[i]] == ORC_FLOATING) row[nv + g->fidx[vb[i]]] = -1.0;
+        if (is_floating_kind(kind)) row[nv + g->fidx[b]] = -1.0;
         return;
     }
     int32_t b = 0;
@@ -1004,9 +1094,22 @@ static void p1_row(const orc_problem* p, const orc_geom* g, const int32_t* vb, i
     double asum = 0.0;
     for (int64_t j = 0; j < p->n_tri; ++j)
         if (p->tri_body[j] == b) asum += g->area[j];
-    for (int64_t j = 0; j < p->n_tri; ++j)
-        if (p->tri_body[j] == b)
-            for (int k = 0; k < 3; ++k) row[p->tri[3 * j + k]] += g->area[j] / 3.0 / asum;
+    const int sheet = p->body_kind[b] == ORC_SHEET;
+    if (!sheet && p->constraint_form == 1) {
+        for (int64_t j = 0; j < p->n_tri; ++j)
+            if (p->tri_body[j] == b)
+                for (int k = 0; k < 3; ++k) row[p->tri[3 * j + k]] += g->area[j] / 3.0 / asum;
+        return;
+    }
+    const double ep = p->eps_plus[b], em = p->eps_minus[b];
+    const double c_self = sheet ? 1.0 : 0.5;
+    const double c_kp = sheet ? 2.0 * (ep - em) / (ep + em) : 1.0;
+    for (int64_t j = 0; j < p->n_tri; ++j) {
+        if (p->tri_body[j] != b) continue;
+        const double wT = g->area[j] / asum;
+        for (int k = 0; k < 3; ++k) row[p->tri[3 * j + k]] += wT * c_self / 3.0;
+        p1_kp_centroid(p, g, j, wT * c_kp, row);
+    }
 }
 
 int orc_p1_assemble(const orc_problem* p, double* A)

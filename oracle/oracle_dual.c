@@ -215,7 +215,9 @@ static void danalytic(const dl x[3], const dl* v, int on_plane, dl* S, dl F[3])
         dl Rm = vnorm(xa), Rp = vnorm(xb);
         dl R02 = add(mul(t, t), mul(w, w));
         dl f;
-        if (sp.v + sm.v > 0.0)
+        if (sm.v < 0.0 && sp.v > 0.0)   /* foot within the edge's span: R- + s- = R0^2 / (R- - s-) */
+            f = dlog(dvd(mul(add(Rp, sp), sub(Rm, sm)), R02));
+        else if (sp.v + sm.v > 0.0)
             f = dlog(dvd(add(Rp, sp), add(Rm, sm)));
         else
             f = dlog(dvd(sub(Rm, sm), sub(Rp, sp)));

@@ -128,6 +128,19 @@ class Context:
                                            int(bool(transpose))), self.lib)
         return y
 
+    def pair_integrals(self, pts, panel, rule=0):
+        """bem_pair_integrals: S [P] and F [P, 3] (numpy) of unit density on panel[p] at pts[p];
+        rule 0 closed forms, 1 the near-singular rule (closest point, subdivision, Duffy)."""
+        torch = _torch()
+        x = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3), device=self.device)
+        pn = torch.as_tensor(np.ascontiguousarray(panel, dtype=np.int32).reshape(-1), device=self.device)
+        P = pn.shape[0]
+        S = torch.empty(P, dtype=torch.float64, device=self.device)
+        F = torch.empty((P, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.bem_pair_integrals(self._ctx, P, _dev_ptr(x), _dev_ptr(pn), int(rule), _dev_ptr(S),
+                                           _dev_ptr(F)), self.lib)
+        return S.cpu().numpy(), F.cpu().numpy()
+
     def solve(self, body_V, tol=1e-10, max_iter=10000, raise_on_noconv=True):
         """Returns (sol [nrhs, n] float64 on the GPU, info dict)."""
         torch = _torch()

@@ -80,7 +80,9 @@ __device__ __forceinline__ void tri_SF_d3(const D3 (&V)[3][3], const D3 (&X)[3],
         const D3 sp = sm + len;
         const D3 t = q0 * m0 + q1 * m1 + q2 * m2;
         D3 f;
-        if (sp.v + sm.v > 0.0)
+        if (sm.v < 0.0 && sp.v > 0.0)   // foot within the edge's span (see flat_tri_SF)
+            f = dlog((Rv[b] + sp) * (Rv[e] - sm) / (t * t + w * w));
+        else if (sp.v + sm.v > 0.0)
             f = dlog((Rv[b] + sp) / (Rv[e] + sm));
         else
             f = dlog((Rv[e] - sm) / (Rv[b] - sp));

@@ -197,12 +197,7 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
     if (o.constraint_form != 0 && o.constraint_form != 1) return fail(BEM_ERR_INVALID, "unknown constraint_form");
     if (o.basis != BEM_BASIS_CONSTANT && o.basis != BEM_BASIS_LINEAR) return fail(BEM_ERR_INVALID, "unknown basis");
     if (o.basis == BEM_BASIS_LINEAR) {
-        if (o.constraint_form != 1)
-            return fail(BEM_ERR_INVALID, "the LINEAR basis uses the net-charge row (constraint_form 1)");
         if (n_tri >= ((int64_t)1 << 29)) return fail(BEM_ERR_INVALID, "mesh too large for the LINEAR basis");
-        for (int32_t b = 0; b < n_body; ++b)
-            if (bodies[b].kind != BEM_DIRICHLET && bodies[b].kind != BEM_FLOATING)
-                return fail(BEM_ERR_INVALID, "the LINEAR basis takes DIRICHLET and FLOATING bodies only");
     }
     for (int64_t k = 0; k < 3 * n_vert; ++k)
         if (!std::isfinite(vert[k])) return fail(BEM_ERR_INVALID, "non-finite vertex coordinate");
@@ -389,6 +384,27 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         c->h_flt_coef[2 * f] = cs;
         c->h_flt_coef[2 * f + 1] = ck;
     }
+    if (o.basis == BEM_BASIS_LINEAR) {
+        // centroid rows of the rows that need n . E: interface bodies, then floating bodies whose
+        // row has a K' term (literal Eq. Final4, sheets), each body's triangles ascending
+        std::vector<int32_t>& crow = c->h_crow_tri;
+        c->h_flt_crange.assign(2 * (size_t)std::max(c->n_float, 1), 0);
+        for (int32_t b = 0; b < n_body; ++b) {
+            const int32_t f = c->h_body_fidx[b];
+            const bool kp = bodies[b].kind == BEM_INTERFACE || (f >= 0 && c->h_flt_coef[2 * f + 1] != 0.0);
+            if (!kp) continue;
+            const int32_t r0 = (int32_t)crow.size();
+            for (int64_t j = 0; j < n_tri; ++j)
+                if (tri_body[j] == b) crow.push_back((int32_t)j);
+            if (f >= 0) {
+                c->h_flt_crange[2 * f] = r0;
+                c->h_flt_crange[2 * f + 1] = (int32_t)crow.size();
+                c->h_flt_kp.push_back(f);
+            }
+        }
+        for (int64_t i = 0; i < n_vert; ++i)
+            if (bodies[c->h_vert_body[i]].kind == BEM_INTERFACE) c->h_iface_v.push_back((int32_t)i);
+    }
     // row segments by kind (Sec. 4: rows grouped by type); floating rows sorted by
     // (body, panel) so that each body's rows are contiguous
     std::vector<int32_t> slot(n_tri, -1);
@@ -428,6 +444,15 @@ bem_status bem_create(int64_t n_vert, const double* vert, int64_t n_tri, const i
         upload(c->grp_ptr, grp_ptr.data(), grp_ptr.size(), s);
         upload(c->grp_tri, grp_tri.data(), grp_tri.size(), s);
         upload(c->grp_loc, grp_loc.data(), grp_loc.size(), s);
+        if (!c->h_crow_tri.empty()) {
+            std::vector<int32_t> tri_crow((size_t)n_tri, -1);
+            for (size_t r = 0; r < c->h_crow_tri.size(); ++r) tri_crow[c->h_crow_tri[r]] = (int32_t)r;
+            upload(c->nod_trow, c->h_crow_tri.data(), c->h_crow_tri.size(), s);
+            upload(c->nod_tri_crow, tri_crow.data(), tri_crow.size(), s);
+            upload(c->nod_iface_v, c->h_iface_v.data(), c->h_iface_v.size(), s);
+            upload(c->nod_frange, c->h_flt_crange.data(), c->h_flt_crange.size(), s);
+            upload(c->nod_flist, c->h_flt_kp.data(), c->h_flt_kp.size(), s);
+        }
     }
     upload(c->rows_pot, c->h_rows_pot.data(), c->h_rows_pot.size(), s);
     upload(c->rows_int, c->h_rows_int.data(), c->h_rows_int.size(), s);
@@ -474,11 +499,12 @@ bem_status bem_assemble(bem_ctx* c) {
         // rows in FP64 (n_float x ld), with an empty list of FP64 near remainders
         const bool mixed = c->opt.precision == BEM_MIXED;
         const size_t nfl = (size_t)(c->n_float > 0 ? c->n_float : 1);
-        const size_t need = mixed ? sizeof(float) * (size_t)c->nb * c->ld + sizeof(double) * nfl * c->ld
-                                  : sizeof(double) * (size_t)c->n * c->ld;
+        const size_t kc = sizeof(double) * c->h_crow_tri.size() * (size_t)c->ld;   // normal-field rows
+        const size_t need = (mixed ? sizeof(float) * (size_t)c->nb * c->ld + sizeof(double) * nfl * c->ld
+                                   : sizeof(double) * (size_t)c->n * c->ld) + kc;
         size_t free_b = 0, total_b = 0;
         BEM_HIP(hipMemGetInfo(&free_b, &total_b));
-        const size_t have = free_b + c->A64.bytes + c->A32.bytes;
+        const size_t have = free_b + c->A64.bytes + c->A32.bytes + c->nod_Kc.bytes;
         if (need > have)
             throw bem::Error(BEM_ERR_OOM, "assembly needs " + std::to_string(need >> 20) + " MiB, " +
                                               std::to_string(have >> 20) + " MiB free");
@@ -494,8 +520,9 @@ bem_status bem_assemble(bem_ctx* c) {
             c->near_nnz = 0;
         } else {
             c->A32.release();
-            c->A64.alloc(need);
+            c->A64.alloc(need - kc);
         }
+        if (kc) c->nod_Kc.alloc(kc);
         c->diag.alloc(sizeof(double) * c->ld);
         bem::launch_nodal_assemble(c);
         BEM_HIP(hipStreamSynchronize(c->stream));
@@ -779,6 +806,25 @@ bem_status bem_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const d
     API_CATCH
 }
 
+bem_status bem_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const int32_t* panel, int32_t rule,
+                              double* S, double* F) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (P < 0 || P >= ((int64_t)1 << 31)) throw bem::Error(BEM_ERR_INVALID, "pair count out of range");
+    if (rule != 0 && rule != 1) throw bem::Error(BEM_ERR_INVALID, "rule must be 0 (closed forms) or 1 (Duffy)");
+    if (P > 0 && (!pts || !panel || !S)) throw bem::Error(BEM_ERR_INVALID, "pts, panel and S are required");
+    auto hp = fetch_i32(c, panel, (size_t)P);
+    for (int32_t v : hp)
+        if (v < 0 || v >= c->N) throw bem::Error(BEM_ERR_INVALID, "panel entry out of range");
+    auto hx = fetch_f64(c, pts, (size_t)P * 3);
+    for (double v : hx)
+        if (!std::isfinite(v)) throw bem::Error(BEM_ERR_INVALID, "non-finite point coordinate");
+    bem::launch_pair_integrals(c, P, pts, panel, rule, S, F, 3);
+    return BEM_OK;
+    API_CATCH
+}
+
 bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return fail(BEM_ERR_INVALID, "NULL argument");
     if (std::strcmp(key, "trace_mode") == 0) {
@@ -789,6 +835,13 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
     if (std::strcmp(key, "batched_solve") == 0) {
         if (value < 0 || value > 1) return fail(BEM_ERR_INVALID, "batched_solve must be 0 or 1");
         c->batched_solve = (int32_t)value;
+        return BEM_OK;
+    }
+    if (std::strcmp(key, "near_rule") == 0) {
+        if (value < 0 || value > 1) return fail(BEM_ERR_INVALID, "near_rule must be 0 or 1");
+        if (value == 1 && c->opt.basis != BEM_BASIS_CONSTANT)
+            return fail(BEM_ERR_INVALID, "near_rule 1 applies to the CONSTANT basis");
+        c->near_rule = (int32_t)value;
         return BEM_OK;
     }
     struct Knob {
@@ -805,7 +858,8 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"trace_tile", &bem_ctx::tune_trace_tile, 64, 256, true},
         {"trace_few", &bem_ctx::tune_trace_few, 0, 16, false},
         {"trace_splitk", &bem_ctx::tune_trace_splitk, 2, 8, true},
-        {"trace_groups", &bem_ctx::tune_trace_groups, 1, 2, false},
+        {"trace_groups", &bem_ctx::tune_trace_groups, 0, 2, false},
+        {"trace_fold", &bem_ctx::tune_trace_fold, 0, 1, false},
         {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
     for (const Knob& k : knobs)
@@ -822,6 +876,7 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     if (!c || !key || !value) return fail(BEM_ERR_INVALID, "NULL argument");
     if (std::strcmp(key, "trace_mode") == 0) *value = c->trace_mode;
     else if (std::strcmp(key, "batched_solve") == 0) *value = c->batched_solve;
+    else if (std::strcmp(key, "near_rule") == 0) *value = c->near_rule;
     else if (std::strcmp(key, "far_rows") == 0) *value = c->tune_far_rows;
     else if (std::strcmp(key, "gemv_rows") == 0) *value = c->tune_gemv_rows;
     else if (std::strcmp(key, "gemm_blocks") == 0) *value = c->tune_gemm_blocks;
@@ -832,6 +887,7 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     else if (std::strcmp(key, "trace_few") == 0) *value = c->tune_trace_few;
     else if (std::strcmp(key, "trace_splitk") == 0) *value = c->tune_trace_splitk;
     else if (std::strcmp(key, "trace_groups") == 0) *value = c->tune_trace_groups;
+    else if (std::strcmp(key, "trace_fold") == 0) *value = c->tune_trace_fold;
     else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
     return BEM_OK;
 }

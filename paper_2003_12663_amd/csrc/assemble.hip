@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_near(const double* __restrict__ tri64, 
                                               const int32_t* __restrict__ nrow, const int32_t* __restrict__ ncol,
                                               double* __restrict__ A64, float* __restrict__ A32, int64_t ld,
                                               double* __restrict__ nval, double* __restrict__ Kf, int64_t N,
-                                              double* __restrict__ diag) {
+                                              double* __restrict__ diag, const double* __restrict__ sf) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= nnz) return;
     const int64_t i = nrow[k], j = ncol[k];
@@ -156,7 +156,14 @@ __global__ __launch_bounds__(256) void k_near(const double* __restrict__ tri64, 
     const int32_t kind = body_kind[b];
     const bool self = (i == j);
     double S, F0, F1, F2;
-    flat_tri_SF<true, true>(Tj, Ti[TR_C + 0], Ti[TR_C + 1], Ti[TR_C + 2], self, S, F0, F1, F2);
+    if (sf) {   // S and F from the near-singular rule (Duffy); the self pair's F is not used
+        S = sf[4 * k];
+        F0 = sf[4 * k + 1];
+        F1 = sf[4 * k + 2];
+        F2 = sf[4 * k + 3];
+    } else {
+        flat_tri_SF<true, true>(Tj, Ti[TR_C + 0], Ti[TR_C + 1], Ti[TR_C + 2], self, S, F0, F1, F2);
+    }
     const double kp = self ? 0.0 : (Ti[TR_N + 0] * F0 + Ti[TR_N + 1] * F1 + Ti[TR_N + 2] * F2);
     double v;
     if (kind == BEM_INTERFACE)
@@ -351,13 +358,20 @@ void launch_near_assemble(bem_ctx* c) {
     if (c->near_nnz == 0) return;
     double* Kf = ((c->opt.constraint_form == 0 || c->has_sheet) && !c->h_rows_flt.empty()) ? c->Kf.as<double>()
                                                                                               : nullptr;
+    const double* sf = nullptr;
+    if (c->near_rule == 1) {   // the paper's near-singular rule instead of the closed forms
+        c->near_sf.alloc(sizeof(double) * 4 * (size_t)c->near_nnz);
+        launch_near_duffy(c, c->near_nnz, c->near_row.as<int32_t>(), c->near_col.as<int32_t>(),
+                          c->near_sf.as<double>());
+        sf = c->near_sf.as<double>();
+    }
     hipLaunchKernelGGL(k_near, dim3((unsigned)ceil_div(c->near_nnz, 256)), dim3(256), 0, c->stream,
                        c->tri64.as<double>(), c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(),
                        c->body_epsp.as<double>(), c->body_epsm.as<double>(), c->row_slot.as<int32_t>(), c->near_nnz,
                        c->near_row.as<int32_t>(), c->near_col.as<int32_t>(), mixed ? nullptr : c->A64.as<double>(),
                        mixed ? c->A32.as<float>() : nullptr, c->ld, mixed ? c->near_val.as<double>() : nullptr, Kf,
                        c->N,
-                       c->diag.as<double>());
+                       c->diag.as<double>(), sf);
     BEM_CHECK_LAUNCH();
 }
 

@@ -30,7 +30,9 @@ __device__ __forceinline__ bool is_regular(double dx, double dy, double dz, doub
 // w the signed height of x over the plane, rho its foot point and, for each
 // edge a -> b with in-plane outward normal m, the edge abscissae s-, s+, the
 // in-plane distance t and the vertex distances R-, R+:
-//   f_e = ln((R+ + s+)/(R- + s-))      (ln((R- - s-)/(R+ - s+)) if s+ + s- <= 0)
+//   f_e = ln((R+ + s+)/(R- + s-))      (ln((R- - s-)/(R+ - s+)) if s+ + s- <= 0, and
+//         ln((R+ + s+)(R- - s-)/R0^2) when s- < 0 < s+, R0^2 = t^2 + w^2: the same value
+//         without the cancellation in R - |s| above an edge)
 //   4 pi S = sum t f_e - |w| Omega,   4 pi F = sum m f_e + sign(w) n Omega,
 // where Omega, the sum of the three edge angles of those papers, is the solid
 // angle the triangle subtends at x, taken here in one step from the formula of
@@ -71,7 +73,9 @@ __device__ __forceinline__ void flat_tri_SF(const double* __restrict__ T, double
         const double t = q0 * m0 + q1 * m1 + q2 * m2;
         const double Rm = Rv[e], Rp = Rv[b];
         double f;
-        if (sp + sm > 0.0)
+        if (sm < 0.0 && sp > 0.0)   // foot within the edge's span: R- + s- = R0^2 / (R- - s-), no cancellation
+            f = log((Rp + sp) * (Rm - sm) / (t * t + w * w));
+        else if (sp + sm > 0.0)
             f = log((Rp + sp) / (Rm + sm));
         else
             f = log((Rm - sm) / (Rp - sp));

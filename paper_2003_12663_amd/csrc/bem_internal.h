@@ -130,6 +130,12 @@ struct bem_ctx {
     // (ascending) and the local column of each corner (8 bits each, 0xff outside the group)
     bem::DBuf grp_ptr, grp_tri, grp_loc;
     bem::DBuf nod_pan64, nod_far64, nod_ones;   // nodal density folded into the panel records (field lines)
+    // nodal rows that need n . E, taken at triangle centroids: the centroid rows (triangles of
+    // interface bodies, then of floating bodies whose row has a K' term, grouped by body), the
+    // triangle -> centroid row map (-1), the interface vertices, each floating body's centroid-row
+    // range and the list of floating bodies with a K' term; Kc is their normal-field matrix
+    std::vector<int32_t> h_crow_tri, h_iface_v, h_flt_crange, h_flt_kp;
+    bem::DBuf nod_trow, nod_tri_crow, nod_iface_v, nod_frange, nod_flist, nod_Kc;
     bem::DBuf tr_cases;                          // staging of the nodal basis's per-load-case line runs
     bem::DBuf far64, far32, tri64;
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
@@ -146,6 +152,7 @@ struct bem_ctx {
     bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part;
 
     bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part, rows_part;   // batched GMRES
+    bem::DBuf near_sf;   // S, F of the near list by the near-singular rule (near_rule 1)
 
     // gradient of the streamer integrals
     bem::DBuf ad_state, ad_part, ad_mask, ad_cnt, ad_self, ad_ppart, ad_list, ad_path, ad_stage, ad_geo, ad_seg,
@@ -157,6 +164,7 @@ struct bem_ctx {
 
     // tuning knobs (bem_set_tuning)
     int32_t trace_mode = 0;   // 0 auto, 1 all lines together (batched passes), 2 persistent per-line workgroups
+    int32_t near_rule = 0;       // near pairs of the assembly: 0 closed forms, 1 the Sec. 4 rule (closest point + Duffy)
     int32_t batched_solve = 1;   // several right-hand sides: 1 one batched solve (shared matrix products), 0 one by one
     // tile shapes (bem_set_tuning / bem_autotune); none changes a result beyond summation order
     int32_t tune_far_rows = 64;       // collocation rows per block of the far-field assembly
@@ -167,7 +175,8 @@ struct bem_ctx {
     int32_t tune_trace_tile = 256;    // lines per block of an unsplit field-line pass (64, 128, 256)
     int32_t tune_trace_splitk = 8;    // waves that split a panel chunk in a split field-line pass (2, 4, 8)
     int32_t tune_trace_few = 8;       // live-line count at or below which the panel-stationary pass is used (<= 16)
-    int32_t tune_trace_groups = 1;    // line groups of a field-line run, each on its own stream (1 or 2)
+    int32_t tune_trace_groups = 0;    // line groups of a field-line run, each on its own stream (1 or 2; 0: 2 from 128 lines)
+    int32_t tune_trace_fold = 1;      // fold the second line group into the first once all live lines fit one tile
     int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
     // profiling: 0 off; 1 every kernel (event pairs around each launch, the field-line far pass
@@ -212,6 +221,11 @@ void push_timing(bem_ctx* c, const char* name, hipEvent_t a, hipEvent_t b);
 
 // ---- launchers (one translation unit each) --------------------------------
 void launch_geometry(bem_ctx* c);                                  // geometry.hip
+// S, F of unit density on panel[p] at pts[p]: rule 0 closed forms, 1 the Sec. 4 rule (duffy.hip)
+void launch_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const int32_t* panel, int rule, double* S,
+                           double* F, int64_t fstride);
+// the Sec. 4 rule for the assembly's near list into sf[4 k .. 4 k + 3] (duffy.hip)
+void launch_near_duffy(bem_ctx* c, int64_t nnz, const int32_t* row, const int32_t* col, double* sf);
 void launch_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const double* bary, double offset,
                          double* out);                                // geometry.hip
 void launch_far_assemble(bem_ctx* c);                              // assemble.hip

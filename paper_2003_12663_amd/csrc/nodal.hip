@@ -5,7 +5,7 @@
 // lambda_k^tau being tau's barycentric coordinate of k.  Conductor and
 // floating-conductor bodies; a floating body's row is its net charge.
 //
-// Assembly keeps the collision-free ownership of Sec. 5 (each collocation
+// Assembly keeps the collision-free ownership of Sec. 4 (each collocation
 // point owns its row) at wave granularity: the 64 lanes of a wave are 64
 // consecutive rows, while the column and the triangle are wave-uniform, so
 // triangle records arrive through the scalar cache and every lane adds into
@@ -92,7 +92,9 @@ __device__ __forceinline__ void hat_edges(const double* __restrict__ T, double x
         double er = 0.5 * (sp * Rp - sm * Rm);
         if (!(vtx && (Rm == 0.0 || Rp == 0.0))) {
             double f;
-            if (sp + sm > 0.0)
+            if (sm < 0.0 && sp > 0.0)   // foot within the edge's span (see flat_tri_SF)
+                f = log((Rp + sp) * (Rm - sm) / (t * t + w * w));
+            else if (sp + sm > 0.0)
                 f = log((Rp + sp) / (Rm + sm));
             else
                 f = log((Rm - sm) / (Rp - sp));
@@ -116,6 +118,26 @@ __device__ __forceinline__ void hat_edges(const double* __restrict__ T, double x
         omega = 2.0 * atan2(fabs(triple), den);
     }
     I0 = st - aw * omega;
+}
+
+// Local corner of the triangle T at x, by position: within 1e-13 of T's longest edge; -1 if none
+// (a vertex of another body that coincides with a corner of T)
+__device__ __forceinline__ int coincident_corner(const double* __restrict__ T, double x0, double x1, double x2) {
+    double L2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int b = (e + 1) % 3;
+        const double d0 = T[3 * b] - T[3 * e], d1 = T[3 * b + 1] - T[3 * e + 1], d2 = T[3 * b + 2] - T[3 * e + 2];
+        const double l2 = d0 * d0 + d1 * d1 + d2 * d2;
+        L2 = l2 > L2 ? l2 : L2;
+    }
+    const double tol2 = 1e-26 * L2;
+#pragma unroll
+    for (int cv = 0; cv < 3; ++cv) {
+        const double d0 = x0 - T[3 * cv], d1 = x1 - T[3 * cv + 1], d2 = x2 - T[3 * cv + 2];
+        if (d0 * d0 + d1 * d1 + d2 * d2 <= tol2) return cv;
+    }
+    return -1;
 }
 
 // lambda_c(rho) I0 + g_c . J over 4 pi (see hat_edges)
@@ -291,21 +313,227 @@ __global__ __launch_bounds__(64) void k_nodal_near(int64_t nv, int64_t ld, int64
             const double crr = lane_bcast(rr, k);
             const int32_t a = __builtin_amdgcn_readlane(v0, k), b = __builtin_amdgcn_readlane(v1, k);
             const int32_t c = __builtin_amdgcn_readlane(v2, k);
-            const bool vtx = (a == i) || (b == i) || (c == i);
+            bool vtx = (a == i) || (b == i) || (c == i);
             const bool near = vtx || !is_regular(x0 - cc0, x1 - cc1, x2 - cc2, crr);
             if (near && live) {
                 // the three entries are read first so that their latency overlaps the closed form;
                 // the sum is formed in FP64 and rounded once to the stored type
                 const double ya = (double)row[a], yb = (double)row[b], yc = (double)row[c];
                 const double* Tr = tri64 + (int64_t)TRI_REC * (t0 + k);
+                // a vertex of another body at x (bodies that touch): the singular closed form at
+                // that vertex's own position
+                double xs0 = x0, xs1 = x1, xs2 = x2;
+                if (!vtx) {
+                    const int cv = coincident_corner(Tr, x0, x1, x2);
+                    if (cv >= 0) {
+                        vtx = true;
+                        xs0 = Tr[TR_V + 3 * cv];
+                        xs1 = Tr[TR_V + 3 * cv + 1];
+                        xs2 = Tr[TR_V + 3 * cv + 2];
+                    }
+                }
                 double I0, r0, r1, r2, J0, J1, J2;
-                hat_edges(Tr, x0, x1, x2, vtx, I0, r0, r1, r2, J0, J1, J2);
+                hat_edges(Tr, xs0, xs1, xs2, vtx, I0, r0, r1, r2, J0, J1, J2);
                 row[a] = (T)(ya + hat_value(Tr, 0, I0, r0, r1, r2, J0, J1, J2));
                 row[b] = (T)(yb + hat_value(Tr, 1, I0, r0, r1, r2, J0, J1, J2));
                 row[c] = (T)(yc + hat_value(Tr, 2, I0, r0, r1, r2, J0, J1, J2));
             }
         }
     }
+}
+
+// ---- rows that need n . E (interface vertices, literal Final4, sheets) ----------------
+// A vertex of flat panels has no normal, so those rows take the normal field at the
+// centroids x_T of triangles T (normal n_T): Kc[r][k] = n_T . (field of hat k over every
+// triangle but T at x_T) for the centroid rows r (trow[r] = T), row stride ld.  T itself adds
+// nothing (in its plane the field of its own density has no normal component).
+
+// Regular pairs of the centroid rows: k_nodal_assemble's walk of column groups, with the
+// kernel n_T . w (x - y)/|x - y|^3 in place of w/|x - y|.  Kc is FP64.
+__global__ __launch_bounds__(256) void k_nodal_kp_assemble(int64_t nc, int64_t nv, int64_t ld, int64_t n_rt,
+                                                           const int32_t* __restrict__ trow,
+                                                           const int32_t* __restrict__ grp_ptr,
+                                                           const int32_t* __restrict__ grp_tri,
+                                                           const uint32_t* __restrict__ grp_loc,
+                                                           const double* __restrict__ pan64,
+                                                           const double* __restrict__ tri64, double* __restrict__ Kc) {
+    __shared__ double tile[4][NODAL_COLS][65];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b = blockIdx.x, xcd = b & 7, slot = b >> 3;
+    const int64_t cg = (slot / n_rt) * 8 + xcd, rt = slot % n_rt;
+    const int64_t r0 = (rt * 4 + wv) * 64;
+    const int64_t r = r0 + lane;
+    const int64_t T = trow[r < nc ? r : nc - 1];
+    const double* Tr = tri64 + (int64_t)TRI_REC * T;
+    const double x0 = Tr[TR_C], x1 = Tr[TR_C + 1], x2 = Tr[TR_C + 2];
+    const double m0 = Tr[TR_N], m1 = Tr[TR_N + 1], m2 = Tr[TR_N + 2];
+    const int64_t j0 = cg * NODAL_COLS;
+#pragma unroll
+    for (int cc = 0; cc < NODAL_COLS; ++cc) tile[wv][cc][lane] = 0.0;
+    if (j0 < nv) {
+        const NodeBary nb0(0), nb1(1), nb2(2);
+        const int32_t e1 = grp_ptr[cg + 1];
+        for (int32_t e = grp_ptr[cg]; e < e1; ++e) {
+            const int64_t t = grp_tri[e];
+            const uint32_t loc = grp_loc[e];
+            const double* P = pan64 + (int64_t)FAR_REC * t;
+            if (t != T && is_regular(x0 - P[FR_CC], x1 - P[FR_CC + 1], x2 - P[FR_CC + 2], P[FR_RR])) {
+                double kq[7];
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const double d0 = x0 - P[FR_X + q], d1 = x1 - P[FR_Y + q], d2 = x2 - P[FR_Z + q];
+                    const double ir = rsqrt_pos(d0 * d0 + d1 * d1 + d2 * d2);
+                    kq[q] = P[FR_W + q] * (d0 * m0 + d1 * m1 + d2 * m2) * (ir * ir * ir);
+                }
+                const uint32_t l0 = loc & 0xffu, l1 = (loc >> 8) & 0xffu, l2 = (loc >> 16) & 0xffu;
+                if (l0 != 0xffu) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) sacc += kq[q] * nb0.b[q];
+                    tile[wv][l0][lane] += sacc;
+                }
+                if (l1 != 0xffu) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) sacc += kq[q] * nb1.b[q];
+                    tile[wv][l1][lane] += sacc;
+                }
+                if (l2 != 0xffu) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) sacc += kq[q] * nb2.b[q];
+                    tile[wv][l2][lane] += sacc;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int sgm = 0; sgm < 16; ++sgm) {
+        const int rr = (lane >> 4) + 4 * sgm, cc = lane & 15;
+        const int64_t ii = r0 + rr, jj = j0 + cc;
+        if (ii < nc && jj < nv) Kc[ii * ld + jj] = tile[wv][cc][rr];
+    }
+}
+
+// Near pairs of the centroid rows (one lane per row, chunks of 64 triangles beyond reach of the
+// rows' ball skipped, as k_nodal_near): the closed form of the three hats' normal field.
+__global__ __launch_bounds__(64) void k_nodal_kp_near(int64_t nc, int64_t ld, int64_t N, int64_t Np,
+                                                      const int32_t* __restrict__ trow,
+                                                      const int32_t* __restrict__ tri,
+                                                      const double* __restrict__ far64, const double* __restrict__ cb,
+                                                      const double* __restrict__ tri64, double* __restrict__ Kc) {
+    const int lane = threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = r < nc;
+    const int64_t rc = live ? r : nc - 1;
+    const int64_t T = trow[rc];
+    const double* Tx = tri64 + (int64_t)TRI_REC * T;
+    const double x0 = Tx[TR_C], x1 = Tx[TR_C + 1], x2 = Tx[TR_C + 2];
+    const double m0 = Tx[TR_N], m1 = Tx[TR_N + 1], m2 = Tx[TR_N + 2];
+    double* row = Kc + rc * ld;
+    const double g0 = wave_sum(x0) / 64.0, g1 = wave_sum(x1) / 64.0, g2 = wave_sum(x2) / 64.0;
+    double rg = sqrt((x0 - g0) * (x0 - g0) + (x1 - g1) * (x1 - g1) + (x2 - g2) * (x2 - g2));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double other = __shfl_xor(rg, o, 64);
+        rg = other > rg ? other : rg;
+    }
+    for (int64_t t0 = 0; t0 < N; t0 += 64) {
+        const double* B = cb + 4 * (t0 >> 6);
+        const double e0 = B[0] - g0, e1 = B[1] - g1, e2 = B[2] - g2;
+        const double reach = (rg + B[3]) * (1.0 + 1e-9) + 1e-300;
+        if (e0 * e0 + e1 * e1 + e2 * e2 > reach * reach) continue;   // every pair regular
+        const int64_t tl = t0 + lane < N ? t0 + lane : N - 1;
+        const double c0 = far64[(int64_t)(FR_CC + 0) * Np + tl], c1 = far64[(int64_t)(FR_CC + 1) * Np + tl];
+        const double c2 = far64[(int64_t)(FR_CC + 2) * Np + tl], rr = far64[(int64_t)FR_RR * Np + tl];
+        const int32_t v0 = tri[3 * tl], v1 = tri[3 * tl + 1], v2 = tri[3 * tl + 2];
+        const int kend = N - t0 < 64 ? (int)(N - t0) : 64;
+        for (int k = 0; k < kend; ++k) {
+            const double cc0 = lane_bcast(c0, k), cc1 = lane_bcast(c1, k), cc2 = lane_bcast(c2, k);
+            const double crr = lane_bcast(rr, k);
+            const int32_t a = __builtin_amdgcn_readlane(v0, k), b = __builtin_amdgcn_readlane(v1, k);
+            const int32_t c = __builtin_amdgcn_readlane(v2, k);
+            const bool near = (t0 + k != T) && !is_regular(x0 - cc0, x1 - cc1, x2 - cc2, crr);
+            if (near && live) {
+                const double ya = row[a], yb = row[b], yc = row[c];
+                double out[3] = {0.0, 0.0, 0.0};
+                nodal_tri_hats_nE(tri64 + (int64_t)TRI_REC * (t0 + k), x0, x1, x2, m0, m1, m2, out);
+                row[a] = ya + out[0];
+                row[b] = yb + out[1];
+                row[c] = yc + out[2];
+            }
+        }
+    }
+}
+
+// Interface vertex rows (Eq. nonconductors at the vertex, taken as the hat-weighted mean over
+// the vertex's triangles T of the condition at x_T): one block per interface vertex i,
+//   A[i][k] = sum_{T in fan(i)} (a_T/3)/m_i [ (eps+ - eps-) Kc[crow(T)][k]
+//                                             + (eps+ + eps-)/2 [k in T]/3 ],
+// m_i = sum over the fan of a_T/3; fan order, so the sums are reproducible.  Columns k < nv.
+template <class TT>
+__global__ __launch_bounds__(256) void k_nodal_iface_rows(int64_t nv, int64_t ld, const int32_t* __restrict__ iface_v,
+                                                          const int32_t* __restrict__ fan_ptr,
+                                                          const int32_t* __restrict__ fan,
+                                                          const int32_t* __restrict__ tri,
+                                                          const int32_t* __restrict__ tri_crow,
+                                                          const int32_t* __restrict__ vert_body,
+                                                          const double* __restrict__ epsp,
+                                                          const double* __restrict__ epsm,
+                                                          const double* __restrict__ tri64,
+                                                          const double* __restrict__ mass,
+                                                          const double* __restrict__ Kc, TT* __restrict__ A) {
+    const int64_t i = iface_v[blockIdx.x];
+    const int32_t bd = vert_body[i];
+    const double dk = epsp[bd] - epsm[bd], hs = 0.5 * (epsp[bd] + epsm[bd]) / 3.0;
+    const double inv_m = 1.0 / mass[i];
+    const int32_t f0 = fan_ptr[i], f1 = fan_ptr[i + 1];
+    for (int64_t k = threadIdx.x; k < nv; k += 256) {
+        double acc = 0.0;
+        for (int32_t e = f0; e < f1; ++e) {
+            const int64_t t = fan[e] >> 2;
+            const double wT = tri64[(int64_t)TRI_REC * t + TR_A] / 3.0 * inv_m;
+            const int32_t* tv = tri + 3 * t;
+            const double self = (tv[0] == k || tv[1] == k || tv[2] == k) ? hs : 0.0;
+            acc += wT * (dk * Kc[(int64_t)tri_crow[t] * ld + k] + self);
+        }
+        A[i * ld + k] = (TT)acc;
+    }
+}
+
+// Rows of floating bodies with a normal-field term (literal Eq. Final4, sheets), the centroid
+// rule over the body's triangles: row f (stored at row0 + f)
+//   A[k] = sum_{T in f} (a_T/area_f) [ c_kp Kc[crow(T)][k] + c_self [k in T]/3 ]
+//        = c_kp sum_T (a_T/area_f) Kc[crow(T)][k] + c_self m_k/area_f [k on f],
+// over the body's contiguous centroid rows [cr0, cr1) in order; 0 in columns >= nv; Jacobi
+// diagonal 1 (the entry is 0).  grid (column chunks, bodies in the list).
+__global__ __launch_bounds__(256) void k_nodal_kp_body_rows(int64_t nv, int64_t ld, int64_t row0,
+                                                            const int32_t* __restrict__ flist,
+                                                            const int32_t* __restrict__ frange,
+                                                            const double* __restrict__ fcoef,
+                                                            const int32_t* __restrict__ trow,
+                                                            const int32_t* __restrict__ vert_body,
+                                                            const int32_t* __restrict__ fidx,
+                                                            const double* __restrict__ tri64,
+                                                            const double* __restrict__ mass,
+                                                            const double* __restrict__ Af,
+                                                            const double* __restrict__ Kc, double* __restrict__ A,
+                                                            double* __restrict__ diag) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int32_t f = flist[blockIdx.y];
+    if (k >= ld) return;
+    const double inv_a = 1.0 / Af[f];
+    const double cs = fcoef[2 * f], ck = fcoef[2 * f + 1];
+    double acc = 0.0;
+    if (k < nv) {
+        double s = 0.0;
+        for (int32_t r = frange[2 * f]; r < frange[2 * f + 1]; ++r)
+            s += tri64[(int64_t)TRI_REC * trow[r] + TR_A] * Kc[(int64_t)r * ld + k];
+        acc = ck * s * inv_a + (fidx[vert_body[k]] == f ? cs * mass[k] * inv_a : 0.0);
+    }
+    A[(row0 + f) * ld + k] = acc;
+    if (k == 0) diag[nv + f] = 1.0;
 }
 
 // Jacobi diagonal of the vertex rows
@@ -504,6 +732,38 @@ static void nodal_assemble_t(bem_ctx* c, T* A, double* Atail, int64_t tail_row0)
                        c->row_order.as<int32_t>(), c->vert.as<double>(), c->tri.as<int32_t>(), c->far64.as<double>(),
                        c->nodal_bounds.as<double>(), c->tri64.as<double>(), A);
     BEM_CHECK_LAUNCH();
+    const int64_t nc = (int64_t)c->h_crow_tri.size(), niv = (int64_t)c->h_iface_v.size();
+    const bool need_mass = c->n_float > 0 || niv > 0;
+    double* mass = nullptr;
+    if (need_mass) {
+        c->nodal_mass.alloc(sizeof(double) * (size_t)(nv + c->n_float));
+        mass = c->nodal_mass.as<double>();
+        hipLaunchKernelGGL(k_nodal_mass, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv,
+                           c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->tri64.as<double>(), mass);
+        BEM_CHECK_LAUNCH();
+    }
+    if (nc > 0) {
+        // normal-field rows at the centroids, then the interface vertex rows from them
+        double* Kc = c->nod_Kc.as<double>();
+        const int64_t n_rtc = ceil_div(nc, 256);
+        if (n_rtc * n_cg > ((int64_t)1 << 31) - 1) throw Error(BEM_ERR_INVALID, "too many centroid rows");
+        hipLaunchKernelGGL(k_nodal_kp_assemble, dim3((unsigned)(n_rtc * n_cg)), dim3(256), 0, s, nc, nv, ld, n_rtc,
+                           c->nod_trow.as<int32_t>(), c->grp_ptr.as<int32_t>(), c->grp_tri.as<int32_t>(),
+                           c->grp_loc.as<uint32_t>(), c->pan64.as<double>(), c->tri64.as<double>(), Kc);
+        BEM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_nodal_kp_near, dim3((unsigned)ceil_div(nc, 64)), dim3(64), 0, s, nc, ld, c->N, Np,
+                           c->nod_trow.as<int32_t>(), c->tri.as<int32_t>(), c->far64.as<double>(),
+                           c->nodal_bounds.as<double>(), c->tri64.as<double>(), Kc);
+        BEM_CHECK_LAUNCH();
+        if (niv > 0) {
+            hipLaunchKernelGGL(k_nodal_iface_rows<T>, dim3((unsigned)niv), dim3(256), 0, s, nv, ld,
+                               c->nod_iface_v.as<int32_t>(), c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(),
+                               c->tri.as<int32_t>(), c->nod_tri_crow.as<int32_t>(), c->vert_body.as<int32_t>(),
+                               c->body_epsp.as<double>(), c->body_epsm.as<double>(), c->tri64.as<double>(), mass, Kc,
+                               A);
+            BEM_CHECK_LAUNCH();
+        }
+    }
     hipLaunchKernelGGL(k_nodal_diag<T>, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv, ld, A,
                        c->diag.as<double>());
     BEM_CHECK_LAUNCH();
@@ -513,12 +773,7 @@ static void nodal_assemble_t(bem_ctx* c, T* A, double* Atail, int64_t tail_row0)
         BEM_CHECK_LAUNCH();
     }
     if (c->n_float > 0) {
-        c->nodal_mass.alloc(sizeof(double) * (size_t)(nv + c->n_float));
-        double* mass = c->nodal_mass.as<double>();
         double* Af = mass + nv;
-        hipLaunchKernelGGL(k_nodal_mass, dim3((unsigned)ceil_div(nv, 256)), dim3(256), 0, s, nv,
-                           c->fan_ptr.as<int32_t>(), c->fan.as<int32_t>(), c->tri64.as<double>(), mass);
-        BEM_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_nodal_body_area, dim3((unsigned)c->n_float), dim3(256), 0, s, nv,
                            c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(), mass, Af);
         BEM_CHECK_LAUNCH();
@@ -526,6 +781,14 @@ static void nodal_assemble_t(bem_ctx* c, T* A, double* Atail, int64_t tail_row0)
                            s, nv, tail_row0, ld, c->n_float, c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(),
                            mass, Af, Atail, c->diag.as<double>());
         BEM_CHECK_LAUNCH();
+        if (!c->h_flt_kp.empty()) {   // rows with a K' term replace their net-charge rows
+            hipLaunchKernelGGL(k_nodal_kp_body_rows, dim3((unsigned)ceil_div(ld, 256), (unsigned)c->h_flt_kp.size()),
+                               dim3(256), 0, s, nv, ld, tail_row0, c->nod_flist.as<int32_t>(),
+                               c->nod_frange.as<int32_t>(), c->flt_coef.as<double>(), c->nod_trow.as<int32_t>(),
+                               c->vert_body.as<int32_t>(), c->body_fidx.as<int32_t>(), c->tri64.as<double>(), mass, Af,
+                               c->nod_Kc.as<double>(), Atail, c->diag.as<double>());
+            BEM_CHECK_LAUNCH();
+        }
     }
 }
 

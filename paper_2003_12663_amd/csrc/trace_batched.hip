@@ -119,10 +119,12 @@ __device__ __forceinline__ double lb_segment_tri(const double* __restrict__ T, d
 // at the start; its live count is count[32 g].
 __global__ __launch_bounds__(256) void k_lb_init(int64_t L, int32_t G, const double* __restrict__ starts, LBState s,
                                                  int32_t* __restrict__ count, double* __restrict__ path,
-                                                 int64_t pstride) {
+                                                 int64_t pstride, unsigned long long* __restrict__ ncnt) {
     const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (l < G) count[32 * l] = (int32_t)((l + 1) * L / G - l * L / G);
     if (l >= L) return;
+    ncnt[2 * l] = 0;
+    ncnt[2 * l + 1] = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double v = starts[3 * l + k];
@@ -230,6 +232,10 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
             for (int k = 0; k < FR_CC; ++k) qv[k] = panR[FAR_REC * j + k];
 #pragma unroll
             for (int k = 0; k < 4; ++k) cc[k] = pan64[FAR_REC * j + FR_CC + k];
+            // the whole record is requested before the classification test and waited for once;
+            // left to itself the compiler sinks the node loads below the test, two round trips per panel
+            asm volatile("" ::"s"(qv[0]), "s"(qv[8]), "s"(qv[16]), "s"(qv[24]), "s"(qv[FR_CC - 1]), "s"(cc[0]),
+                         "s"(cc[3]));
             pair(pj, qv, cc);
         }
     }
@@ -366,7 +372,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
     const int32_t* __restrict__ line_rhs, const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind,
     int32_t* __restrict__ n_steps, int32_t* __restrict__ stop_code, double* __restrict__ integral,
     uint8_t* __restrict__ exceeds, double* __restrict__ path, int64_t pstride,
-    unsigned long long* __restrict__ near_count, const int32_t* __restrict__ ntri, const double* __restrict__ nu) {
+    unsigned long long* __restrict__ ncnt, const int32_t* __restrict__ ntri, const double* __restrict__ nu) {
     __shared__ int32_t list[LB_Q];
     __shared__ int32_t scan[4];
     __shared__ double red[4][4];
@@ -388,18 +394,28 @@ __global__ __launch_bounds__(256) void k_lb_step(
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     uint32_t mreg[LB_MREG];
     int cnt = 0;
+    // every load of the sweep is issued before any is used (indices clamped into the row, the
+    // clamped values dropped below): left conditional, each would wait for the one before
+    double pr[LB_MREG][3];
 #pragma unroll
     for (int t = 0; t < LB_MREG; ++t) {
         const int64_t k = tid + 256 * t;
-        uint32_t m = 0;
+        const int64_t kp = k < KSP ? k : KSP - 1, km = k < KS ? k : KS - 1;
+        pr[t][0] = prow[3 * kp];
+        pr[t][1] = prow[3 * kp + 1];
+        pr[t][2] = prow[3 * kp + 2];
+        mreg[t] = mrow[km];
+    }
+#pragma unroll
+    for (int t = 0; t < LB_MREG; ++t) {
+        const int64_t k = tid + 256 * t;
         if (k < KSP) {
-            e0 += prow[3 * k];
-            e1 += prow[3 * k + 1];
-            e2 += prow[3 * k + 2];
+            e0 += pr[t][0];
+            e1 += pr[t][1];
+            e2 += pr[t][2];
         }
-        if (k < KS) m = mrow[k];
-        mreg[t] = m;
-        cnt += __popc(m);
+        if (k >= KS) mreg[t] = 0;
+        cnt += __popc(mreg[t]);
     }
     for (int64_t k = tid + 256 * LB_MREG; k < KS || k < KSP; k += 256) {
         if (k < KSP) {
@@ -426,11 +442,11 @@ __global__ __launch_bounds__(256) void k_lb_step(
     for (int w = 0; w < wv; ++w) wbase += scan[w];
     const int total = scan[0] + scan[1] + scan[2] + scan[3];
     const int off = wbase + incl - cnt;
-    if (tid == 0 && near_count) {
-        atomicAdd(near_count, (unsigned long long)total);
+    if (tid == 0) {   // the line's own pair counters (one block per line and pass: no atomics)
+        ncnt[2 * l] += (unsigned long long)total;
         // every other panel of this line was a regular pair of the chunked far pass (k_lb_far);
         // the panel-stationary few-line pass (KSP != KS) is not counted
-        if (KSP == KS) atomicAdd(near_count + 1, (unsigned long long)(N - total));
+        if (KSP == KS) ncnt[2 * l + 1] += (unsigned long long)(N - total);
     }
     double n0 = 0.0, n1 = 0.0, n2 = 0.0, bt = 2.0;
     int bj = INT_MAX;
@@ -640,6 +656,29 @@ __global__ __launch_bounds__(256) void k_lb_merge(LBState s, int32_t* __restrict
 __global__ void k_lb_set_count(int32_t* __restrict__ count, int32_t v) {
     if (threadIdx.x == 0) count[0] = v;
 }
+
+// the lines' near and far pair counts added to the context's counters (one block, fixed order)
+__global__ __launch_bounds__(256) void k_lb_count_sum(int64_t L, const unsigned long long* __restrict__ ncnt,
+                                                      unsigned long long* __restrict__ counters) {
+    __shared__ unsigned long long red[2][256];
+    unsigned long long a = 0, b = 0;
+    for (int64_t l = threadIdx.x; l < L; l += 256) {
+        a += ncnt[2 * l];
+        b += ncnt[2 * l + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sa = 0, sb = 0;
+        for (int k = 0; k < 256; ++k) {
+            sa += red[0][k];
+            sb += red[1][k];
+        }
+        counters[0] += sa;
+        counters[1] += sb;
+    }
+}
 }  // namespace
 
 // Duration (ms, best of 3 after a warm-up) of one far-field pass over L lines at the points pts
@@ -750,10 +789,13 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     // group's slots stay in its range, so the groups share the buffers without overlap.  Once the
     // live lines fit one 64-line tile the groups are folded into one (two part-empty tiles would
     // cost twice the blocks of one).
-    const int32_t G = (int32_t)std::min<int64_t>(c->tune_trace_groups, L);
-    // two state buffers (x, y, ks: 3 doubles; asum, I: 1 double; ns, line: 1 int32 per slot)
-    // and two live counters per group
-    c->lb_state.alloc(sizeof(double) * (size_t)L * 22 + sizeof(int32_t) * ((size_t)L * 4 + 32 * 4));
+    // (default: two groups from 128 lines, where one group's step kernel has the other's far
+    // pass to overlap; measured 194 against 214 ms for 256 lines on the 19,732-panel coax)
+    const int32_t G = (int32_t)std::min<int64_t>(c->tune_trace_groups > 0 ? c->tune_trace_groups : (L >= 128 ? 2 : 1), L);
+    // two state buffers (x, y, ks: 3 doubles; asum, I: 1 double; ns, line: 1 int32 per slot), two
+    // live counters per group, and two pair counters per line
+    c->lb_state.alloc(sizeof(double) * (size_t)L * 22 + sizeof(int32_t) * ((size_t)L * 4 + 32 * 4) +
+                      sizeof(unsigned long long) * 2 * (size_t)L);
     c->lb_part.alloc(sizeof(double) * 3 * (size_t)KS * L + sizeof(uint32_t) * (size_t)KS * L);
     double* dbase = c->lb_state.as<double>();
     int32_t* ibase = reinterpret_cast<int32_t*>(dbase + (size_t)L * 22);
@@ -764,10 +806,11 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         buf[k] = {d, d + 3 * L, d + 6 * L, d + 9 * L, d + 10 * L, i, i + L};
     }
     int32_t* cnt0 = ibase + (size_t)L * 4;
+    unsigned long long* ncnt = reinterpret_cast<unsigned long long*>(cnt0 + 32 * 4);
     double* part = c->lb_part.as<double>();
     uint32_t* pmask = reinterpret_cast<uint32_t*>(part + 3 * (size_t)KS * L);
     hipLaunchKernelGGL(k_lb_init, dim3((unsigned)ceil_div(L, 256)), dim3(256), 0, c->stream, L, G, starts, buf[0],
-                       cnt0, path, pstride);
+                       cnt0, path, pstride, ncnt);
     BEM_CHECK_LAUNCH();
     struct Group {
         int64_t lo, size, known;   // slot range [lo, lo + size); known: upper bound on the live count
@@ -803,7 +846,6 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                 (void)hipStreamWaitEvent(c->stream, c->join_ev, 0);
         }
     } join{c, G > 1};
-    unsigned long long* near_count = reinterpret_cast<unsigned long long*>(c->counters.p);
     // nodal basis (one load case): the far passes read records whose node weights carry the
     // density, with a density of one per panel; the step kernel's near pairs read the vertex values.
     // Those records exist in FP64 only, so nodal lines take the FP64 far passes in either
@@ -895,12 +937,12 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                 hipLaunchKernelGGL(k_lb_step<true>, dim3((unsigned)q.known), dim3(256), 0, q.st, N, KS, KSP,
                                    q.cnt[cur], q.cnt[cur ^ 1], gpart, gmask, phase, sc, sn, a, c->tri64.as<double>(),
                                    sol, c->n, line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps,
-                                   stop_code, integral, exceeds, path, pstride, near_count, c->tri.as<int32_t>(), sol);
+                                   stop_code, integral, exceeds, path, pstride, ncnt, c->tri.as<int32_t>(), sol);
             else
                 hipLaunchKernelGGL(k_lb_step<false>, dim3((unsigned)q.known), dim3(256), 0, q.st, N, KS, KSP,
                                    q.cnt[cur], q.cnt[cur ^ 1], gpart, gmask, phase, sc, sn, a, c->tri64.as<double>(),
                                    sol, c->n, line_rhs, c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), n_steps,
-                                   stop_code, integral, exceeds, path, pstride, near_count, (const int32_t*)nullptr,
+                                   stop_code, integral, exceeds, path, pstride, ncnt, (const int32_t*)nullptr,
                                    (const double*)nullptr);
             BEM_CHECK_LAUNCH();
             }
@@ -921,7 +963,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             if (live == 0) break;
             // fold group 1 into group 0 once all live lines fit one tile and group 0's slot range
             // (both streams are idle here: the counts above were read after synchronising them)
-            if (G > 1 && grp[1].known > 0 && live <= std::min<int64_t>(64, grp[1].lo)) {
+            if (G > 1 && c->tune_trace_fold && grp[1].known > 0 && live <= std::min<int64_t>(64, grp[1].lo)) {
                 hipLaunchKernelGGL(k_lb_merge, dim3(1), dim3(256), 0, grp[0].st, buf[cur], grp[0].cnt[cur],
                                    grp[1].cnt[cur], grp[1].lo);
                 BEM_CHECK_LAUNCH();
@@ -930,6 +972,13 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             }
         }
     }
+    if (G > 1) {   // the counts below need both groups' step kernels
+        BEM_HIP(hipEventRecord(c->join_ev, c->aux_stream));
+        BEM_HIP(hipStreamWaitEvent(c->stream, c->join_ev, 0));
+    }
+    hipLaunchKernelGGL(k_lb_count_sum, dim3(1), dim3(256), 0, c->stream, L, ncnt,
+                       reinterpret_cast<unsigned long long*>(c->counters.p));
+    BEM_CHECK_LAUNCH();
 }
 
 namespace {

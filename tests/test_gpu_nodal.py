@@ -56,7 +56,7 @@ CASES = [
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_nodal_matrix_rhs_solution(bem, name, make):
     p = make()
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(p, constraint_form=1)
     A = o.p1_assemble()
     b_ref = o.p1_rhs(p.body_V)
     x_ref = np.linalg.solve(A, b_ref)
@@ -107,13 +107,13 @@ def test_nodal_large_sampled_rows(bem):
     p = sphere_problem(5)
     c = _ctx(bem, p)
     rows = np.unique(np.concatenate([[0, 1, 63, 64, p.n_vert - 1], np.random.default_rng(2).integers(0, p.n_vert, 11)]))
-    R = oracle.Oracle(p).p1_assemble_rows(rows)
+    R = oracle.Oracle(p, constraint_form=1).p1_assemble_rows(rows)
     for k, r in enumerate(rows):
         g = c.copy_rows(int(r), 1)[0].cpu().numpy()
         assert np.abs(g - R[k]).max() <= 1e-12 * np.abs(R[k]).max(), r
     sol, info = c.solve(p.body_V, tol=1e-12, max_iter=5000)
     x = sol[0].cpu().numpy()
-    b = oracle.Oracle(p).p1_rhs(p.body_V)[rows]
+    b = oracle.Oracle(p, constraint_form=1).p1_rhs(p.body_V)[rows]
     assert np.abs(R @ x - b).max() <= 1e-10
     c.close()
 
@@ -127,7 +127,7 @@ def test_nodal_paper_size_sampled_rows(bem):
     c = _ctx(bem, p)
     nv = p.n_vert
     rows = np.unique(np.concatenate([[0, 255, 256, nv - 1, nv], np.random.default_rng(5).integers(0, nv, 7)]))
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(p, constraint_form=1)
     R = o.p1_assemble_rows(rows)
     for k, r in enumerate(rows):
         g = c.copy_rows(int(r), 1)[0].cpu().numpy()
@@ -142,7 +142,7 @@ def test_nodal_paper_size_sampled_rows(bem):
 
 
 def _lines_vs_oracle(bem, p, starts, tp_kw):
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(p, constraint_form=1)
     u_ref = np.linalg.solve(o.p1_assemble(), o.p1_rhs(p.body_V))
     c = _ctx(bem, p)
     sol, info = c.solve(p.body_V, tol=1e-13, max_iter=5000)
@@ -200,7 +200,7 @@ def test_nodal_field_lines_two_load_cases(bem):
     ns_p, st_p, path = c.trace_lines(sol, torch.tensor(starts, device="cuda"), tp, line_rhs=lr, want_path=True)
     I, ns, st = I.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
     assert np.array_equal(ns, ns_p.cpu().numpy()) and np.array_equal(st, st_p.cpu().numpy())
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(p, constraint_form=1)
     for r in range(2):
         sel = np.nonzero(lr == r)[0]
         I1, ns1, st1, _ = c.streamer_integral(sol[r:r + 1], torch.tensor(starts[sel], device="cuda"), tp)
@@ -277,7 +277,7 @@ def test_nodal_mixed_field_lines(bem):
     print(f"[nodal] mixed lines: integral error vs FP64 {e:.2e}", flush=True)
     assert e <= 1e-4
     # the same lines against the oracle's nodal trace of the FP64 vertex values
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(p, constraint_form=1)
     ns_o, st_o, I_o = o.p1_trace(s64[0].cpu().numpy(), starts, oracle.trace_params(**kw))
     assert np.array_equal(ns32.cpu().numpy(), ns_o) and np.array_equal(st32.cpu().numpy(), st_o)
     assert np.abs(I32.cpu().numpy() - I_o).max() <= 1e-10 * np.abs(I_o).max()
@@ -297,7 +297,7 @@ def test_nodal_mixed_232k_sampled_rows(bem):
     c.assemble()
     nv = p.n_vert
     rows = np.unique(np.concatenate([[0, nv - 1, nv], np.random.default_rng(6).integers(0, nv, 5)]))
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(p, constraint_form=1)
     R = o.p1_assemble_rows(rows)
     for k, r in enumerate(rows):
         g = c.copy_rows(int(r), 1)[0].cpu().numpy()
@@ -346,11 +346,6 @@ def test_nodal_batched_load_cases(bem):
 
 def test_nodal_refusals(bem):
     p = sphere_problem(1)
-    with pytest.raises(bem.BemError):   # the net-charge row is required
-        bem.Context.from_problem(p, basis=bem.BASIS_LINEAR, constraint_form=0)
-    from workloads import coated_sphere_problem
-    with pytest.raises(bem.BemError):   # interface bodies need a normal at the vertex
-        bem.Context.from_problem(coated_sphere_problem(1), basis=bem.BASIS_LINEAR, constraint_form=1)
     c = _ctx(bem, p)
     sol, _ = c.solve(p.body_V, tol=1e-10)
     with pytest.raises(bem.BemError):   # volume points only

@@ -66,10 +66,13 @@ def test_tuning_knob_validation(bem):
     p = sphere_problem(1)
     ctx = bem.Context.from_problem(p)
     for key, bad in (("far_rows", 48), ("gemv_rows", 3), ("eval_blocks", 10), ("trace_split", -1),
-                     ("trace_tile", 96), ("trace_groups", 0), ("trace_groups", 3), ("grad_batch", 8), ("nope", 1)):
+                     ("trace_tile", 96), ("trace_groups", -1), ("trace_groups", 3), ("trace_fold", 2),
+                     ("near_rule", 2), ("grad_batch", 8), ("nope", 1)):
         with pytest.raises(bem.BemError):
             ctx.set_tuning(key, bad)
     assert ctx.get_tuning("gemv_rows") == 4      # FP64 default
+    assert ctx.get_tuning("trace_groups") == 0   # two line groups from 128 lines
+    assert ctx.get_tuning("trace_fold") == 1 and ctx.get_tuning("near_rule") == 0
     ctx.set_tuning("gemv_rows", 8)
     assert ctx.get_tuning("gemv_rows") == 8
     with pytest.raises(bem.BemError):

@@ -82,6 +82,34 @@ def test_duffy_against_closed_forms(oracle_mod, dmin, dmax, bar):
     assert worst <= bar, worst
 
 
+def test_closed_forms_above_an_edge(oracle_mod):
+    """Points a short height above an edge of slender triangles (foot on the edge): the
+    closed form's log term (R- + s-) loses digits to R - |s| there unless it is taken as
+    R0^2 / (R- - s-); against the near-singular rule, which has no such cancellation.
+    Both forms of the log term are the same number; the bar, 3e-10, is set by the height
+    itself, known to about eps |x - v1| / |w| (1e-9 relative at 1e-7 of the edge), while the
+    cancelling form was off by 7e-8 on such points."""
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for s in range(30):
+        # a slender triangle: base along x, apex displaced, height 0.1..0.3 of the base
+        L = 1.0
+        v = np.array([[0.0, 0.0, 0.0], [L, 0.0, 0.0], [rng.uniform(0.1, 0.9), rng.uniform(0.1, 0.3), 0.0]])
+        R = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+        v = v @ R.T + rng.standard_normal(3)
+        nrm = np.cross(v[1] - v[0], v[2] - v[0])
+        nrm /= np.linalg.norm(nrm)
+        for _ in range(6):
+            a = rng.uniform(0.05, 0.95)
+            foot = v[0] + a * (v[1] - v[0])
+            h = 10 ** rng.uniform(-7, -4) * rng.choice([-1.0, 1.0])
+            x = foot + h * nrm
+            S, F = oracle_mod.tri_duffy(x, *v)
+            Sa, Fa = oracle_mod.tri_analytic(x, *v)
+            worst = max(worst, abs(S - Sa) / abs(Sa), np.abs(F - Fa).max() / np.abs(Fa).max())
+    assert worst <= 3e-10, worst
+
+
 def test_duffy_singular_potential(oracle_mod):
     # x on the triangle (the self pair at the centroid, and other interior points): the
     # potential against the principal-value closed form; F is not produced (NaN)
