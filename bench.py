@@ -82,6 +82,8 @@ def parse():
                     help="skip the gradient and the 64-load-case x 64-line runs")
     ap.add_argument("--extras-only", action="store_true", help="only the gradient and 4096-line runs")
     ap.add_argument("--nodal-only", action="store_true", help="only the nodal-basis sphere run")
+    ap.add_argument("--mixed-step", action="store_true",
+                    help="only the benchmark step in MIXED precision (FP32 far field), for kernel profiles")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON): reuse one tile choice across runs, e.g. for counter runs")
     ap.add_argument("--set-tuning", default=None,
@@ -214,6 +216,42 @@ def cases_by_lines_run(bem, torch, p, ctx):
         out[name] = {"s": dt, "field_evals": passes, "pairs_per_s": passes * p.n_tri / dt,
                      "integral_sum": float(I.sum().item())}
     ctx.set_tuning("trace_mode", 0)
+    return out
+
+
+def mixed_step_run(bem, torch, p, cen, on_panel, starts, tp, args):
+    """The benchmark step in MIXED precision (FP32 far field, FP64 near entries, Krylov vectors
+    and refinement): assembly, solve to 1e-8, E at the centroids and the 256 field lines, after
+    one warm-up step; per-phase kernel times from the library's event timers."""
+    ctx = bem.Context.from_problem(p, precision=bem.MIXED, eta=6.0, restart=100)
+    ctx.assemble()
+    ctx.autotune(None)
+
+    def step():
+        ctx.assemble()
+        sol, info = ctx.solve(p.body_V, tol=1e-8, max_iter=5000)
+        ctx.eval_field(sol, cen, on_panel=on_panel, want_phi=False)
+        I, ns, st, _ = ctx.streamer_integral(sol, starts, tp)
+        return sol, info, I, ns, st
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sol, info, I, ns, st = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ctx.set_profiling(1)
+    ctx.reset_stats()
+    step()
+    torch.cuda.synchronize()
+    phases = {k: ctx.kernel_stats(k)[1] for k in ("far_assemble", "near_assemble", "gemv", "eval_far", "trace",
+                                                    "trace_far", "trace_step")}
+    ctx.set_profiling(0)
+    out = {"ms_per_step": ms, "gmres_iters": info["iters"], "refinements": info["refinements"],
+           "streamer_integral_sum": float(I.sum().item()), "phase_ms": phases,
+           "stop_code_counts": {str(k): int((st.cpu().numpy() == k).sum()) for k in range(6)}}
+    ctx.close()
     return out
 
 
@@ -479,6 +517,10 @@ def main():
     if args.nodal_only:
         ctx.close()
         print(json.dumps({"nodal_basis": nodal_run(bem, torch)}))
+        return
+    if args.mixed_step:
+        ctx.close()
+        print(json.dumps({"mixed_step": mixed_step_run(bem, torch, p, cen, on_panel, starts, tp, args)}))
         return
     if args.tts_only:
         ctx.assemble()

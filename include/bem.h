@@ -193,6 +193,33 @@ bem_status bem_matvec(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, in
  * transpose in MIXED precision), STATE (not assembled), HIP. */
 bem_status bem_matvec_noalloc(bem_ctx* ctx, int32_t nrhs, const double* x, double* y, int32_t transpose);
 
+/* Sizes of a compressed operator (bem_compress). */
+typedef struct {
+    int64_t blocks;          /* blocks of the block tree */
+    int64_t lowrank_blocks;  /* of them stored as U V^T */
+    int64_t dense_entries;   /* doubles in the dense blocks */
+    int64_t factor_entries;  /* doubles in the low-rank factors */
+    int64_t max_rank;        /* largest rank of a low-rank block */
+} bem_compress_info;
+
+/* Compress the collocation operator (the outlook of Sec. 6: hierarchical matrices in place of
+ * the dense N x N matrix) and use it for the products of bem_matvec and bem_solve_gmres.
+ * The panel-panel block becomes a hierarchical matrix: a cluster tree of the panels by
+ * geometric bisection down to leaves of at most `leaf` panels (8..256); cluster pairs whose
+ * bounding boxes are admissible, min(diam) <= eta_adm * dist (eta_adm > 0), are stored in low
+ * rank by adaptive cross approximation with partial pivoting to the relative tolerance eps
+ * (0 < eps < 1; rank at most 64, else the block is stored dense), the others dense at leaf
+ * level.  Every entry is the assembly's own (Sec. 4 classification, 7-point rule, closed
+ * forms, the row scaling of Eqs. Final1-Final3), evaluated on demand: no N x N array is
+ * formed.  The floating bodies' potential columns and constraint rows (Eq. Final4, sheets,
+ * net charge) are kept exactly.  Replaces the dense operator (its memory is released);
+ * bem_assemble restores the dense one.  CONSTANT basis, FP64.  While it is in use: no
+ * transpose product (bem_matvec transpose, bem_streamer_grad), no bem_copy_rows, no
+ * bem_matvec_noalloc (INVALID), and several right-hand sides are solved one after another.
+ * info may be NULL.  Errors: INVALID (options, basis, precision), OOM (checked before the
+ * factors are allocated), HIP. */
+bem_status bem_compress(bem_ctx* ctx, double eps, double eta_adm, int32_t leaf, bem_compress_info* info);
+
 /* Single-layer potential S = (1/4pi) int 1/|x - y| dS and field F = -grad S =
  * (1/4pi) int (x - y)/|x - y|^3 dS of unit density on panel[p] at pts[p], p < P (Sec. 4 and
  * the field formula closing Sec. 2).  rule 0: the closed forms of the flat triangle

@@ -128,6 +128,12 @@ class Context:
                                            int(bool(transpose))), self.lib)
         return y
 
+    def compress(self, eps=1e-8, eta_adm=1.0, leaf=64):
+        """bem_compress: the hierarchical-matrix operator in place of the dense one; returns its sizes."""
+        info = _lib.CompressInfo()
+        _check(self.lib.bem_compress(self._ctx, float(eps), float(eta_adm), int(leaf), ctypes.byref(info)), self.lib)
+        return {k: int(getattr(info, k)) for k, _ in _lib.CompressInfo._fields_}
+
     def pair_integrals(self, pts, panel, rule=0):
         """bem_pair_integrals: S [P] and F [P, 3] (numpy) of unit density on panel[p] at pts[p];
         rule 0 closed forms, 1 the near-singular rule (closest point, subdivision, Duffy)."""

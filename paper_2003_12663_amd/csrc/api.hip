@@ -483,6 +483,7 @@ void bem_destroy(bem_ctx* c) {
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->aux_stream) (void)hipStreamSynchronize(c->aux_stream);
+    bem::hmatrix_release(c);
     delete c;
 }
 
@@ -494,6 +495,7 @@ bem_status bem_assemble(bem_ctx* c) {
     if (!c) return fail(BEM_ERR_INVALID, "NULL context");
     DeviceGuard g(c->device);
     API_TRY
+    bem::hmatrix_release(c);   // the dense operator replaces a compressed one
     if (c->opt.basis == BEM_BASIS_LINEAR) {
         // FP64: one n x ld matrix.  MIXED: the vertex rows in FP32 (nb x ld) and the constraint
         // rows in FP64 (n_float x ld), with an empty list of FP64 near remainders
@@ -577,6 +579,7 @@ bem_status bem_copy_rows(bem_ctx* c, int64_t row0, int64_t n_rows, double* out) 
     DeviceGuard g(c->device);
     API_TRY
     check_assembled(c);
+    if (c->hm) throw bem::Error(BEM_ERR_INVALID, "the compressed operator keeps no dense rows");
     if (row0 < 0 || n_rows < 0 || row0 + n_rows > c->n) throw bem::Error(BEM_ERR_INVALID, "row range out of bounds");
     if (n_rows == 0) return BEM_OK;
     if (!out) throw bem::Error(BEM_ERR_INVALID, "out pointer is NULL");
@@ -606,7 +609,8 @@ bem_status bem_matvec(bem_ctx* c, int32_t nrhs, const double* x, double* y, int3
     check_assembled(c);
     if (nrhs < 1 || !x || !y) throw bem::Error(BEM_ERR_INVALID, "nrhs >= 1 and non-NULL vectors required");
     if (transpose != 0 && transpose != 1) throw bem::Error(BEM_ERR_INVALID, "transpose must be 0 or 1");
-    if (nrhs >= 2 && !transpose && c->batched_solve) {
+    if (transpose && c->hm) throw bem::Error(BEM_ERR_INVALID, "the compressed operator has no transpose product");
+    if (nrhs >= 2 && !transpose && c->batched_solve && !c->hm) {
         for (int32_t r0 = 0; r0 < nrhs; r0 += 64)
             bem::batched_apply_exact(c, (int)std::min<int32_t>(64, nrhs - r0), x + (int64_t)r0 * c->n,
                                      y + (int64_t)r0 * c->n);
@@ -658,7 +662,7 @@ bem_status bem_solve_gmres(bem_ctx* c, int32_t nrhs, const double* body_V, doubl
     int total_it = 0, total_ref = 0;
     double worst = 0.0;
     bool all_conv = true;
-    if (nrhs >= 2 && c->batched_solve) {
+    if (nrhs >= 2 && c->batched_solve && !c->hm) {
         // groups of up to 64 load cases, one shared matrix product per iteration
         for (int32_t r0 = 0; r0 < nrhs; r0 += 64) {
             const int nr = (int)std::min<int32_t>(64, nrhs - r0);
@@ -802,6 +806,36 @@ bem_status bem_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const d
     for (double v : hb)
         if (!std::isfinite(v)) throw bem::Error(BEM_ERR_INVALID, "non-finite barycentric coordinate");
     bem::launch_panel_points(c, L, panel, bary, offset, out);
+    return BEM_OK;
+    API_CATCH
+}
+
+bem_status bem_compress(bem_ctx* c, double eps, double eta_adm, int32_t leaf, bem_compress_info* info) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (c->opt.basis != BEM_BASIS_CONSTANT || c->opt.precision != BEM_FP64)
+        throw bem::Error(BEM_ERR_INVALID, "compression needs the CONSTANT basis in FP64");
+    if (!(eps > 0.0 && eps < 1.0)) throw bem::Error(BEM_ERR_INVALID, "eps must lie in (0, 1)");
+    if (!(eta_adm > 0.0) || !std::isfinite(eta_adm)) throw bem::Error(BEM_ERR_INVALID, "eta_adm must be finite and > 0");
+    if (leaf < 8 || leaf > 256) throw bem::Error(BEM_ERR_INVALID, "leaf must lie in 8..256");
+    // the dense operator is released first: the compressed one is built in its place
+    c->assembled = false;
+    c->A64.release();
+    c->A32.release();
+    c->Kf.release();
+    c->nearmask.release();
+    bem::HmStats st{};
+    bem::hmatrix_build(c, eps, eta_adm, leaf, &st);
+    c->near_nnz = 0;
+    c->assembled = true;
+    if (info) {
+        info->blocks = st.blocks;
+        info->lowrank_blocks = st.lowrank_blocks;
+        info->dense_entries = st.dense_entries;
+        info->factor_entries = st.factor_entries;
+        info->max_rank = st.max_rank;
+    }
     return BEM_OK;
     API_CATCH
 }

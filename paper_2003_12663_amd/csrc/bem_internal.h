@@ -96,6 +96,13 @@ struct KStat {
 
 }  // namespace bem
 
+namespace bem {
+struct HMatrix;   // compressed operator (hmatrix.hip)
+struct HmStats {
+    int64_t blocks, lowrank_blocks, dense_entries, factor_entries, max_rank;
+};
+}  // namespace bem
+
 struct bem_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -153,6 +160,7 @@ struct bem_ctx {
 
     bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part, rows_part;   // batched GMRES
     bem::DBuf near_sf;   // S, F of the near list by the near-singular rule (near_rule 1)
+    bem::HMatrix* hm = nullptr;   // compressed operator in use (bem_compress), else the dense matrix
 
     // gradient of the streamer integrals
     bem::DBuf ad_state, ad_part, ad_mask, ad_cnt, ad_self, ad_ppart, ad_list, ad_path, ad_stage, ad_geo, ad_seg,
@@ -240,6 +248,10 @@ void launch_nodal_records(bem_ctx* c, const double* u);                         
 void launch_nodal_field(bem_ctx* c, int32_t nrhs, const double* sol, int64_t P, const double* pts, double* phi,
                         double* E);                                                  // nodal.hip
 void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);      // gemv.hip
+// compressed operator (hmatrix.hip): build (replacing any earlier one), product, release
+void hmatrix_build(bem_ctx* c, double eps, double eta, int leaf, HmStats* st);
+void hmatrix_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s);
+void hmatrix_release(bem_ctx* c);
 void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s);    // gemv.hip
 // the product without allocation: its work array's device address for the current device (looked
 // up once per device), and the product through that array (gemv.hip)

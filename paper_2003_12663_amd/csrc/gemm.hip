@@ -132,63 +132,96 @@ __global__ __launch_bounds__(256) void k_gemm_f32_sum(const float* __restrict__ 
 // columns over one of GD_KS ranges of K.  Workgroups are dealt to the 8 XCDs round-robin, so with
 // the K range taken as blockIdx % GD_KS every block of one XCD works one K range: that range's
 // slice of Z (64 x K/8 doubles, 1.3 MB at 20k unknowns) stays in the XCD's L2 for all row blocks,
-// while each A entry is read from HBM once.  Per 16-wide k step a lane holds 4 consecutive k of
-// its A row and of 4 Z columns, and the wave runs 16 MFMAs; the next step's operands are loaded
-// before this step's MFMAs are issued.  The 64 x 64 partial tile is transposed through LDS and
-// leaves as column segments of 64 rows; k_gemm_f64_sum adds the K ranges in order.
-constexpr int GD_ROWS = 64, GD_KS = 8;
-
-template <typename TA>
-__device__ __forceinline__ void gd_load(const TA* __restrict__ Ap, const double* __restrict__ Zt, int64_t ldz, int r,
-                                        int64_t k, double a[4], double b[4][4]) {
-    if (sizeof(TA) == 4) {
-        const f4v av = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k));
-        a[0] = av[0]; a[1] = av[1]; a[2] = av[2]; a[3] = av[3];
-    } else {
-        const d2v a0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k));
-        const d2v a1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k) + 1);
-        a[0] = a0[0]; a[1] = a0[1]; a[2] = a1[0]; a[3] = a1[1];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const double* zp = Zt + (int64_t)(16 * c + r) * ldz + k;
-        const d2v z0 = reinterpret_cast<const d2v*>(zp)[0];
-        const d2v z1 = reinterpret_cast<const d2v*>(zp)[1];
-        b[c][0] = z0[0]; b[c][1] = z0[1]; b[c][2] = z1[0]; b[c][3] = z1[1];
-    }
-}
+// while each A entry is read from HBM once.  Per 32-wide k step the block stages a 64 x 32 tile of
+// A (FP32 entries widened) and a 64 x 32 tile of Z in LDS with row-contiguous loads (4 threads
+// cover a 256-byte row segment), the next step's tiles prefetched into registers; each wave then
+// runs 32 MFMAs with its operands read from LDS (a lane takes 4 consecutive k of its A row and of
+// 4 Z columns per 16 k).  The 64 x 64 partial tile is transposed through the same LDS and leaves
+// as column segments of 64 rows; k_gemm_f64_sum adds the K ranges in order.
+constexpr int GD_ROWS = 64, GD_KS = 8, GD_KC = 32, GD_PAD = 34;
 
 template <typename TA>
 __global__ __launch_bounds__(256) void k_gemm_f64(const TA* __restrict__ A, int64_t lda, int64_t M, int64_t K,
                                                   const double* __restrict__ Zt, int64_t ldz, int64_t kb_per, int KS,
                                                   double* __restrict__ Ypart) {
-    __shared__ double tile[64][GD_ROWS + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // A and Z tiles, reused after the loop for the 64 x 65 output tile (4160 <= 4352 doubles)
+    __shared__ __attribute__((aligned(16))) double smem[2 * 64 * GD_PAD];
+    double(*As)[GD_PAD] = reinterpret_cast<double(*)[GD_PAD]>(smem);
+    double(*Bs)[GD_PAD] = reinterpret_cast<double(*)[GD_PAD]>(smem + 64 * GD_PAD);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q4 = lane >> 4;   // row (A) / column (Z) within 16, k group 0..3
     const int64_t ks = blockIdx.x % KS, rb = blockIdx.x / KS;
     const int64_t row0 = rb * GD_ROWS;
-    const int64_t arow = row0 + 16 * wv + r < M ? row0 + 16 * wv + r : M - 1;   // rows past M: read, not stored
-    const TA* __restrict__ Ap = A + arow * lda;
-    const int64_t kblocks = K / 16;
+    const int64_t kblocks = K / GD_KC;
     const int64_t kb0 = ks * kb_per, kb1 = kb0 + kb_per < kblocks ? kb0 + kb_per : kblocks;
+    // this thread's staging slot: A row / Z column sr, 8 doubles from sc
+    const int sr = tid >> 2, sc = 8 * (tid & 3);
+    const int64_t ar = row0 + sr < M ? row0 + sr : M - 1;   // rows past M: read, never stored
+    const TA* __restrict__ Ap = A + ar * lda + sc;
+    const double* __restrict__ Zp = Zt + (int64_t)sr * ldz + sc;
+    double ra[8], rz[8];
+    auto load = [&](int64_t k) {
+        if (sizeof(TA) == 4) {
+            const f4v x0 = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k));
+            const f4v x1 = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(Ap + k) + 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ra[e] = x0[e];
+                ra[4 + e] = x1[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Ap + k) + e);
+                ra[2 * e] = x[0];
+                ra[2 * e + 1] = x[1];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const d2v z = reinterpret_cast<const d2v*>(Zp + k)[e];
+            rz[2 * e] = z[0];
+            rz[2 * e + 1] = z[1];
+        }
+    };
     d4v acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = (d4v){0.0, 0.0, 0.0, 0.0};
-    double a[4], b[4][4], an[4], bn[4][4];
-    if (kb0 < kb1) gd_load(Ap, Zt, ldz, r, kb0 * 16 + 4 * q4, a, b);
+    if (kb0 < kb1) load(kb0 * GD_KC);
     for (int64_t kb = kb0; kb < kb1; ++kb) {
-        if (kb + 1 < kb1) gd_load(Ap, Zt, ldz, r, (kb + 1) * 16 + 4 * q4, an, bn);
+        __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int e = 0; e < 4; ++e) {
+            *reinterpret_cast<d2v*>(&As[sr][sc + 2 * e]) = (d2v){ra[2 * e], ra[2 * e + 1]};
+            *reinterpret_cast<d2v*>(&Bs[sr][sc + 2 * e]) = (d2v){rz[2 * e], rz[2 * e + 1]};
+        }
+        __syncthreads();
+        if (kb + 1 < kb1) load((kb + 1) * GD_KC);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[c][s], acc[c], 0, 0, 0);
+        for (int u = 0; u < 2; ++u) {
+            const int kk = 16 * u + 4 * q4;
+            const d2v a0 = *reinterpret_cast<const d2v*>(&As[16 * wv + r][kk]);
+            const d2v a1 = *reinterpret_cast<const d2v*>(&As[16 * wv + r][kk + 2]);
+            const double a[4] = {a0[0], a0[1], a1[0], a1[1]};
+            double b[4][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            a[s] = an[s];
+            for (int c = 0; c < 4; ++c) {
+                const d2v b0 = *reinterpret_cast<const d2v*>(&Bs[16 * c + r][kk]);
+                const d2v b1 = *reinterpret_cast<const d2v*>(&Bs[16 * c + r][kk + 2]);
+                b[c][0] = b0[0];
+                b[c][1] = b0[1];
+                b[c][2] = b1[0];
+                b[c][3] = b1[1];
+            }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c][s] = bn[c][s];
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], b[c][s4], acc[c], 0, 0, 0);
         }
     }
+    __syncthreads();   // every wave is done with the tiles before they are overwritten
+    double(*tile)[GD_ROWS + 1] = reinterpret_cast<double(*)[GD_ROWS + 1]>(smem);
     // accumulator element v of lane (r, q4): row 4 v + q4 (+16 wv), column r (+16 c)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -239,16 +272,24 @@ __global__ __launch_bounds__(256) void k_rows_part(const double* __restrict__ A,
     }
 }
 
-// Y[col][m] (+)= alpha * sum_b part[b][m][col], blocks in order
-__global__ __launch_bounds__(64) void k_rows_sum(const double* __restrict__ part, int G, int M, int ncols,
-                                                 double* __restrict__ Y, int64_t ldy, int accumulate, double alpha) {
-    const int col = threadIdx.x, m = blockIdx.x;
-    if (col >= ncols) return;
+// Y[col][m] (+)= alpha * sum_b part[b][m][col]: 16 lanes per column each sum every 16th block,
+// then the 16 sums are added in lane order (a fixed order; one block per row)
+__global__ __launch_bounds__(1024) void k_rows_sum(const double* __restrict__ part, int G, int M, int ncols,
+                                                   double* __restrict__ Y, int64_t ldy, int accumulate,
+                                                   double alpha) {
+    __shared__ double red[16][64];
+    const int col = threadIdx.x & 63, q = threadIdx.x >> 6, m = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < G; ++b) s += part[((int64_t)b * M + m) * 64 + col];
-    s *= alpha;
+    for (int b = q; b < G; b += 16) s += part[((int64_t)b * M + m) * 64 + col];
+    red[q][col] = s;
+    __syncthreads();
+    if (q != 0 || col >= ncols) return;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += red[k][col];
+    t *= alpha;
     double* y = Y + (int64_t)col * ldy + m;
-    *y = accumulate ? *y + s : s;
+    *y = accumulate ? *y + t : t;
 }
 
 }  // namespace
@@ -277,10 +318,10 @@ void launch_gemm_f32(bem_ctx* c, const float* A, int64_t lda, int64_t M, int64_t
 void launch_gemm_f64(bem_ctx* c, const void* A, bool a_is_f32, int64_t lda, int64_t M, int64_t K, const double* Zt,
                      int64_t ldz, int ncols, double* Y, int64_t ldy, bool accumulate, double alpha) {
     if (M <= 0) return;
-    if (K % 16 != 0 || ldz % 2 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f64 shape not padded");
+    if (K % GD_KC != 0 || ldz % 2 != 0 || lda % 4 != 0) throw Error(BEM_ERR_INVALID, "gemm_f64 shape not padded");
     KTimer t(c, "gemm_f64");
     const int64_t rb = ceil_div(M, GD_ROWS);
-    const int64_t kblocks = K / 16;
+    const int64_t kblocks = K / GD_KC;
     int64_t KS = std::min<int64_t>(GD_KS, kblocks);
     const int64_t kb_per = ceil_div(kblocks, KS);
     KS = ceil_div(kblocks, kb_per);
@@ -315,7 +356,7 @@ void launch_gemm_rows(bem_ctx* c, const double* A, int64_t lda, int64_t M, int64
     hipLaunchKernelGGL(k_rows_part, dim3((unsigned)Gn), dim3(256), 0, c->stream, A, lda, (int)M, K, Zn, kper,
                        c->rows_part.as<double>());
     BEM_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)M), dim3(64), 0, c->stream, c->rows_part.as<double>(), (int)Gn,
+    hipLaunchKernelGGL(k_rows_sum, dim3((unsigned)M), dim3(1024), 0, c->stream, c->rows_part.as<double>(), (int)Gn,
                        (int)M, ncols, Y, ldy, (int)accumulate, alpha);
     BEM_CHECK_LAUNCH();
 }

@@ -193,6 +193,10 @@ void matvec_rb(bem_ctx* c, const double* x, double* y, hipStream_t s) {
 
 // y = A x for the assembled operator (FP64 or mixed); rows per block from the tuning
 void launch_matvec(bem_ctx* c, const double* x, double* y, hipStream_t s) {
+    if (c->hm) {
+        hmatrix_matvec(c, x, y, s);
+        return;
+    }
     KTimer t(c, "gemv");
     switch (c->tune_gemv_rows) {
         case 2: matvec_rb<2>(c, x, y, s); break;
@@ -215,6 +219,7 @@ void matvec_t_into(bem_ctx* c, const double* x, double* y, double* part, hipStre
 }
 
 void launch_matvec_t(bem_ctx* c, const double* x, double* y, hipStream_t s) {
+    if (c->hm) throw Error(BEM_ERR_INVALID, "the compressed operator has no transpose product");
     KTimer t(c, "gemvT");
     if (c->opt.precision != BEM_FP64) throw Error(BEM_ERR_INVALID, "transpose matvec needs precision FP64");
     c->ev_tmp.alloc(sizeof(double) * GT_SLABS * c->n);
@@ -261,6 +266,7 @@ void matvec_noalloc(bem_ctx* c, int32_t nrhs, const double* x, double* y, int tr
     if (transpose && c->opt.precision != BEM_FP64)
         throw Error(BEM_ERR_INVALID, "transpose matvec needs precision FP64");
     if (!c->assembled) throw Error(BEM_ERR_STATE, "bem_assemble has not run");
+    if (c->hm) throw Error(BEM_ERR_INVALID, "bem_matvec_noalloc needs the dense operator");
     double* base = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
