@@ -60,6 +60,8 @@ FLOP_FIELD_PAIR = 141
 K_LB_FAR_FETCH_KIB = 5062.3
 K_LB_FAR_WRITE_KIB = 2852.8
 K_LB_FAR_TRAFFIC_BYTES = (2.0 * K_LB_FAR_FETCH_KIB + 1.0 * K_LB_FAR_WRITE_KIB) * 1024.0
+# the same for k_lf_pass, the default one-launch-per-stage layout: not yet taken (None)
+K_LF_PASS_TRAFFIC_BYTES = None
 FLOP_POT_PAIR = 86
 FP64_VALU_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -225,7 +227,7 @@ def mixed_step_run(bem, torch, p, cen, on_panel, starts, tp, args):
     one warm-up step; per-phase kernel times from the library's event timers."""
     ctx = bem.Context.from_problem(p, precision=bem.MIXED, eta=6.0, restart=100)
     ctx.assemble()
-    ctx.autotune(None)
+    ctx.autotune(args.tune_cache)
 
     def step():
         ctx.assemble()
@@ -246,7 +248,7 @@ def mixed_step_run(bem, torch, p, cen, on_panel, starts, tp, args):
     step()
     torch.cuda.synchronize()
     phases = {k: ctx.kernel_stats(k)[1] for k in ("far_assemble", "near_assemble", "gemv", "eval_far", "trace",
-                                                    "trace_far", "trace_step")}
+                                                    "trace_far", "trace_step", "trace_pass")}
     ctx.set_profiling(0)
     out = {"ms_per_step": ms, "gmres_iters": info["iters"], "refinements": info["refinements"],
            "streamer_integral_sum": float(I.sum().item()), "phase_ms": phases,
@@ -546,8 +548,9 @@ def main():
         for kv in args.set_tuning.split(","):
             key, val = kv.split("=")
             ctx.set_tuning(key.strip(), int(val))
-    tuning = {k: ctx.get_tuning(k) for k in ("far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_tile",
-                                              "trace_splitk", "trace_split", "trace_few", "trace_groups")}
+    tuning = {k: ctx.get_tuning(k) for k in ("far_rows", "gemv_rows", "gemm_blocks", "eval_blocks", "trace_mode",
+                                              "trace_lpb", "trace_rnd", "trace_tile", "trace_splitk", "trace_split",
+                                              "trace_few", "trace_groups")}
     if tuning["trace_groups"] == 0:   # the library's default: two line groups from 128 lines
         tuning["trace_groups"] = 2 if args.lines >= 128 else 1
 
@@ -573,9 +576,13 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.1f} ms/step", file=sys.stderr, flush=True)
+    # regular pairs and launches of the two-kernel far passes (k_lb_far) and of the one-launch stages
+    # (k_lf_pass: the last few lines by default, every stage with trace_mode 3)
     far_launches = ctx.counter("trace_far_launches") / args.steps
-    far_pairs = ctx.counter("trace_far_pairs") / args.steps   # regular pairs of the far passes
-    near_line_pairs = ctx.counter("trace_near_pairs") / args.steps
+    far_pairs = ctx.counter("trace_far_pairs") / args.steps
+    pass_launches = ctx.counter("trace_pass_launches") / args.steps
+    pass_pairs = ctx.counter("trace_pass_pairs") / args.steps
+    near_line_pairs = (ctx.counter("trace_near_pairs") + ctx.counter("trace_pass_near_pairs")) / args.steps
     # the same steps again with the dominant kernel timed by events carried in its own dispatches
     # (profiling mode 2): its launch durations for the roofline (the events slow the step, so these
     # steps are not the timed ones)
@@ -587,7 +594,10 @@ def main():
         step()
     torch.cuda.synchronize()
     ms_step_prof = (time.perf_counter() - t2) * 1e3 / args.steps
-    tf_n, tf_ms = ctx.kernel_stats("trace_far")
+    fused = ctx.kernel_stats("trace_far")[0] == 0   # one launch per stage throughout (trace_mode 3)
+    tf_n, tf_ms = ctx.kernel_stats("trace_pass" if fused else "trace_far")
+    if fused:
+        far_launches, far_pairs = pass_launches, pass_pairs
     # one more step, untimed, with every kernel timed: the per-phase breakdown
     ctx.set_profiling(1)
     ctx.reset_stats()
@@ -607,7 +617,7 @@ def main():
     stats = {k: ctx.kernel_stats(k) for k in ("geometry", "far_assemble", "near_mask_csr", "near_assemble",
                                                 "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
                                                 "eval_near_csr", "eval_far", "eval_near", "trace", "trace_far",
-                                                "trace_step")}
+                                                "trace_step", "trace_pass")}
     tr_n, tr_ms = stats["trace"]
     trace_ms = tr_ms / max(tr_n, 1)
     # dominant kernel: the far-field pass of the field-line tracer (k_lb_far), one launch per RK4 stage,
@@ -670,9 +680,12 @@ def main():
         "phase_ms_per_step": phases,
         "streamer_integral_sum": float(I.sum().item()),
         "stop_code_counts": {str(k): int(np.sum(st_h == k)) for k in range(6)},
-        "roofline": {"kernel": "k_lb_far (far-field pass of the field-line tracer, FP64)", "bound": "alu",
+        "roofline": {"kernel": ("k_lf_pass (one launch per RK4 stage of the field lines: the previous stage's "
+                                "step, then the regular and near pairs of all live lines, FP64)") if fused else
+                               "k_lb_far (far-field pass of the field-line tracer, FP64)", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": K_LB_FAR_TRAFFIC_BYTES,
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": K_LF_PASS_TRAFFIC_BYTES if fused else K_LB_FAR_TRAFFIC_BYTES,
                      "traffic_unit": "bytes per launch (HBM, counters)",
                      "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": far_pairs / far_launches,
                      "launches_per_step": far_launches, "avg_launch_ms": far_avg_ms,

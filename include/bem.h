@@ -80,7 +80,7 @@ typedef enum { BEM_FP64 = 0, BEM_MIXED = 1 } bem_precision;
  *            all triangles at a vertex of one body.  Supported calls: bem_assemble,
  *            bem_copy_rows, bem_rhs, bem_matvec, bem_solve_gmres, bem_eval_field at volume
  *            points (on_panel NULL; phi or E may be NULL), and bem_trace_lines /
- *            bem_streamer_integral in the batched layout (trace_mode 0 or 1; lines of several
+ *            bem_streamer_integral in the all-lines layouts (trace_mode 0, 1 or 3; lines of several
  *            load cases run case by case; the line passes read FP64 panel records carrying
  *            the nodal density, in MIXED contexts too); the gradient and the autotuner need
  *            CONSTANT (INVALID otherwise). */
@@ -315,9 +315,14 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
                             double* out);
 
 /* Tuning knobs (no effect on results beyond summation order).
- *  "trace_mode": 0 (default) or 1 = all lines advance together (one batched
- *                evaluation per RK4 stage, spread over the GPU), 2 = one
- *                persistent launch, one workgroup per line.
+ *  "trace_mode": how field lines advance.  1 = all lines together, each RK4 stage one
+ *                far-field pass spread over the GPU and one step kernel (one block per
+ *                line); 3 = all lines together, each stage one launch whose blocks first
+ *                finish the previous stage of their lines from the partial fields the
+ *                previous launch wrote, then evaluate the new stage (at most 131072 panels);
+ *                2 = one persistent launch, one workgroup per line; 0 (default) = 1 while
+ *                more than "trace_tail" lines are live, then 3 (1 throughout above 131072
+ *                panels).
  *  "batched_solve": 1 (default) = bem_solve_gmres with nrhs >= 2 runs up to 64
  *                independent GMRES recurrences together, one multi-right-hand-
  *                side matrix product per iteration on the matrix cores (FP64:
@@ -349,6 +354,12 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
  *                 trace_split 0 or above the line count) results do not depend on the grouping
  *  "trace_fold":  1 (default) = with two line groups, fold the second into the first once all
  *                 live lines fit one 64-line tile; 0 = keep both groups to the end
+ *  "trace_tail":  trace_mode 0: live-line count at or below which the run goes on in the
+ *                 one-launch layout (0..4096; default 16; 0 = never); checked every 32 passes
+ *  "trace_lpb":   one-launch layout: line slots per block (1, 2, 4, 8; 0, the default: by the
+ *                 live count)
+ *  "trace_rnd":   one-launch layout: 256-panel rounds per block (1, 2, 4; 0, the default: by
+ *                 the live count)
  *  "grad_batch":  points per batch of the pair passes of bem_streamer_grad (64..2^24; default
  *                 131072; bounds scratch memory)
  * Errors: INVALID for an unknown key or value. */
@@ -380,10 +391,12 @@ bem_status bem_autotune(bem_ctx* ctx, const char* cache_path, int32_t* from_cach
  *            16th pass is timed, so its launch count is a sample and total_ms covers that
  *            sample), "gemm_f32", "gemm_f64", "gemm_rows", "bgmres_iter", "grad",
  *            "grad_reverse", "grad_rows_EH", "grad_panel_far", "grad_panel_near", "gemvT".
- *  enable 1 or 2: "trace_far", every chunked far pass of the batched field-line layout, timed
- *            by events carried in its own dispatch (hipExtLaunchKernelGGL): the kernel's
- *            execution interval, with nothing added to the stream.
- *  enable 2: only "trace_far", so that all other work runs as it does unprofiled.
+ *  enable 1 or 2: "trace_far", every chunked far pass of the two-kernel field-line layout, and
+ *            "trace_pass", every launch of the one-launch layout, timed by events carried in
+ *            their own dispatches (hipExtLaunchKernelGGL): the kernel's execution interval,
+ *            with nothing added to the stream.
+ *  enable 2: only "trace_far" and "trace_pass", so that all other work runs as it does
+ *            unprofiled.
  * Errors: INVALID for another value. */
 bem_status bem_set_profiling(bem_ctx* ctx, int32_t enable);
 bem_status bem_kernel_stats(bem_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
@@ -391,12 +404,15 @@ bem_status bem_reset_stats(bem_ctx* ctx);   /* also zeroes the counters below */
 
 /* Work counters since creation or the last bem_reset_stats:
  * "trace_near_pairs"   = (point, panel) pairs of field-line evaluations that
- *                        took the closed-form (near) path in the batched layout;
+ *                        took the closed-form (near) path in the two-kernel layout;
  * "trace_far_pairs"    = regular (7-point rule) pairs evaluated by the chunked
- *                        far-field passes (k_lb_far) of the batched layout;
- * "trace_far_launches" = launches of those chunked passes ("trace_far" times
- *                        a sample of them); the panel-stationary few-line
- *                        passes are in neither. */
+ *                        far-field passes (k_lb_far) of the two-kernel layout;
+ * "trace_far_launches" = launches of those chunked passes (each timed as
+ *                        "trace_far" when profiling); the panel-stationary
+ *                        few-line passes are in neither;
+ * "trace_pass_near_pairs", "trace_pass_pairs", "trace_pass_launches" = the
+ *                        same for the one-launch layout (k_lf_pass, timed as
+ *                        "trace_pass"; every launch counted). */
 bem_status bem_get_counter(bem_ctx* ctx, const char* name, int64_t* value);
 
 #ifdef __cplusplus

@@ -585,7 +585,7 @@ void streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const
     double* path = c->ad_path.as<double>();
     int32_t* ns = reinterpret_cast<int32_t*>(path + (size_t)std::max<int64_t>(L, 1) * pstride);
     int32_t* stop = ns + L + 16;
-    if (L > 0) launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, ns, stop, path, nullptr, nullptr);
+    if (L > 0) launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, ns, stop, path, nullptr, nullptr, false);
     // 2. lines grouped by load case; stage-record offsets
     std::vector<int32_t> h_ns(L), h_rhs(L, 0);
     if (L > 0) {

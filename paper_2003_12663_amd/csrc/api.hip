@@ -83,7 +83,9 @@ void check_points(const bem_ctx* c, int64_t P, const double* pts) {
 void check_trace(const bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                  const double* starts, const bem_trace_params* tp) {
     if (c->opt.basis == BEM_BASIS_LINEAR && c->trace_mode == 2)
-        throw bem::Error(BEM_ERR_INVALID, "field lines of the LINEAR basis need the batched layout (trace_mode 0/1)");
+        throw bem::Error(BEM_ERR_INVALID, "field lines of the LINEAR basis need an all-lines layout (trace_mode 0, 1 or 3)");
+    if (c->trace_mode == 3 && bem::fused_trace_blocks(c->N, 4) == 0)
+        throw bem::Error(BEM_ERR_INVALID, "trace_mode 3 takes at most 131072 panels");
     if (!tp) throw bem::Error(BEM_ERR_INVALID, "trace parameters are NULL");
     if (nrhs < 1) throw bem::Error(BEM_ERR_INVALID, "nrhs must be >= 1");
     if (!sol) throw bem::Error(BEM_ERR_INVALID, "solution pointer is NULL");
@@ -862,7 +864,7 @@ bem_status bem_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const in
 bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return fail(BEM_ERR_INVALID, "NULL argument");
     if (std::strcmp(key, "trace_mode") == 0) {
-        if (value < 0 || value > 2) return fail(BEM_ERR_INVALID, "trace_mode must be 0, 1 or 2");
+        if (value < 0 || value > 3) return fail(BEM_ERR_INVALID, "trace_mode must be 0, 1, 2 or 3");
         c->trace_mode = (int32_t)value;
         return BEM_OK;
     }
@@ -894,6 +896,9 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"trace_splitk", &bem_ctx::tune_trace_splitk, 2, 8, true},
         {"trace_groups", &bem_ctx::tune_trace_groups, 0, 2, false},
         {"trace_fold", &bem_ctx::tune_trace_fold, 0, 1, false},
+        {"trace_lpb", &bem_ctx::tune_trace_lpb, 0, 8, true},
+        {"trace_rnd", &bem_ctx::tune_trace_rnd, 0, 4, true},
+        {"trace_tail", &bem_ctx::tune_trace_tail, 0, 4096, false},
         {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
     for (const Knob& k : knobs)
@@ -922,6 +927,9 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     else if (std::strcmp(key, "trace_splitk") == 0) *value = c->tune_trace_splitk;
     else if (std::strcmp(key, "trace_groups") == 0) *value = c->tune_trace_groups;
     else if (std::strcmp(key, "trace_fold") == 0) *value = c->tune_trace_fold;
+    else if (std::strcmp(key, "trace_lpb") == 0) *value = c->tune_trace_lpb;
+    else if (std::strcmp(key, "trace_rnd") == 0) *value = c->tune_trace_rnd;
+    else if (std::strcmp(key, "trace_tail") == 0) *value = c->tune_trace_tail;
     else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
     return BEM_OK;
 }
@@ -963,6 +971,7 @@ bem_status bem_reset_stats(bem_ctx* c) {
     bem::resolve_stats(c);
     c->stats.clear();
     c->trace_far_launches = 0;
+    c->trace_pass_launches = 0;
     BEM_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(uint64_t) * 8, c->stream));
     BEM_HIP(hipStreamSynchronize(c->stream));
     return BEM_OK;
@@ -977,9 +986,15 @@ bem_status bem_get_counter(bem_ctx* c, const char* name, int64_t* value) {
         *value = c->trace_far_launches;
         return BEM_OK;
     }
+    if (std::strcmp(name, "trace_pass_launches") == 0) {
+        *value = c->trace_pass_launches;
+        return BEM_OK;
+    }
     int idx = -1;
     if (std::strcmp(name, "trace_near_pairs") == 0) idx = 0;
     if (std::strcmp(name, "trace_far_pairs") == 0) idx = 1;
+    if (std::strcmp(name, "trace_pass_near_pairs") == 0) idx = 2;
+    if (std::strcmp(name, "trace_pass_pairs") == 0) idx = 3;
     if (idx < 0) throw bem::Error(BEM_ERR_INVALID, std::string("unknown counter ") + name);
     uint64_t v = 0;
     BEM_HIP(hipMemcpyAsync(&v, c->counters.as<uint64_t>() + idx, sizeof(v), hipMemcpyDeviceToHost, c->stream));

@@ -110,6 +110,7 @@ struct bem_ctx {
     // events that order it after / before the context stream; created on first use
     hipStream_t aux_stream = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipEvent_t lf_ev[8] = {};   // live-count read-backs of the one-launch-per-stage tracer
     bem_options opt{};
     int64_t N = 0, n = 0, ld = 0, n_vert = 0;
     // rows that carry a body's density: N panels, or n_vert vertices for the LINEAR basis; in
@@ -156,7 +157,7 @@ struct bem_ctx {
     // scratch
     bem::DBuf gm_V, gm_w, gm_z, gm_h, gm_part, gm_x, gm_r, gm_b, gm_misc;
     bem::HBuf host_stage;
-    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part;
+    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part, lf_part, lf_cnt;
 
     bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part, rows_part;   // batched GMRES
     bem::DBuf near_sf;   // S, F of the near list by the near-singular rule (near_rule 1)
@@ -166,12 +167,17 @@ struct bem_ctx {
     bem::DBuf ad_state, ad_part, ad_mask, ad_cnt, ad_self, ad_ppart, ad_list, ad_path, ad_stage, ad_geo, ad_seg,
         ad_vptr, ad_vcorner;
 
-    // device counters (bem_get_counter): [0] near pairs evaluated by the batched field-line passes
+    // device counters (bem_get_counter): near [0] and regular [1] pairs of the two-kernel field-line
+    // passes, near [2] and regular [3] pairs of the one-launch passes
     bem::DBuf counters;
-    int64_t trace_far_launches = 0;   // host-side count of batched field-line passes (bem_get_counter)
+    int64_t trace_far_launches = 0;   // host-side count of two-kernel field-line far passes (bem_get_counter)
+    int64_t trace_pass_launches = 0;  // host-side count of one-launch field-line stages (bem_get_counter)
 
     // tuning knobs (bem_set_tuning)
-    int32_t trace_mode = 0;   // 0 auto, 1 all lines together (batched passes), 2 persistent per-line workgroups
+    // field-line layout: 1 all lines together, a far pass and a step kernel per stage; 2 persistent
+    // per-line workgroups; 3 all lines together, one launch per stage; 0 (default) 1 until at most
+    // tune_trace_tail lines are live, then 3 (1 throughout when the panel count exceeds what 3 takes)
+    int32_t trace_mode = 0;
     int32_t near_rule = 0;       // near pairs of the assembly: 0 closed forms, 1 the Sec. 4 rule (closest point + Duffy)
     int32_t batched_solve = 1;   // several right-hand sides: 1 one batched solve (shared matrix products), 0 one by one
     // tile shapes (bem_set_tuning / bem_autotune); none changes a result beyond summation order
@@ -185,6 +191,9 @@ struct bem_ctx {
     int32_t tune_trace_few = 8;       // live-line count at or below which the panel-stationary pass is used (<= 16)
     int32_t tune_trace_groups = 0;    // line groups of a field-line run, each on its own stream (1 or 2; 0: 2 from 128 lines)
     int32_t tune_trace_fold = 1;      // fold the second line group into the first once all live lines fit one tile
+    int32_t tune_trace_lpb = 0;       // one-launch layout: line slots per block (1, 2, 4, 8; 0: by the live count)
+    int32_t tune_trace_rnd = 0;       // one-launch layout: 256-panel rounds per block (1, 2, 4; 0: by the live count)
+    int32_t tune_trace_tail = 16;     // trace_mode 0: live lines at or below which the one-launch layout takes over
     int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
     // profiling: 0 off; 1 every kernel (event pairs around each launch, the field-line far pass
@@ -204,6 +213,8 @@ struct bem_ctx {
         if (fork_ev) (void)hipEventDestroy(fork_ev);
         if (join_ev) (void)hipEventDestroy(join_ev);
         if (aux_stream) (void)hipStreamDestroy(aux_stream);
+        for (hipEvent_t e : lf_ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -277,9 +288,20 @@ void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const 
 void launch_trace_nodal_cases(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                               const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
                               double* path, double* integral, uint8_t* exceeds);   // trace_batched.hip
+// fused_tail: hand the last tune_trace_tail live lines to the one-launch layout
 void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                           const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
-                          double* path, double* integral, uint8_t* exceeds);   // trace_batched.hip
+                          double* path, double* integral, uint8_t* exceeds, bool fused_tail);   // trace_batched.hip
+// one launch per RK4 stage (trace_fused.hip); fused_trace_blocks: its panel blocks of 256 rnd
+// panels, 0 when N needs more than it allows
+void launch_trace_fused(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
+                        const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
+                        double* path, double* integral, uint8_t* exceeds);
+int fused_trace_blocks(int64_t N, int rnd);
+// trace_mode 3 (one launch per stage throughout), and trace_mode 0 (two kernels, then one launch
+// per stage for the last lines) where the panel count allows the one-launch layout
+bool trace_fused_layout(const bem_ctx* c);
+bool trace_fused_tail(const bem_ctx* c);
 
 int autotune(bem_ctx* c, const char* cache_path);   // autotune.hip; 1 = loaded from the cache
 void streamer_grad(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,

@@ -350,6 +350,11 @@ void launch_trace_T(bem_ctx* c, int64_t Np, const double* sol, int64_t L, const 
 
 }  // namespace
 
+bool trace_fused_layout(const bem_ctx* c) { return c->trace_mode == 3; }
+bool trace_fused_tail(const bem_ctx* c) {
+    return c->trace_mode == 0 && c->tune_trace_tail > 0 && fused_trace_blocks(c->N, 4) > 0;
+}
+
 void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                   const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code, double* path,
                   double* integral, uint8_t* exceeds) {
@@ -357,14 +362,20 @@ void launch_trace(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const 
     int cus = 0;
     BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     // default: all lines advance together (measured faster than one workgroup per line for
-    // 4 to 4096 lines; the per-line layout is bound by per-CU load bandwidth)
+    // 4 to 4096 lines; the per-line layout is bound by per-CU load bandwidth), a far pass and a
+    // step kernel per stage while many lines are live, one launch per stage for the last few
+    // (measured on the 19,732-panel coax: 47 against 64 us a stage at 256 lines, 21.4 against
+    // 17.1 us at 16, 16.1 against 12.4 us at 3)
     const int mode = c->trace_mode != 0 ? c->trace_mode : 1;
-    if (mode == 1) {
+    if (mode == 1 || mode == 3) {
         if (c->opt.basis == BEM_BASIS_LINEAR && nrhs > 1 && line_rhs)
             launch_trace_nodal_cases(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral,
                                      exceeds);
+        else if (trace_fused_layout(c))
+            launch_trace_fused(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds);
         else
-            launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds);
+            launch_trace_batched(c, nrhs, sol, L, line_rhs, starts, tp, n_steps, stop_code, path, integral, exceeds,
+                                 trace_fused_tail(c));
         return;
     }
     KTimer t(c, "trace");

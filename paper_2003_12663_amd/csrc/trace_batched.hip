@@ -29,6 +29,7 @@
 
 #include "bem_device.h"
 #include "nodal_device.h"
+#include "trace_device.h"
 
 #include <hip/hip_ext.h>
 
@@ -37,82 +38,16 @@ namespace {
 
 constexpr int LB_C = 32;         // panels per chunk
 
-struct LBArgs {
-    double h, e_min, dir, a, e0, p, k_str;
-    int32_t max_steps;
-};
 
-// One buffer of slot-indexed line state.  A live line sits in slot s of the current buffer
-// (slots [0, count) are live); each pass moves every line that goes on to the slot it draws in
-// the other buffer, so every kernel indexes by slot and nothing waits on an active-list lookup.
-struct LBState {
-    double* x;       // [slots][3] current point
-    double* y;       // [slots][3] query point of the pass
-    double* ks;      // [slots][3] k1 + 2 k2 + 2 k3 + k4 so far
-    double* asum;    // [slots] alpha sum of the stages
-    double* I;       // [slots] integral
-    int32_t* ns;     // [slots] accepted steps
-    int32_t* line;   // [slots] line id held by the slot
-};
+
+// slot-indexed line state: slots [0, count) of a buffer hold the live lines (trace_device.h);
+// each pass moves every line that goes on to the slot it draws in the other buffer, so every
+// kernel indexes by slot and nothing waits on an active-list lookup
+using LBState = LFState;
 
 // the same buffer seen from slot lo on (a line group's slot range)
 inline LBState lb_shift(LBState s, int64_t lo) {
     return {s.x + 3 * lo, s.y + 3 * lo, s.ks + 3 * lo, s.asum + lo, s.I + lo, s.ns + lo, s.line + lo};
-}
-
-__device__ __noinline__ double lb_pow(double d, double p) { return pow(d, p); }
-
-__device__ __forceinline__ double lb_alpha(const LBArgs& a, double e) {
-    const double d = e - a.e0;
-    if (!(d > 0.0)) return 0.0;
-    return a.a * (a.p == 2.0 ? d * d : lb_pow(d, a.p));
-}
-
-// w / r^3 from r^2.  FP64: from the hardware estimate y of r^-1/2 (relative error about 2^-24),
-// e = 1 - r^2 y^2 and r^-3 = y^3 (1 - e)^(-3/2) = y^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)): seven
-// operations, truncation error below 2^-68.  FP32: the hardware estimate is the answer.
-// The series coefficients come in as k.c15 = 1.5 and k.c1875 = 1.875, held in registers by the
-// caller (lb_series_consts): neither is an inline FP64 constant, and left as literals they are
-// rebuilt inside the pair loop at every use.
-struct LBSeries {
-    double c15, c1875;
-};
-__device__ __forceinline__ LBSeries lb_series_consts() {
-    LBSeries k{1.5, 1.875};
-    asm volatile("" : "+v"(k.c15), "+v"(k.c1875));   // opaque: stays in a register
-    return k;
-}
-__device__ __forceinline__ double lb_w_r3(double w, double r2, const LBSeries& k) {
-    const double y = __builtin_amdgcn_rsq(r2);
-    const double y2 = y * y;
-    const double e = __fma_rn(-r2, y2, 1.0);
-    const double wy3 = w * (y2 * y);
-    return __fma_rn(wy3 * e, __fma_rn(e, k.c1875, k.c15), wy3);
-}
-__device__ __forceinline__ float lb_w_r3(float w, float r2, const LBSeries&) {
-    const float ir = rsqrt_pos(r2);
-    return w * ir * ir * ir;
-}
-
-// Moeller-Trumbore test of the closed segment q -> q + d against the closed
-// triangle T; t in [0,1], or -1 when there is no hit.
-__device__ __forceinline__ double lb_segment_tri(const double* __restrict__ T, double q0, double q1, double q2,
-                                                 double d0, double d1, double d2) {
-    const double a0 = T[3] - T[0], a1 = T[4] - T[1], a2 = T[5] - T[2];
-    const double b0 = T[6] - T[0], b1 = T[7] - T[1], b2 = T[8] - T[2];
-    const double pv0 = d1 * b2 - d2 * b1, pv1 = d2 * b0 - d0 * b2, pv2 = d0 * b1 - d1 * b0;
-    const double det = a0 * pv0 + a1 * pv1 + a2 * pv2;
-    if (det == 0.0) return -1.0;
-    const double inv = 1.0 / det;
-    const double t0 = q0 - T[0], t1 = q1 - T[1], t2 = q2 - T[2];
-    const double u = (t0 * pv0 + t1 * pv1 + t2 * pv2) * inv;
-    if (u < 0.0 || u > 1.0) return -1.0;
-    const double qv0 = t1 * a2 - t2 * a1, qv1 = t2 * a0 - t0 * a2, qv2 = t0 * a1 - t1 * a0;
-    const double v = (d0 * qv0 + d1 * qv1 + d2 * qv2) * inv;
-    if (v < 0.0 || u + v > 1.0) return -1.0;
-    const double t = (b0 * qv0 + b1 * qv1 + b2 * qv2) * inv;
-    if (t < 0.0 || t > 1.0) return -1.0;
-    return t;
 }
 
 // Lines [g L / G, (g + 1) L / G) form group g, in slots [g L / G, (g + 1) L / G) of buffer 0
@@ -653,6 +588,11 @@ __global__ __launch_bounds__(256) void k_lb_merge(LBState s, int32_t* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void k_lb_zero_u64(int64_t m, unsigned long long* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) v[i] = 0;
+}
+
 __global__ void k_lb_set_count(int32_t* __restrict__ count, int32_t v) {
     if (threadIdx.x == 0) count[0] = v;
 }
@@ -766,7 +706,7 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
 
 void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, const int32_t* line_rhs,
                           const double* starts, const bem_trace_params* tp, int32_t* n_steps, int32_t* stop_code,
-                          double* path, double* integral, uint8_t* exceeds) {
+                          double* path, double* integral, uint8_t* exceeds, bool fused_tail) {
     if (L == 0) return;
     KTimer t(c, "trace");
     const int64_t Np = (int64_t)(c->far64.bytes / (sizeof(double) * FAR_REC));
@@ -970,6 +910,21 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                 grp[0].known = live;
                 grp[1].known = 0;
             }
+            // the last few lines (all in group 0's slots [0, live)) go on one launch per stage,
+            // from the next pass, with their own pair counters
+            if (fused_tail && live <= c->tune_trace_tail && (G == 1 || grp[1].known == 0)) {
+                c->lf_cnt.alloc(sizeof(unsigned long long) * 2 * (size_t)L);
+                unsigned long long* fcnt = c->lf_cnt.as<unsigned long long>();
+                hipLaunchKernelGGL(k_lb_zero_u64, dim3((unsigned)ceil_div(2 * L, 256)), dim3(256), 0, c->stream,
+                                   2 * L, fcnt);
+                BEM_CHECK_LAUNCH();
+                fused_trace_loop(c, sol, L, line_rhs, tp, n_steps, stop_code, path, integral, exceeds, buf[cur],
+                                 buf[cur ^ 1], live, pass + 1, fcnt);
+                hipLaunchKernelGGL(k_lb_count_sum, dim3(1), dim3(256), 0, c->stream, L, fcnt,
+                                   reinterpret_cast<unsigned long long*>(c->counters.p) + 2);
+                BEM_CHECK_LAUNCH();
+                break;
+            }
         }
     }
     if (G > 1) {   // the counts below need both groups' step kernels
@@ -1044,8 +999,13 @@ void launch_trace_nodal_cases(bem_ctx* c, int32_t nrhs, const double* sol, int64
         hipLaunchKernelGGL(k_gather_starts, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, c->stream, m, didx, starts,
                            tst);
         BEM_CHECK_LAUNCH();
-        launch_trace_batched(c, 1, sol + (int64_t)r * c->n, m, nullptr, tst, tp, tns, tsc, path ? tpath : nullptr,
-                             integral ? tI : nullptr, exceeds ? tex : nullptr);
+        if (trace_fused_layout(c))
+            launch_trace_fused(c, 1, sol + (int64_t)r * c->n, m, nullptr, tst, tp, tns, tsc, path ? tpath : nullptr,
+                               integral ? tI : nullptr, exceeds ? tex : nullptr);
+        else
+            launch_trace_batched(c, 1, sol + (int64_t)r * c->n, m, nullptr, tst, tp, tns, tsc,
+                                 path ? tpath : nullptr, integral ? tI : nullptr, exceeds ? tex : nullptr,
+                                 trace_fused_tail(c));
         hipLaunchKernelGGL(k_scatter_lines, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, c->stream, m, didx, tns,
                            tsc, tI, tex, tpath, pstride, n_steps, stop_code, integral, exceeds, path);
         BEM_CHECK_LAUNCH();

@@ -66,9 +66,9 @@ def test_nonfinite_density(bem):
     assert not torch.isfinite(phi).any() and not torch.isfinite(E).any()
     starts, _, _ = electrode_line_starts(p, 12, seed=6)
     tp = bem.trace_params(h=1e-3, max_steps=20)
-    for mode in (1, 2):
+    for mode in (1, 2, 3):
         c.set_tuning("trace_mode", mode)
-        for few in (0, 16):
+        for few in ((0, 16) if mode == 1 else (0,)):
             c.set_tuning("trace_few", few)
             I, ns, st, _ = c.streamer_integral(bad, starts, tp)
             assert np.all(st.cpu().numpy() == 5), (mode, few, st)

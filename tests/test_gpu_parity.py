@@ -196,7 +196,7 @@ def _trace_compare(bem, c, o, x, starts, params_kw, L_check=None):
     return I, ns, st
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_sphere_trace(bem, mode):
     p = sphere_problem(3, V0=50.0)
     _say(f"sphere trace mode {mode}")
@@ -208,7 +208,7 @@ def test_sphere_trace(bem, mode):
     c.close()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_coax_trace_stop_codes(bem, mode):
     p = coax_problem(0.012)
     _say(f"coax trace mode {mode}")
@@ -226,18 +226,32 @@ _LAYOUT_REF = {}
 
 
 @pytest.mark.parametrize("layout", [
-    dict(trace_splitk=2, trace_split=4096, trace_few=0),    # every pass split over 2, 4 or 8 waves
-    dict(trace_splitk=4, trace_split=4096, trace_few=0),
-    dict(trace_splitk=8, trace_split=4096, trace_few=0),
-    dict(trace_tile=64, trace_split=0, trace_few=0),        # every pass unsplit, 64/128/256-line tiles
-    dict(trace_tile=128, trace_split=0, trace_few=0),
-    dict(trace_tile=256, trace_split=0, trace_few=0),
-    dict(trace_splitk=4, trace_split=256, trace_tile=128, trace_few=8),   # split, then few-line tail
-], ids=["split2", "split4", "split8", "tile64", "tile128", "tile256", "split4_few8"])
+    # far pass + step kernel (trace_mode 1): split over 2, 4 or 8 waves, unsplit 64/128/256-line
+    # tiles, split then the few-line tail
+    dict(trace_mode=1, trace_splitk=2, trace_split=4096, trace_few=0),
+    dict(trace_mode=1, trace_splitk=4, trace_split=4096, trace_few=0),
+    dict(trace_mode=1, trace_splitk=8, trace_split=4096, trace_few=0),
+    dict(trace_mode=1, trace_tile=64, trace_split=0, trace_few=0),
+    dict(trace_mode=1, trace_tile=128, trace_split=0, trace_few=0),
+    dict(trace_mode=1, trace_tile=256, trace_split=0, trace_few=0),
+    dict(trace_mode=1, trace_splitk=4, trace_split=256, trace_tile=128, trace_few=8),
+    # one launch per stage (trace_mode 3): 1, 2, 4, 8 line slots and 1, 2, 4 panel rounds per
+    # block, fixed, and the shape chosen by the live count (with the fold of live slots)
+    dict(trace_mode=3, trace_lpb=1, trace_rnd=1),
+    dict(trace_mode=3, trace_lpb=2, trace_rnd=4),
+    dict(trace_mode=3, trace_lpb=4, trace_rnd=2),
+    dict(trace_mode=3, trace_lpb=8, trace_rnd=4),
+    dict(trace_mode=3, trace_lpb=8, trace_rnd=1),
+    dict(trace_mode=3),
+    # the default: two kernels, then one launch per stage once at most trace_tail lines are live
+    dict(trace_mode=0, trace_tail=8),
+    dict(trace_mode=0, trace_tail=16),
+], ids=["split2", "split4", "split8", "tile64", "tile128", "tile256", "split4_few8",
+        "fused_l1r1", "fused_l2r4", "fused_l4r2", "fused_l8r4", "fused_l8r1", "fused_auto", "tail8", "tail16"])
 def test_trace_layouts(bem, layout):
-    """Every tile shape of the batched far pass (the split kernels at 2, 4 and 8 waves per
-    chunk, the unsplit ones at 64, 128 and 256 lines per block, the few-line tail) against
-    the oracle on 16 coax lines (seed 21) that end on the shell or the ring or run out of
+    """Every tile shape of the two-kernel layout (the split far passes at 2, 4 and 8 waves per
+    chunk, the unsplit ones at 64, 128 and 256 lines per block, the few-line tail) and of the
+    one-launch layout (line slots and panel rounds per block) against the oracle on 16 coax lines (seed 21) that end on the shell or the ring or run out of
     steps: step counts and stop codes exact, integrals and paths 1e-10 / 1e-9."""
     p = coax_problem(0.012)
     _say(f"trace layout {layout}")
@@ -265,7 +279,7 @@ def test_trace_layouts(bem, layout):
     c.close()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_trace_edge_cases(bem, mode):
     p = sphere_problem(2)
     _say(f"trace edge cases mode {mode}")
@@ -363,7 +377,7 @@ def test_multi_rhs_linearity(bem):
     c.close()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_trace_multi_rhs_lines(bem, mode):
     # lines driven by different load cases (line_rhs), both trace layouts
     p = coax_problem(0.012)
@@ -396,6 +410,7 @@ def test_trace_line_groups(bem):
     p = coax_problem(0.012)
     _say("line groups")
     c, o, x, x_ref = _sigma_case(bem, p)
+    c.set_tuning("trace_mode", 1)   # line groups belong to the two-kernel layout
     sol = torch.tensor(x, device="cuda")
     starts, _, _ = electrode_line_starts(p, 37, seed=4)
     params = dict(h=1e-3, max_steps=120)
