@@ -324,6 +324,28 @@ def tri_duffy(x, v1, v2, v3):
     return S.value, F
 
 
+def quad_duffy(x, nodes):
+    """The near-singular rule of Sec. 4 on a curved quadratic panel (six nodes: the corners,
+    then the edge nodes of edges 1-2, 2-3, 3-1): (S, F) of unit density at x; F is NaN when x
+    lies on the panel."""
+    lib = _load()
+    S = ctypes.c_double(0.0)
+    F = np.empty(3)
+    P = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(6, 3))
+    lib.orc_quad_duffy(_ptr(_f64(x)), _ptr(P), ctypes.byref(S), _ptr(F))
+    return S.value, F
+
+
+def quad_closest(x, nodes):
+    """Parameter point (s, t) of the reference triangle whose image on the quadratic panel is
+    closest to x (step 1 of the rule)."""
+    lib = _load()
+    c = np.empty(2)
+    P = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64).reshape(6, 3))
+    lib.orc_quad_closest(_ptr(P), _ptr(_f64(x)), _ptr(c))
+    return c
+
+
 def closest_point(x, v1, v2, v3):
     """Closest point of the closed triangle to x (step 1 of the near-singular rule)."""
     lib = _load()

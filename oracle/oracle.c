@@ -412,6 +412,232 @@ void orc_tri_duffy(const double x[3], const double v1[3], const double v2[3], co
     for (int k = 0; k < 3; ++k) F[k] = (d > 0.0) ? f[k] / (4.0 * ORC_PI) : NAN;
 }
 
+/* ------------------------------------------- curved quadratic panels (Sec. 3, Sec. 4)
+ * The paper's panels are curved triangles with a piecewise quadratic
+ * parametrization (Sec. 3).  Reading: the image of the reference triangle
+ * T = {(s, t): s, t >= 0, s + t <= 1} under the quadratic Lagrange map through
+ * six nodes, the corners P1 = y(0,0), P2 = y(1,0), P3 = y(0,1) and the edge
+ * nodes P4 = y(1/2,0), P5 = y(1/2,1/2), P6 = y(0,1/2):
+ *   y(s,t) = sum_k N_k(s,t) P_k,  l1 = 1 - s - t, l2 = s, l3 = t,
+ *   N1 = l1 (2 l1 - 1), N2 = l2 (2 l2 - 1), N3 = l3 (2 l3 - 1),
+ *   N4 = 4 l1 l2, N5 = 4 l2 l3, N6 = 4 l3 l1,
+ * with dS = |y_s x y_t| ds dt.  The near-singular rule of Sec. 4 on it, in the
+ * paper's order, with every step taken in the parameter plane:
+ *   1. the closest point: the parameter point c of T minimizing |x - y(s,t)|:
+ *      the best of an interior minimum (Newton on the gradient of
+ *      |x - y|^2 / 2 from the best of a 17 x 17 sampling, kept if it stays in
+ *      T), the three edge minima (Newton along each edge from the best of 17
+ *      samples, clipped to the edge) and the corners;
+ *   2. pieces (c, a, b) of T for its edges a -> b, a piece of zero area
+ *      (c on that edge) dropped;
+ *   3. the Duffy map of a piece, (s, t) = c + u ((1 - v)(a - c) + v (b - c)),
+ *      whose Jacobian u |det(a - c, b - c)| cancels the 1/r at the corner, times
+ *      the surface Jacobian |y_s x y_t| at (s, t);
+ *   4. the graded Gauss-Legendre rule of orc_tri_duffy, with the piece's
+ *      edge vectors a - c, b - c, b - a taken through the tangent map
+ *      (y_s, y_t) at c: near the corner the distance to x grows with the
+ *      map's local metric there, not with the parameters (on a flat panel
+ *      with mid-edge nodes at the edge midpoints the map is affine and this
+ *      is orc_tri_duffy).
+ * Unit density; S = (1/4pi) int 1/|x - y| dS, F = (1/4pi) int (x - y)/|x - y|^3 dS;
+ * x on the panel (within 1e-14 of its size): S, and F = NaN. */
+static void orc_quad_eval(const double P[6][3], double s, double t, double y[3], double ys[3], double yt[3],
+                          double yss[3], double yst[3], double ytt[3])
+{
+    double l1 = 1.0 - s - t;
+    /* N and its derivatives in s and t (dl1 = -ds - dt) */
+    double N[6] = {l1 * (2.0 * l1 - 1.0), s * (2.0 * s - 1.0), t * (2.0 * t - 1.0), 4.0 * l1 * s, 4.0 * s * t,
+                   4.0 * t * l1};
+    double Ns[6] = {-(4.0 * l1 - 1.0), 4.0 * s - 1.0, 0.0, 4.0 * (l1 - s), 4.0 * t, -4.0 * t};
+    double Nt[6] = {-(4.0 * l1 - 1.0), 0.0, 4.0 * t - 1.0, -4.0 * s, 4.0 * s, 4.0 * (l1 - t)};
+    double Nss[6] = {4.0, 4.0, 0.0, -8.0, 0.0, 0.0};
+    double Nst[6] = {4.0, 0.0, 0.0, -4.0, 4.0, -4.0};
+    double Ntt[6] = {4.0, 0.0, 4.0, 0.0, 0.0, -8.0};
+    for (int k = 0; k < 3; ++k) {
+        y[k] = ys[k] = yt[k] = 0.0;
+        if (yss) yss[k] = yst[k] = ytt[k] = 0.0;
+        for (int m = 0; m < 6; ++m) {
+            y[k] += N[m] * P[m][k];
+            ys[k] += Ns[m] * P[m][k];
+            yt[k] += Nt[m] * P[m][k];
+            if (yss) {
+                yss[k] += Nss[m] * P[m][k];
+                yst[k] += Nst[m] * P[m][k];
+                ytt[k] += Ntt[m] * P[m][k];
+            }
+        }
+    }
+}
+
+static double orc_quad_dist2(const double P[6][3], const double x[3], double s, double t)
+{
+    double y[3], ys[3], yt[3], r[3];
+    orc_quad_eval(P, s, t, y, ys, yt, NULL, NULL, NULL);
+    sub3(y, x, r);
+    return dot3(r, r);
+}
+
+void orc_quad_closest(const double P[6][3], const double x[3], double c[2])
+{
+    double best = INFINITY;
+    /* corners */
+    const double cs[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+    for (int k = 0; k < 3; ++k) {
+        double d2 = orc_quad_dist2(P, x, cs[k][0], cs[k][1]);
+        if (d2 < best) { best = d2; c[0] = cs[k][0]; c[1] = cs[k][1]; }
+    }
+    /* edges a -> b: (s, t) = a + tau (b - a) */
+    for (int e = 0; e < 3; ++e) {
+        const double* a = cs[e];
+        const double* b = cs[(e + 1) % 3];
+        double ds = b[0] - a[0], dt = b[1] - a[1], tau = 0.0, f0 = INFINITY;
+        for (int i = 0; i <= 16; ++i) {
+            double tt = i / 16.0, d2 = orc_quad_dist2(P, x, a[0] + tt * ds, a[1] + tt * dt);
+            if (d2 < f0) { f0 = d2; tau = tt; }
+        }
+        for (int it = 0; it < 50; ++it) {
+            double y[3], ys[3], yt[3], yss[3], yst[3], ytt[3], r[3], yd[3], ydd[3];
+            orc_quad_eval(P, a[0] + tau * ds, a[1] + tau * dt, y, ys, yt, yss, yst, ytt);
+            sub3(y, x, r);
+            for (int k = 0; k < 3; ++k) {
+                yd[k] = ys[k] * ds + yt[k] * dt;
+                ydd[k] = yss[k] * ds * ds + 2.0 * yst[k] * ds * dt + ytt[k] * dt * dt;
+            }
+            double g = dot3(yd, r), h = dot3(yd, yd) + dot3(ydd, r);
+            if (h <= 0.0) h = dot3(yd, yd);
+            double nt = tau - g / h;
+            if (nt < 0.0) nt = 0.0;
+            if (nt > 1.0) nt = 1.0;
+            double step = fabs(nt - tau);
+            tau = nt;
+            if (step <= 1e-16) break;
+        }
+        double d2 = orc_quad_dist2(P, x, a[0] + tau * ds, a[1] + tau * dt);
+        if (d2 < best) { best = d2; c[0] = a[0] + tau * ds; c[1] = a[1] + tau * dt; }
+    }
+    /* interior: damped Newton on |x - y|^2 / 2 from the best sample, every step shortened to
+     * stay in T and halved until the distance falls */
+    double s = 0.0, t = 0.0, f0 = INFINITY;
+    for (int i = 0; i <= 16; ++i)
+        for (int j = 0; i + j <= 16; ++j) {
+            double d2 = orc_quad_dist2(P, x, i / 16.0, j / 16.0);
+            if (d2 < f0) { f0 = d2; s = i / 16.0; t = j / 16.0; }
+        }
+    for (int it = 0; it < 60; ++it) {
+        double y[3], ys[3], yt[3], yss[3], yst[3], ytt[3], r[3];
+        orc_quad_eval(P, s, t, y, ys, yt, yss, yst, ytt);
+        sub3(y, x, r);
+        double g0 = dot3(ys, r), g1 = dot3(yt, r);
+        double h00 = dot3(ys, ys) + dot3(yss, r), h01 = dot3(ys, yt) + dot3(yst, r);
+        double h11 = dot3(yt, yt) + dot3(ytt, r);
+        double det = h00 * h11 - h01 * h01;
+        if (!(h00 > 0.0 && det > 0.0)) {   /* Hessian not positive definite: Gauss-Newton */
+            h00 = dot3(ys, ys);
+            h01 = dot3(ys, yt);
+            h11 = dot3(yt, yt);
+            det = h00 * h11 - h01 * h01;
+        }
+        double d0 = -(h11 * g0 - h01 * g1) / det, d1 = -(h00 * g1 - h01 * g0) / det;
+        /* the longest fraction of the step that stays in T */
+        double a = 1.0;
+        if (d0 < 0.0 && s + a * d0 < 0.0) a = -s / d0;
+        if (d1 < 0.0 && t + a * d1 < 0.0) a = -t / d1;
+        if (d0 + d1 > 0.0 && s + t + a * (d0 + d1) > 1.0) a = (1.0 - s - t) / (d0 + d1);
+        double fn = INFINITY, sn = s, tn = t;
+        for (int h = 0; h < 40; ++h, a *= 0.5) {
+            sn = s + a * d0;
+            tn = t + a * d1;
+            if (sn < 0.0) sn = 0.0;
+            if (tn < 0.0) tn = 0.0;
+            if (sn + tn > 1.0) tn = 1.0 - sn;
+            fn = orc_quad_dist2(P, x, sn, tn);
+            if (fn <= f0) break;
+        }
+        if (!(fn <= f0)) break;   /* no decrease along the step: converged */
+        double step = fabs(sn - s) + fabs(tn - t);
+        s = sn;
+        t = tn;
+        f0 = fn;
+        if (step <= 1e-16) break;
+    }
+    if (f0 < best) { best = f0; c[0] = s; c[1] = t; }
+}
+
+void orc_quad_duffy(const double x[3], const double* nodes /* [6][3] */, double* S, double F[3])
+{
+    double P[6][3];
+    for (int m = 0; m < 6; ++m)
+        for (int k = 0; k < 3; ++k) P[m][k] = nodes[3 * m + k];
+    double tu[ORC_DUFFY_NU], wu[ORC_DUFFY_NU], tv[ORC_DUFFY_NV], wv[ORC_DUFFY_NV];
+    orc_gauss_legendre01(ORC_DUFFY_NU, tu, wu);
+    orc_gauss_legendre01(ORC_DUFFY_NV, tv, wv);
+    double ch[2];
+    orc_quad_closest(P, x, ch);
+    double yc[3], ys[3], yt[3], xc[3];
+    orc_quad_eval(P, ch[0], ch[1], yc, ys, yt, NULL, NULL, NULL);
+    sub3(x, yc, xc);
+    double d = norm3(xc);
+    double size = 0.0;   /* the longest corner-to-corner chord */
+    for (int k = 0; k < 3; ++k) {
+        double e[3];
+        sub3(P[(k + 1) % 3], P[k], e);
+        if (norm3(e) > size) size = norm3(e);
+    }
+    if (d <= 1e-14 * size) d = 0.0;   /* on the panel: the singular pair */
+    const double cs[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+    double s = 0.0, f[3] = {0.0, 0.0, 0.0};
+    double bu[260], bv[260];
+    for (int e = 0; e < 3; ++e) {
+        const double* a = cs[e];
+        const double* b = cs[(e + 1) % 3];
+        double qa[2] = {a[0] - ch[0], a[1] - ch[1]}, qb[2] = {b[0] - ch[0], b[1] - ch[1]};
+        double detp = qa[0] * qb[1] - qa[1] * qb[0];   /* > 0: T is counter-clockwise */
+        if (detp <= 1e-14) continue;                   /* c on this edge: no piece */
+        /* the piece's edge vectors through the tangent map at c: the scales of the grading */
+        double pa[3], pb[3], ab[3], cr[3];
+        for (int k = 0; k < 3; ++k) {
+            pa[k] = ys[k] * qa[0] + yt[k] * qa[1];
+            pb[k] = ys[k] * qb[0] + yt[k] * qb[1];
+            ab[k] = pb[k] - pa[k];
+        }
+        cross3(pa, pb, cr);
+        double Jc = norm3(cr), lab = norm3(ab), L = norm3(pa);
+        if (norm3(pb) > L) L = norm3(pb);
+        if (lab > L) L = lab;
+        int nu = 2;
+        bu[0] = 0.0;
+        bu[1] = 1.0;
+        if (d > 0.0) nu = orc_graded_breaks(0.0, d / L, bu);
+        double vs = -dot3(pa, ab) / (lab * lab);
+        if (vs < 0.0) vs = 0.0;
+        if (vs > 1.0) vs = 1.0;
+        int nv = orc_graded_breaks(vs, (Jc / lab) / lab, bv);
+        for (int iu = 0; iu + 1 < nu; ++iu)
+            for (int i = 0; i < ORC_DUFFY_NU; ++i) {
+                double u = bu[iu] + (bu[iu + 1] - bu[iu]) * tu[i];
+                double wuu = (bu[iu + 1] - bu[iu]) * wu[i];
+                for (int iv = 0; iv + 1 < nv; ++iv)
+                    for (int j = 0; j < ORC_DUFFY_NV; ++j) {
+                        double vv = bv[iv] + (bv[iv + 1] - bv[iv]) * tv[j];
+                        double wvv = (bv[iv + 1] - bv[iv]) * wv[j];
+                        double sp = ch[0] + u * ((1.0 - vv) * qa[0] + vv * qb[0]);
+                        double tp = ch[1] + u * ((1.0 - vv) * qa[1] + vv * qb[1]);
+                        double y[3], dys[3], dyt[3], n[3], r[3];
+                        orc_quad_eval(P, sp, tp, y, dys, dyt, NULL, NULL, NULL);
+                        cross3(dys, dyt, n);
+                        sub3(x, y, r);
+                        double R = norm3(r);
+                        double jw = u * detp * norm3(n) * wuu * wvv;
+                        s += jw / R;
+                        if (d > 0.0)
+                            for (int k = 0; k < 3; ++k) f[k] += jw * r[k] / (R * R * R);
+                    }
+            }
+    }
+    *S = s / (4.0 * ORC_PI);
+    for (int k = 0; k < 3; ++k) F[k] = (d > 0.0) ? f[k] / (4.0 * ORC_PI) : NAN;
+}
+
 /* ------------------------------------------------------------- problem geometry */
 typedef struct {
     int64_t N;
