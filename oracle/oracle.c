@@ -573,8 +573,8 @@ void orc_quad_duffy(const double x[3], const double* nodes /* [6][3] */, double*
     orc_gauss_legendre01(ORC_DUFFY_NV, tv, wv);
     double ch[2];
     orc_quad_closest(P, x, ch);
-    double yc[3], ys[3], yt[3], xc[3];
-    orc_quad_eval(P, ch[0], ch[1], yc, ys, yt, NULL, NULL, NULL);
+    double yc[3], ys[3], yt[3], yss[3], yst[3], ytt[3], xc[3];
+    orc_quad_eval(P, ch[0], ch[1], yc, ys, yt, yss, yst, ytt);
     sub3(x, yc, xc);
     double d = norm3(xc);
     double size = 0.0;   /* the longest corner-to-corner chord */
@@ -620,12 +620,20 @@ void orc_quad_duffy(const double x[3], const double* nodes /* [6][3] */, double*
                     for (int j = 0; j < ORC_DUFFY_NV; ++j) {
                         double vv = bv[iv] + (bv[iv + 1] - bv[iv]) * tv[j];
                         double wvv = (bv[iv + 1] - bv[iv]) * wv[j];
-                        double sp = ch[0] + u * ((1.0 - vv) * qa[0] + vv * qb[0]);
-                        double tp = ch[1] + u * ((1.0 - vv) * qa[1] + vv * qb[1]);
-                        double y[3], dys[3], dyt[3], n[3], r[3];
-                        orc_quad_eval(P, sp, tp, y, dys, dyt, NULL, NULL, NULL);
+                        /* the node c + (ds, dt); y and its tangents there from c in exact
+                         * Taylor form (the map is quadratic), so that x - y, short near the
+                         * corner, is not the difference of two long vectors */
+                        double dsn = u * ((1.0 - vv) * qa[0] + vv * qb[0]);
+                        double dtn = u * ((1.0 - vv) * qa[1] + vv * qb[1]);
+                        double dys[3], dyt[3], n[3], r[3];
+                        for (int k = 0; k < 3; ++k) {
+                            double dy = ys[k] * dsn + yt[k] * dtn +
+                                        0.5 * (yss[k] * dsn * dsn + 2.0 * yst[k] * dsn * dtn + ytt[k] * dtn * dtn);
+                            r[k] = xc[k] - dy;
+                            dys[k] = ys[k] + yss[k] * dsn + yst[k] * dtn;
+                            dyt[k] = yt[k] + yst[k] * dsn + ytt[k] * dtn;
+                        }
                         cross3(dys, dyt, n);
-                        sub3(x, y, r);
                         double R = norm3(r);
                         double jw = u * detp * norm3(n) * wuu * wvv;
                         s += jw / R;
