@@ -235,6 +235,25 @@ bem_status bem_compress(bem_ctx* ctx, double eps, double eta_adm, int32_t leaf, 
 bem_status bem_pair_integrals(bem_ctx* ctx, int64_t P, const double* pts, const int32_t* panel, int32_t rule,
                               double* S, double* F);
 
+/* The near-singular rule of Sec. 4 on curved panels: S = (1/4pi) int 1/|x - y| dS and
+ * F = (1/4pi) int (x - y)/|x - y|^3 dS of unit density on the curved quadratic panel p at
+ * pts[p], p < P.  A curved panel (Sec. 3: piecewise quadratic parametrization of curved
+ * triangles) is the quadratic Lagrange map of the reference triangle {(s, t): s, t >= 0,
+ * s + t <= 1} through its six nodes, nodes[p][0..2] the corners y(0,0), y(1,0), y(0,1) and
+ * nodes[p][3..5] the edge nodes y(1/2,0), y(1/2,1/2), y(0,1/2).  The rule runs in the
+ * parameter plane: the closest parameter point c (Newton's method, with the edges and
+ * corners), the reference triangle cut into pieces with c as a corner, the Duffy map of
+ * each piece times the surface Jacobian |y_s x y_t|, and tensor Gauss-Legendre (16 x 16 nodes
+ * per cell) on cells graded geometrically towards c and towards its foot on the opposite
+ * edge, scaled by the piece's edges through the tangent map at c.  A point on the panel
+ * (within 1e-14 of its size) gets S, and F = NaN.  The context supplies the device and the
+ * stream only; the panels need not belong to its mesh.
+ *  pts dev [P][3]; nodes dev [P][6][3]; S dev [P] (written); F dev [P][3] (written) or NULL.
+ * Errors: INVALID (P < 0 or >= 2^31, NULL arrays, non-finite input, a panel whose corner
+ * triangle has no area), HIP. */
+bem_status bem_quad_pair_integrals(bem_ctx* ctx, int64_t P, const double* pts, const double* nodes, double* S,
+                                   double* F);
+
 /* Solve A sol = b(body_V) for nrhs load cases by restarted GMRES with the
  * diagonal (Jacobi) preconditioner applied on the right (Sec. 5.2), CGS2
  * orthogonalisation, zero initial guess, stopping at ||b - A x|| <= tol ||b||

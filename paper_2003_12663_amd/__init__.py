@@ -147,6 +147,22 @@ class Context:
                                            _dev_ptr(F)), self.lib)
         return S.cpu().numpy(), F.cpu().numpy()
 
+    def quad_pair_integrals(self, pts, nodes, want_F=True):
+        """bem_quad_pair_integrals: S [P] and F [P, 3] (numpy; F None when not wanted) of unit
+        density on the curved quadratic panel nodes[p] (six nodes: corners, then the edge nodes of
+        edges 1-2, 2-3, 3-1) at pts[p], by the near-singular rule of Sec. 4."""
+        torch = _torch()
+        x = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3), device=self.device)
+        q = torch.as_tensor(np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 6, 3), device=self.device)
+        P = x.shape[0]
+        if q.shape[0] != P:
+            raise ValueError("pts and nodes disagree in length")
+        S = torch.empty(P, dtype=torch.float64, device=self.device)
+        F = torch.empty((P, 3), dtype=torch.float64, device=self.device) if want_F else None
+        _check(self.lib.bem_quad_pair_integrals(self._ctx, P, _dev_ptr(x), _dev_ptr(q), _dev_ptr(S),
+                                                _dev_ptr(F)), self.lib)
+        return S.cpu().numpy(), (F.cpu().numpy() if F is not None else None)
+
     def solve(self, body_V, tol=1e-10, max_iter=10000, raise_on_noconv=True):
         """Returns (sol [nrhs, n] float64 on the GPU, info dict)."""
         torch = _torch()

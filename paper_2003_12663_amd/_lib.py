@@ -16,7 +16,7 @@ EXPORTS = [
     "bem_near_pairs", "bem_rhs", "bem_matvec", "bem_solve_gmres", "bem_eval_field", "bem_trace_lines",
     "bem_streamer_integral", "bem_set_tuning", "bem_set_profiling", "bem_kernel_stats", "bem_reset_stats",
     "bem_get_counter", "bem_streamer_grad", "bem_get_tuning", "bem_autotune", "bem_panel_points",
-    "bem_matvec_noalloc", "bem_pair_integrals", "bem_compress",
+    "bem_matvec_noalloc", "bem_pair_integrals", "bem_quad_pair_integrals", "bem_compress",
 ]
 
 
@@ -69,6 +69,7 @@ def load() -> ctypes.CDLL:
         "bem_matvec": (i32, [P, i32, P, P, i32]),
         "bem_matvec_noalloc": (i32, [P, i32, P, P, i32]),
         "bem_pair_integrals": (i32, [P, i64, P, P, i32, P, P]),
+        "bem_quad_pair_integrals": (i32, [P, i64, P, P, P, P]),
         "bem_compress": (i32, [P, f64, f64, i32, P]),
         "bem_solve_gmres": (i32, [P, i32, P, f64, i32, P, P]),
         "bem_eval_field": (i32, [P, i32, P, i64, P, P, P, P]),

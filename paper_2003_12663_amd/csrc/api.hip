@@ -861,6 +861,40 @@ bem_status bem_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const in
     API_CATCH
 }
 
+bem_status bem_quad_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const double* nodes, double* S,
+                                   double* F) {
+    if (!c) return fail(BEM_ERR_INVALID, "NULL context");
+    DeviceGuard g(c->device);
+    API_TRY
+    if (P < 0 || P >= ((int64_t)1 << 31)) throw bem::Error(BEM_ERR_INVALID, "pair count out of range");
+    if (P > 0 && (!pts || !nodes || !S)) throw bem::Error(BEM_ERR_INVALID, "pts, nodes and S are required");
+    if (P == 0) return BEM_OK;
+    auto hx = fetch_f64(c, pts, (size_t)P * 3);
+    for (double v : hx)
+        if (!std::isfinite(v)) throw bem::Error(BEM_ERR_INVALID, "non-finite point coordinate");
+    auto hn = fetch_f64(c, nodes, (size_t)P * 18);
+    for (int64_t p = 0; p < P; ++p) {
+        const double* q = hn.data() + 18 * p;
+        for (int k = 0; k < 18; ++k)
+            if (!std::isfinite(q[k])) throw bem::Error(BEM_ERR_INVALID, "non-finite panel node");
+        double e1[3], e2[3], cr[3], l1 = 0.0, l2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = q[3 + k] - q[k];
+            e2[k] = q[6 + k] - q[k];
+            l1 += e1[k] * e1[k];
+            l2 += e2[k] * e2[k];
+        }
+        cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double a2 = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(a2 > 1e-14 * std::max(l1, l2))) throw bem::Error(BEM_ERR_INVALID, "curved panel without area");
+    }
+    bem::launch_quad_pair_integrals(c, P, pts, nodes, S, F);
+    return BEM_OK;
+    API_CATCH
+}
+
 bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return fail(BEM_ERR_INVALID, "NULL argument");
     if (std::strcmp(key, "trace_mode") == 0) {

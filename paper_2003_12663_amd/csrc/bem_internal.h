@@ -243,6 +243,9 @@ void launch_geometry(bem_ctx* c);                                  // geometry.h
 // S, F of unit density on panel[p] at pts[p]: rule 0 closed forms, 1 the Sec. 4 rule (duffy.hip)
 void launch_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const int32_t* panel, int rule, double* S,
                            double* F, int64_t fstride);
+// S, F of unit density on curved quadratic panels (six nodes each) by the Sec. 4 rule (duffy.hip)
+void launch_quad_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const double* nodes, double* S,
+                                double* F);
 // the Sec. 4 rule for the assembly's near list into sf[4 k .. 4 k + 3] (duffy.hip)
 void launch_near_duffy(bem_ctx* c, int64_t nnz, const int32_t* row, const int32_t* col, double* sf);
 void launch_panel_points(bem_ctx* c, int64_t L, const int32_t* panel, const double* bary, double offset,

@@ -272,6 +272,281 @@ __global__ __launch_bounds__(256) void k_pair_closed(int64_t P, const double* __
     }
 }
 
+// ---- curved quadratic panels (Sec. 3) ----------------------------------------
+// A curved panel is the quadratic Lagrange map of the reference triangle
+// {(s, t): s, t >= 0, s + t <= 1} through six nodes: corners P0 = y(0,0),
+// P1 = y(1,0), P2 = y(0,1), edge nodes P3 = y(1/2,0), P4 = y(1/2,1/2), P5 = y(0,1/2).
+// The rule of Sec. 4 runs in the parameter plane: the closest parameter point c
+// (damped Newton on |x - y|^2 / 2 from the best of a 17 x 17 sampling, the three
+// edge minima by Newton along each edge from 17 samples, the corners), pieces of
+// the reference triangle with c as a corner, the Duffy map of each piece times
+// the surface Jacobian |y_s x y_t|, and the graded cells of the flat rule with
+// the piece's edge vectors taken through the tangent map at c.
+
+struct QMap {
+    double P[6][3];
+    // y and its first (and, when ys2 != NULL, second) derivatives at (s, t)
+    __device__ void eval(double s, double t, double y[3], double ys[3], double yt[3], double* ys2 = nullptr,
+                         double* yst = nullptr, double* yt2 = nullptr) const {
+        const double l1 = 1.0 - s - t;
+        const double N[6] = {l1 * (2.0 * l1 - 1.0), s * (2.0 * s - 1.0), t * (2.0 * t - 1.0), 4.0 * l1 * s,
+                             4.0 * s * t, 4.0 * t * l1};
+        const double Ns[6] = {-(4.0 * l1 - 1.0), 4.0 * s - 1.0, 0.0, 4.0 * (l1 - s), 4.0 * t, -4.0 * t};
+        const double Nt[6] = {-(4.0 * l1 - 1.0), 0.0, 4.0 * t - 1.0, -4.0 * s, 4.0 * s, 4.0 * (l1 - t)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                a += N[m] * P[m][k];
+                b += Ns[m] * P[m][k];
+                c += Nt[m] * P[m][k];
+            }
+            y[k] = a;
+            ys[k] = b;
+            yt[k] = c;
+            if (ys2) {   // constant second derivatives of the shape functions
+                ys2[k] = 4.0 * P[0][k] + 4.0 * P[1][k] - 8.0 * P[3][k];
+                yst[k] = 4.0 * P[0][k] - 4.0 * P[3][k] + 4.0 * P[4][k] - 4.0 * P[5][k];
+                yt2[k] = 4.0 * P[0][k] + 4.0 * P[2][k] - 8.0 * P[5][k];
+            }
+        }
+    }
+    __device__ double dist2(const double x[3], double s, double t) const {
+        double y[3], ys[3], yt[3];
+        eval(s, t, y, ys, yt);
+        const double r0 = y[0] - x[0], r1 = y[1] - x[1], r2 = y[2] - x[2];
+        return r0 * r0 + r1 * r1 + r2 * r2;
+    }
+};
+
+// closest parameter point of the panel to x (step 1); uniform over the wave
+__device__ void quad_closest(const QMap& Q, const double x[3], double c[2]) {
+    const double cs[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+    double best = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        const double d2 = Q.dist2(x, cs[k][0], cs[k][1]);
+        if (d2 < best) {
+            best = d2;
+            c[0] = cs[k][0];
+            c[1] = cs[k][1];
+        }
+    }
+    for (int e = 0; e < 3; ++e) {   // edges a -> b
+        const double a0 = cs[e][0], a1 = cs[e][1];
+        const double ds = cs[(e + 1) % 3][0] - a0, dt = cs[(e + 1) % 3][1] - a1;
+        double tau = 0.0, f0 = INFINITY;
+        for (int i = 0; i <= 16; ++i) {
+            const double tt = i / 16.0, d2 = Q.dist2(x, a0 + tt * ds, a1 + tt * dt);
+            if (d2 < f0) {
+                f0 = d2;
+                tau = tt;
+            }
+        }
+        for (int it = 0; it < 50; ++it) {
+            double y[3], ys[3], yt[3], yss[3], yst[3], ytt[3];
+            Q.eval(a0 + tau * ds, a1 + tau * dt, y, ys, yt, yss, yst, ytt);
+            double g = 0.0, h1 = 0.0, h2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double r = y[k] - x[k];
+                const double yd = ys[k] * ds + yt[k] * dt;
+                const double ydd = yss[k] * ds * ds + 2.0 * yst[k] * ds * dt + ytt[k] * dt * dt;
+                g += yd * r;
+                h1 += yd * yd;
+                h2 += ydd * r;
+            }
+            double h = h1 + h2;
+            if (h <= 0.0) h = h1;
+            double nt = tau - g / h;
+            nt = nt < 0.0 ? 0.0 : (nt > 1.0 ? 1.0 : nt);
+            const double step = fabs(nt - tau);
+            tau = nt;
+            if (step <= 1e-16) break;
+        }
+        const double d2 = Q.dist2(x, a0 + tau * ds, a1 + tau * dt);
+        if (d2 < best) {
+            best = d2;
+            c[0] = a0 + tau * ds;
+            c[1] = a1 + tau * dt;
+        }
+    }
+    // interior: damped Newton from the best sample, steps kept in the triangle
+    double s = 0.0, t = 0.0, f0 = INFINITY;
+    for (int i = 0; i <= 16; ++i)
+        for (int j = 0; i + j <= 16; ++j) {
+            const double d2 = Q.dist2(x, i / 16.0, j / 16.0);
+            if (d2 < f0) {
+                f0 = d2;
+                s = i / 16.0;
+                t = j / 16.0;
+            }
+        }
+    for (int it = 0; it < 60; ++it) {
+        double y[3], ys[3], yt[3], yss[3], yst[3], ytt[3];
+        Q.eval(s, t, y, ys, yt, yss, yst, ytt);
+        double g0 = 0.0, g1 = 0.0, a00 = 0.0, a01 = 0.0, a11 = 0.0, b00 = 0.0, b01 = 0.0, b11 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double r = y[k] - x[k];
+            g0 += ys[k] * r;
+            g1 += yt[k] * r;
+            a00 += ys[k] * ys[k];
+            a01 += ys[k] * yt[k];
+            a11 += yt[k] * yt[k];
+            b00 += yss[k] * r;
+            b01 += yst[k] * r;
+            b11 += ytt[k] * r;
+        }
+        double h00 = a00 + b00, h01 = a01 + b01, h11 = a11 + b11;
+        double det = h00 * h11 - h01 * h01;
+        if (!(h00 > 0.0 && det > 0.0)) {   // not positive definite: Gauss-Newton
+            h00 = a00;
+            h01 = a01;
+            h11 = a11;
+            det = h00 * h11 - h01 * h01;
+        }
+        const double d0 = -(h11 * g0 - h01 * g1) / det, d1 = -(h00 * g1 - h01 * g0) / det;
+        double al = 1.0;
+        if (d0 < 0.0 && s + al * d0 < 0.0) al = -s / d0;
+        if (d1 < 0.0 && t + al * d1 < 0.0) al = -t / d1;
+        if (d0 + d1 > 0.0 && s + t + al * (d0 + d1) > 1.0) al = (1.0 - s - t) / (d0 + d1);
+        double fn = INFINITY, sn = s, tn = t;
+        for (int hh = 0; hh < 40; ++hh, al *= 0.5) {
+            sn = s + al * d0;
+            tn = t + al * d1;
+            if (sn < 0.0) sn = 0.0;
+            if (tn < 0.0) tn = 0.0;
+            if (sn + tn > 1.0) tn = 1.0 - sn;
+            fn = Q.dist2(x, sn, tn);
+            if (fn <= f0) break;
+        }
+        if (!(fn <= f0)) break;
+        const double step = fabs(sn - s) + fabs(tn - t);
+        s = sn;
+        t = tn;
+        f0 = fn;
+        if (step <= 1e-16) break;
+    }
+    if (f0 < best) {
+        c[0] = s;
+        c[1] = t;
+    }
+}
+
+// one wave per (point, curved panel) pair; lanes take the cells' nodes as in k_duffy
+__global__ __launch_bounds__(256) void k_quad_duffy(int64_t P, const double* __restrict__ pts,
+                                                    const double* __restrict__ nodes, GLRule gl,
+                                                    double* __restrict__ S, double* __restrict__ F) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= P) return;   // uniform over the wave
+    QMap Q;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Q.P[m][k] = nodes[18 * p + 3 * m + k];
+    const double x[3] = {pts[3 * p], pts[3 * p + 1], pts[3 * p + 2]};
+    double ch[2];
+    quad_closest(Q, x, ch);
+    double yc[3], ys[3], yt[3], yss[3], yst[3], ytt[3];
+    Q.eval(ch[0], ch[1], yc, ys, yt, yss, yst, ytt);
+    const double xc[3] = {x[0] - yc[0], x[1] - yc[1], x[2] - yc[2]};
+    double d = sqrt(dot(xc, xc));
+    double size = 0.0;   // the longest corner-to-corner chord
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double e0 = Q.P[(k + 1) % 3][0] - Q.P[k][0], e1 = Q.P[(k + 1) % 3][1] - Q.P[k][1];
+        const double e2 = Q.P[(k + 1) % 3][2] - Q.P[k][2];
+        size = fmax(size, sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+    }
+    if (d <= 1e-14 * size) d = 0.0;   // on the panel: the singular pair
+    const int jn = lane & 15, in0 = lane >> 4;
+    const double tvj = gl.t[jn], wvj = gl.w[jn];
+    double tu[4], wu[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        tu[k] = gl.t[in0 + 4 * k];
+        wu[k] = gl.w[in0 + 4 * k];
+    }
+    const double cs[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+    double sacc = 0.0, f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        const double qa0 = cs[e][0] - ch[0], qa1 = cs[e][1] - ch[1];
+        const double qb0 = cs[(e + 1) % 3][0] - ch[0], qb1 = cs[(e + 1) % 3][1] - ch[1];
+        const double detp = qa0 * qb1 - qa1 * qb0;   // > 0: counter-clockwise
+        if (detp <= 1e-14) continue;                 // c on this edge: no piece
+        double pa[3], pb[3], ab[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            pa[k] = ys[k] * qa0 + yt[k] * qa1;
+            pb[k] = ys[k] * qb0 + yt[k] * qb1;
+            ab[k] = pb[k] - pa[k];
+        }
+        double cr[3];
+        cross(pa, pb, cr);
+        const double Jc = sqrt(dot(cr, cr)), lab = sqrt(dot(ab, ab));
+        double L = sqrt(dot(pa, pa));
+        L = fmax(L, sqrt(dot(pb, pb)));
+        L = fmax(L, lab);
+        Graded gu, gv;
+        if (d > 0.0)
+            gu.init(0.0, d / L);
+        else
+            gu.unit();
+        double vs = -dot(pa, ab) / (lab * lab);
+        vs = vs < 0.0 ? 0.0 : (vs > 1.0 ? 1.0 : vs);
+        gv.init(vs, (Jc / lab) / lab);
+        for (int iu = 0; iu + 1 < gu.n; ++iu) {
+            const double u0 = gu.at(iu), du = gu.at(iu + 1) - u0;
+            for (int iv = 0; iv + 1 < gv.n; ++iv) {
+                const double v0 = gv.at(iv), dv = gv.at(iv + 1) - v0;
+                const double vv = v0 + dv * tvj, wvv = dv * wvj;
+                const double dir0 = (1.0 - vv) * qa0 + vv * qb0, dir1 = (1.0 - vv) * qa1 + vv * qb1;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    // the node c + (ds, dt): x - y and the tangents there from c in exact Taylor
+                    // form (the map is quadratic), so that x - y, short near the corner, is not
+                    // the difference of two long vectors
+                    const double u = u0 + du * tu[k];
+                    const double dsn = u * dir0, dtn = u * dir1;
+                    double r[3], dys[3], dyt[3], nv[3];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        const double dy = ys[m] * dsn + yt[m] * dtn +
+                                          0.5 * (yss[m] * dsn * dsn + 2.0 * yst[m] * dsn * dtn + ytt[m] * dtn * dtn);
+                        r[m] = xc[m] - dy;
+                        dys[m] = ys[m] + yss[m] * dsn + yst[m] * dtn;
+                        dyt[m] = yt[m] + yst[m] * dsn + ytt[m] * dtn;
+                    }
+                    cross(dys, dyt, nv);
+                    const double r0 = r[0], r1 = r[1], r2 = r[2];
+                    const double ir = rsqrt_pos(r0 * r0 + r1 * r1 + r2 * r2);
+                    const double jw = u * detp * sqrt(dot(nv, nv)) * (du * wu[k]) * wvv;
+                    sacc += jw * ir;
+                    const double t3 = jw * ir * ir * ir;
+                    f0 += t3 * r0;
+                    f1 += t3 * r1;
+                    f2 += t3 * r2;
+                }
+            }
+        }
+    }
+    sacc = wave_sum(sacc);
+    f0 = wave_sum(f0);
+    f1 = wave_sum(f1);
+    f2 = wave_sum(f2);
+    if (lane == 0) {
+        S[p] = sacc * INV4PI;
+        if (F) {
+            const double nan = __builtin_nan("");
+            F[3 * p + 0] = d > 0.0 ? f0 * INV4PI : nan;
+            F[3 * p + 1] = d > 0.0 ? f1 * INV4PI : nan;
+            F[3 * p + 2] = d > 0.0 ? f2 * INV4PI : nan;
+        }
+    }
+}
+
 // n-point Gauss-Legendre rule on [0, 1]: the roots of P_n by Newton's method from the
 // asymptotic guess cos(pi (i + 3/4) / (n + 1/2)), P_n and P_n' from the three-term recurrence;
 // weight 1 / ((1 - z^2) P_n'(z)^2) on [0, 1].
@@ -327,6 +602,18 @@ void launch_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const int32
         hipLaunchKernelGGL(k_duffy, dim3((unsigned)ceil_div(P, 4)), dim3(256), 0, c->stream, P, pts,
                            (const int32_t*)nullptr, panel, c->tri64.as<double>(), gl, S, (int64_t)1, F, fstride);
     }
+    BEM_CHECK_LAUNCH();
+}
+
+// S[p], F[p][0..3) (F may be NULL) of unit density on the curved quadratic panel nodes[p] (six
+// nodes, [P][6][3]) at pts[p], by the Sec. 4 rule in the panel's parameter plane.
+void launch_quad_pair_integrals(bem_ctx* c, int64_t P, const double* pts, const double* nodes, double* S,
+                                double* F) {
+    if (P == 0) return;
+    KTimer t(c, "pair_quad");
+    static const GLRule gl = make_gl16();
+    hipLaunchKernelGGL(k_quad_duffy, dim3((unsigned)ceil_div(P, 4)), dim3(256), 0, c->stream, P, pts, nodes, gl, S,
+                       F);
     BEM_CHECK_LAUNCH();
 }
 
