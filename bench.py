@@ -10,12 +10,14 @@ integral, all from inputs already resident in GPU memory.
 Prints one JSON line.  value = panel-pair evaluations per second over the
 whole step (matrix entries + surface-field pairs + field-line pairs).
 The roofline entry is for the dominant kernel, the far-field pass of the
-field-line tracer (k_lb_far, one launch per RK4 stage of all live lines):
-algorithmic FP64 flops per launch (regular pairs x 141 flop) / its average
-duration over every launch of a repeat of the timed steps, measured by HIP
-events carried in the kernel's own dispatches (profiling mode 2: nothing else
-is timed).  The events slow the steps, so the timed steps themselves run with
-nothing profiled.  The per-phase breakdown comes from one more step after
+field-line tracer (k_lb_far, one launch per RK4 stage of the live lines of a
+line group): algorithmic FP64 flops per launch (regular pairs x 141 flop) / its
+average duration over every launch of a repeat of the timed steps, each launch
+timed by the kernel itself (profiling mode 2: the earliest block start to the
+latest wave end on the device's wall clock; nothing else is timed).  Events
+carried in the dispatch would also count the wait for the other line group's
+kernel on the second stream (2.2 us a launch more than rocprofv3 measured on
+the same box).  The timed steps themselves run with nothing profiled.  The per-phase breakdown comes from one more step after
 those, with every kernel timed.  cpu_baseline times
 the plain FP64 CPU oracle, compiled on the host with -march=native, on a
 bounded sample of the same workload.  The 64-load-case time-to-solve stops
@@ -92,6 +94,8 @@ def parse():
                     help="comma-separated key=value tuning knobs applied after the autotuner (experiments)")
     ap.add_argument("--trace-groups", type=int, default=None,
                     help="line groups of the field-line tracer (1..4; default: the library's)")
+    ap.add_argument("--no-far-events", action="store_true",
+                    help="skip the repeat of the steps that times the dominant kernel by events (for kernel traces)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -586,15 +590,17 @@ def main():
     # the same steps again with the dominant kernel timed by events carried in its own dispatches
     # (profiling mode 2): its launch durations for the roofline (the events slow the step, so these
     # steps are not the timed ones)
-    ctx.set_profiling(2)
-    ctx.reset_stats()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_step_prof = (time.perf_counter() - t2) * 1e3 / args.steps
-    fused = ctx.kernel_stats("trace_far")[0] == 0   # one launch per stage throughout (trace_mode 3)
+    ms_step_prof = None
+    if not args.no_far_events:
+        ctx.set_profiling(2)
+        ctx.reset_stats()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for k in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms_step_prof = (time.perf_counter() - t2) * 1e3 / args.steps
+    fused = far_launches == 0   # one launch per stage throughout (trace_mode 3)
     tf_n, tf_ms = ctx.kernel_stats("trace_pass" if fused else "trace_far")
     if fused:
         far_launches, far_pairs = pass_launches, pass_pairs
@@ -621,10 +627,10 @@ def main():
     tr_n, tr_ms = stats["trace"]
     trace_ms = tr_ms / max(tr_n, 1)
     # dominant kernel: the far-field pass of the field-line tracer (k_lb_far), one launch per RK4 stage,
-    # every launch of the timed steps timed by its dispatch's own events
+    # every launch of a repeat of the timed steps timed by its own clock stamps (profiling mode 2)
     far_flop_per_launch = far_pairs * FLOP_FIELD_PAIR / far_launches
-    far_avg_ms = tf_ms / max(tf_n, 1)
-    achieved = far_flop_per_launch / (far_avg_ms * 1e-3) / 1e12
+    far_avg_ms = tf_ms / tf_n if tf_n > 0 else None
+    achieved = far_flop_per_launch / (far_avg_ms * 1e-3) / 1e12 if far_avg_ms else None
     gv_n, gv_ms = stats["gemv"]
     gemv_ms = gv_ms / max(gv_n, 1)
     gemv_gbs = (8.0 * n_unk * n_unk) / (gemv_ms * 1e-3) / 1e9
@@ -684,7 +690,7 @@ def main():
                                 "step, then the regular and near pairs of all live lines, FP64)") if fused else
                                "k_lb_far (far-field pass of the field-line tracer, FP64)", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS if achieved else None,
                      "traffic": K_LF_PASS_TRAFFIC_BYTES if fused else K_LB_FAR_TRAFFIC_BYTES,
                      "traffic_unit": "bytes per launch (HBM, counters)",
                      "flop_per_pair": FLOP_FIELD_PAIR, "pairs_per_launch": far_pairs / far_launches,

@@ -410,12 +410,15 @@ bem_status bem_autotune(bem_ctx* ctx, const char* cache_path, int32_t* from_cach
  *            16th pass is timed, so its launch count is a sample and total_ms covers that
  *            sample), "gemm_f32", "gemm_f64", "gemm_rows", "bgmres_iter", "grad",
  *            "grad_reverse", "grad_rows_EH", "grad_panel_far", "grad_panel_near", "gemvT".
- *  enable 1 or 2: "trace_far", every chunked far pass of the two-kernel field-line layout, and
+ *  enable 1: also "trace_far", every chunked far pass of the two-kernel field-line layout, and
  *            "trace_pass", every launch of the one-launch layout, timed by events carried in
- *            their own dispatches (hipExtLaunchKernelGGL): the kernel's execution interval,
- *            with nothing added to the stream.
+ *            their own dispatches (hipExtLaunchKernelGGL), nothing added to the stream.
  *  enable 2: only "trace_far" and "trace_pass", so that all other work runs as it does
- *            unprofiled.
+ *            unprofiled, each launch timed by the kernel itself: the earliest block start to
+ *            the latest wave end on the device's constant-rate wall clock (with two line
+ *            groups on two streams, an event interval also counts the wait for the other
+ *            group's kernel to free the compute units).  A field-line call then waits for its
+ *            stream at the end to collect the stamps.
  * Errors: INVALID for another value. */
 bem_status bem_set_profiling(bem_ctx* ctx, int32_t enable);
 bem_status bem_kernel_stats(bem_ctx* ctx, const char* name, int64_t* launches, double* total_ms);

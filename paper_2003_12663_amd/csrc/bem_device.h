@@ -115,6 +115,20 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
 }
 __device__ __forceinline__ float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// ---- kernel-side launch timing (profiling mode 2) ----------------------------
+// A timed launch owns KCLK_SUB pairs of device words: the earliest block start and the latest
+// wave end on the device's constant-rate wall clock, spread over sub-slots by block so that few
+// atomics meet on one word.  ts == nullptr: not timed.
+constexpr int KCLK_SUB = 64;
+__device__ __forceinline__ void kclock_start(unsigned long long* ts) {
+    if (ts && threadIdx.x == 0)
+        atomicMin(ts + 2 * (blockIdx.x % KCLK_SUB), (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void kclock_stop(unsigned long long* ts) {
+    if (ts && (threadIdx.x & 63) == 0)
+        atomicMax(ts + 2 * (blockIdx.x % KCLK_SUB) + 1, (unsigned long long)wall_clock64());
+}
+
 // ---- wave / block reductions (wave64) --------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

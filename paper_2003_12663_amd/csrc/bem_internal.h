@@ -167,6 +167,13 @@ struct bem_ctx {
     bem::DBuf ad_state, ad_part, ad_mask, ad_cnt, ad_self, ad_ppart, ad_list, ad_path, ad_stage, ad_geo, ad_seg,
         ad_vptr, ad_vcorner;
 
+    // kernel-side launch timing (profiling mode 2): KCLK_SUB word pairs per launch slot, the
+    // statistic each used slot feeds, the device's wall-clock rate (kHz)
+    bem::DBuf kclk, kclk_dur;
+    int64_t kclk_cap = 0;
+    std::vector<std::string> kclk_names;
+    int kclk_khz = 0;
+
     // device counters (bem_get_counter): near [0] and regular [1] pairs of the two-kernel field-line
     // passes, near [2] and regular [3] pairs of the one-launch passes
     bem::DBuf counters;
@@ -231,6 +238,12 @@ struct KTimer {
     KTimer(bem_ctx* ctx, const char* nm, bool enabled = true, hipStream_t st = nullptr);
     ~KTimer();
 };
+// Kernel-side launch timing (profiling mode 2): kclock_begin readies max_launches slots,
+// kclock_slot hands out the next one (nullptr when not timing or when the slots are used up),
+// kclock_end adds each used slot's duration to its statistic (it waits for the stream).
+void kclock_begin(bem_ctx* c, int64_t max_launches);
+unsigned long long* kclock_slot(bem_ctx* c, const char* name);
+void kclock_end(bem_ctx* c);
 // resolve_stats waits for every pending event; resolve_ready takes only the completed prefix
 void resolve_stats(bem_ctx* c);
 void resolve_ready(bem_ctx* c);

@@ -90,8 +90,10 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
                                                  const int32_t* __restrict__ line_of, int64_t cap,
                                                  const int32_t* __restrict__ count, int32_t* __restrict__ count_next,
                                                  const double* __restrict__ ys, double* __restrict__ part,
-                                                 uint32_t* __restrict__ pmask, int32_t tiles, int64_t KS) {
+                                                 uint32_t* __restrict__ pmask, int32_t tiles, int64_t KS,
+                                                 unsigned long long* __restrict__ kts) {
     constexpr int TILE = SPLIT > 1 ? 64 : TILE_LINES;         // lines per block
+    kclock_start(kts);
     constexpr int PER = LB_C / SPLIT;
     __shared__ double wred[SPLIT > 1 ? SPLIT : 1][64][3];
     __shared__ uint32_t wmask[SPLIT > 1 ? SPLIT : 1][64];
@@ -128,8 +130,14 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     const int32_t A = count[0];
     asm volatile("" ::"s"(A), "v"(p0), "v"(p1), "v"(p2), "s"(qf[0]), "s"(qf[FR_CC - 1]), "s"(cf[0]), "s"(cf[3]));
     if (bid == 0 && threadIdx.x == 0) count_next[0] = 0;
-    if (chunk >= KS) return;   // padding of the chunk count to a multiple of 8
-    if (tile0 >= A) return;    // uniform over the block
+    if (chunk >= KS) {   // padding of the chunk count to a multiple of 8
+        kclock_stop(kts);
+        return;
+    }
+    if (tile0 >= A) {    // uniform over the block
+        kclock_stop(kts);
+        return;
+    }
     const bool live = t < A;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     uint32_t nmask = 0;
@@ -180,7 +188,10 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
         wred[wv][lane][2] = e2;
         wmask[wv][lane] = nmask;
         __syncthreads();
-        if (wv != 0 || !live) return;
+        if (wv != 0 || !live) {
+            kclock_stop(kts);
+            return;
+        }
         e0 = wred[0][lane][0];
         e1 = wred[0][lane][1];
         e2 = wred[0][lane][2];
@@ -193,6 +204,7 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
             nmask |= wmask[w][lane];
         }
     } else if (!live) {
+        kclock_stop(kts);
         return;
     }
     double* o = part + (t * KS + chunk) * 3;
@@ -200,6 +212,7 @@ __global__ __launch_bounds__(SPLIT > 1 ? 64 * SPLIT : TILE_LINES) void k_lb_far(
     o[1] = e1;
     o[2] = e2;
     pmask[t * KS + chunk] = nmask;
+    kclock_stop(kts);
 }
 
 
@@ -662,7 +675,7 @@ double time_far_pass(bem_ctx* c, int64_t L, bool split, int tile_lines, int spli
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                                 \
     hipLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, c->stream, c->pan64.as<double>(), \
                        FR, N, sol, c->n, (const int32_t*)nullptr, (const int32_t*)nullptr, L, cnt, cnt + 16, pts, \
-                       part, pmask, ntile, KS)
+                       part, pmask, ntile, KS, (unsigned long long*)nullptr)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -798,6 +811,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     const double* fsol = nodal ? c->nod_ones.as<double>() : sol;
     const int64_t fn = nodal ? 0 : c->n;
     const int64_t max_pass = 4 * (int64_t)tp->max_steps + 1;
+    kclock_begin(c, (max_pass + 2) * (G + 1));
     int cur = 0;
     int32_t* host = c->host_stage.as<int32_t>();
     for (int64_t pass = 0; pass < max_pass; ++pass) {
@@ -824,9 +838,13 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             const bool split = q.known <= c->tune_trace_split;
             int64_t KSP = KS;   // partial rows the step kernel sums
             {
-            hipEvent_t fa = nullptr, fb = nullptr;   // dispatch timestamps of a chunked far pass
-            const bool tfar = c->profiling != 0 && !few;
+            // timing of a chunked far pass: events carried in its dispatch (profiling mode 1), or the
+            // kernel's own clock stamps (mode 2; events would also count the wait for the other
+            // line group's kernel)
+            hipEvent_t fa = nullptr, fb = nullptr;
+            const bool tfar = c->profiling == 1 && !few;
             if (tfar) timing_events(c, &fa, &fb);
+            unsigned long long* kts = few ? nullptr : kclock_slot(c, "trace_far");
             // blocks of tiles past the live count would only launch and exit: size the grids by
             // the last known live count (an upper bound, the count only falls)
             const int tile = split ? 64 : c->tune_trace_tile;
@@ -836,7 +854,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
 #define BEM_LB_FAR(R, SP, TL, FR)                                                                              \
     hipExtLaunchKernelGGL((k_lb_far<R, SP, TL>), g1, dim3(SP > 1 ? 64 * SP : TL), 0, q.st, fa, fb, 0, P64, FR, N, \
                           fsol, fn, line_rhs, sc.line, q.size, q.cnt[cur], q.cnt[cur ^ 1], sc.y, gpart, gmask,     \
-                          ntile, KS)
+                          ntile, KS, kts)
 #define BEM_LB_FAR_ALL(R, FR)                      \
     if (split && splitk == 2)                      \
         BEM_LB_FAR(R, 2, 64, FR);                  \
@@ -934,6 +952,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     hipLaunchKernelGGL(k_lb_count_sum, dim3(1), dim3(256), 0, c->stream, L, ncnt,
                        reinterpret_cast<unsigned long long*>(c->counters.p));
     BEM_CHECK_LAUNCH();
+    kclock_end(c);
 }
 
 namespace {

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void k_lf_pass(
     int rnd, int64_t S, int64_t pstride_part, LFState cur, LFState nxt, const double* __restrict__ part_prev,
     double* __restrict__ part_cur, LBArgs a, int32_t* __restrict__ n_steps, int32_t* __restrict__ stop_code,
     double* __restrict__ integral, uint8_t* __restrict__ exceeds, double* __restrict__ path, int64_t pstride,
-    unsigned long long* __restrict__ ncnt, int32_t* __restrict__ live, int pidx) {
+    unsigned long long* __restrict__ ncnt, int32_t* __restrict__ live, int pidx, unsigned long long* __restrict__ kts) {
+    kclock_start(kts);
     constexpr int G = 256 / LPB;           // threads per slot in the near pass
     constexpr int GW = G < 64 ? G : 64;    // of them in one wave
     constexpr int NU = G / GW;             // waves per slot in the near pass
@@ -272,7 +273,10 @@ __global__ __launch_bounds__(256) void k_lf_pass(
     }
     bool any = false;
     for (int q = 0; q < LPB; ++q) any |= sl[q] >= 0;
-    if (!any) return;   // uniform over the block
+    if (!any) {   // uniform over the block
+        kclock_stop(kts);
+        return;
+    }
     const bool hit_stage = (step_phase == 3);   // the query points are proposed end points
 
     // ---- 2a. regular pairs, one panel per lane; near pairs queued per (slot, wave) ----
@@ -449,6 +453,7 @@ __global__ __launch_bounds__(256) void k_lf_pass(
         rec[4] = (double)jb;
         rec[5] = (double)(nqc[q][0] + nqc[q][1] + nqc[q][2] + nqc[q][3]);
     }
+    kclock_stop(kts);
 }
 
 __global__ __launch_bounds__(256) void k_lf_init(int64_t L, const double* __restrict__ starts, LFState s,
@@ -663,15 +668,17 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
         const int step_phase = p == 0 ? -1 : lf_phase_of(pass0 + p - 1);
         const int pidx = (int)(p % 3);
         const dim3 grid((unsigned)(nb * ceil_div(S, lpb)));
+        // timing: events carried in the dispatch (profiling mode 1) or the kernel's own clock (mode 2)
         hipEvent_t fa = nullptr, fb = nullptr;
-        const bool timed = c->profiling != 0;
+        const bool timed = c->profiling == 1;
         if (timed) timing_events(c, &fa, &fb);
+        unsigned long long* kts = kclock_slot(c, "trace_pass");
 #define BEM_LF(R, LPB, ND, FR)                                                                                      \
     hipExtLaunchKernelGGL((k_lf_pass<R, LPB, ND>), grid, dim3(256), 0, c->stream, fa, fb, 0, F64, FR, Np, N,          \
                           c->tri64.as<double>(), c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), fsol, fn, sol, \
                           c->n, line_rhs, c->tri.as<int32_t>(), step_phase, nb_prev, nb, rnd, S, prs, buf[rd],         \
                           buf[rd ^ 1], part[pw ^ 1], part[pw], a, n_steps, stop_code, integral, exceeds, path,         \
-                          pstride, ncnt, live, pidx)
+                          pstride, ncnt, live, pidx, kts)
 #define BEM_LF_LPB(R, ND, FR)    \
     if (lpb == 1)                \
         BEM_LF(R, 1, ND, FR);    \
@@ -739,8 +746,10 @@ void launch_trace_fused(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L, 
                        pstride, ncnt);
     BEM_CHECK_LAUNCH();
     if (c->opt.basis == BEM_BASIS_LINEAR) launch_nodal_records(c, sol);
+    kclock_begin(c, 4 * (int64_t)tp->max_steps + 3);
     fused_trace_loop(c, sol, L, line_rhs, tp, n_steps, stop_code, path, integral, exceeds, buf[0], buf[1], L, 0,
                      ncnt);
+    kclock_end(c);
     hipLaunchKernelGGL(k_lf_count_sum, dim3(1), dim3(256), 0, c->stream, L, ncnt,
                        reinterpret_cast<unsigned long long*>(c->counters.p) + 2);
     BEM_CHECK_LAUNCH();
