@@ -54,13 +54,12 @@ if ROOT not in sys.path:
 #   sigma_j * F accumulation 6  -> field-only pair 141
 #   potential-only pair (assembly of S rows): 9 + 7 x (3 + 5 + 1 + 2) = 86
 FLOP_FIELD_PAIR = 141
-# HBM traffic of one k_lb_far launch (this workload, FP64; the 4- and 8-wave chunk splits the autotuner
-# picks between read and write the same to 0.2 %): rocprofv3 FETCH_SIZE and
-# WRITE_SIZE per dispatch, averaged over the 5024 chunked passes of one step, scaled by the device-copy
-# calibration (FETCH x 2, WRITE x 1); see profiles/hbm_counters_coax20k.md.  Re-measure when the
-# kernel changes.
-K_LB_FAR_FETCH_KIB = 5062.3
-K_LB_FAR_WRITE_KIB = 2852.8
+# HBM traffic of one k_lb_far launch (this workload, FP64, the autotuned 4-wave chunk split, two line
+# groups of up to 128 lines): rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, averaged over the
+# 7616 chunked passes of a step, scaled by the device-copy calibration (FETCH x 2, WRITE x 1); see
+# profiles/hbm_counters_coax20k.md.  Re-measure when the kernel changes.
+K_LB_FAR_FETCH_KIB = 5058.2
+K_LB_FAR_WRITE_KIB = 1862.8
 K_LB_FAR_TRAFFIC_BYTES = (2.0 * K_LB_FAR_FETCH_KIB + 1.0 * K_LB_FAR_WRITE_KIB) * 1024.0
 # the same for k_lf_pass, the default one-launch-per-stage layout: not yet taken (None)
 K_LF_PASS_TRAFFIC_BYTES = None

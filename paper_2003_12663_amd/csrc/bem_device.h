@@ -117,15 +117,19 @@ __device__ __forceinline__ float rsqrt_pos(float x) { return __builtin_amdgcn_rs
 
 // ---- kernel-side launch timing (profiling mode 2) ----------------------------
 // A timed launch owns KCLK_SUB pairs of device words: the earliest block start and the latest
-// wave end on the device's constant-rate wall clock, spread over sub-slots by block so that few
-// atomics meet on one word.  ts == nullptr: not timed.
+// block end on the device's constant-rate wall clock, spread over sub-slots by block so that few
+// atomics meet on one word.  Blocks are dispatched in order of their index, so only the first
+// KCLK_SUB stamp their start; a block's end is stamped by its thread 0, whose wave finishes the
+// block's reduction last in the kernels timed this way.  Stamps cost the kernel an atomic each
+// (one per wave measured 6 % longer launches than rocprofv3), so they are kept this few.
+// ts == nullptr: not timed.
 constexpr int KCLK_SUB = 64;
 __device__ __forceinline__ void kclock_start(unsigned long long* ts) {
-    if (ts && threadIdx.x == 0)
-        atomicMin(ts + 2 * (blockIdx.x % KCLK_SUB), (unsigned long long)wall_clock64());
+    if (ts && blockIdx.x < KCLK_SUB && threadIdx.x == 0)
+        atomicMin(ts + 2 * blockIdx.x, (unsigned long long)wall_clock64());
 }
 __device__ __forceinline__ void kclock_stop(unsigned long long* ts) {
-    if (ts && (threadIdx.x & 63) == 0)
+    if (ts && threadIdx.x == 0)
         atomicMax(ts + 2 * (blockIdx.x % KCLK_SUB) + 1, (unsigned long long)wall_clock64());
 }
 
