@@ -341,7 +341,11 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
  *                previous launch wrote, then evaluate the new stage (at most 131072 panels);
  *                2 = one persistent launch, one workgroup per line; 0 (default) = 1 while
  *                more than "trace_tail" lines are live, then 3 (1 throughout above 131072
- *                panels).
+ *                panels).  Layout 3 (and the tail of 0) runs all its remaining stages in one
+ *                persistent launch once at most "trace_loop" line slots remain and their grid
+ *                fits the GPU at once (cooperative launch): blocks of a line group then exchange
+ *                their partial fields through device memory and wait for each other between
+ *                stages instead of ending the launch.
  *  "batched_solve": 1 (default) = bem_solve_gmres with nrhs >= 2 runs up to 64
  *                independent GMRES recurrences together, one multi-right-hand-
  *                side matrix product per iteration on the matrix cores (FP64:
@@ -375,6 +379,11 @@ bem_status bem_panel_points(bem_ctx* ctx, int64_t L, const int32_t* panel, const
  *                 live lines fit one 64-line tile; 0 = keep both groups to the end
  *  "trace_tail":  trace_mode 0: live-line count at or below which the run goes on in the
  *                 one-launch layout (0..4096; default 16; 0 = never); checked every 32 passes
+ *  "trace_loop":  one-launch layout: line-slot count at or below which the remaining stages
+ *                 run in one persistent launch (0..4096; default 4; 0 = never)
+ *  "trace_spin":  persistent launch: polls of one wait between its blocks before the launch
+ *                 gives up and the call fails with BEM_ERR_HIP (0..2^30; default 2^22, seconds;
+ *                 a safety bound, not reached in normal runs)
  *  "trace_lpb":   one-launch layout: line slots per block (1, 2, 4, 8; 0, the default: by the
  *                 live count)
  *  "trace_rnd":   one-launch layout: 256-panel rounds per block (1, 2, 4; 0, the default: by

@@ -933,6 +933,8 @@ bem_status bem_set_tuning(bem_ctx* c, const char* key, int64_t value) {
         {"trace_lpb", &bem_ctx::tune_trace_lpb, 0, 8, true},
         {"trace_rnd", &bem_ctx::tune_trace_rnd, 0, 4, true},
         {"trace_tail", &bem_ctx::tune_trace_tail, 0, 4096, false},
+        {"trace_loop", &bem_ctx::tune_trace_loop, 0, 4096, false},
+        {"trace_spin", &bem_ctx::tune_trace_spin, 0, 1 << 30, false},
         {"grad_batch", &bem_ctx::grad_batch, 64, 1 << 24, false},
     };
     for (const Knob& k : knobs)
@@ -964,6 +966,8 @@ bem_status bem_get_tuning(const bem_ctx* c, const char* key, int64_t* value) {
     else if (std::strcmp(key, "trace_lpb") == 0) *value = c->tune_trace_lpb;
     else if (std::strcmp(key, "trace_rnd") == 0) *value = c->tune_trace_rnd;
     else if (std::strcmp(key, "trace_tail") == 0) *value = c->tune_trace_tail;
+    else if (std::strcmp(key, "trace_loop") == 0) *value = c->tune_trace_loop;
+    else if (std::strcmp(key, "trace_spin") == 0) *value = c->tune_trace_spin;
     else return fail(BEM_ERR_INVALID, std::string("unknown tuning key ") + key);
     return BEM_OK;
 }

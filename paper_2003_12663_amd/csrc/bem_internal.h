@@ -201,6 +201,9 @@ struct bem_ctx {
     int32_t tune_trace_lpb = 0;       // one-launch layout: line slots per block (1, 2, 4, 8; 0: by the live count)
     int32_t tune_trace_rnd = 0;       // one-launch layout: 256-panel rounds per block (1, 2, 4; 0: by the live count)
     int32_t tune_trace_tail = 16;     // trace_mode 0: live lines at or below which the one-launch layout takes over
+    int32_t tune_trace_loop = 4;      // one-launch layout: line slots at or below which one persistent launch runs the rest
+    int32_t tune_trace_spin = 1 << 22;   // persistent launch: polls of one wait between its blocks at most
+    int32_t coop_launch = -1;         // the device takes cooperative launches (1) or not (0); -1: not asked yet
     int32_t grad_batch = 131072;      // points per batch of the gradient's pair passes (bounds scratch memory)
 
     // profiling: 0 off; 1 every kernel (event pairs around each launch, the field-line far pass

@@ -39,24 +39,109 @@ namespace {
 constexpr int LF_REC = 6;        // partial record: E (3), hit parameter (2: none), hit panel, near pairs
 constexpr int LF_RNDMAX = 4;     // 256-panel rounds per block at most
 constexpr int LF_NBMAX = 128;    // panel blocks of a launch at most
+constexpr int LF_GSTRIDE = 64;   // persistent loop: arrival counters 256 bytes apart (one per slot group)
+
+// the RK4 phase of pass p: 0 the start point, then 1, 2, 3 (stage points) and 4 (a step's end point)
+__host__ __device__ inline int lf_phase_of(int64_t pass) { return pass == 0 ? 0 : (int)((pass - 1) % 4) + 1; }
 
 
-// step_phase: the RK4 stage whose field the previous launch evaluated (0: start point, 1..3:
-// stage points, 4: a step's end point), or -1 in the first launch (query points = starts).
-template <typename R, int LPB, bool NODAL>
-__global__ __launch_bounds__(256) void k_lf_pass(
-    const double* __restrict__ far64, const R* __restrict__ farR, int64_t Np, int64_t N,
-    const double* __restrict__ tri64, const int32_t* __restrict__ tri_body, const int32_t* __restrict__ body_kind,
-    const double* __restrict__ fsol, int64_t fn, const double* __restrict__ sol, int64_t n,
-    const int32_t* __restrict__ line_rhs, const int32_t* __restrict__ ntri, int step_phase, int nb_prev, int nb,
-    int rnd, int64_t S, int64_t pstride_part, LFState cur, LFState nxt, const double* __restrict__ part_prev,
-    double* __restrict__ part_cur, LBArgs a, int32_t* __restrict__ n_steps, int32_t* __restrict__ stop_code,
-    double* __restrict__ integral, uint8_t* __restrict__ exceeds, double* __restrict__ path, int64_t pstride,
-    unsigned long long* __restrict__ ncnt, int32_t* __restrict__ live, int pidx, unsigned long long* __restrict__ kts) {
-    kclock_start(kts);
+// What a stage launch, or the persistent loop, works on.
+struct LFArgs {
+    const double* far64;   // far-field records, component-major (FP64 part)
+    const void* farR;      // the same in the pass precision R
+    int64_t Np, N;
+    const double* tri64;
+    const int32_t* tri_body;
+    const int32_t* body_kind;
+    const double* fsol;    // densities of the far pass ([rhs][fn]; fn 0: one row)
+    int64_t fn;
+    const double* sol;     // solutions ([rhs][n]) for the near pairs
+    int64_t n;
+    const int32_t* line_rhs;
+    const int32_t* ntri;   // nodal basis: vertices of each triangle
+    // the phase of the pass whose records part_prev holds (0: start point, 1..3: stage points, 4:
+    // a step's end point), -1 when there is none (the query points in cur are to be evaluated)
+    int step_phase;
+    int eval_phase;        // one-stage launch: the phase of the pass it evaluates
+    int nb_prev, nb, rnd;
+    int64_t S, pstride_part;
+    LFState cur, nxt;
+    const double* part_prev;
+    double* part_cur;
+    LBArgs a;
+    int32_t* n_steps;
+    int32_t* stop_code;
+    double* integral;
+    uint8_t* exceeds;
+    double* path;
+    int64_t pstride;
+    unsigned long long* ncnt;
+    int32_t* live;         // one-stage launch: live-line counters (three, used in turn)
+    int pidx;
+    // persistent loop: passes pass0 .., the arrival counter of each slot group, the error flag
+    // and the bound of every wait (polls)
+    int64_t pass0, max_pass;
+    uint32_t* gcnt;
+    int32_t* err;
+    uint32_t spin_limit;
+    unsigned long long* kts;
+};
+
+// the near-pair closed forms as calls of their own: inlined into the persistent loop they raise
+// the loop's register count past two blocks per CU
+struct LFVec3 {
+    double x, y, z;
+};
+__device__ __noinline__ LFVec3 flat_tri_F_call(const double* __restrict__ T, double x0, double x1, double x2) {
+    LFVec3 F;
+    flat_tri_F_seq(T, x0, x1, x2, F.x, F.y, F.z);
+    return F;
+}
+__device__ __noinline__ LFVec3 nodal_tri_E_call(const double* __restrict__ T, double x0, double x1, double x2, double u0,
+                                                double u1, double u2) {
+    LFVec3 E{0.0, 0.0, 0.0};
+    double ph = 0.0;
+    nodal_tri_phiE(T, x0, x1, x2, u0, u1, u2, ph, E.x, E.y, E.z);
+    return E;
+}
+
+// Coherent accesses for records that blocks of one launch exchange (agent scope: seen across
+// the XCDs' L2 caches without writing back or invalidating them).
+__device__ __forceinline__ double lf_load_coh(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lf_store_coh(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One stage per launch (LOOP false) or every remaining stage in one launch (LOOP true), for the
+// lines in slots [0, S).  Grid: (panel block b, slot group o) blocks, b fastest.
+//
+// LOOP: the blocks of slot group o keep the group's line state in LDS (each block its own copy,
+// all computed alike) and loop over the passes.  After writing its records of a pass, a block
+// waits until its stores have completed and counts itself in gcnt[o]; before finishing the pass
+// it waits until all nb blocks of the group have done so.  Records go through coherent stores
+// and loads into two buffers used in turn: a block overwrites the buffer of pass p - 1 only at
+// pass p + 1, after every block of the group has counted itself for pass p, which it does after
+// reading the records of pass p - 1.  Every wait is bounded (spin_limit polls); at the bound the
+// block raises err and leaves, and so, at their own bounds, do the blocks waiting for it.  The
+// grid must be resident at once (cooperative launch).
+template <typename R, int LPB, bool NODAL, bool LOOP>
+__device__ __forceinline__ void lf_run(const LFArgs& P) {
+    const double* __restrict__ far64 = P.far64;
+    const R* __restrict__ farR = static_cast<const R*>(P.farR);
+    const int64_t Npa = P.Np, N = P.N, S = P.S, pstride_part = P.pstride_part;
+    const double* __restrict__ tri64 = P.tri64;
+    const double* __restrict__ sol = P.sol;
+    const double* __restrict__ fsol = P.fsol;
+    const int64_t fn = P.fn, n = P.n;
+    const int32_t* __restrict__ ntri = P.ntri;
+    const LBArgs& a = P.a;
+    kclock_start(P.kts);
     constexpr int G = 256 / LPB;           // threads per slot in the near pass
     constexpr int GW = G < 64 ? G : 64;    // of them in one wave
     constexpr int NU = G / GW;             // waves per slot in the near pass
+    constexpr int LS = LOOP ? LPB : 1;
     __shared__ double sy[LPB][3], sx[LPB][3];
     __shared__ int32_t sl[LPB], srhs[LPB];
     __shared__ double fred[4][LPB][3];
@@ -64,14 +149,49 @@ __global__ __launch_bounds__(256) void k_lf_pass(
     __shared__ int32_t nqc[LPB][4];
     __shared__ double nred[LPB][NU][4];
     __shared__ int32_t nredj[LPB][NU];
+    // LOOP: the rest of the slots' state (the line point and query point stay in sx, sy)
+    __shared__ double lks[LS][3], lasum[LS], lI[LS];
+    __shared__ int32_t lns[LS], lline[LS];
+    __shared__ int32_t sabort;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = P.nb, rnd = P.rnd;
     const int64_t b = blockIdx.x % nb, o = blockIdx.x / nb;
     const int64_t s0 = o * LPB;
-    const int64_t jb0 = b * 256 * (int64_t)rnd;
-    if (blockIdx.x == 0 && tid == 0) live[(pidx + 1) % 3] = 0;   // the next launch's counter
+    const int64_t jbb = b * 256 * (int64_t)rnd;
+    if (!LOOP && blockIdx.x == 0 && tid == 0) P.live[(P.pidx + 1) % 3] = 0;   // the next launch's counter
 
+    // LOOP: the slots' state from cur, and pair counts of the slots this wave finishes
+    unsigned long long nacc[2] = {0, 0}, facc[2] = {0, 0};
+    if constexpr (LOOP) {
+        if (tid < LPB) {
+            const int64_t s = s0 + tid;
+            const int32_t l = s < S ? P.cur.line[s] : -1;
+            lline[tid] = l;
+            sl[tid] = l;
+            if (l >= 0) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    sx[tid][k] = P.cur.x[3 * s + k];
+                    sy[tid][k] = P.cur.y[3 * s + k];
+                    lks[tid][k] = P.cur.ks[3 * s + k];
+                }
+                lasum[tid] = P.cur.asum[s];
+                lI[tid] = P.cur.I[s];
+                lns[tid] = P.cur.ns[s];
+                srhs[tid] = P.line_rhs ? P.line_rhs[l] : 0;
+            }
+        }
+        if (tid == 0) sabort = 0;
+        __syncthreads();
+    }
+
+    for (int64_t it = 0;; ++it) {
+    // the block's first panel, opaque in the loop: otherwise the compiler computes the per-lane
+    // record addresses of every round once, before the loop, and holds them in registers
+    int64_t jb0 = jbb, Np = Npa;
+    if (LOOP) asm volatile("" : "+s"(jb0), "+s"(Np));
     // the panel records of the first round do not depend on the step: requested first, so that
     // they arrive while the step waits for its own loads (index clamped to a real panel slot)
     R rx[7], ry[7], rz[7], rw[7];
@@ -90,53 +210,102 @@ __global__ __launch_bounds__(256) void k_lf_pass(
         rc2 = far64[(int64_t)(FR_CC + 2) * Np + j];
         rrr = far64[(int64_t)FR_RR * Np + j];
     }
+    const int step_phase = LOOP ? (it == 0 ? P.step_phase : lf_phase_of(P.pass0 + it - 1)) : P.step_phase;
+    const int eval_phase = LOOP ? lf_phase_of(P.pass0 + it) : P.eval_phase;
+    // records of the pass to finish: part_prev (nb_prev blocks) first, then the loop's own
+    const double* part_rd = (!LOOP || it == 0) ? P.part_prev : ((it & 1) ? P.part_cur : P.part_prev);
+    const int nbr = (!LOOP || it == 0) ? P.nb_prev : nb;
+    double* part_wr = (!LOOP || (it & 1) == 0) ? P.part_cur : const_cast<double*>(P.part_prev);
+    if constexpr (LOOP) {
+        if (it > 0) {   // every block of the group has written its records of the previous pass
+            if (tid == 0) {
+                const uint32_t target = (uint32_t)nb * (uint32_t)it;
+                uint32_t polls = 0;
+                while (__hip_atomic_load(P.gcnt + o * LF_GSTRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (++polls > P.spin_limit) {
+                        sabort = 1;
+                        __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            __syncthreads();
+            if (sabort) break;   // uniform over the block
+        }
+    }
 
     // ---- 1. the previous stage of the group's lines: wave w takes slots w, w + 4 ----
     for (int q = wv; q < LPB; q += 4) {
         const int64_t s = s0 + q;
-        const int32_t l = (s < S) ? cur.line[s] : -1;
+        // the one-stage launch reads the slot's state from cur: requested together with its line
+        // id (slot clamped to [0, S)) rather than after it
+        const int64_t sc = s < S ? s : S - 1;
+        double cst[11];
+        int32_t cns = 0, cl = -1;
+        if constexpr (!LOOP) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cst[k] = P.cur.y[3 * sc + k];
+                cst[3 + k] = P.cur.x[3 * sc + k];
+                cst[6 + k] = P.cur.ks[3 * sc + k];
+            }
+            cst[9] = P.cur.asum[sc];
+            cst[10] = P.cur.I[sc];
+            cns = P.cur.ns[sc];
+            cl = P.cur.line[sc];
+            asm volatile("" ::"v"(cst[0]), "v"(cst[5]), "v"(cst[8]), "v"(cst[9]), "v"(cns), "v"(cl));
+        }
+        const int32_t l = LOOP ? sl[q] : ((s < S) ? cl : -1);
         double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0;
+        double K0 = 0.0, K1 = 0.0, K2 = 0.0, AS = 0.0, II = 0.0;   // LOOP: the slot's new state
+        int32_t NS = 0;
         int32_t lo = -1;   // the line if it goes on
         if (l >= 0) {
-            const double p0 = cur.y[3 * s], p1 = cur.y[3 * s + 1], p2 = cur.y[3 * s + 2];
-            const double q0 = cur.x[3 * s], q1 = cur.x[3 * s + 1], q2 = cur.x[3 * s + 2];
-            if (step_phase < 0) {   // first launch: the start is the query point
+            const double p0 = LOOP ? sy[q][0] : cst[0], p1 = LOOP ? sy[q][1] : cst[1], p2 = LOOP ? sy[q][2] : cst[2];
+            const double q0 = LOOP ? sx[q][0] : cst[3], q1 = LOOP ? sx[q][1] : cst[4], q2 = LOOP ? sx[q][2] : cst[5];
+            if (step_phase < 0) {   // nothing to finish: the query point is evaluated as it is
                 Y0 = p0; Y1 = p1; Y2 = p2;
                 X0 = q0; X1 = q1; X2 = q2;
                 lo = l;
-                if (b == 0 && lane == 0) {
+                if constexpr (LOOP) {
+                    K0 = lks[q][0]; K1 = lks[q][1]; K2 = lks[q][2];
+                    AS = lasum[q]; II = lI[q]; NS = lns[q];
+                }
+                if (!LOOP && b == 0 && lane == 0) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        nxt.x[3 * s + k] = cur.x[3 * s + k];
-                        nxt.y[3 * s + k] = cur.y[3 * s + k];
-                        nxt.ks[3 * s + k] = cur.ks[3 * s + k];
+                        P.nxt.x[3 * s + k] = P.cur.x[3 * s + k];
+                        P.nxt.y[3 * s + k] = P.cur.y[3 * s + k];
+                        P.nxt.ks[3 * s + k] = P.cur.ks[3 * s + k];
                     }
-                    nxt.asum[s] = cur.asum[s];
-                    nxt.I[s] = cur.I[s];
-                    nxt.ns[s] = cur.ns[s];
-                    nxt.line[s] = l;
+                    P.nxt.asum[s] = P.cur.asum[s];
+                    P.nxt.I[s] = P.cur.I[s];
+                    P.nxt.ns[s] = P.cur.ns[s];
+                    P.nxt.line[s] = l;
                 }
             } else {
-                const int32_t ns0 = cur.ns[s];
-                const double asum0 = cur.asum[s], I0 = cur.I[s];
-                const double ks0 = cur.ks[3 * s], ks1 = cur.ks[3 * s + 1], ks2 = cur.ks[3 * s + 2];
+                const int32_t ns0 = LOOP ? lns[q] : cns;
+                const double asum0 = LOOP ? lasum[q] : cst[9], I0 = LOOP ? lI[q] : cst[10];
+                const double ks0 = LOOP ? lks[q][0] : cst[6], ks1 = LOOP ? lks[q][1] : cst[7],
+                             ks2 = LOOP ? lks[q][2] : cst[8];
                 // field at the query point: the partial records in block order, lane k taking blocks k, k + 64
                 double F0 = 0.0, F1 = 0.0, F2 = 0.0, nn = 0.0, tb = 2.0;
                 int jb = INT_MAX;
-                const double* prow = part_prev + s * pstride_part;
-                // both records of the lane (blocks lane and lane + 64; nb_prev <= 128) requested at
+                const double* prow = part_rd + s * pstride_part;
+                // both records of the lane (blocks lane and lane + 64; nbr <= 128) requested at
                 // once, indices clamped into the row and the clamped values dropped
                 double rv[2][LF_REC];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int bb = lane + 64 * u;
-                    const double* r = prow + (int64_t)(bb < nb_prev ? bb : 0) * LF_REC;
+                    const double* r = prow + (int64_t)(bb < nbr ? bb : 0) * LF_REC;
 #pragma unroll
-                    for (int c = 0; c < LF_REC; ++c) rv[u][c] = r[c];
+                    for (int c = 0; c < LF_REC; ++c) rv[u][c] = (LOOP && it > 0) ? lf_load_coh(r + c) : r[c];
                 }
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    if (lane + 64 * u >= nb_prev) continue;
+                    if (lane + 64 * u >= nbr) continue;
                     F0 += rv[u][0];
                     F1 += rv[u][1];
                     F2 += rv[u][2];
@@ -162,9 +331,12 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                     }
                 }
                 const bool own = (b == 0 && lane == 0);   // the writer of the group's lines
-                if (own) {
-                    ncnt[2 * l] += (unsigned long long)nn;
-                    ncnt[2 * l + 1] += (unsigned long long)(N - (int64_t)nn);
+                if constexpr (LOOP) {   // counted here, written once at the end
+                    nacc[q >> 2] += (unsigned long long)nn;
+                    facc[q >> 2] += (unsigned long long)(N - (int64_t)nn);
+                } else if (own) {
+                    P.ncnt[2 * l] += (unsigned long long)nn;
+                    P.ncnt[2 * l + 1] += (unsigned long long)(N - (int64_t)nn);
                 }
                 const int phase = step_phase;
                 const double h = a.h;
@@ -173,7 +345,7 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                 int code = -1;   // -1: the line goes on
                 if (phase == 4) {
                     if (jb != INT_MAX) {   // the step's segment hit a panel: the step is discarded
-                        const int32_t k = body_kind[tri_body[jb]];
+                        const int32_t k = P.body_kind[P.tri_body[jb]];
                         code = (k == BEM_DIRICHLET) ? BEM_STOP_DIRICHLET
                                                     : ((k == BEM_FLOATING) ? BEM_STOP_FLOATING : BEM_STOP_INTERFACE);
                     } else {   // accepted: its end point becomes the line's point
@@ -182,10 +354,10 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                         x1 = p1;
                         x2 = p2;
                         ++ns;
-                        if (path && own) {
-                            path[l * pstride + 3 * ns + 0] = x0;
-                            path[l * pstride + 3 * ns + 1] = x1;
-                            path[l * pstride + 3 * ns + 2] = x2;
+                        if (P.path && own) {
+                            P.path[l * P.pstride + 3 * ns + 0] = x0;
+                            P.path[l * P.pstride + 3 * ns + 1] = x1;
+                            P.path[l * P.pstride + 3 * ns + 2] = x2;
                         }
                         if (ns >= a.max_steps) code = BEM_STOP_MAXSTEPS;
                     }
@@ -228,13 +400,14 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                         if (!(isfinite(y0) && isfinite(y1) && isfinite(y2))) code = BEM_STOP_NONFINITE;
                     }
                 }
-                if (own) {
-                    if (code >= 0) {
-                        n_steps[l] = ns;
-                        stop_code[l] = code;
-                        if (integral) integral[l] = I;
-                        if (exceeds) exceeds[l] = (I > a.k_str) ? 1 : 0;
-                    }
+                if (own && code >= 0) {
+                    P.n_steps[l] = ns;
+                    P.stop_code[l] = code;
+                    if (P.integral) P.integral[l] = I;
+                    if (P.exceeds) P.exceeds[l] = (I > a.k_str) ? 1 : 0;
+                }
+                if (!LOOP && own) {
+                    LFState nxt = P.nxt;
                     nxt.x[3 * s] = x0;
                     nxt.x[3 * s + 1] = x1;
                     nxt.x[3 * s + 2] = x2;
@@ -253,31 +426,35 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                     lo = l;
                     Y0 = y0; Y1 = y1; Y2 = y2;
                     X0 = x0; X1 = x1; X2 = x2;
+                    K0 = k0; K1 = k1; K2 = k2;
+                    AS = asum; II = I; NS = ns;
                 }
             }
-        } else if (s < S && b == 0 && lane == 0) {
-            nxt.line[s] = -1;   // an empty slot stays empty in the other buffer
+        } else if (!LOOP && s < S && b == 0 && lane == 0) {
+            P.nxt.line[s] = -1;   // an empty slot stays empty in the other buffer
         }
         if (lane == 0) {
             sl[q] = lo;
-            srhs[q] = (lo >= 0 && line_rhs) ? line_rhs[lo] : 0;
+            if (!LOOP) srhs[q] = (lo >= 0 && P.line_rhs) ? P.line_rhs[lo] : 0;
             sy[q][0] = Y0; sy[q][1] = Y1; sy[q][2] = Y2;
             sx[q][0] = X0; sx[q][1] = X1; sx[q][2] = X2;
+            if constexpr (LOOP) {
+                lks[q][0] = K0; lks[q][1] = K1; lks[q][2] = K2;
+                lasum[q] = AS; lI[q] = II; lns[q] = NS;
+            }
         }
     }
     __syncthreads();
-    if (b == 0 && tid == 0) {   // lines of the group still live after this step
+    if (!LOOP && b == 0 && tid == 0) {   // lines of the group still live after this step
         int nl = 0;
         for (int q = 0; q < LPB; ++q) nl += sl[q] >= 0 ? 1 : 0;
-        if (nl > 0) atomicAdd(live + pidx, nl);
+        if (nl > 0) atomicAdd(P.live + P.pidx, nl);
     }
     bool any = false;
     for (int q = 0; q < LPB; ++q) any |= sl[q] >= 0;
-    if (!any) {   // uniform over the block
-        kclock_stop(kts);
-        return;
-    }
-    const bool hit_stage = (step_phase == 3);   // the query points are proposed end points
+    if (!any) break;   // uniform over the block, and over the group's blocks
+    if (LOOP && P.pass0 + it >= P.max_pass) break;   // not reached: the step limit stops every line first
+    const bool hit_stage = (eval_phase == 4);   // the query points are proposed end points
 
     // ---- 2a. regular pairs, one panel per lane; near pairs queued per (slot, wave) ----
     double acc[LPB][3];
@@ -383,13 +560,26 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                 }
                 const int64_t j = jb0 + nq[q][w][i];
                 const double* Tj = tri64 + (int64_t)TRI_REC * j;
-                if constexpr (NODAL) {
+                if constexpr (NODAL && LOOP) {
+                    const LFVec3 E = nodal_tri_E_call(Tj, p0, p1, p2, sol[ntri[3 * j]], sol[ntri[3 * j + 1]],
+                                                      sol[ntri[3 * j + 2]]);
+                    n0 += E.x;
+                    n1 += E.y;
+                    n2 += E.z;
+                } else if constexpr (NODAL) {
                     double ph = 0.0;
                     nodal_tri_phiE(Tj, p0, p1, p2, sol[ntri[3 * j]], sol[ntri[3 * j + 1]], sol[ntri[3 * j + 2]], ph,
                                    n0, n1, n2);
                 } else {
                     double F0, F1, F2;
-                    flat_tri_F_seq(Tj, p0, p1, p2, F0, F1, F2);
+                    if constexpr (LOOP) {
+                        const LFVec3 F = flat_tri_F_call(Tj, p0, p1, p2);
+                        F0 = F.x;
+                        F1 = F.y;
+                        F2 = F.z;
+                    } else {
+                        flat_tri_F_seq(Tj, p0, p1, p2, F0, F1, F2);
+                    }
                     const double sg = sig[j];
                     n0 = fma(sg, F0, n0);
                     n1 = fma(sg, F1, n1);
@@ -445,15 +635,52 @@ __global__ __launch_bounds__(256) void k_lf_pass(
                 tb = nred[q][u][3];
                 jb = nredj[q][u];
             }
-        double* rec = part_cur + (s0 + q) * pstride_part + b * LF_REC;
-        rec[0] = e[0];
-        rec[1] = e[1];
-        rec[2] = e[2];
-        rec[3] = tb;
-        rec[4] = (double)jb;
-        rec[5] = (double)(nqc[q][0] + nqc[q][1] + nqc[q][2] + nqc[q][3]);
+        double* rec = part_wr + (s0 + q) * pstride_part + b * LF_REC;
+        const double rv[LF_REC] = {e[0], e[1], e[2], tb, (double)jb,
+                                   (double)(nqc[q][0] + nqc[q][1] + nqc[q][2] + nqc[q][3])};
+#pragma unroll
+        for (int c = 0; c < LF_REC; ++c) {
+            if constexpr (LOOP)
+                lf_store_coh(rec + c, rv[c]);
+            else
+                rec[c] = rv[c];
+        }
     }
-    kclock_stop(kts);
+    if constexpr (LOOP) {
+        // the records (all written by wave 0) complete before the group counts this block
+        if (wv == 0) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (tid == 0)
+                __hip_atomic_fetch_add(P.gcnt + o * LF_GSTRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        break;
+    }
+    }   // passes
+    if constexpr (LOOP) {   // the pair counts of the lines this wave finished
+        for (int q = wv; q < LPB; q += 4) {
+            const int32_t l = lline[q];
+            if (b == 0 && lane == 0 && l >= 0) {
+                P.ncnt[2 * l] += nacc[q >> 2];
+                P.ncnt[2 * l + 1] += facc[q >> 2];
+            }
+        }
+    }
+    kclock_stop(P.kts);
+}
+
+template <typename R, int LPB, bool NODAL>
+__global__ __launch_bounds__(256) void k_lf_pass(LFArgs P) {
+    lf_run<R, LPB, NODAL, false>(P);
+}
+
+template <typename R, int LPB, bool NODAL>
+__global__ __launch_bounds__(256) void k_lf_loop(LFArgs P) {
+    lf_run<R, LPB, NODAL, true>(P);
+}
+
+__global__ void k_lf_zero_u32(int64_t m, uint32_t* __restrict__ v) {
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) v[i] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_lf_init(int64_t L, const double* __restrict__ starts, LFState s,
@@ -564,7 +791,69 @@ __global__ __launch_bounds__(256) void k_lf_count_sum(int64_t L, const unsigned 
     }
 }
 
-inline int lf_phase_of(int64_t pass) { return pass == 0 ? 0 : (int)((pass - 1) % 4) + 1; }
+// the persistent loop's kernel for a precision and a block shape
+const void* lf_loop_kernel(bool nodal, bool fp64, int lpb) {
+#define BEM_LK(R, ND)                                                                                    \
+    (lpb == 1 ? reinterpret_cast<const void*>(&k_lf_loop<R, 1, ND>)                                      \
+              : lpb == 2 ? reinterpret_cast<const void*>(&k_lf_loop<R, 2, ND>)                           \
+                         : lpb == 4 ? reinterpret_cast<const void*>(&k_lf_loop<R, 4, ND>)                \
+                                    : reinterpret_cast<const void*>(&k_lf_loop<R, 8, ND>))
+    return nodal ? BEM_LK(double, true) : (fp64 ? BEM_LK(double, false) : BEM_LK(float, false));
+#undef BEM_LK
+}
+
+// Every remaining pass of the slots [0, S) in one persistent launch (k_lf_loop): the fewest line
+// slots per block whose grid the GPU holds at once, which a cooperative launch guarantees, and
+// one 256-panel round per block where the panel count allows.  Waits for the launch and raises
+// an error if one of its waits reached its bound.  Returns false, launching nothing, when no
+// block shape fits.
+template <typename MakeArgs>
+bool fused_loop_launch(bem_ctx* c, bool nodal, bool fp64, int64_t S, int64_t N, MakeArgs&& args) {
+    int cus = 0;
+    BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    // shapes by the pairs a thread evaluates per pass (slots x rounds), fewer slots first: a block
+    // evaluates its slots one after another, while the groups of one slot run side by side and
+    // leave the launch as their lines stop
+    static const int shapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {1, 4}, {2, 2}, {4, 1}, {2, 4}, {4, 2}, {8, 1},
+                                    {4, 4}, {8, 2}, {8, 4}};
+    for (const auto& sh : shapes) {
+        const int lpb = sh[0], rnd = sh[1];
+        if ((c->tune_trace_lpb > 0 && lpb != c->tune_trace_lpb) || (c->tune_trace_rnd > 0 && rnd != c->tune_trace_rnd))
+            continue;
+        const int nb = fused_trace_blocks(N, rnd);
+        if (nb == 0) continue;
+        const void* f = lf_loop_kernel(nodal, fp64, lpb);
+        int per_cu = 0;
+        BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0));
+        const int64_t grid = ceil_div(S, lpb) * nb;
+        if (grid > (int64_t)per_cu * cus) continue;
+        LFArgs P = args(lpb, rnd, nb);
+        // the arrival counters (one per slot group, LF_GSTRIDE apart) and the error flag after them
+        // (the flag's place is fixed by the slot count the buffers were laid out for, which folds
+        // may since have lowered)
+        const int64_t nz = (int64_t)(reinterpret_cast<uint32_t*>(P.err) - P.gcnt) + 1;
+        hipLaunchKernelGGL(k_lf_zero_u32, dim3(1), dim3(256), 0, c->stream, nz, P.gcnt);
+        BEM_CHECK_LAUNCH();
+        hipEvent_t fa = nullptr, fb = nullptr;
+        const bool timed = c->profiling == 1;
+        if (timed) {
+            timing_events(c, &fa, &fb);
+            BEM_HIP(hipEventRecord(fa, c->stream));
+        }
+        void* kargs[] = {&P};
+        BEM_HIP(hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(256), kargs, 0, c->stream));
+        if (timed) {
+            BEM_HIP(hipEventRecord(fb, c->stream));
+            push_timing(c, "trace_pass", fa, fb);
+        }
+        int32_t* host = c->host_stage.as<int32_t>() + 32;
+        BEM_HIP(hipMemcpyAsync(host, P.err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        BEM_HIP(hipStreamSynchronize(c->stream));
+        if (*host != 0) throw Error(BEM_ERR_HIP, "field lines: a wait between the blocks of the persistent pass loop reached its bound");
+        return true;
+    }
+    return false;
+}
 
 }  // namespace
 
@@ -604,13 +893,22 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
         while (*rnd < LF_RNDMAX && fused_trace_blocks(N, *rnd) == 0) *rnd *= 2;
     };
     const int64_t prs = (int64_t)LF_NBMAX * LF_REC;   // partial row stride per slot
-    // two partial buffers, the fold map, three live counters
-    c->lf_part.alloc(sizeof(double) * 2 * (size_t)prs * (size_t)S + sizeof(int32_t) * ((size_t)S + 64));
+    // two partial buffers, the fold map, three live counters; the persistent loop's arrival
+    // counters (one per slot group) and error flag
+    c->lf_part.alloc(sizeof(double) * 2 * (size_t)prs * (size_t)S +
+                     sizeof(int32_t) * ((size_t)S + 64 + (size_t)LF_GSTRIDE * ((size_t)S + 1)));
     double* part[2] = {c->lf_part.as<double>(), c->lf_part.as<double>() + prs * S};
     int32_t* src_of = reinterpret_cast<int32_t*>(part[1] + prs * S);
     int32_t* live = src_of + S;
+    uint32_t* gcnt = reinterpret_cast<uint32_t*>(live + 64);
+    int32_t* err = reinterpret_cast<int32_t*>(gcnt + LF_GSTRIDE * S);
     hipLaunchKernelGGL(k_lf_zero3, dim3(1), dim3(64), 0, c->stream, live);
     BEM_CHECK_LAUNCH();
+    if (c->coop_launch < 0) {
+        int v = 0;
+        BEM_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, c->device));
+        c->coop_launch = v ? 1 : 0;
+    }
     LFState buf[2] = {buf0, buf1};
     // nodal basis (one load case): records whose node weights carry the density, with a density
     // of one per panel, in FP64 in either precision; the near pairs read the vertex values
@@ -650,7 +948,7 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
             ++tail;
         }
         if (known == 0) break;
-        if (known <= S / 2 && S >= 16 && p > 0) {
+        if (known <= S / 2 && p > 0) {
             // fold the live slots to the front: state of buffer rd and partial rows of buffer pw ^ 1
             // (those of the last launch) into the other buffers, which become the current ones
             hipLaunchKernelGGL(k_lf_fold_map, dim3(1), dim3(1024), 0, c->stream, S, known, buf[rd].line, src_of);
@@ -662,38 +960,85 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
             pw ^= 1;
             S = known;
         }
+        // the arguments of a launch that finishes pass pass0 + p - 1 and evaluates pass pass0 + p
+        auto args = [&](int lpb, int rnd, int nb) {
+            LFArgs P;
+            P.far64 = F64;
+            P.farR = fp64 ? static_cast<const void*>(F64) : static_cast<const void*>(c->far32.as<float>());
+            P.Np = Np;
+            P.N = N;
+            P.tri64 = c->tri64.as<double>();
+            P.tri_body = c->tri_body.as<int32_t>();
+            P.body_kind = c->body_kind.as<int32_t>();
+            P.fsol = fsol;
+            P.fn = fn;
+            P.sol = sol;
+            P.n = c->n;
+            P.line_rhs = line_rhs;
+            P.ntri = c->tri.as<int32_t>();
+            P.step_phase = p == 0 ? -1 : lf_phase_of(pass0 + p - 1);
+            P.eval_phase = lf_phase_of(pass0 + p);
+            P.nb_prev = nb_prev;
+            P.nb = nb;
+            P.rnd = rnd;
+            P.S = S;
+            P.pstride_part = prs;
+            P.cur = buf[rd];
+            P.nxt = buf[rd ^ 1];
+            P.part_prev = part[pw ^ 1];
+            P.part_cur = part[pw];
+            P.a = a;
+            P.n_steps = n_steps;
+            P.stop_code = stop_code;
+            P.integral = integral;
+            P.exceeds = exceeds;
+            P.path = path;
+            P.pstride = pstride;
+            P.ncnt = ncnt;
+            P.live = live;
+            P.pidx = (int)(p % 3);
+            P.pass0 = pass0 + p;
+            P.max_pass = max_pass;
+            P.gcnt = gcnt;
+            P.err = err;
+            P.spin_limit = (uint32_t)c->tune_trace_spin;
+            P.kts = kclock_slot(c, "trace_pass");
+            (void)lpb;
+            return P;
+        };
+        // every remaining pass in one persistent launch, once the slots fit the GPU at once
+        if (S <= c->tune_trace_loop && c->coop_launch > 0) {
+            if (fused_loop_launch(c, nodal, fp64, S, N, args)) {
+                ++c->trace_pass_launches;
+                break;
+            }
+        }
         int lpb, rnd;
         shape(S, &lpb, &rnd);
         const int nb = fused_trace_blocks(N, rnd);
-        const int step_phase = p == 0 ? -1 : lf_phase_of(pass0 + p - 1);
-        const int pidx = (int)(p % 3);
+        const LFArgs P = args(lpb, rnd, nb);
         const dim3 grid((unsigned)(nb * ceil_div(S, lpb)));
         // timing: events carried in the dispatch (profiling mode 1) or the kernel's own clock (mode 2)
         hipEvent_t fa = nullptr, fb = nullptr;
         const bool timed = c->profiling == 1;
         if (timed) timing_events(c, &fa, &fb);
-        unsigned long long* kts = kclock_slot(c, "trace_pass");
-#define BEM_LF(R, LPB, ND, FR)                                                                                      \
-    hipExtLaunchKernelGGL((k_lf_pass<R, LPB, ND>), grid, dim3(256), 0, c->stream, fa, fb, 0, F64, FR, Np, N,          \
-                          c->tri64.as<double>(), c->tri_body.as<int32_t>(), c->body_kind.as<int32_t>(), fsol, fn, sol, \
-                          c->n, line_rhs, c->tri.as<int32_t>(), step_phase, nb_prev, nb, rnd, S, prs, buf[rd],         \
-                          buf[rd ^ 1], part[pw ^ 1], part[pw], a, n_steps, stop_code, integral, exceeds, path,         \
-                          pstride, ncnt, live, pidx, kts)
-#define BEM_LF_LPB(R, ND, FR)    \
-    if (lpb == 1)                \
-        BEM_LF(R, 1, ND, FR);    \
-    else if (lpb == 2)           \
-        BEM_LF(R, 2, ND, FR);    \
-    else if (lpb == 4)           \
-        BEM_LF(R, 4, ND, FR);    \
-    else                         \
-        BEM_LF(R, 8, ND, FR)
+#define BEM_LF(R, LPB, ND) \
+    hipExtLaunchKernelGGL((k_lf_pass<R, LPB, ND>), grid, dim3(256), 0, c->stream, fa, fb, 0, P)
+#define BEM_LF_LPB(R, ND)    \
+    if (lpb == 1)            \
+        BEM_LF(R, 1, ND);    \
+    else if (lpb == 2)       \
+        BEM_LF(R, 2, ND);    \
+    else if (lpb == 4)       \
+        BEM_LF(R, 4, ND);    \
+    else                     \
+        BEM_LF(R, 8, ND)
         if (nodal) {
-            BEM_LF_LPB(double, true, F64);
+            BEM_LF_LPB(double, true);
         } else if (fp64) {
-            BEM_LF_LPB(double, false, F64);
+            BEM_LF_LPB(double, false);
         } else {
-            BEM_LF_LPB(float, false, c->far32.as<float>());
+            BEM_LF_LPB(float, false);
         }
 #undef BEM_LF_LPB
 #undef BEM_LF
@@ -703,6 +1048,7 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
         rd ^= 1;
         pw ^= 1;
         nb_prev = nb;
+        const int pidx = (int)(p % 3);
         if ((p & 15) == 15) {   // this launch's live count, read back without waiting
             if (head - tail == NEV) {   // ring full: take the oldest
                 const int k = tail % NEV;

@@ -222,6 +222,50 @@ def test_coax_trace_stop_codes(bem, mode):
     c.close()
 
 
+@pytest.mark.parametrize("loop", [0, 64])
+def test_tail_starts_on_a_hit_step(bem, loop):
+    """The one-launch tail takes over after pass 31 (live counts are read every 32 passes), so
+    its first launch evaluates the end point of step 8 (pass 32).  With h = 0.0105 from the coax
+    rod, 26 of 32 lines cross the shell during step 8: the step's segment must be tested against
+    the near panels in that first launch, and the lines must stop there (7 steps, Dirichlet
+    hit) as in the oracle.  Both forms of the tail: one launch per stage (trace_loop 0) and one
+    persistent launch."""
+    p = coax_problem(0.012)
+    _say(f"tail from a hit step, trace_loop {loop}")
+    c, o, x, x_ref = _sigma_case(bem, p)
+    c.set_tuning("trace_mode", 0)
+    c.set_tuning("trace_tail", 4096)
+    c.set_tuning("trace_loop", loop)
+    starts, _, _ = electrode_line_starts(p, 32, seed=3)
+    I, ns, st = _trace_compare(bem, c, o, x, starts, dict(h=0.0105, max_steps=12))
+    assert ((ns == 7) & (st == 1)).sum() >= 20
+    c.close()
+
+
+def test_persistent_tail_wait_bound(bem):
+    """A bound of zero polls on the persistent launch's waits between blocks (forced from the
+    host): the call either reports that a wait reached its bound or, had no wait needed a poll,
+    returns the oracle's results; the context traces correctly afterwards either way."""
+    p = coax_problem(0.012)
+    c, o, x, x_ref = _sigma_case(bem, p)
+    c.set_tuning("trace_mode", 3)
+    c.set_tuning("trace_loop", 64)   # the 16 lines in one persistent launch from the start
+    starts, _, _ = electrode_line_starts(p, 16, seed=21)
+    kw = dict(h=1e-3, max_steps=100)
+    sol = torch.tensor(x, device="cuda")
+    c.set_tuning("trace_spin", 0)
+    try:
+        ns, st, _ = c.trace_lines(sol, starts, bem.trace_params(**kw))
+        raised = False
+    except bem.BemError as e:
+        assert "bound" in str(e)
+        raised = True
+    _say(f"zero-poll bound raised: {raised}")
+    c.set_tuning("trace_spin", 1 << 22)
+    _trace_compare(bem, c, o, x, starts, kw)
+    c.close()
+
+
 _LAYOUT_REF = {}
 
 
@@ -243,11 +287,21 @@ _LAYOUT_REF = {}
     dict(trace_mode=3, trace_lpb=8, trace_rnd=4),
     dict(trace_mode=3, trace_lpb=8, trace_rnd=1),
     dict(trace_mode=3),
+    # all 16 lines in one persistent launch from the first stage
+    dict(trace_mode=3, trace_loop=64),
+    dict(trace_mode=3, trace_loop=64, trace_lpb=2, trace_rnd=2),
+    # the same, one launch per stage to the end (no persistent launch)
+    dict(trace_mode=3, trace_loop=0, trace_lpb=1, trace_rnd=1),
+    dict(trace_mode=3, trace_loop=0, trace_lpb=4, trace_rnd=2),
+    dict(trace_mode=3, trace_loop=0),
     # the default: two kernels, then one launch per stage once at most trace_tail lines are live
     dict(trace_mode=0, trace_tail=8),
     dict(trace_mode=0, trace_tail=16),
+    dict(trace_mode=0, trace_tail=16, trace_loop=0),
 ], ids=["split2", "split4", "split8", "tile64", "tile128", "tile256", "split4_few8",
-        "fused_l1r1", "fused_l2r4", "fused_l4r2", "fused_l8r4", "fused_l8r1", "fused_auto", "tail8", "tail16"])
+        "fused_l1r1", "fused_l2r4", "fused_l4r2", "fused_l8r4", "fused_l8r1", "fused_auto", "loop_auto", "loop_l2r2",
+    "stage_l1r1", "stage_l4r2",
+    "stage_auto", "tail8", "tail16", "tail16_stage"])
 def test_trace_layouts(bem, layout):
     """Every tile shape of the two-kernel layout (the split far passes at 2, 4 and 8 waves per
     chunk, the unsplit ones at 64, 128 and 256 lines per block, the few-line tail) and of the
