@@ -841,7 +841,15 @@ bool fused_loop_launch(bem_ctx* c, bool nodal, bool fp64, int64_t S, int64_t N, 
             BEM_HIP(hipEventRecord(fa, c->stream));
         }
         void* kargs[] = {&P};
-        BEM_HIP(hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(256), kargs, 0, c->stream));
+        const hipError_t le = hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(256), kargs, 0, c->stream);
+        if (le != hipSuccess) {   // refused (nothing launched): the caller goes on one launch per stage
+            (void)hipGetLastError();
+            if (timed) {
+                c->event_pool.push_back(fa);
+                c->event_pool.push_back(fb);
+            }
+            return false;
+        }
         if (timed) {
             BEM_HIP(hipEventRecord(fb, c->stream));
             push_timing(c, "trace_pass", fa, fb);
