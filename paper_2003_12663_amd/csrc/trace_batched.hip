@@ -345,6 +345,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
     // every load of the sweep is issued before any is used (indices clamped into the row, the
     // clamped values dropped below): left conditional, each would wait for the one before
     double pr[LB_MREG][3];
+    const int32_t A = count[0];
 #pragma unroll
     for (int t = 0; t < LB_MREG; ++t) {
         const int64_t k = tid + 256 * t;
@@ -354,6 +355,11 @@ __global__ __launch_bounds__(256) void k_lb_step(
         pr[t][2] = prow[3 * kp + 2];
         mreg[t] = mrow[km];
     }
+    // a stage-point pass (phase 1 or 2) never stops a line: its slot in the next pass is drawn
+    // now, while the sweep's loads are in flight, rather than after the step
+    const bool goes_on = (phase == 1 || phase == 2);
+    int32_t sn_early = 0;
+    if (goes_on && tid == 0 && b < A) sn_early = atomicAdd(count_next, 1);
 #pragma unroll
     for (int t = 0; t < LB_MREG; ++t) {
         const int64_t k = tid + 256 * t;
@@ -373,7 +379,6 @@ __global__ __launch_bounds__(256) void k_lb_step(
         }
         if (k < KS) cnt += __popc(mrow[k]);
     }
-    const int32_t A = count[0];
     if (b >= A) return;   // uniform over the block
     const double* sigma = sol + (line_rhs ? (int64_t)line_rhs[l] : 0) * n;
     const bool hit_pass = (phase == 4);
@@ -390,11 +395,11 @@ __global__ __launch_bounds__(256) void k_lb_step(
     for (int w = 0; w < wv; ++w) wbase += scan[w];
     const int total = scan[0] + scan[1] + scan[2] + scan[3];
     const int off = wbase + incl - cnt;
-    if (tid == 0) {   // the line's own pair counters (one block per line and pass: no atomics)
-        ncnt[2 * l] += (unsigned long long)total;
+    if (tid == 0) {   // the line's own pair counters, added without waiting for them
+        atomicAdd(ncnt + 2 * l, (unsigned long long)total);
         // every other panel of this line was a regular pair of the chunked far pass (k_lb_far);
         // the panel-stationary few-line pass (KSP != KS) is not counted
-        if (KSP == KS) ncnt[2 * l + 1] += (unsigned long long)(N - total);
+        if (KSP == KS) atomicAdd(ncnt + 2 * l + 1, (unsigned long long)(N - total));
     }
     double n0 = 0.0, n1 = 0.0, n2 = 0.0, bt = 2.0;
     int bj = INT_MAX;
@@ -554,7 +559,7 @@ __global__ __launch_bounds__(256) void k_lb_step(
         if (integral) integral[l] = I;
         if (exceeds) exceeds[l] = (I > a.k_str) ? 1 : 0;
     } else {
-        const int32_t sn = atomicAdd(count_next, 1);
+        const int32_t sn = goes_on ? sn_early : atomicAdd(count_next, 1);
         nxt.x[3 * sn] = x0;
         nxt.x[3 * sn + 1] = x1;
         nxt.x[3 * sn + 2] = x2;

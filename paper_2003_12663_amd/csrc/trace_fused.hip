@@ -334,9 +334,9 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
                 if constexpr (LOOP) {   // counted here, written once at the end
                     nacc[q >> 2] += (unsigned long long)nn;
                     facc[q >> 2] += (unsigned long long)(N - (int64_t)nn);
-                } else if (own) {
-                    P.ncnt[2 * l] += (unsigned long long)nn;
-                    P.ncnt[2 * l + 1] += (unsigned long long)(N - (int64_t)nn);
+                } else if (own) {   // added without waiting for them
+                    atomicAdd(P.ncnt + 2 * l, (unsigned long long)nn);
+                    atomicAdd(P.ncnt + 2 * l + 1, (unsigned long long)(N - (int64_t)nn));
                 }
                 const int phase = step_phase;
                 const double h = a.h;
