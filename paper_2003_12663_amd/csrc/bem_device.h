@@ -72,13 +72,14 @@ __device__ __forceinline__ void flat_tri_SF(const double* __restrict__ T, double
         const double sp = sm + len;
         const double t = q0 * m0 + q1 * m1 + q2 * m2;
         const double Rm = Rv[e], Rp = Rv[b];
-        double f;
-        if (sm < 0.0 && sp > 0.0)   // foot within the edge's span: R- + s- = R0^2 / (R- - s-), no cancellation
-            f = log((Rp + sp) * (Rm - sm) / (t * t + w * w));
-        else if (sp + sm > 0.0)
-            f = log((Rp + sp) / (Rm + sm));
-        else
-            f = log((Rm - sm) / (Rp - sp));
+        // the quotient under the logarithm by case, picked before the one division and logarithm
+        // (lanes of one wave that take different cases would otherwise run each case's in turn):
+        // foot within the edge's span, R- + s- = R0^2 / (R- - s-) without cancellation; else the
+        // side without cancellation
+        const bool span = sm < 0.0 && sp > 0.0, fwd = sp + sm > 0.0;
+        const double num = span ? (Rp + sp) * (Rm - sm) : (fwd ? Rp + sp : Rm - sm);
+        const double den = span ? t * t + w * w : (fwd ? Rm + sm : Rp - sp);
+        const double f = log(num / den);
         st += t * f;
         m0s += m0 * f;
         m1s += m1 * f;

@@ -108,13 +108,14 @@ __device__ __forceinline__ void flat_tri_F_seq(const double* __restrict__ T, dou
         const double vb0 = bx - x0, vb1 = by - x1, vb2 = bz - x2;
         const double Rm = sqrt(va0 * va0 + va1 * va1 + va2 * va2);
         const double Rp = sqrt(vb0 * vb0 + vb1 * vb1 + vb2 * vb2);
-        double f;
-        if (sm < 0.0 && sp > 0.0)
-            f = log((Rp + sp) * (Rm - sm) / (t * t + w * w));
-        else if (sp + sm > 0.0)
-            f = log((Rp + sp) / (Rm + sm));
-        else
-            f = log((Rm - sm) / (Rp - sp));
+        // the quotient under the logarithm by case, picked before the one division and logarithm
+        // (lanes of one wave that take different cases would otherwise run each case's in turn):
+        // foot within the edge's span, R- + s- = R0^2 / (R- - s-) without cancellation; else the
+        // side without cancellation
+        const bool span = sm < 0.0 && sp > 0.0, fwd = sp + sm > 0.0;
+        const double num = span ? (Rp + sp) * (Rm - sm) : (fwd ? Rp + sp : Rm - sm);
+        const double den = span ? t * t + w * w : (fwd ? Rm + sm : Rp - sp);
+        const double f = log(num / den);
         m0s += m0 * f;
         m1s += m1 * f;
         m2s += m2 * f;
