@@ -811,11 +811,14 @@ template <typename MakeArgs>
 bool fused_loop_launch(bem_ctx* c, bool nodal, bool fp64, int64_t S, int64_t N, MakeArgs&& args) {
     int cus = 0;
     BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-    // shapes by the pairs a thread evaluates per pass (slots x rounds), fewer slots first: a block
-    // evaluates its slots one after another, while the groups of one slot run side by side and
-    // leave the launch as their lines stop
-    static const int shapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {1, 4}, {2, 2}, {4, 1}, {2, 4}, {4, 2}, {8, 1},
-                                    {4, 4}, {8, 2}, {8, 4}};
+    // shapes by the pairs a thread evaluates per pass (slots x rounds), one round first (a second
+    // round's records are loaded again every pass).  A grid of at most one block per CU first: a
+    // CU holding two blocks takes twice as long over each pass, and every block waits for it
+    // (measured on the 19,732-panel coax, us a stage: 4 slots 12.9 with one slot a block, 312
+    // blocks, against 10.9 with two, 156 blocks; 3 slots 9.4 with one slot a block, 234 blocks)
+    static const int shapes[][2] = {{1, 1}, {2, 1}, {1, 2}, {4, 1}, {2, 2}, {1, 4}, {8, 1}, {4, 2}, {2, 4},
+                                    {8, 2}, {4, 4}, {8, 4}};
+    for (int pass = 0; pass < 2; ++pass)
     for (const auto& sh : shapes) {
         const int lpb = sh[0], rnd = sh[1];
         if ((c->tune_trace_lpb > 0 && lpb != c->tune_trace_lpb) || (c->tune_trace_rnd > 0 && rnd != c->tune_trace_rnd))
@@ -826,7 +829,7 @@ bool fused_loop_launch(bem_ctx* c, bool nodal, bool fp64, int64_t S, int64_t N, 
         int per_cu = 0;
         BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0));
         const int64_t grid = ceil_div(S, lpb) * nb;
-        if (grid > (int64_t)per_cu * cus) continue;
+        if (grid > (int64_t)per_cu * cus || (pass == 0 && grid > cus)) continue;
         LFArgs P = args(lpb, rnd, nb);
         // the arrival counters (one per slot group, LF_GSTRIDE apart) and the error flag after them
         // (the flag's place is fixed by the slot count the buffers were laid out for, which folds
