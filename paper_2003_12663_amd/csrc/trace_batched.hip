@@ -325,6 +325,9 @@ __global__ __launch_bounds__(256) void k_lb_step(
     __shared__ int32_t scan[4];
     __shared__ double red[4][4];
     __shared__ int32_t redj[4];
+    // a latency chain that shares its CUs with the other line group's far pass: its waves issue
+    // first, and the far pass's waves fill the cycles it spends waiting
+    __builtin_amdgcn_s_setprio(3);
     const int64_t b = blockIdx.x;   // < the group's slot count (the grid is sized by an upper bound)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
