@@ -13,6 +13,8 @@
 // so that the divergent work runs on its own (Sec. 4, deferred near pass).
 // Pass 3 forms the constraint rows of floating bodies (Eq. Final4) and the
 // -1 columns of their potentials (Eq. Final2).
+#include <algorithm>
+
 #include "bem_device.h"
 
 namespace bem {
@@ -187,18 +189,35 @@ __global__ __launch_bounds__(256) void k_near(const double* __restrict__ tri64, 
 // with (c_self, c_kp) = (1/2, 1) for a closed body (Eq. Final4, eps+ (sigma/2 + K' sigma), scaled
 // by 1/(eps+ sum a_i)) and (1, 2 (eps+ - eps-) / (eps+ + eps-)) for a thin sheet (Eq. sheets,
 // (eps+ + eps-)/2 sigma + (eps+ - eps-) K' sigma, scaled by 2/((eps+ + eps-) sum a_i)).
+// The body's rows s0..s1 are cut into slabs of `per` rows, one per grid row y, each summed in
+// order into part[y][j] (and its area sum into apart[y]); k_constraint_sum adds the slabs in order.
 __global__ __launch_bounds__(256) void k_constraint(const double* __restrict__ Kf, int64_t N,
                                                     const int32_t* __restrict__ rows_flt, int64_t s0, int64_t s1,
-                                                    const double* __restrict__ tri64, double c_self, double c_kp,
-                                                    double* __restrict__ out) {
+                                                    int64_t per, const double* __restrict__ tri64, double c_self,
+                                                    double c_kp, double* __restrict__ part,
+                                                    double* __restrict__ apart) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t y = blockIdx.y;
+    const int64_t a0 = s0 + y * per, a1 = (a0 + per < s1) ? a0 + per : s1;
+    double acc = 0.0, asum = 0.0;
+    for (int64_t s = a0; s < a1; ++s) {
+        const int64_t i = rows_flt[s];
+        const double a = tri64[(int64_t)TRI_REC * i + TR_A];
+        if (j < N) acc += a * (c_kp * Kf[s * N + j] + (i == j ? c_self : 0.0));
+        asum += a;
+    }
+    if (j < N) part[y * N + j] = acc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) apart[y] = asum;
+}
+
+__global__ __launch_bounds__(256) void k_constraint_sum(int64_t N, int64_t slabs, const double* __restrict__ part,
+                                                        const double* __restrict__ apart, double* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= N) return;
     double acc = 0.0, asum = 0.0;
-    for (int64_t s = s0; s < s1; ++s) {
-        const int64_t i = rows_flt[s];
-        const double a = tri64[(int64_t)TRI_REC * i + TR_A];
-        acc += a * (c_kp * Kf[s * N + j] + (i == j ? c_self : 0.0));
-        asum += a;
+    for (int64_t y = 0; y < slabs; ++y) {
+        acc += part[y * N + j];
+        asum += apart[y];
     }
     out[j] = acc / asum;
 }
@@ -389,11 +408,21 @@ void launch_finalize(bem_ctx* c) {
         int64_t s1 = s0;
         while (s1 < (int64_t)c->h_rows_flt.size() && c->h_tri_body[c->h_rows_flt[s1]] == fb) ++s1;
         // Eq. sheets for a sheet whatever the constraint form; Eq. Final4 literal for a closed body
-        if (c->h_body_kind[fb] == BEM_FLOATING_SHEET || c->opt.constraint_form == 0)
-            hipLaunchKernelGGL(k_constraint, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream,
-                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(),
-                               c->h_flt_coef[2 * f], c->h_flt_coef[2 * f + 1], tail + (int64_t)f * ld);
-        else
+        if (c->h_body_kind[fb] == BEM_FLOATING_SHEET || c->opt.constraint_form == 0) {
+            // rows in slabs over a second grid dimension, so that about 1024 blocks stream the
+            // body's K' block (one block row alone used a third of the CUs)
+            const int64_t cb = ceil_div(N, 256), rows = s1 - s0;
+            const int64_t slabs = std::max<int64_t>(1, std::min<int64_t>(rows, 1024 / cb));
+            const int64_t per = ceil_div(std::max<int64_t>(rows, 1), slabs);
+            c->cons_part.alloc(sizeof(double) * (size_t)(slabs * N + slabs));
+            double* part = c->cons_part.as<double>();
+            hipLaunchKernelGGL(k_constraint, dim3((unsigned)cb, (unsigned)slabs), dim3(256), 0, c->stream,
+                               c->Kf.as<double>(), N, c->rows_flt.as<int32_t>(), s0, s1, per, c->tri64.as<double>(),
+                               c->h_flt_coef[2 * f], c->h_flt_coef[2 * f + 1], part, part + slabs * N);
+            BEM_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_constraint_sum, dim3((unsigned)cb), dim3(256), 0, c->stream, N, slabs, part,
+                               part + slabs * N, tail + (int64_t)f * ld);
+        } else
             hipLaunchKernelGGL(k_constraint_reduced, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, c->stream, N,
                                c->rows_flt.as<int32_t>(), s0, s1, c->tri64.as<double>(), tail + (int64_t)f * ld);
         BEM_CHECK_LAUNCH();

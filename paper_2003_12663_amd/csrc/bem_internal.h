@@ -149,6 +149,7 @@ struct bem_ctx {
     bem::DBuf pan64, pan32;                 // far64 / far32 panel-major: [Np][FAR_REC]
     bem::DBuf rows_pot, rows_int, rows_flt, row_slot;
     bem::DBuf A64, A32, Kf;                 // dense operator (FP64 or FP32) and the K' block of floating rows
+    bem::DBuf cons_part;                    // slab sums of a floating body's constraint row
     bem::DBuf nearmask, near_ptr, near_row, near_col, near_val;
     bem::DBuf diag;
     int64_t near_nnz = 0;
