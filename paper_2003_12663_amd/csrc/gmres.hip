@@ -27,13 +27,18 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int6
     if (threadIdx.x == 0) part[(int64_t)k * G + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// h[k] = sum_b part[k * G + b];  H[k] (+)= h[k]
-__global__ void k_reduce_parts(const double* __restrict__ part, int G, int kcount, double* __restrict__ h,
-                               double* __restrict__ Hcol, int accumulate, int take_sqrt) {
-    const int k = threadIdx.x + blockIdx.x * blockDim.x;
+// h[k] = sum_b part[k * G + b];  H[k] (+)= h[k].  One wave per k: lane l sums b = l, l + 64, ...
+// in order, then a fixed-order butterfly (a thread summing all G partials in turn was a chain of
+// G dependent adds behind their loads).
+__global__ __launch_bounds__(64) void k_reduce_parts(const double* __restrict__ part, int G, int kcount,
+                                                     double* __restrict__ h, double* __restrict__ Hcol, int accumulate,
+                                                     int take_sqrt) {
+    const int k = blockIdx.x;
     if (k >= kcount) return;
     double s = 0.0;
-    for (int b = 0; b < G; ++b) s += part[(int64_t)k * G + b];
+    for (int b = threadIdx.x; b < G; b += 64) s += part[(int64_t)k * G + b];
+    s = wave_sum(s);
+    if (threadIdx.x != 0) return;
     if (take_sqrt) s = sqrt(s);
     h[k] = s;
     if (Hcol) Hcol[k] = accumulate ? Hcol[k] + s : s;
@@ -181,7 +186,7 @@ int gmres_core(Work& W, const double* b, double* x, double tol, int max_iter, in
                 for (int pass = 0; pass < 2; ++pass) {
                     hipLaunchKernelGGL(k_dots, dim3(W.G, j + 1), dim3(256), 0, W.s, W.V, W.vs, n, W.w, W.part, W.G);
                     BEM_CHECK_LAUNCH();
-                    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)ceil_div(j + 1, 64)), dim3(64), 0, W.s, W.part,
+                    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)(j + 1)), dim3(64), 0, W.s, W.part,
                                        W.G, j + 1, W.h, W.Hcol, pass, 0);
                     BEM_CHECK_LAUNCH();
                     hipLaunchKernelGGL(k_orth_update, W.g1(), dim3(256), 0, W.s, W.V, W.vs, n, j + 1, W.h, W.w);
