@@ -111,6 +111,7 @@ struct bem_ctx {
     hipStream_t aux_stream = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     hipEvent_t lf_ev[8] = {};   // live-count read-backs of the one-launch-per-stage tracer
+    hipEvent_t lb_ev[4] = {};   // live-count read-backs of the two-kernel tracer (2 checkpoints x 2 groups)
     bem_options opt{};
     int64_t N = 0, n = 0, ld = 0, n_vert = 0;
     // rows that carry a body's density: N panels, or n_vert vertices for the LINEAR basis; in
@@ -225,6 +226,8 @@ struct bem_ctx {
         if (join_ev) (void)hipEventDestroy(join_ev);
         if (aux_stream) (void)hipStreamDestroy(aux_stream);
         for (hipEvent_t e : lf_ev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : lb_ev)
             if (e) (void)hipEventDestroy(e);
     }
 };

@@ -609,6 +609,12 @@ __global__ __launch_bounds__(256) void k_lb_merge(LBState s, int32_t* __restrict
     }
 }
 
+// slots [count, S) of a buffer hold no line (line -1)
+__global__ __launch_bounds__(256) void k_lb_clear_slots(int32_t* __restrict__ line, const int32_t* __restrict__ count,
+                                                        int64_t S) {
+    for (int64_t s = (int64_t)count[0] + threadIdx.x; s < S; s += 256) line[s] = -1;
+}
+
 __global__ __launch_bounds__(256) void k_lb_zero_u64(int64_t m, unsigned long long* __restrict__ v) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < m) v[i] = 0;
@@ -822,6 +828,20 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
     kclock_begin(c, (max_pass + 2) * (G + 1));
     int cur = 0;
     int32_t* host = c->host_stage.as<int32_t>();
+    // pending count copies: checkpoint parity x group (host slots 8 + 2 parity + group)
+    for (int k = 0; k < 4; ++k)
+        if (!c->lb_ev[k]) BEM_HIP(hipEventCreateWithFlags(&c->lb_ev[k], hipEventDisableTiming));
+    bool pend[2][2] = {{false, false}, {false, false}};
+    int ck = 0;
+    // wait for the copies in flight and drop their counts
+    auto settle = [&]() {
+        for (int k = 0; k < 2; ++k)
+            for (int g = 0; g < 2; ++g)
+                if (pend[k][g]) {
+                    BEM_HIP(hipEventSynchronize(c->lb_ev[2 * k + g]));
+                    pend[k][g] = false;
+                }
+    };
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
         // Profiling: the far pass is timed at every launch by events carried in its dispatch
@@ -915,30 +935,65 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         }
         cur ^= 1;
         if ((pass & 31) == 31 || pass == max_pass - 1) {
+            // Live counts every 32 passes.  Those of this checkpoint are copied without waiting, and
+            // those of the checkpoint before (32 passes back, normally arrived) are taken, so the
+            // GPU never waits for the host; a count only falls, so an older one is an upper bound,
+            // and the kernels read the exact counts on the device.  The last pass reads its own.
             int64_t live = 0;
-            for (int32_t g = 0; g < G; ++g)
-                if (grp[g].known > 0)
-                    BEM_HIP(hipMemcpyAsync(host + g, grp[g].cnt[cur], sizeof(int32_t), hipMemcpyDeviceToHost,
-                                           grp[g].st));
-            for (int32_t g = 0; g < G; ++g)
-                if (grp[g].known > 0) {
-                    BEM_HIP(hipStreamSynchronize(grp[g].st));
-                    grp[g].known = host[g];
-                    live += host[g];
-                }
+            const bool last = pass == max_pass - 1;
+            if (last) {
+                for (int32_t g = 0; g < G; ++g)
+                    if (grp[g].known > 0)
+                        BEM_HIP(hipMemcpyAsync(host + g, grp[g].cnt[cur], sizeof(int32_t), hipMemcpyDeviceToHost,
+                                               grp[g].st));
+                for (int32_t g = 0; g < G; ++g)
+                    if (grp[g].known > 0) {
+                        BEM_HIP(hipStreamSynchronize(grp[g].st));
+                        grp[g].known = host[g];
+                    }
+            } else {
+                for (int32_t g = 0; g < G; ++g)
+                    if (grp[g].known > 0) {
+                        BEM_HIP(hipMemcpyAsync(host + 8 + 2 * ck + g, grp[g].cnt[cur], sizeof(int32_t),
+                                               hipMemcpyDeviceToHost, grp[g].st));
+                        BEM_HIP(hipEventRecord(c->lb_ev[2 * ck + g], grp[g].st));
+                        pend[ck][g] = true;
+                    }
+                ck ^= 1;
+                for (int32_t g = 0; g < G; ++g)
+                    if (pend[ck][g]) {
+                        BEM_HIP(hipEventSynchronize(c->lb_ev[2 * ck + g]));
+                        grp[g].known = std::min<int64_t>(grp[g].known, host[8 + 2 * ck + g]);
+                        pend[ck][g] = false;
+                    }
+            }
+            for (int32_t g = 0; g < G; ++g) live += grp[g].known;
             if (live == 0) break;
             // fold group 1 into group 0 once all live lines fit one tile and group 0's slot range
-            // (both streams are idle here: the counts above were read after synchronising them)
+            // (the merge on group 0's stream after everything enqueued on group 1's; counts copied
+            // before it no longer describe the groups)
             if (G > 1 && c->tune_trace_fold && grp[1].known > 0 && live <= std::min<int64_t>(64, grp[1].lo)) {
+                BEM_HIP(hipEventRecord(c->fork_ev, grp[1].st));
+                BEM_HIP(hipStreamWaitEvent(grp[0].st, c->fork_ev, 0));
                 hipLaunchKernelGGL(k_lb_merge, dim3(1), dim3(256), 0, grp[0].st, buf[cur], grp[0].cnt[cur],
                                    grp[1].cnt[cur], grp[1].lo);
                 BEM_CHECK_LAUNCH();
                 grp[0].known = live;
                 grp[1].known = 0;
+                settle();
             }
             // the last few lines (all in group 0's slots [0, live)) go on one launch per stage,
             // from the next pass, with their own pair counters
             if (fused_tail && live <= c->tune_trace_tail && (G == 1 || grp[1].known == 0)) {
+                settle();
+                if (G > 1) {   // group 1's stream may still hold its last (empty) passes
+                    BEM_HIP(hipEventRecord(c->fork_ev, grp[1].st));
+                    BEM_HIP(hipStreamWaitEvent(c->stream, c->fork_ev, 0));
+                }
+                // live is an upper bound: slots from the device's live count on hold no line
+                hipLaunchKernelGGL(k_lb_clear_slots, dim3(1), dim3(256), 0, c->stream, buf[cur].line, grp[0].cnt[cur],
+                                   live);
+                BEM_CHECK_LAUNCH();
                 c->lf_cnt.alloc(sizeof(unsigned long long) * 2 * (size_t)L);
                 unsigned long long* fcnt = c->lf_cnt.as<unsigned long long>();
                 hipLaunchKernelGGL(k_lb_zero_u64, dim3((unsigned)ceil_div(2 * L, 256)), dim3(256), 0, c->stream,
@@ -953,6 +1008,7 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
             }
         }
     }
+    settle();   // the staging slots are the context's: no copy may land after this call
     if (G > 1) {   // the counts below need both groups' step kernels
         BEM_HIP(hipEventRecord(c->join_ev, c->aux_stream));
         BEM_HIP(hipStreamWaitEvent(c->stream, c->join_ev, 0));
