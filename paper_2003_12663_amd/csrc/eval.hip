@@ -7,9 +7,10 @@
 //   LDS and read by broadcast; 7-point rule for regular pairs, near pairs
 //   masked by select.  The panel range is split over blockIdx.y so that few
 //   points still fill the GPU; each split writes its own partial sums.
-// k_eval_finish: one lane per point: sums the partials in a fixed order and
-//   adds its near pairs (closed forms, FP64) from the CSR list, plus the
-//   exterior jump sigma n / 2 for on-surface points.
+// k_eval_finish: one wave per point: its lanes share the partials and the
+//   point's near pairs (closed forms, FP64) from the CSR list, summed over the
+//   wave in a fixed order, plus the exterior jump sigma n / 2 for on-surface
+//   points.
 #include "bem_device.h"
 
 namespace bem {
@@ -108,10 +109,11 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ 
                                                      const double* __restrict__ tri64, const double* __restrict__ sigma,
                                                      const double* __restrict__ pts, const int32_t* __restrict__ on_panel,
                                                      double* __restrict__ phi_out, double* __restrict__ E_out) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // wave-uniform
+    const int lane = threadIdx.x & 63;
     if (p >= P) return;
     double phi = 0.0, e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    for (int k = 0; k < KS; ++k) {
+    for (int k = lane; k < KS; k += 64) {
         const double* o = part + ((int64_t)k * P + p) * 4;
         phi += o[0];
         e0 += o[1];
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ 
     }
     const double x0 = pts[3 * p], x1 = pts[3 * p + 1], x2 = pts[3 * p + 2];
     const int64_t op = on_panel ? on_panel[p] : -1;
-    for (int64_t e = nptr[p]; e < nptr[p + 1]; ++e) {
+    for (int64_t e = nptr[p] + lane; e < nptr[p + 1]; e += 64) {
         const int64_t j = ncol[e];
         double S, F0, F1, F2;
         flat_tri_SF<true, true>(tri64 + (int64_t)TRI_REC * j, x0, x1, x2, j == op, S, F0, F1, F2);
@@ -130,6 +132,11 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ 
         e1 = fma(s, F1, e1);
         e2 = fma(s, F2, e2);
     }
+    phi = wave_sum(phi);
+    e0 = wave_sum(e0);
+    e1 = wave_sum(e1);
+    e2 = wave_sum(e2);
+    if (lane != 0) return;
     if (op >= 0) {
         const double* T = tri64 + (int64_t)TRI_REC * op;
         const double hs = 0.5 * sigma[op];
@@ -201,7 +208,7 @@ void launch_eval(bem_ctx* c, const double* sigma, int64_t P, const double* pts, 
     }
     {
         KTimer t(c, "eval_near");
-        hipLaunchKernelGGL(k_eval_finish, dim3((unsigned)ceil_div(P, 256)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_eval_finish, dim3((unsigned)ceil_div(P, 4)), dim3(256), 0, c->stream,
                            c->ev_part.as<double>(), (int)KS, P, c->ev_ptr.as<int64_t>(), c->ev_col.as<int32_t>(),
                            c->tri64.as<double>(), sigma, pts, on_panel, phi, E);
         BEM_CHECK_LAUNCH();
