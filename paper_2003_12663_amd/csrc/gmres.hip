@@ -54,6 +54,40 @@ __global__ __launch_bounds__(256) void k_orth_update(const double* __restrict__ 
     w[i] = s;
 }
 
+// the second orthogonalisation pass with the block partials of |w|^2 of its output: one element
+// per thread and block b covering [256 b, 256 b + 256), the partition k_dots takes when its G
+// blocks cover n at one element per thread, so the norm is the same to the bit
+__global__ __launch_bounds__(256) void k_orth_update_norm(const double* __restrict__ V, int64_t vstride, int64_t n,
+                                                          int kcount, const double* __restrict__ h,
+                                                          double* __restrict__ w, double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    if (i < n) {
+        s = w[i];
+        for (int k = 0; k < kcount; ++k) s -= h[k] * V[k * vstride + i];
+        w[i] = s;
+    }
+    double q = fma(s, s, 0.0);
+    q = wave_sum(q);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// the next Krylov vector out = w / (*nrm) and the product's input z = out / d of the next
+// iteration (both left untouched if the norm is zero)
+__global__ __launch_bounds__(256) void k_scale_div(const double* __restrict__ w, const double* __restrict__ nrm,
+                                                   const double* __restrict__ d, int64_t n, double* __restrict__ out,
+                                                   double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double v = *nrm;
+    if (i >= n || v == 0.0) return;
+    const double o = w[i] / v;
+    out[i] = o;
+    z[i] = o / d[i];
+}
+
 // out = w / (*nrm) (left untouched if the norm is zero)
 __global__ __launch_bounds__(256) void k_scale_by_norm(const double* __restrict__ w, const double* __restrict__ nrm,
                                                        int64_t n, double* __restrict__ out) {
@@ -172,11 +206,16 @@ int gmres_core(Work& W, const double* b, double* x, double tol, int max_iter, in
         std::fill(H.begin(), H.end(), 0.0);
         g[0] = beta;
         int jend = 0;
+        // the norm's block partials from the second orthogonalisation pass and the next product's
+        // input from the scaling, when the dot products' blocks cover w at one element per thread
+        const bool fused = W.G == ceil_div(n, 256);
         for (int j = 0; j < m; ++j) {
             KTimer tj(c, "gmres_iter");
             double* Vj = W.V + (int64_t)j * W.vs;
-            hipLaunchKernelGGL(k_div_diag, W.g1(), dim3(256), 0, W.s, Vj, d, n, W.z);
-            BEM_CHECK_LAUNCH();
+            if (j == 0 || !fused) {   // else the scaling that made V[j] also wrote z
+                hipLaunchKernelGGL(k_div_diag, W.g1(), dim3(256), 0, W.s, Vj, d, n, W.z);
+                BEM_CHECK_LAUNCH();
+            }
             if (W.transpose)
                 launch_matvec_t(c, W.z, W.w, W.s);
             else
@@ -189,12 +228,26 @@ int gmres_core(Work& W, const double* b, double* x, double tol, int max_iter, in
                     hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)(j + 1)), dim3(64), 0, W.s, W.part,
                                        W.G, j + 1, W.h, W.Hcol, pass, 0);
                     BEM_CHECK_LAUNCH();
-                    hipLaunchKernelGGL(k_orth_update, W.g1(), dim3(256), 0, W.s, W.V, W.vs, n, j + 1, W.h, W.w);
+                    if (fused && pass == 1)
+                        hipLaunchKernelGGL(k_orth_update_norm, W.g1(), dim3(256), 0, W.s, W.V, W.vs, n, j + 1, W.h,
+                                           W.w, W.part);
+                    else
+                        hipLaunchKernelGGL(k_orth_update, W.g1(), dim3(256), 0, W.s, W.V, W.vs, n, j + 1, W.h, W.w);
                     BEM_CHECK_LAUNCH();
                 }
-                device_norm(W, W.w, W.Hcol + j + 1);
-                hipLaunchKernelGGL(k_scale_by_norm, W.g1(), dim3(256), 0, W.s, W.w, W.Hcol + j + 1, n,
-                                   W.V + (int64_t)(j + 1) * W.vs);
+                if (fused) {
+                    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, W.s, W.part, W.G, 1, W.Hcol + j + 1,
+                                       (double*)nullptr, 0, 1);
+                    BEM_CHECK_LAUNCH();
+                } else {
+                    device_norm(W, W.w, W.Hcol + j + 1);
+                }
+                if (fused && j + 1 < m)
+                    hipLaunchKernelGGL(k_scale_div, W.g1(), dim3(256), 0, W.s, W.w, W.Hcol + j + 1, d, n,
+                                       W.V + (int64_t)(j + 1) * W.vs, W.z);
+                else
+                    hipLaunchKernelGGL(k_scale_by_norm, W.g1(), dim3(256), 0, W.s, W.w, W.Hcol + j + 1, n,
+                                       W.V + (int64_t)(j + 1) * W.vs);
                 BEM_CHECK_LAUNCH();
             }
             BEM_HIP(hipMemcpyAsync(W.host, W.Hcol, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, W.s));

@@ -833,7 +833,8 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
         if (!c->lb_ev[k]) BEM_HIP(hipEventCreateWithFlags(&c->lb_ev[k], hipEventDisableTiming));
     bool pend[2][2] = {{false, false}, {false, false}};
     int ck = 0;
-    // wait for the copies in flight and drop their counts
+    // wait for the copies in flight and drop their counts; also on every exit, an error thrown
+    // by a launch included (the staging slots are the context's: no copy may land after this call)
     auto settle = [&]() {
         for (int k = 0; k < 2; ++k)
             for (int g = 0; g < 2; ++g)
@@ -842,6 +843,15 @@ void launch_trace_batched(bem_ctx* c, int32_t nrhs, const double* sol, int64_t L
                     pend[k][g] = false;
                 }
     };
+    struct Settle {
+        bem_ctx* c;
+        bool (*pend)[2];
+        ~Settle() {
+            for (int k = 0; k < 2; ++k)
+                for (int g = 0; g < 2; ++g)
+                    if (pend[k][g]) (void)hipEventSynchronize(c->lb_ev[2 * k + g]);
+        }
+    } settle_on_exit{c, pend};
     for (int64_t pass = 0; pass < max_pass; ++pass) {
         const int phase = pass == 0 ? 0 : (int)((pass - 1) % 4) + 1;
         // Profiling: the far pass is timed at every launch by events carried in its dispatch
