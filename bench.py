@@ -17,8 +17,12 @@ timed by the kernel itself (profiling mode 2: the earliest block start to the
 latest wave end on the device's wall clock; nothing else is timed).  Events
 carried in the dispatch would also count the wait for the other line group's
 kernel on the second stream (2.2 us a launch more than rocprofv3 measured on
-the same box).  The timed steps themselves run with nothing profiled.  The per-phase breakdown comes from one more step after
-those, with every kernel timed.  cpu_baseline times
+the same box).  The timed steps themselves run with nothing profiled.
+phase_ms_per_step (and trace_ms_per_step) come from three more unprofiled steps,
+the host clock read after each call (assemble, solve, eval_field,
+streamer_integral) has finished; kernel_ms_profiled_step from one more step
+with every kernel timed by events (which slow the two-stream tracer, so its
+"trace" entry exceeds the unprofiled one).  cpu_baseline times
 the plain FP64 CPU oracle, compiled on the host with -march=native, on a
 bounded sample of the same workload.  The 64-load-case time-to-solve stops
 each path at the loosest tolerance that brings sigma within 1e-5 of the
@@ -623,8 +627,6 @@ def main():
                                                 "finalize", "gemv", "gmres_ortho", "gmres_iter", "eval_mask",
                                                 "eval_near_csr", "eval_far", "eval_near", "trace", "trace_far",
                                                 "trace_step", "trace_pass")}
-    tr_n, tr_ms = stats["trace"]
-    trace_ms = tr_ms / max(tr_n, 1)
     # dominant kernel: the far-field pass of the field-line tracer (k_lb_far), one launch per RK4 stage,
     # every launch of a repeat of the timed steps timed by its own clock stamps (profiling mode 2)
     far_flop_per_launch = far_pairs * FLOP_FIELD_PAIR / far_launches
@@ -634,7 +636,31 @@ def main():
     gemv_ms = gv_ms / max(gv_n, 1)
     gemv_gbs = (8.0 * n_unk * n_unk) / (gemv_ms * 1e-3) / 1e9
     fa_n, fa_ms = stats["far_assemble"]
-    phases = {k: v[1] for k, v in stats.items()}   # one profiled step after the timed ones
+    kernel_ms = {k: v[1] for k, v in stats.items()}   # one profiled step after the timed ones
+
+    # wall time of each phase, unprofiled: a few more steps with the host clock read after each
+    # call has finished (each call depends on the one before, so the synchronisations add little
+    # more than the launch latency of the next call's first kernel)
+    wall = {"assemble": 0.0, "solve": 0.0, "eval_field": 0.0, "trace": 0.0}
+    n_wall = 3
+    for _ in range(n_wall):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ctx.assemble()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        sol, info = ctx.solve(p.body_V, tol=1e-10, max_iter=5000)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        ctx.eval_field(sol, cen, on_panel=on_panel, want_phi=False)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        ctx.streamer_integral(sol, starts, tp)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        for k, dt in zip(wall, (tb - ta, tc - tb, td - tc, te - td)):
+            wall[k] += dt * 1e3 / n_wall
+    trace_ms = wall["trace"]
 
     extras = {}
     if not args.no_extras:
@@ -682,7 +708,8 @@ def main():
         "assembly_pairs_per_s": pairs_matrix / (fa_ms / max(fa_n, 1) * 1e-3),
         "gemv_GBps": gemv_gbs,
         "gemv_frac_hbm": gemv_gbs / HBM_PEAK_GBS,
-        "phase_ms_per_step": phases,
+        "phase_ms_per_step": wall,
+        "kernel_ms_profiled_step": kernel_ms,
         "streamer_integral_sum": float(I.sum().item()),
         "stop_code_counts": {str(k): int(np.sum(st_h == k)) for k in range(6)},
         "roofline": {"kernel": ("k_lf_pass (one launch per RK4 stage of the field lines: the previous stage's "
