@@ -159,7 +159,7 @@ struct bem_ctx {
     // scratch
     bem::DBuf gm_V, gm_w, gm_z, gm_h, gm_part, gm_x, gm_r, gm_b, gm_misc;
     bem::HBuf host_stage;
-    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part, lf_part, lf_cnt;
+    bem::DBuf ev_part, ev_mask, ev_ptr, ev_col, ev_row, ev_tmp, tr_queue, lb_state, lb_part, lf_part, lf_loop, lf_cnt;
 
     bem::DBuf bg_V, bg_W, bg_part, bg_small, bg_z, bg_B, bg_X, gemm_part, rows_part;   // batched GMRES
     bem::DBuf near_sf;   // S, F of the near list by the near-singular rule (near_rule 1)

@@ -39,7 +39,6 @@ namespace {
 constexpr int LF_REC = 6;        // partial record: E (3), hit parameter (2: none), hit panel, near pairs
 constexpr int LF_RNDMAX = 4;     // 256-panel rounds per block at most
 constexpr int LF_NBMAX = 128;    // panel blocks of a launch at most
-constexpr int LF_GSTRIDE = 64;   // persistent loop: arrival counters 256 bytes apart (one per slot group)
 
 // the RK4 phase of pass p: 0 the start point, then 1, 2, 3 (stage points) and 4 (a step's end point)
 __host__ __device__ inline int lf_phase_of(int64_t pass) { return pass == 0 ? 0 : (int)((pass - 1) % 4) + 1; }
@@ -78,10 +77,11 @@ struct LFArgs {
     unsigned long long* ncnt;
     int32_t* live;         // one-stage launch: live-line counters (three, used in turn)
     int pidx;
-    // persistent loop: passes pass0 .., the arrival counter of each slot group, the error flag
-    // and the bound of every wait (polls)
+    // persistent loop: passes pass0 .., its three record buffers (lstride doubles apart, every
+    // word the sentinel at the start), the error flag and the bound of every wait (polls)
     int64_t pass0, max_pass;
-    uint32_t* gcnt;
+    double* lbuf;
+    int64_t lstride;
     int32_t* err;
     uint32_t spin_limit;
     unsigned long long* kts;
@@ -114,18 +114,33 @@ __device__ __forceinline__ void lf_store_coh(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The persistent loop's "not written yet" word: a signalling NaN with its own payload.  Every
+// record word is an arithmetic result (IEEE arithmetic returns quiet NaNs) or an integer
+// converted to double, so no record ever holds it.
+constexpr unsigned long long LF_SENT = 0x7FF4C0DE5EA1ED00ull;
+__device__ __forceinline__ bool lf_is_sent(double v) {
+    return (unsigned long long)__double_as_longlong(v) == LF_SENT;
+}
+
+__global__ __launch_bounds__(256) void k_lf_fill_sent(int64_t m, unsigned long long* __restrict__ v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) v[i] = LF_SENT;
+}
+
 // One stage per launch (LOOP false) or every remaining stage in one launch (LOOP true), for the
 // lines in slots [0, S).  Grid: (panel block b, slot group o) blocks, b fastest.
 //
 // LOOP: the blocks of slot group o keep the group's line state in LDS (each block its own copy,
-// all computed alike) and loop over the passes.  After writing its records of a pass, a block
-// waits until its stores have completed and counts itself in gcnt[o]; before finishing the pass
-// it waits until all nb blocks of the group have done so.  Records go through coherent stores
-// and loads into two buffers used in turn: a block overwrites the buffer of pass p - 1 only at
-// pass p + 1, after every block of the group has counted itself for pass p, which it does after
-// reading the records of pass p - 1.  Every wait is bounded (spin_limit polls); at the bound the
-// block raises err and leaves, and so, at their own bounds, do the blocks waiting for it.  The
-// grid must be resident at once (cooperative launch).
+// all computed alike) and loop over the passes.  The records themselves carry the signal: the
+// loop's pass i (i = 0, 1, ...) writes buffer i mod 3 of lbuf, every word of which starts as
+// the sentinel, and a block finishing pass i polls the records of pass i - 1 (coherent loads)
+// until none of their words is the sentinel any more.  A buffer comes round again at pass
+// i + 3; at pass i + 2 each block puts the sentinel back into its own records there (rows of
+// live slots: pass i + 1's records of every block of the group are then in, and each block
+// wrote them after reading those of pass i), and it waits for those stores to land before it
+// stores its records of pass i + 2, which any later reader sees only after them.  Every wait is
+// bounded (spin_limit polls); at the bound the block raises err and leaves, and so, at their
+// own bounds, do the blocks waiting for it.  The grid must be resident at once (cooperative
+// launch).
 template <typename R, int LPB, bool NODAL, bool LOOP>
 __device__ __forceinline__ void lf_run(const LFArgs& P) {
     const double* __restrict__ far64 = P.far64;
@@ -213,27 +228,9 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
     const int step_phase = LOOP ? (it == 0 ? P.step_phase : lf_phase_of(P.pass0 + it - 1)) : P.step_phase;
     const int eval_phase = LOOP ? lf_phase_of(P.pass0 + it) : P.eval_phase;
     // records of the pass to finish: part_prev (nb_prev blocks) first, then the loop's own
-    const double* part_rd = (!LOOP || it == 0) ? P.part_prev : ((it & 1) ? P.part_cur : P.part_prev);
+    const double* part_rd = (!LOOP || it == 0) ? P.part_prev : P.lbuf + ((it - 1) % 3) * P.lstride;
     const int nbr = (!LOOP || it == 0) ? P.nb_prev : nb;
-    double* part_wr = (!LOOP || (it & 1) == 0) ? P.part_cur : const_cast<double*>(P.part_prev);
-    if constexpr (LOOP) {
-        if (it > 0) {   // every block of the group has written its records of the previous pass
-            if (tid == 0) {
-                const uint32_t target = (uint32_t)nb * (uint32_t)it;
-                uint32_t polls = 0;
-                while (__hip_atomic_load(P.gcnt + o * LF_GSTRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                    if (++polls > P.spin_limit) {
-                        sabort = 1;
-                        __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(8);
-                }
-            }
-            __syncthreads();
-            if (sabort) break;   // uniform over the block
-        }
-    }
+    double* part_wr = !LOOP ? P.part_cur : P.lbuf + (it % 3) * P.lstride;
 
     // ---- 1. the previous stage of the group's lines: wave w takes slots w, w + 4 ----
     for (int q = wv; q < LPB; q += 4) {
@@ -296,16 +293,56 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
                 // both records of the lane (blocks lane and lane + 64; nbr <= 128) requested at
                 // once, indices clamped into the row and the clamped values dropped
                 double rv[2][LF_REC];
+                bool rec_ok = true;
+                if (LOOP && it > 0) {
+                    // the loop's own records: polled until the writers' words have replaced the
+                    // sentinel, first word 0 of both records, then every word (the words of a
+                    // record land in any order); a clamped index reads block 0's record, a real one
+                    const double* r0 = prow + (int64_t)(lane < nbr ? lane : 0) * LF_REC;
+                    const double* r1 = prow + (int64_t)(lane + 64 < nbr ? lane + 64 : 0) * LF_REC;
+                    uint32_t polls = 0;
+                    for (;;) {
+                        rv[0][0] = lf_load_coh(r0);
+                        rv[1][0] = lf_load_coh(r1);
+                        const bool w = lf_is_sent(rv[0][0]) || lf_is_sent(rv[1][0]);
+                        if (__ballot(w) == 0) break;   // uniform over the wave
+                        if (++polls > P.spin_limit) {
+                            rec_ok = false;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                    while (rec_ok) {
+                        bool w = false;
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int bb = lane + 64 * u;
-                    const double* r = prow + (int64_t)(bb < nbr ? bb : 0) * LF_REC;
+                        for (int c = 0; c < LF_REC; ++c) {
+                            rv[0][c] = lf_load_coh(r0 + c);
+                            rv[1][c] = lf_load_coh(r1 + c);
+                            w |= lf_is_sent(rv[0][c]) || lf_is_sent(rv[1][c]);
+                        }
+                        if (__ballot(w) == 0) break;
+                        if (++polls > P.spin_limit) {
+                            rec_ok = false;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                    if (!rec_ok && lane == 0) {   // the records are left unused and the loop ends
+                        sabort = 1;
+                        __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                } else {
 #pragma unroll
-                    for (int c = 0; c < LF_REC; ++c) rv[u][c] = (LOOP && it > 0) ? lf_load_coh(r + c) : r[c];
+                    for (int u = 0; u < 2; ++u) {
+                        const int bb = lane + 64 * u;
+                        const double* r = prow + (int64_t)(bb < nbr ? bb : 0) * LF_REC;
+#pragma unroll
+                        for (int c = 0; c < LF_REC; ++c) rv[u][c] = r[c];
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    if (lane + 64 * u >= nbr) continue;
+                    if (lane + 64 * u >= nbr || !rec_ok) continue;
                     F0 += rv[u][0];
                     F1 += rv[u][1];
                     F2 += rv[u][2];
@@ -445,6 +482,7 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
         }
     }
     __syncthreads();
+    if (LOOP && sabort) break;   // uniform over the block
     if (!LOOP && b == 0 && tid == 0) {   // lines of the group still live after this step
         int nl = 0;
         for (int q = 0; q < LPB; ++q) nl += sl[q] >= 0 ? 1 : 0;
@@ -454,6 +492,11 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
     for (int q = 0; q < LPB; ++q) any |= sl[q] >= 0;
     if (!any) break;   // uniform over the block, and over the group's blocks
     if (LOOP && P.pass0 + it >= P.max_pass) break;   // not reached: the step limit stops every line first
+    if (LOOP && it >= 2 && tid < LPB && s0 + tid < S) {   // the sentinel back into this block's records
+        double* rr = P.lbuf + ((it + 1) % 3) * P.lstride + (s0 + tid) * pstride_part + b * LF_REC;
+#pragma unroll
+        for (int c = 0; c < LF_REC; ++c) lf_store_coh(rr + c, __longlong_as_double((long long)LF_SENT));
+    }
     const bool hit_stage = (eval_phase == 4);   // the query points are proposed end points
 
     // ---- 2a. regular pairs, one panel per lane; near pairs queued per (slot, wave) ----
@@ -638,6 +681,8 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
         double* rec = part_wr + (s0 + q) * pstride_part + b * LF_REC;
         const double rv[LF_REC] = {e[0], e[1], e[2], tb, (double)jb,
                                    (double)(nqc[q][0] + nqc[q][1] + nqc[q][2] + nqc[q][3])};
+        // LOOP: the sentinel stores of this pass (same lanes) land before any record word
+        if constexpr (LOOP) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
         for (int c = 0; c < LF_REC; ++c) {
             if constexpr (LOOP)
@@ -646,16 +691,7 @@ __device__ __forceinline__ void lf_run(const LFArgs& P) {
                 rec[c] = rv[c];
         }
     }
-    if constexpr (LOOP) {
-        // the records (all written by wave 0) complete before the group counts this block
-        if (wv == 0) {
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            if (tid == 0)
-                __hip_atomic_fetch_add(P.gcnt + o * LF_GSTRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else {
-        break;
-    }
+    if constexpr (!LOOP) break;
     }   // passes
     if constexpr (LOOP) {   // the pair counts of the lines this wave finished
         for (int q = wv; q < LPB; q += 4) {
@@ -831,11 +867,16 @@ bool fused_loop_launch(bem_ctx* c, bool nodal, bool fp64, int64_t S, int64_t N, 
         const int64_t grid = ceil_div(S, lpb) * nb;
         if (grid > (int64_t)per_cu * cus || (pass == 0 && grid > cus)) continue;
         LFArgs P = args(lpb, rnd, nb);
-        // the arrival counters (one per slot group, LF_GSTRIDE apart) and the error flag after them
-        // (the flag's place is fixed by the slot count the buffers were laid out for, which folds
-        // may since have lowered)
-        const int64_t nz = (int64_t)(reinterpret_cast<uint32_t*>(P.err) - P.gcnt) + 1;
-        hipLaunchKernelGGL(k_lf_zero_u32, dim3(1), dim3(256), 0, c->stream, nz, P.gcnt);
+        // the three record buffers, every word the sentinel, and the error flag cleared
+        P.lstride = S * P.pstride_part;
+        c->lf_loop.alloc(sizeof(double) * 3 * (size_t)P.lstride);
+        P.lbuf = c->lf_loop.as<double>();
+        const int64_t nw = 3 * P.lstride;
+        hipLaunchKernelGGL(k_lf_fill_sent, dim3((unsigned)std::min<int64_t>(ceil_div(nw, 256), 1024)), dim3(256), 0,
+                           c->stream, nw, reinterpret_cast<unsigned long long*>(P.lbuf));
+        BEM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_lf_zero_u32, dim3(1), dim3(256), 0, c->stream, (int64_t)1,
+                           reinterpret_cast<uint32_t*>(P.err));
         BEM_CHECK_LAUNCH();
         hipEvent_t fa = nullptr, fb = nullptr;
         const bool timed = c->profiling == 1;
@@ -904,15 +945,12 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
         while (*rnd < LF_RNDMAX && fused_trace_blocks(N, *rnd) == 0) *rnd *= 2;
     };
     const int64_t prs = (int64_t)LF_NBMAX * LF_REC;   // partial row stride per slot
-    // two partial buffers, the fold map, three live counters; the persistent loop's arrival
-    // counters (one per slot group) and error flag
-    c->lf_part.alloc(sizeof(double) * 2 * (size_t)prs * (size_t)S +
-                     sizeof(int32_t) * ((size_t)S + 64 + (size_t)LF_GSTRIDE * ((size_t)S + 1)));
+    // two partial buffers, the fold map, three live counters and the persistent loop's error flag
+    c->lf_part.alloc(sizeof(double) * 2 * (size_t)prs * (size_t)S + sizeof(int32_t) * ((size_t)S + 64));
     double* part[2] = {c->lf_part.as<double>(), c->lf_part.as<double>() + prs * S};
     int32_t* src_of = reinterpret_cast<int32_t*>(part[1] + prs * S);
     int32_t* live = src_of + S;
-    uint32_t* gcnt = reinterpret_cast<uint32_t*>(live + 64);
-    int32_t* err = reinterpret_cast<int32_t*>(gcnt + LF_GSTRIDE * S);
+    int32_t* err = live + 32;
     hipLaunchKernelGGL(k_lf_zero3, dim3(1), dim3(64), 0, c->stream, live);
     BEM_CHECK_LAUNCH();
     if (c->coop_launch < 0) {
@@ -1010,7 +1048,8 @@ void fused_trace_loop(bem_ctx* c, const double* sol, int64_t L, const int32_t* l
             P.pidx = (int)(p % 3);
             P.pass0 = pass0 + p;
             P.max_pass = max_pass;
-            P.gcnt = gcnt;
+            P.lbuf = nullptr;
+            P.lstride = 0;
             P.err = err;
             P.spin_limit = (uint32_t)c->tune_trace_spin;
             P.kts = kclock_slot(c, "trace_pass");
